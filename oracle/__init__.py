@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for cut-circuit reconstruction -- TEST INFRASTRUCTURE.
+
+A plain, slow, obviously correct implementation of what the reconstruction
+library computes, written from the paper ("Cutting Quantum Circuits to Run on
+Quantum and Classical Platforms", Tang & Martonosi):
+
+* ``statevector``  -- state-vector simulation (Section 2) of whole circuits
+  and of every subcircuit variant (Section 3.1: each Pauli assignment of the
+  cuts initialises and measures the subcircuits differently).
+* ``attribution``  -- variant probabilities -> entry vectors p_{i,k}.
+* ``reconstruct``  -- Eq. 1, the Kronecker sum over all 4^K cut labelings,
+  as a literal loop, per output bin, and as one einsum contraction.
+* ``dd``           -- dynamic definition, Algorithm 1.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the HIP library and must never
+serve as a fallback for it.  numpy float64 throughout.
+
+Every function that has no independent pin says "parity unpinned" in its
+docstring; all functions here are pinned by tests/test_oracle_*.py.
+"""
