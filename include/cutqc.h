@@ -1,0 +1,225 @@
+/*
+ * cutqc.h -- C ABI of the MI355X cut-circuit reconstruction library.
+ *
+ * The library reconstructs the output distribution of a quantum circuit that
+ * has been cut into subcircuits (Tang & Martonosi, "Cutting Quantum Circuits
+ * to Run on Quantum and Classical Platforms").  K wire cuts split an n-qubit
+ * circuit into n_C subcircuits (Section 3.1).  Each subcircuit c is run in
+ * every variant -- each downstream cut end initialised in |0>, |1>, |+> or
+ * |+i>, each upstream cut end measured in the Z, X or Y basis -- and its
+ * variant probabilities are turned into entry vectors E_c(l), one per Pauli
+ * labelling l in {I,X,Y,Z} of the cuts it touches.  Eq. 1 then gives
+ *
+ *     p = 2^-K  sum over all 4^K labellings l  of  kron_c E_c(l restricted to c)
+ *
+ * (the printed Eq. 1 omits the 1/2 per cut of the Pauli decomposition; it is
+ * applied here, once).  Full definition (Section 4.2) builds all 2^n values of
+ * p; dynamic definition (Section 4.3, Algorithm 1) builds 2^{#active} bins per
+ * recursion and zooms into the largest.
+ *
+ * Conventions (all entry points):
+ *  - Subcircuit c has `width` register slots; slot 0 is the most significant
+ *    bit of its outcome index.  init_cut[s] is the id of the cut whose
+ *    downstream end initialises slot s, or -1; meas_cut[s] is the id of the
+ *    cut whose upstream end is measured on slot s, or -1.  Slots with
+ *    meas_cut == -1 are the subcircuit's outputs, n_c of them, in slot order.
+ *    Cut ids are 0..K-1; each appears exactly once as init and once as meas,
+ *    in two different subcircuits.
+ *  - Label digits: I = 0, X = 1, Y = 2, Z = 3.  Row l of E_c is
+ *    sum_j d_j 4^{k_c-1-j} over c's k_c cuts in ascending id order (the
+ *    lowest id is the most significant digit).
+ *  - Variant layout V_c[init][basis][outcome], row-major, shape
+ *    (4^{r_c}, 3^{o_c}, 2^{w_c}): init digits |0>,|1>,|+>,|+i> = 0..3 over the
+ *    init slots (slot order, first most significant), basis digits Z,X,Y =
+ *    0..2 over the measured slots, then the register outcome.
+ *  - Entry layout E_c[l][b], row-major (4^{k_c}, 2^{n_c}), b over c's outputs.
+ *  - Output order: index = concatenation of b_0, b_1, ... with subcircuit 0
+ *    most significant.  An optional out_perm[i] names the uncut qubit carried
+ *    by concatenated bit i; the output is then in uncut-qubit order (qubit 0
+ *    most significant).
+ *
+ * Memory and errors:
+ *  - Pointers documented as "device" are HIP device memory owned by the
+ *    caller; "host" arrays are read during the call only.  The library never
+ *    allocates device memory: every intermediate lives in the caller's
+ *    workspace, whose size the *_workspace_size queries return.
+ *  - All arguments are validated before any launch; on error nothing is
+ *    written and a status < 0 is returned (cq_last_error() has the detail).
+ *    Nothing throws across the ABI and nothing aborts.
+ *  - cq_attribute and cq_reconstruct_fd are asynchronous on `stream`.
+ *    cq_reconstruct_dd synchronises `stream` between recursions and returns
+ *    after the last one.  Calls are thread-safe; calls that share a workspace
+ *    must not overlap.
+ */
+#ifndef CUTQC_H
+#define CUTQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cq_status {
+  CQ_OK = 0,
+  CQ_ERR_ARG = -1,         /* null pointer, bad enum, bad count */
+  CQ_ERR_SHAPE = -2,       /* sizes exceed the limits below */
+  CQ_ERR_CUTMAP = -3,      /* inconsistent cut map */
+  CQ_ERR_MASK = -4,        /* DD masks do not partition a subcircuit's outputs */
+  CQ_ERR_WORKSPACE = -5,   /* workspace missing or too small */
+  CQ_ERR_UNSUPPORTED = -6, /* valid but not supported by this build */
+  CQ_ERR_HIP = -7          /* a HIP runtime call failed */
+} cq_status;
+
+/* Arithmetic of the label contractions.  Entries are always FP64 on input.
+ * CQ_FP64: FP64 operands, FP64 matrix-core products, FP64 output.
+ * CQ_FP32: FP32 operands, FP32 matrix-core products, FP32 output.
+ * CQ_BF16 / CQ_FP16: 16-bit operands, FP32 accumulation, FP32 output.
+ * CQ_BF16_SPLIT / CQ_FP16_SPLIT: each operand x = hi + lo with hi = rn16(x),
+ *   lo = rn16(x - hi); products hi*hi + hi*lo + lo*hi, FP32 accumulation.
+ * The FP16 forms scale every operand column by a power of two so that its
+ * largest magnitude is near 1 and undo it in the FP32 epilogue (exact). */
+typedef enum cq_precision {
+  CQ_FP64 = 0,
+  CQ_FP32 = 1,
+  CQ_BF16 = 2,
+  CQ_BF16_SPLIT = 3,
+  CQ_FP16 = 4,
+  CQ_FP16_SPLIT = 5
+} cq_precision;
+
+#define CQ_MAX_SUBCIRCUITS 8   /* the paper caps cut solutions at 5 (Section 4.1) */
+#define CQ_MAX_CUTS 24         /* K */
+#define CQ_MAX_LOCAL_CUTS 8    /* k_c: at most 4^8 label rows per subcircuit */
+#define CQ_MAX_WIDTH 32        /* register slots per subcircuit */
+#define CQ_MAX_FD_BITS 36      /* n for full definition (2^36 FP32 = 256 GiB) */
+#define CQ_MAX_DD_ACTIVE 36    /* active qubits per DD recursion */
+#define CQ_MAX_DD_R 16         /* DD recursions and list capacity */
+
+typedef struct cq_subcircuit {
+  int32_t width;            /* register slots w_c, 0..CQ_MAX_WIDTH */
+  const int32_t* init_cut;  /* host, length width: cut id or -1 */
+  const int32_t* meas_cut;  /* host, length width: cut id or -1 */
+} cq_subcircuit;
+
+/* Name of a status code (static string). */
+const char* cq_status_string(cq_status s);
+
+/* Detail of the last failing call on the calling thread (static per thread). */
+const char* cq_last_error(void);
+
+/* Host-only check of a cut map (no GPU needed).  Reports K and the total
+ * number of outputs n when the pointers are non-null. */
+cq_status cq_validate_cutmap(int32_t n_sub, const cq_subcircuit* subs, int32_t* n_cuts,
+                             int32_t* n_outputs);
+
+/* ---------------------------------------------------------------------------
+ * Entry attribution (Section 3.1): variant probabilities -> entries.
+ *
+ *   E[l][b] = sum_j prod_t alpha(l_t, j_t)
+ *             * sum_m prod_u sigma(l_u, m_u) * V[j][basis(l)][compose(b, m)]
+ *
+ * t over init slots, u over measured slots; alpha(I) = (1, 1, 0, 0),
+ * alpha(X) = (-1, -1, 2, 0), alpha(Y) = (-1, -1, 0, 2), alpha(Z) = (1, -1, 0, 0)
+ * over the prepared states |0>,|1>,|+>,|+i>; basis(I) = basis(Z) = Z,
+ * basis(X) = X, basis(Y) = Y; sigma(I, m) = 1, otherwise (-1)^m.
+ *
+ * variants: device, FP64, layout V_c above.  entries: device, FP64, layout E_c
+ * above (written whole).  workspace: device, at least
+ * cq_attribute_workspace_size bytes (4^k_c * 2^n_c doubles).  FP64 throughout.
+ * ------------------------------------------------------------------------- */
+cq_status cq_attribute_workspace_size(const cq_subcircuit* sub, size_t* bytes);
+cq_status cq_attribute(const cq_subcircuit* sub, const double* variants, double* entries,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Full-definition reconstruction (Eq. 1, Section 4.2).
+ *
+ * entries: host array of n_sub device pointers, FP64, layout E_c.
+ * out: device, 2^n values, double when prec == CQ_FP64 else float, in
+ *   concatenated order, or uncut-qubit order when out_perm (host, length n,
+ *   a permutation of 0..n-1) is given.
+ * The contraction runs as a sequence of label GEMMs on the matrix cores (the
+ * shared cut labels are the reduction dimension); intermediates live in the
+ * workspace (cq_fd_workspace_size bytes, which may be 0).
+ * ------------------------------------------------------------------------- */
+cq_status cq_fd_workspace_size(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec,
+                               const int32_t* out_perm, size_t* bytes);
+cq_status cq_reconstruct_fd(int32_t n_sub, const cq_subcircuit* subs,
+                            const double* const* entries, cq_precision prec,
+                            const int32_t* out_perm, void* out, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Dynamic-definition reconstruction (Algorithm 1, Section 4.3).
+ *
+ * Masks are per subcircuit; bit i stands for output i of the subcircuit,
+ * i = 0 being its most significant output.  active | merged | fixed must
+ * partition the subcircuit's outputs; fixed_vals gives the zoomed values of
+ * the fixed outputs (other bits must be 0).  Bins of a recursion are indexed
+ * by the active outputs concatenated over subcircuits (subcircuit 0 most
+ * significant, output order inside each), and bin v is the sum of p over all
+ * states that agree with v on the active outputs, take the fixed values on
+ * the fixed outputs and anything on the merged outputs.
+ *
+ * Per recursion the library: sums the entries over the merged outputs at the
+ * fixed values (FP64); contracts the reduced entries in `prec` into the
+ * 2^{#active} bins; when merged outputs remain, takes the 4R largest bins in
+ * working precision, re-evaluates them in FP64 and appends the R largest to
+ * the list L; sorts L (FP64 value descending, then recursion, then bin index),
+ * keeps R entries and pops the head.  The popped bin's active outputs become
+ * fixed at the bin's values and the first max_active[c] of its merged outputs
+ * (output order) become active for the next recursion.  The run stops after R
+ * recursions or when L is empty at a pop.
+ * ------------------------------------------------------------------------- */
+typedef struct cq_dd_instance {
+  int32_t n_sub;
+  const cq_subcircuit* subs;     /* host, n_sub */
+  const double* const* entries;  /* host array of n_sub device pointers, FP64, layout E_c */
+  const uint64_t* active;        /* host, n_sub: recursion-0 masks */
+  const uint64_t* merged;
+  const uint64_t* fixed;
+  const uint64_t* fixed_vals;
+  const int32_t* max_active;     /* host, n_sub: outputs activated per zoom */
+} cq_dd_instance;
+
+typedef struct cq_dd_params {
+  cq_precision prec;  /* arithmetic of the bin contraction */
+  int32_t R;          /* recursions and list capacity, 1..CQ_MAX_DD_R */
+} cq_dd_params;
+
+typedef struct cq_dd_record {  /* one recursion, written by the library */
+  uint64_t active[CQ_MAX_SUBCIRCUITS];
+  uint64_t merged[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
+  int32_t n_active;             /* log2 of the number of bins */
+  double total;                 /* FP64 sum of all bins of the recursion */
+  int32_t n_list;               /* entries of L after the update, before the pop */
+  double list_val[CQ_MAX_DD_R]; /* FP64 values, sorted */
+  int32_t list_rec[CQ_MAX_DD_R];
+  uint64_t list_bin[CQ_MAX_DD_R];
+  int32_t popped;               /* 1 when a bin was popped */
+} cq_dd_record;
+
+/* Workspace for one instance at a time (instances run one after another).
+ * bins_stored != 0 when the caller passes bin buffers (then no bin scratch is
+ * counted). */
+cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
+                               const cq_dd_params* params, int32_t bins_stored, size_t* bytes);
+
+/* records: host, n_inst * R records (instance-major).  bins: NULL, or a host
+ * array of n_inst * R device pointers, each NULL or a buffer of 2^n_active
+ * values (double for CQ_FP64 else float) that receives that recursion's bins.
+ * recursions_done: host, n_inst. */
+cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params* params,
+                            cq_dd_record* records, void* const* bins, int32_t* recursions_done,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTQC_H */

@@ -1,0 +1,43 @@
+/*
+ * cutqc_plan.h -- host-only introspection of the contraction plan behind
+ * cq_reconstruct_fd (and the bin contraction of cq_reconstruct_dd).
+ *
+ * Eq. 1 (Section 3.1) is evaluated as a sequence of batched label GEMMs
+ *   C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n],
+ *   stored at C[z*sCz + m*ldc + n],
+ * and axis permutes dst[i] = alpha * src[sum_a idx_a(i) * sstride[a]], where
+ * idx_a(i) are the digits of i in the mixed radix 2^log2[a] (last fastest).
+ * This entry point reports that plan as JSON so tools and tests can inspect
+ * or replay it without a GPU.  It launches nothing.
+ */
+#ifndef CUTQC_PLAN_H
+#define CUTQC_PLAN_H
+
+#include "cutqc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out_bits: host, n_sub, number of output bits each subcircuit contributes
+ * (NULL: all of its outputs; the dynamic-definition bin contraction passes
+ * the active counts).  out_perm as in cq_reconstruct_fd (NULL: none).
+ * Writes a NUL-terminated JSON object into buf (host, buf_bytes) when it
+ * fits and always sets *needed to the bytes required (including the NUL):
+ *   {"workspace_bytes": W, "work_elem_bytes": 8|4, "flops": F,
+ *    "tensors": [{"loc": "input"|"work"|"out", "index": i, "elems": n,
+ *                 "offset": byte offset (work only)}, ...],
+ *    "steps": [{"op": "gemm", "a", "b", "c", "Z", "M", "N", "K", "sAz", "sAk",
+ *               "sBz", "sBk", "sCz", "ldc", "alpha"} |
+ *              {"op": "permute", "src", "dst", "log2": [...], "sstride": [...],
+ *               "alpha"}, ...]}
+ * Returns CQ_ERR_ARG (with *needed set) when buf is too small. */
+cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec,
+                       const int32_t* out_bits, const int32_t* out_perm, char* buf,
+                       size_t buf_bytes, size_t* needed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTQC_PLAN_H */

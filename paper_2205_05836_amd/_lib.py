@@ -1,0 +1,100 @@
+"""ctypes view of include/cutqc.h.  Loading fails loudly when the built
+library is missing: there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcutqc.so")
+
+CQ_OK = 0
+STATUS = {0: "CQ_OK", -1: "CQ_ERR_ARG", -2: "CQ_ERR_SHAPE", -3: "CQ_ERR_CUTMAP",
+          -4: "CQ_ERR_MASK", -5: "CQ_ERR_WORKSPACE", -6: "CQ_ERR_UNSUPPORTED", -7: "CQ_ERR_HIP"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_split": 3, "fp16": 4, "fp16_split": 5}
+
+MAX_SUBCIRCUITS = 8
+MAX_DD_R = 16
+
+EXPORTED = ["cq_status_string", "cq_last_error", "cq_validate_cutmap",
+            "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
+            "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd"]
+
+
+class cq_subcircuit(C.Structure):
+    _fields_ = [("width", C.c_int32), ("init_cut", C.POINTER(C.c_int32)),
+                ("meas_cut", C.POINTER(C.c_int32))]
+
+
+class cq_dd_instance(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("subs", C.POINTER(cq_subcircuit)),
+                ("entries", C.POINTER(C.c_void_p)),
+                ("active", C.POINTER(C.c_uint64)), ("merged", C.POINTER(C.c_uint64)),
+                ("fixed", C.POINTER(C.c_uint64)), ("fixed_vals", C.POINTER(C.c_uint64)),
+                ("max_active", C.POINTER(C.c_int32))]
+
+
+class cq_dd_params(C.Structure):
+    _fields_ = [("prec", C.c_int), ("R", C.c_int32)]
+
+
+class cq_dd_record(C.Structure):
+    _fields_ = [("active", C.c_uint64 * MAX_SUBCIRCUITS), ("merged", C.c_uint64 * MAX_SUBCIRCUITS),
+                ("fixed", C.c_uint64 * MAX_SUBCIRCUITS),
+                ("fixed_vals", C.c_uint64 * MAX_SUBCIRCUITS),
+                ("n_active", C.c_int32), ("total", C.c_double), ("n_list", C.c_int32),
+                ("list_val", C.c_double * MAX_DD_R), ("list_rec", C.c_int32 * MAX_DD_R),
+                ("list_bin", C.c_uint64 * MAX_DD_R), ("popped", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2205_05836_amd.build` "
+            "(there is no fallback implementation)")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    p = C.c_void_p
+    L.cq_status_string.restype = C.c_char_p
+    L.cq_status_string.argtypes = [st]
+    L.cq_last_error.restype = C.c_char_p
+    L.cq_last_error.argtypes = []
+    L.cq_validate_cutmap.restype = st
+    L.cq_validate_cutmap.argtypes = [C.c_int32, C.POINTER(cq_subcircuit),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.cq_attribute_workspace_size.restype = st
+    L.cq_attribute_workspace_size.argtypes = [C.POINTER(cq_subcircuit), C.POINTER(C.c_size_t)]
+    L.cq_attribute.restype = st
+    L.cq_attribute.argtypes = [C.POINTER(cq_subcircuit), p, p, p, C.c_size_t, p]
+    L.cq_fd_workspace_size.restype = st
+    L.cq_fd_workspace_size.argtypes = [C.c_int32, C.POINTER(cq_subcircuit), C.c_int,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
+    L.cq_reconstruct_fd.restype = st
+    L.cq_reconstruct_fd.argtypes = [C.c_int32, C.POINTER(cq_subcircuit), C.POINTER(C.c_void_p),
+                                    C.c_int, C.POINTER(C.c_int32), p, p, C.c_size_t, p]
+    L.cq_dd_workspace_size.restype = st
+    L.cq_dd_workspace_size.argtypes = [C.c_int32, C.POINTER(cq_dd_instance),
+                                       C.POINTER(cq_dd_params), C.c_int32, C.POINTER(C.c_size_t)]
+    L.cq_reconstruct_dd.restype = st
+    L.cq_reconstruct_dd.argtypes = [C.c_int32, C.POINTER(cq_dd_instance), C.POINTER(cq_dd_params),
+                                    C.POINTER(cq_dd_record), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_int32), p, C.c_size_t, p]
+    _lib = L
+    return L
+
+
+class CQError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+
+
+def check(status: int):
+    if status != CQ_OK:
+        raise CQError(status, lib().cq_last_error().decode())

@@ -1,0 +1,229 @@
+"""Thin Python binding of the C ABI (include/cutqc.h): argument marshalling
+only.  torch provides device memory and the current stream; every step of the
+reconstruction runs in the library's HIP kernels.
+
+A subcircuit is a ``(width, init_cut, meas_cut)`` tuple or any object with
+those attributes (see include/cutqc.h for the conventions).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _sub_fields(sub):
+    if isinstance(sub, (tuple, list)):
+        w, ic, mc = sub
+    else:
+        w, ic, mc = sub.width, sub.init_cut, sub.meas_cut
+    return int(w), [int(x) for x in ic], [int(x) for x in mc]
+
+
+class _Subs:
+    """Keeps the ctypes arrays of a subcircuit list alive for one call."""
+
+    def __init__(self, subs):
+        self.keep = []
+        self.arr = (_lib.cq_subcircuit * len(subs))()
+        self.n_out = []
+        for i, s in enumerate(subs):
+            w, ic, mc = _sub_fields(s)
+            a = (C.c_int32 * max(w, 1))(*ic)
+            b = (C.c_int32 * max(w, 1))(*mc)
+            self.keep += [a, b]
+            self.arr[i].width = w
+            self.arr[i].init_cut = C.cast(a, C.POINTER(C.c_int32))
+            self.arr[i].meas_cut = C.cast(b, C.POINTER(C.c_int32))
+            self.n_out.append(sum(1 for m in mc if m == -1))
+
+    def ptr(self, i=0):
+        return C.cast(C.byref(self.arr, i * C.sizeof(_lib.cq_subcircuit)),
+                      C.POINTER(_lib.cq_subcircuit))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes, device, workspace=None):
+    import torch
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError("workspace too small")
+        return workspace
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def cq_validate_cutmap(subs):
+    """(K, n) of a cut map; raises CQError when it is inconsistent.  Host only."""
+    s = _Subs(subs)
+    k, n = C.c_int32(), C.c_int32()
+    check(lib().cq_validate_cutmap(len(subs), s.ptr(), C.byref(k), C.byref(n)))
+    return k.value, n.value
+
+
+def cq_attribute_workspace_size(sub):
+    s = _Subs([sub])
+    b = C.c_size_t()
+    check(lib().cq_attribute_workspace_size(s.ptr(), C.byref(b)))
+    return b.value
+
+
+def cq_attribute(sub, variants, entries=None, workspace=None, stream=None):
+    """Entries (4^k, 2^n) FP64 of one subcircuit from its variant
+    probabilities (4^r, 3^o, 2^w) FP64, both on the device."""
+    import torch
+    s = _Subs([sub])
+    w, ic, mc = _sub_fields(sub)
+    k = len({c for c in ic + mc if c != -1})
+    n = s.n_out[0]
+    if entries is None:
+        entries = torch.empty((4 ** k, 2 ** n), dtype=torch.float64, device=variants.device)
+    nbytes = cq_attribute_workspace_size(sub)
+    ws = _workspace(nbytes, variants.device, workspace)
+    check(lib().cq_attribute(s.ptr(), _dev_ptr(variants, torch.float64),
+                             _dev_ptr(entries, torch.float64), _dev_ptr(ws), C.c_size_t(nbytes),
+                             _stream(stream)))
+    return entries
+
+
+def _perm_arr(out_perm):
+    if out_perm is None:
+        return None
+    return (C.c_int32 * len(out_perm))(*[int(q) for q in out_perm])
+
+
+def cq_fd_workspace_size(subs, prec="fp64", out_perm=None):
+    s = _Subs(subs)
+    perm = _perm_arr(out_perm)
+    b = C.c_size_t()
+    check(lib().cq_fd_workspace_size(len(subs), s.ptr(), _lib.PRECISION[prec],
+                                     C.cast(perm, C.POINTER(C.c_int32)) if perm else None,
+                                     C.byref(b)))
+    return b.value
+
+
+def cq_reconstruct_fd(subs, entries, prec="fp64", out_perm=None, out=None, workspace=None,
+                      stream=None):
+    """Full-definition output (2^n) from FP64 device entries, one per
+    subcircuit.  Returns float64 for prec='fp64', else float32."""
+    import torch
+    s = _Subs(subs)
+    n = sum(s.n_out)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    dev = entries[0].device
+    if out is None:
+        out = torch.empty(2 ** n, dtype=dtype, device=dev)
+    elif out.dtype != dtype or out.numel() != 2 ** n:
+        raise ValueError("output tensor has the wrong dtype or size")
+    perm = _perm_arr(out_perm)
+    nbytes = cq_fd_workspace_size(subs, prec, out_perm)
+    ws = _workspace(nbytes, dev, workspace)
+    ptrs = (C.c_void_p * len(entries))(*[_dev_ptr(e, torch.float64).value for e in entries])
+    check(lib().cq_reconstruct_fd(len(subs), s.ptr(), ptrs, _lib.PRECISION[prec],
+                                  C.cast(perm, C.POINTER(C.c_int32)) if perm else None,
+                                  _dev_ptr(out), _dev_ptr(ws), C.c_size_t(nbytes),
+                                  _stream(stream)))
+    return out
+
+
+def _mask(positions):
+    m = 0
+    for p in positions:
+        m |= 1 << int(p)
+    return m
+
+
+class _Instances:
+    def __init__(self, instances):
+        self.keep = []
+        self.arr = (_lib.cq_dd_instance * len(instances))()
+        for i, inst in enumerate(instances):
+            subs = _Subs(inst["subs"])
+            ns = len(inst["subs"])
+            ptrs = (C.c_void_p * ns)(*[e.data_ptr() for e in inst["entries"]])
+            act = (C.c_uint64 * ns)(*inst["active"])
+            mer = (C.c_uint64 * ns)(*inst["merged"])
+            fix = (C.c_uint64 * ns)(*inst.get("fixed", [0] * ns))
+            fv = (C.c_uint64 * ns)(*inst.get("fixed_vals", [0] * ns))
+            ma = (C.c_int32 * ns)(*inst["max_active"])
+            self.keep += [subs, ptrs, act, mer, fix, fv, ma, inst["entries"]]
+            a = self.arr[i]
+            a.n_sub = ns
+            a.subs = subs.ptr()
+            a.entries = C.cast(ptrs, C.POINTER(C.c_void_p))
+            a.active = C.cast(act, C.POINTER(C.c_uint64))
+            a.merged = C.cast(mer, C.POINTER(C.c_uint64))
+            a.fixed = C.cast(fix, C.POINTER(C.c_uint64))
+            a.fixed_vals = C.cast(fv, C.POINTER(C.c_uint64))
+            a.max_active = C.cast(ma, C.POINTER(C.c_int32))
+
+
+def cq_dd_workspace_size(instances, prec="fp64", R=4, bins_stored=False):
+    ins = _Instances(instances)
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R))
+    b = C.c_size_t()
+    check(lib().cq_dd_workspace_size(len(instances), ins.arr, C.byref(par), int(bins_stored),
+                                     C.byref(b)))
+    return b.value
+
+
+def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, stream=None):
+    """Dynamic definition over a batch of instances.  Each instance is a dict
+    with keys subs, entries (FP64 device tensors), active, merged, fixed,
+    fixed_vals (recursion-0 masks, bit i = output i, i = 0 most significant)
+    and max_active.  ``bins``: optional list (instance-major, R per instance)
+    of device tensors or None that receive each recursion's bins.
+    Returns (records, recursions_done): records[i][r] is a dict."""
+    import torch
+    ins = _Instances(instances)
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R))
+    nbytes = cq_dd_workspace_size(instances, prec, R, bins is not None)
+    dev = instances[0]["entries"][0].device
+    ws = _workspace(nbytes, dev, workspace)
+    recs = (_lib.cq_dd_record * (len(instances) * R))()
+    done = (C.c_int32 * len(instances))()
+    bin_ptrs = None
+    if bins is not None:
+        bin_ptrs = (C.c_void_p * (len(instances) * R))(
+            *[(b.data_ptr() if b is not None else None) for b in bins])
+    check(lib().cq_reconstruct_dd(len(instances), ins.arr, C.byref(par), recs,
+                                  C.cast(bin_ptrs, C.POINTER(C.c_void_p)) if bin_ptrs else None,
+                                  done, _dev_ptr(ws), C.c_size_t(nbytes), _stream(stream)))
+    out = []
+    for i, inst in enumerate(instances):
+        ns = len(inst["subs"])
+        rows = []
+        for r in range(done[i]):
+            rc = recs[i * R + r]
+            rows.append(dict(
+                active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
+                fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
+                n_active=rc.n_active, total=rc.total,
+                list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],
+                popped=bool(rc.popped)))
+        out.append(rows)
+    return out, list(done)
+
+
+# Friendlier aliases
+attribute = cq_attribute
+reconstruct_fd = cq_reconstruct_fd
+reconstruct_dd = cq_reconstruct_dd
+validate_cutmap = cq_validate_cutmap
+mask = _mask

@@ -1,0 +1,115 @@
+// Internal host-side structures of the reconstruction library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cutqc.h"
+
+namespace cq {
+
+// Thread-local error detail behind cq_last_error().
+void set_error(const std::string& msg);
+cq_status fail(cq_status s, const std::string& msg);
+
+// Facts derived from one subcircuit's cut map.
+struct SubInfo {
+  int width = 0;
+  std::vector<int> init_cut, meas_cut;
+  std::vector<int> outputs;     // output slots, slot order
+  std::vector<int> init_slots;  // slots initialised by a cut, slot order
+  std::vector<int> meas_slots;  // slots measured for a cut, slot order
+  std::vector<int> cuts;        // incident cut ids, ascending (label digit order)
+  int n() const { return (int)outputs.size(); }
+  int r() const { return (int)init_slots.size(); }
+  int o() const { return (int)meas_slots.size(); }
+  int k() const { return (int)cuts.size(); }
+  // position of cut id in `cuts` (-1 when not incident)
+  int digit_pos(int cut) const {
+    for (int i = 0; i < (int)cuts.size(); ++i)
+      if (cuts[i] == cut) return i;
+    return -1;
+  }
+};
+
+struct CutMap {
+  int n_sub = 0;
+  int K = 0;
+  int n_total = 0;
+  std::vector<SubInfo> subs;
+  std::vector<int> up, down;  // per cut: measuring / initialising subcircuit
+};
+
+// Validates and derives.  Returns CQ_OK or an error (message set).
+cq_status build_cutmap(int32_t n_sub, const cq_subcircuit* subs, CutMap& cm);
+cq_status build_subinfo(const cq_subcircuit* sub, SubInfo& si);
+
+// ---------------------------------------------------------------------------
+// Contraction plan for Eq. 1.
+//
+// A tensor is an ordered list of axes, row-major.  An axis is either the
+// 4-valued label of one cut or the 2^{n_c} outputs of one subcircuit.
+// ---------------------------------------------------------------------------
+struct Axis {
+  int kind;   // 0: cut label, 1: subcircuit outputs
+  int id;     // cut id or subcircuit id
+  int log2;   // log2 of the axis size
+  bool operator==(const Axis& o) const { return kind == o.kind && id == o.id; }
+};
+
+enum class Loc { Input, Work, Out };
+
+struct TensorRef {
+  Loc loc = Loc::Work;
+  int index = 0;          // input subcircuit id, or workspace buffer id
+  std::vector<Axis> axes;
+  int64_t elems = 0;      // elements the tensor's buffer holds
+  int log2_size() const {
+    int s = 0;
+    for (auto& a : axes) s += a.log2;
+    return s;
+  }
+};
+
+// Batched "TN" GEMM:  C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
+// stored at C[z*sCz + m*ldc + n].
+struct GemmStep {
+  int a, b, c;  // tensor ids
+  int64_t Z, M, N, K;
+  int64_t sAz, sAk, sBz, sBk, sCz, ldc;
+  double alpha;
+};
+
+// dst[i] = alpha * src[offset(i)], offset from per-axis source strides over the
+// destination's axes (sizes 2^log2, last axis fastest).
+struct PermuteStep {
+  int src, dst;
+  std::vector<int> log2;
+  std::vector<int64_t> sstride;
+  double alpha;
+};
+
+struct Step {
+  bool is_gemm;
+  GemmStep g;
+  PermuteStep p;
+};
+
+struct Plan {
+  std::vector<TensorRef> tensors;
+  std::vector<Step> steps;
+  std::vector<int64_t> work_offset;  // byte offset of each workspace buffer
+  std::vector<int64_t> work_bytes;
+  int64_t workspace_bytes = 0;
+  int work_elem_bytes = 8;  // 8 for FP64 intermediates, 4 otherwise
+  double flops = 0.0;       // algorithmic flops of the GEMM steps
+};
+
+// `out_log2` per subcircuit = number of outputs taking part (n_c for FD, the
+// active count for DD bins).  `out_perm` (may be empty): bit permutation to
+// apply to the final concatenated order.
+cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work_elem_bytes,
+                    const std::vector<int>& out_perm, Plan& plan);
+
+}  // namespace cq

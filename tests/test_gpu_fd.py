@@ -1,0 +1,240 @@
+"""GPU parity of entry attribution and full-definition reconstruction against
+the FP64 oracle, through the C ABI.
+
+Tolerances: the FP64 path must match the oracle within 1e-10 max-abs;
+integer-valued entries make every sum exact, so there the GPU must match
+bit for bit (FP64 and FP32); the FP32 path on Dirichlet/uniform data must stay
+within 1e-6 max-abs.
+
+Because the Dirichlet(0.1) workloads put most bins at tiny values, each check
+also bounds the error relative to the bin's rounding scale
+2^-K sum_l prod_c |E_c[l, b_c]|: 1e-13 for FP64, 1e-5 for FP32.  FP32 has no
+normal numbers below about 1.2e-38, so the FP32 bound carries an absolute floor
+FP32_FLOOR (1e-32, far below the 1e-6 bar) for bins whose terms underflow."""
+import numpy as np
+import pytest
+
+from oracle import attribution as at
+from oracle import cutmap
+from oracle import reconstruct as rc
+from oracle import statevector as sv
+from workloads import circuits as wc
+from workloads import synthetic as syn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+FP32_FLOOR = 1e-32
+
+
+def cq():
+    import paper_2205_05836_amd as m
+    return m
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_attribute(spec, V):
+    return cq().cq_attribute(spec, to_dev(V)).cpu().numpy()
+
+
+def gpu_fd(subs, ents, prec, out_perm=None):
+    out = cq().cq_reconstruct_fd(subs, [to_dev(e) for e in ents], prec=prec, out_perm=out_perm)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("which", ["8q", "20q"])
+def test_circuit_attribution_and_fd_match_oracle_and_statevector(which):
+    cc = wc.two_way_circuit_8q(0) if which == "8q" else wc.two_way_circuit_20q(1)
+    print(f"case {which}", flush=True)
+    subs = cc.subcircuits()
+    Vs = [sv.variant_probabilities(s) for s in subs]
+    E_or = [at.attribute(s, V) for s, V in zip(subs, Vs)]
+    E_gpu = [gpu_attribute(s, V) for s, V in zip(subs, Vs)]
+    for a, b in zip(E_gpu, E_or):
+        assert a.shape == b.shape
+        assert np.max(np.abs(a - b)) < 1e-13
+    p_or = rc.apply_out_perm(rc.fd_contract(subs, E_or), cc.out_perm())
+    p_sv = sv.probabilities(cc.n_qubits, cc.ops)
+    p64 = gpu_fd(subs, E_gpu, "fp64", cc.out_perm())
+    assert np.max(np.abs(p64 - p_or)) < 1e-10
+    assert np.max(np.abs(p64 - p_sv)) < 1e-10
+    p32 = gpu_fd(subs, E_gpu, "fp32", cc.out_perm())
+    assert np.max(np.abs(p32 - p_or)) < 1e-6
+
+
+def _random_circuits(count, seed0=900):
+    out, seed = [], seed0
+    while len(out) < count:
+        rng = np.random.default_rng(seed)
+        seed += 1
+        cc = wc.random_cut_circuit(rng, int(rng.integers(4, 9)), int(rng.integers(2, 4)),
+                                   int(rng.integers(1, 4)), depth=5)
+        if cc is None or not cc.cuts:
+            continue
+        if sum(len(cutmap.outputs(s)) for s in cc.subcircuits()) != cc.n_qubits:
+            continue
+        out.append(cc)
+    return out
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_random_cut_circuits(idx):
+    cc = _random_circuits(8)[idx]
+    subs = cc.subcircuits()
+    print(f"random circuit {idx}: n={cc.n_qubits} subs={len(subs)} cuts={len(cc.cuts)}", flush=True)
+    Vs = [sv.variant_probabilities(s) for s in subs]
+    E_gpu = [gpu_attribute(s, V) for s, V in zip(subs, Vs)]
+    E_or = [at.attribute(s, V) for s, V in zip(subs, Vs)]
+    for a, b in zip(E_gpu, E_or):
+        assert np.max(np.abs(a - b)) < 1e-13
+    p_sv = sv.probabilities(cc.n_qubits, cc.ops)
+    p64 = gpu_fd(subs, E_gpu, "fp64", cc.out_perm())
+    assert np.max(np.abs(p64 - p_sv)) < 1e-10
+
+
+INT_CASES = [
+    ([2, 1], [3, 5, 7]),       # ragged tiles everywhere
+    ([1, 2], [7, 6, 7]),       # 2^20 outputs, several tiles
+    ([3], [9, 8]),             # two subcircuits
+    ([0, 2], [4, 4, 5]),       # a bond without cuts: outer product
+    ([2, 1, 2], [4, 3, 4, 5]), # chain of four
+    ([2], [0, 6]),             # a subcircuit without outputs
+]
+
+
+@pytest.mark.parametrize("bonds,ns", INT_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_integer_entries_bit_exact(bonds, ns, prec):
+    print(f"int case bonds={bonds} ns={ns} {prec}", flush=True)
+    rng = np.random.default_rng(sum(ns) * 7 + len(bonds))
+    cm = syn.chain_cutmap(bonds, ns)
+    ks = syn.chain_ks(bonds, len(ns))
+    E = [syn.integer_entries(rng, k, n, lo=-4, hi=4) for k, n in zip(ks, ns)]
+    ref = rc.fd_contract(cm, E)
+    got = gpu_fd(cm, E, prec)
+    assert np.array_equal(got, ref)
+
+
+def test_single_subcircuit_no_cuts():
+    rng = np.random.default_rng(3)
+    E = [rng.standard_normal((1, 2 ** 11))]
+    cm = [(11, [-1] * 11, [-1] * 11)]
+    assert np.array_equal(gpu_fd(cm, E, "fp64"), E[0][0])
+    perm = list(rng.permutation(11))
+    assert np.array_equal(gpu_fd(cm, E, "fp64", perm), rc.apply_out_perm(E[0][0], perm))
+
+
+def test_out_perm_bit_exact_on_chain():
+    rng = np.random.default_rng(5)
+    cm = syn.chain_cutmap([2, 1], [5, 4, 6])
+    E = [syn.integer_entries(rng, k, n) for k, n in zip(syn.chain_ks([2, 1], 3), [5, 4, 6])]
+    perm = [int(x) for x in rng.permutation(15)]
+    ref = rc.apply_out_perm(rc.fd_contract(cm, E), perm)
+    for prec in ("fp64", "fp32"):
+        assert np.array_equal(gpu_fd(cm, E, prec, perm), ref)
+
+
+def test_dirichlet_chain_fp64_and_fp32():
+    cm, E = syn.chain_instance(12, [3, 2], [8, 6, 7])
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    e64 = np.abs(gpu_fd(cm, E, "fp64") - ref)
+    e32 = np.abs(gpu_fd(cm, E, "fp32") - ref)
+    assert e64.max() < 1e-10 and np.max(e64 / scale) < 1e-13
+    assert e32.max() < 1e-6 and np.all(e32 <= 1e-5 * scale + FP32_FLOOR)
+
+
+def test_deterministic_repeat():
+    cm, E = syn.chain_instance(13, [4, 4], [8, 8, 8])
+    a = gpu_fd(cm, E, "fp32")
+    b = gpu_fd(cm, E, "fp32")
+    assert np.array_equal(a, b)
+
+
+def test_workspace_too_small_writes_nothing():
+    m = cq()
+    cm, E = syn.chain_instance(14, [4, 4], [6, 6, 6])
+    need = m.cq_fd_workspace_size(cm, "fp32")
+    assert need > 0
+    out = torch.full((2 ** 18,), 7.0, dtype=torch.float32, device=DEV)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device=DEV)
+    import ctypes as C
+    from paper_2205_05836_amd import _lib
+    from paper_2205_05836_amd.api import _Subs, _dev_ptr, _stream
+    s = _Subs(cm)
+    ents = [to_dev(e) for e in E]
+    ptrs = (C.c_void_p * 3)(*[e.data_ptr() for e in ents])
+    st = _lib.lib().cq_reconstruct_fd(3, s.ptr(), ptrs, 1, None, _dev_ptr(out), _dev_ptr(ws),
+                                      C.c_size_t(need - 256), _stream(None))
+    torch.cuda.synchronize()
+    assert st == -5
+    assert bool(torch.all(out == 7.0))
+
+
+# --- the 30-qubit, three-subcircuit workload at full size ------------------
+
+SEED_30Q = 2
+BONDS_30Q = [4, 4]
+NS_30Q = [10, 10, 10]
+
+
+def _entries_30q():
+    ks = syn.chain_ks(BONDS_30Q, 3)
+    return [syn.entries_torch(SEED_30Q, c, ks[c], NS_30Q[c], DEV) for c in range(3)]
+
+
+def _sampled_reference(bins, absolute=False):
+    """Oracle values at the sampled bins (or, with ``absolute``, the error
+    scale 2^-K sum_l prod_c |E_c[l, b_c]| of each bin).  The needed entry columns are rebuilt
+    on the host from the counter-based generator; sample j's columns are
+    placed in column j of small local entry tensors, and the per-bin oracle is
+    asked for the bin whose three parts all equal j."""
+    cm = syn.chain_cutmap(BONDS_30Q, NS_30Q)
+    ks = syn.chain_ks(BONDS_30Q, 3)
+    parts = [(bins >> 20) & 1023, (bins >> 10) & 1023, bins & 1023]
+    assert len(bins) <= 1024
+    local = []
+    for c in range(3):
+        e = np.zeros((4 ** ks[c], 1024))
+        e[:, :len(bins)] = syn.entries_columns(SEED_30Q, c, ks[c], 10, parts[c])
+        local.append(np.abs(e) if absolute else e)
+    j = np.arange(len(bins), dtype=np.int64)
+    return rc.fd_per_bin(cm, local, (j << 20) | (j << 10) | j)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_30_qubit_chain_full_size_sampled(prec, tol):
+    m = cq()
+    cm = syn.chain_cutmap(BONDS_30Q, NS_30Q)
+    ents = _entries_30q()
+    print(f"30q full size {prec}", flush=True)
+    out = m.cq_reconstruct_fd(cm, ents, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    # uniform samples, the corners, and the heaviest bins (largest identity rows)
+    heavy = [np.argsort(syn.identity_row(SEED_30Q, c, 10))[-4:] for c in range(3)]
+    hb = [(a << 20) | (b << 10) | c for a in heavy[0] for b in heavy[1] for c in heavy[2]]
+    bins = np.concatenate([rng.integers(0, 2 ** 30, size=900), hb,
+                           [0, 2 ** 30 - 1, 1023, 2 ** 20, 2 ** 30 - 1024]]).astype(np.int64)
+    got = out[torch.from_numpy(bins).to(DEV)].cpu().numpy().astype(np.float64)
+    ref = _sampled_reference(bins)
+    scale = _sampled_reference(bins, absolute=True)
+    err = np.abs(got - ref)
+    print(f"max abs err {err.max():.3e}, max |p| {np.abs(ref).max():.3e}, "
+          f"max err/scale {np.max(err / scale):.3e}", flush=True)
+    assert err.max() < tol
+    # error relative to the rounding scale of each bin
+    if prec == "fp64":
+        assert np.max(err / scale) < 1e-13
+    else:
+        assert np.all(err <= 1e-5 * scale + FP32_FLOOR)
+    # closed form of the total (sum over all bins): 2^-K sum_l prod_c rowsum_c(l_c)
+    rs = [e.sum(dim=1).cpu().numpy() for e in ents]
+    tot = 2.0 ** -8 * float(rs[0] @ rs[1].reshape(256, 256) @ rs[2])
+    got_tot = float(torch.sum(out, dtype=torch.float64).item())
+    assert abs(got_tot - tot) < (1e-9 if prec == "fp64" else 1e-4)
