@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark of the reconstruction hot path on one MI355X.
+
+Workload: full-definition reconstruction of a 30-qubit output from a chain of
+three subcircuits with 10 outputs each and 4 + 4 wire cuts (K = 8), entries
+drawn as in the paper's runtime study (random subcircuit outputs): identity
+rows Dirichlet(0.1) over 2^10 bins, other rows that times Uniform[-1, 1]
+(seed 2).  One step = one cq_reconstruct_fd call: the two label GEMMs
+(2^10 x 2^18 x 2^8, then 2^10 batches of 2^10 x 2^10 x 2^8) writing all 2^30
+probabilities, inputs already resident in HBM.
+
+Prints one JSON line.  `value` is algorithmic TFLOP/s of the headline
+precision (Sum 2*M*N*K over the minimum-flop contraction plan, 0.687 TFLOP per
+step); the FP64 path is timed beside it.  Per-kernel durations come from HIP
+events the library records around each launch on the stream it launches on.
+The `cpu_baseline` leg times the FP64 oracle on a slice of the same workload
+and computes oracle values for sampled bins (the only use of the oracle here).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Kron-sum reconstruction TFLOP/s & %peak: FP32/BF16 MFMA vs FP64, err<1e-6"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6, "bf16_split": 2516.6,
+               "fp16": 2516.6, "fp16_split": 2516.6}
+DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16_split": "bf16",
+              "fp16": "f16", "fp16_split": "f16"}
+HBM_PEAK_GBS = 8000.0
+
+SEED, BONDS, NS = 2, [4, 4], [10, 10, 10]
+WORKLOAD = ("30-qubit FD: chain of 3 subcircuits x 10 outputs, 4+4 wire cuts (K=8), "
+            "entries (256|65536|256, 1024) FP64, identity rows Dirichlet(0.1), "
+            "other rows x Uniform[-1,1], seed 2")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp32", help="headline precision")
+    ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def timed_steps(cq, torch, cm, ents, prec, out, steps, warmup):
+    """Runs warmup + timed steps; returns (ms per step, per-launch records)."""
+    ws = torch.empty(max(cq.cq_fd_workspace_size(cm, prec), 1), dtype=torch.uint8,
+                     device="cuda:0")
+    for _ in range(warmup):
+        cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    cq.cq_profile_read()
+    cq.cq_profile_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out, workspace=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    cq.cq_profile_enable(False)
+    recs = cq.cq_profile_read()
+    return start.elapsed_time(stop) / steps, recs
+
+
+def dominant(recs):
+    groups = {}
+    for name, ms, fl in recs:
+        g = groups.setdefault((name, fl), [0, 0.0])
+        g[0] += 1
+        g[1] += ms
+    (name, fl), (cnt, tot) = max(groups.items(), key=lambda kv: kv[1][1])
+    return name, fl, tot / cnt, cnt
+
+
+def compare_outputs(torch, a, b, chunk=1 << 26):
+    """max |a-b| and total variation 1/2 sum |a-b| over all outputs (float64)."""
+    mx, tv = 0.0, 0.0
+    for i in range(0, a.numel(), chunk):
+        d = (a[i:i + chunk].double() - b[i:i + chunk].double()).abs()
+        mx = max(mx, float(d.max()))
+        tv += float(d.sum())
+    return mx, 0.5 * tv
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_30q_fd.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2205_05836_amd", "csrc", "gemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("gemm_src_sha256") != sha or rec.get("kernel") != kernel:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline_leg(torch, ents, out_fp, budget_s):
+    """Times the FP64 oracle on leading-bit slices of the workload and
+    evaluates it on sampled bins for the error report."""
+    import numpy as np
+
+    from oracle import reconstruct as rc
+    from workloads import synthetic as syn
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    cm = syn.chain_cutmap(BONDS, NS)
+    E = [e.cpu().numpy() for e in ents]
+    total_flops = 2.0 * (2 ** 10 * 2 ** 18 * 2 ** 8 + 2 ** 20 * 2 ** 10 * 2 ** 8)
+    # calibrate on a slice, then run the largest slice that fits the time budget
+    t0 = time.perf_counter()
+    rc.fd_contract(cm, E, lead=(0, 32))
+    t_small = time.perf_counter() - t0
+    rows = int(min(1024, max(32, 32 * budget_s / max(t_small, 1e-3))))
+    t0 = time.perf_counter()
+    part = rc.fd_contract(cm, E, lead=(0, rows))
+    t = time.perf_counter() - t0
+    frac = rows / 1024.0
+    cpu = {"value": total_flops * frac / t / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"oracle einsum contraction (numpy FP64, BLAS) of subcircuit-0 outputs "
+                     f"0..{rows - 1} of 1024 ({rows * 2 ** 20} of 2^30 probabilities), {t:.1f} s",
+           "outputs_per_s": rows * 2 ** 20 / t}
+    # error of the GPU output on those slice values and on sampled bins
+    got = out_fp[:rows * 2 ** 20].double().cpu().numpy()
+    slice_err = float(np.max(np.abs(got - part)))
+    rng = np.random.default_rng(31)
+    bins = rng.integers(0, 2 ** 30, size=1000).astype(np.int64)
+    parts = [(bins >> 20) & 1023, (bins >> 10) & 1023, bins & 1023]
+    local = []
+    for c in range(3):
+        e = np.zeros((E[c].shape[0], 1024))
+        e[:, :len(bins)] = E[c][:, parts[c]]
+        local.append(e)
+    j = np.arange(len(bins), dtype=np.int64)
+    ref = rc.fd_per_bin(cm, local, (j << 20) | (j << 10) | j)
+    got = out_fp[torch.from_numpy(bins).to(out_fp.device)].double().cpu().numpy()
+    samp_err = float(np.max(np.abs(got - ref)))
+    return cpu, {"max_abs_vs_oracle_slice": slice_err, "max_abs_vs_oracle_sampled_1000": samp_err}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the reconstruction "
+              "would shard the last GEMM's leading output bits across GPUs with no exchange "
+              "beyond one entry broadcast.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2205_05836_amd as cq
+    from workloads import synthetic as syn
+
+    dev = "cuda:0"
+    cm = syn.chain_cutmap(BONDS, NS)
+    ks = syn.chain_ks(BONDS, 3)
+    ents = [syn.entries_torch(SEED, c, ks[c], NS[c], dev) for c in range(3)]
+    plan = cq.cq_plan_json(cm, args.prec)
+    flops = plan["flops"]
+
+    prec = args.prec
+    out = torch.empty(2 ** 30, dtype=torch.float64 if prec == "fp64" else torch.float32,
+                      device=dev)
+    ms, recs = timed_steps(cq, torch, cm, ents, prec, out, args.steps, args.warmup)
+    name, kfl, kms, kcnt = dominant(recs)
+    out64 = torch.empty(2 ** 30, dtype=torch.float64, device=dev)
+    ms64, recs64 = timed_steps(cq, torch, cm, ents, "fp64", out64, max(2, args.steps // 2), 1)
+    max_abs, tv = compare_outputs(torch, out, out64) if prec != "fp64" else (0.0, 0.0)
+
+    tflops = flops / (ms * 1e-3) / 1e12
+    achieved = kfl / (kms * 1e-3) / 1e12
+    traffic = traffic_record(name)
+    result = {
+        "metric": METRIC,
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE_NAME[prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "precision": prec, "outputs": 2 ** 30,
+                   "algorithmic_flops_per_step": flops},
+        "pct_peak": round(100.0 * tflops / PEAK_TFLOPS[prec], 2),
+        "outputs_per_s": 2 ** 30 / (ms * 1e-3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": traffic,
+                     "kernel": name, "kernel_flops": kfl, "kernel_ms": round(kms, 4),
+                     "launches_timed": kcnt},
+        "fp64_path": {"ms_per_step": round(ms64, 4),
+                      "tflops": round(flops / (ms64 * 1e-3) / 1e12, 3),
+                      "pct_peak": round(100.0 * flops / (ms64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"], 2)},
+        "speedup_vs_fp64_path": round(ms64 / ms, 3),
+        "error_vs_fp64_gpu": {"max_abs": max_abs, "tv": tv},
+        "kernels": {f"{n}@{fl:.3g}": round(t, 4) for n, t, fl in
+                    [(k[0], v[1] / v[0], k[1]) for k, v in _groups(recs).items()]},
+    }
+    del out64
+    if not args.skip_cpu:
+        cpu, err = cpu_baseline_leg(torch, ents, out, args.cpu_seconds)
+        result["cpu_baseline"] = cpu
+        result["error_vs_oracle"] = err
+    print(json.dumps(result), flush=True)
+
+
+def _groups(recs):
+    groups = {}
+    for name, ms, fl in recs:
+        g = groups.setdefault((name, fl), [0, 0.0])
+        g[0] += 1
+        g[1] += ms
+    return groups
+
+
+if __name__ == "__main__":
+    main()

@@ -36,6 +36,19 @@ cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_precision pr
                        const int32_t* out_bits, const int32_t* out_perm, char* buf,
                        size_t buf_bytes, size_t* needed);
 
+/* Per-launch timing for tools and benchmarks.  While enabled (on != 0) every
+ * kernel the library enqueues is bracketed by two HIP events recorded on the
+ * caller's stream; the events add a few microseconds per launch and change
+ * nothing else.  Process-wide switch. */
+cq_status cq_profile_enable(int32_t on);
+
+/* Waits for the recorded events, then writes up to `cap` records in launch
+ * order -- kernel name (NUL-terminated, at most 31 characters), elapsed
+ * milliseconds, and algorithmic floating-point operations of the launch
+ * (0 when not a contraction) -- and clears them.  names: host, cap * 32 bytes;
+ * ms, flops: host, cap entries each.  *count = records that were pending. */
+cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -221,6 +221,36 @@ def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, st
     return out, list(done)
 
 
+def cq_plan_json(subs, prec="fp64", out_bits=None, out_perm=None):
+    """The contraction plan as a dict (host only, launches nothing)."""
+    import json
+    s = _Subs(subs)
+    ob = (C.c_int32 * len(subs))(*out_bits) if out_bits is not None else None
+    op = _perm_arr(out_perm)
+    need = C.c_size_t()
+    lib().cq_plan_json(len(subs), s.ptr(), _lib.PRECISION[prec], ob, op, None, 0, C.byref(need))
+    buf = C.create_string_buffer(need.value)
+    check(lib().cq_plan_json(len(subs), s.ptr(), _lib.PRECISION[prec], ob, op, buf, need.value,
+                             C.byref(need)))
+    return json.loads(buf.value.decode())
+
+
+def cq_profile_enable(on=True):
+    check(lib().cq_profile_enable(1 if on else 0))
+
+
+def cq_profile_read(cap=65536):
+    """[(kernel name, milliseconds, flops)] of the launches since the last read."""
+    names = C.create_string_buffer(32 * cap)
+    ms = (C.c_double * cap)()
+    fl = (C.c_double * cap)()
+    cnt = C.c_int32()
+    check(lib().cq_profile_read(names, ms, fl, cap, C.byref(cnt)))
+    raw = names.raw
+    return [(raw[32 * i:32 * i + 32].split(b"\0")[0].decode(), ms[i], fl[i])
+            for i in range(min(cnt.value, cap))]
+
+
 # Friendlier aliases
 attribute = cq_attribute
 reconstruct_fd = cq_reconstruct_fd

@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -23,6 +25,41 @@ bool fault_injected(const char* stage) {
 cq_status hip_fail(hipError_t e, const char* what) {
   return fail(CQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// ---- per-launch timing (cq_profile_enable / cq_profile_read) ----
+struct ProfRecord {
+  std::string name;
+  hipEvent_t start, stop;
+  double flops;
+};
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::vector<ProfRecord> g_prof;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  bool on = false;
+  ProfRecord rec;
+  hipStream_t stream;
+  ProfScope(const char* name, double flops, hipStream_t s) : stream(s) {
+    if (!g_prof_on.load()) return;
+    rec.name = name;
+    rec.flops = flops;
+    if (hipEventCreate(&rec.start) != hipSuccess) return;
+    if (hipEventCreate(&rec.stop) != hipSuccess) {
+      (void)hipEventDestroy(rec.start);
+      return;
+    }
+    on = hipEventRecord(rec.start, stream) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    if (hipEventRecord(rec.stop, stream) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back(rec);
+    }
+  }
+};
 
 bool valid_prec(cq_precision p) { return p >= CQ_FP64 && p <= CQ_FP16_SPLIT; }
 
@@ -84,7 +121,10 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
       L.sCz = g.sCz;
       L.ldc = g.ldc;
       L.alpha = g.alpha;
-      e = launch_gemm(prec, L, stream);
+      {
+        ProfScope ps(prec == CQ_FP64 ? "gemm_f64" : "gemm_f32", 2.0 * g.Z * g.M * g.N * g.K, stream);
+        e = launch_gemm(prec, L, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
     } else {
       const PermuteStep& p = s.p;
@@ -101,7 +141,10 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
         L.sstride[i] = p.sstride[i];
       }
       L.alpha = p.alpha;
-      e = launch_permute(L, stream);
+      {
+        ProfScope ps("permute", 0.0, stream);
+        e = launch_permute(L, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "permute launch");
     }
   }
@@ -169,7 +212,11 @@ extern "C" cq_status cq_attribute(const cq_subcircuit* sub, const double* varian
   }
   for (int t = 0; t < si.r(); ++t)
     L.init_w[t] = (int64_t)1 << (2 * (si.k() - 1 - si.digit_pos(si.init_cut[si.init_slots[t]])));
-  hipError_t e = launch_attribute(L, stream);
+  hipError_t e;
+  {
+    ProfScope ps("attribute", 0.0, stream);
+    e = launch_attribute(L, stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "attribution launch");
   return CQ_OK;
 }
@@ -376,7 +423,10 @@ cq_status dd_run_instance(const cq_dd_instance& in, const cq_dd_params& p, cq_dd
       M.active_flat = to_flat(d.active, n);
       M.merged_flat = to_flat(d.merged, n);
       M.fixed_vals_flat = to_flat(d.fixed_vals, n);
-      e = launch_merge(M, stream);
+      {
+        ProfScope ps("dd_merge", 0.0, stream);
+        e = launch_merge(M, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "merge launch");
       // row sums of the reduced entries give the recursion total
       MergeLaunch S;
@@ -438,7 +488,10 @@ cq_status dd_run_instance(const cq_dd_instance& in, const cq_dd_params& p, cq_dd
       K.cand_capacity = L.cand_cap;
       K.out_val = top_val;
       K.out_idx = top_idx;
-      e = launch_topk(K, stream);
+      {
+        ProfScope ps("dd_topk", 0.0, stream);
+        e = launch_topk(K, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "top-C launch");
       RefineLaunch F;
       std::memset(&F, 0, sizeof(F));
@@ -455,7 +508,10 @@ cq_status dd_run_instance(const cq_dd_instance& in, const cq_dd_params& p, cq_dd
       F.nbins = C;
       F.scale = scale;
       F.out = ref_out;
-      e = launch_refine(F, stream);
+      {
+        ProfScope ps("dd_refine", 0.0, stream);
+        e = launch_refine(F, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "refine launch");
     }
     std::vector<uint64_t> h_idx(64);
@@ -653,4 +709,36 @@ extern "C" cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_p
   if (!buf || buf_bytes < js.size() + 1) return fail(CQ_ERR_ARG, "buffer too small");
   std::memcpy(buf, js.c_str(), js.size() + 1);
   return CQ_OK;
+}
+
+extern "C" cq_status cq_profile_enable(int32_t on) {
+  g_prof_on.store(on ? 1 : 0);
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap,
+                                     int32_t* count) {
+  if (!count || (cap > 0 && (!names || !ms || !flops))) return fail(CQ_ERR_ARG, "null argument");
+  std::vector<ProfRecord> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  *count = (int32_t)recs.size();
+  cq_status st = CQ_OK;
+  for (size_t i = 0; i < recs.size(); ++i) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(recs[i].stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, recs[i].start, recs[i].stop);
+    if (e != hipSuccess) st = hip_fail(e, "profile event");
+    if ((int32_t)i < cap) {
+      std::memset(names + 32 * i, 0, 32);
+      std::strncpy(names + 32 * i, recs[i].name.c_str(), 31);
+      ms[i] = t;
+      flops[i] = recs[i].flops;
+    }
+    (void)hipEventDestroy(recs[i].start);
+    (void)hipEventDestroy(recs[i].stop);
+  }
+  return st;
 }
