@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="fp32", help="headline precision")
+    ap.add_argument("--prec", default="bf16_split", help="headline precision")
+    ap.add_argument("--forms", default="fp32,bf16",
+                    help="other precisions timed beside the headline and FP64")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -175,14 +177,26 @@ def main():
     flops = plan["flops"]
 
     prec = args.prec
-    out = torch.empty(2 ** 30, dtype=torch.float64 if prec == "fp64" else torch.float32,
-                      device=dev)
-    ms, recs = timed_steps(cq, torch, cm, ents, prec, out, args.steps, args.warmup)
-    name, kfl, kms, kcnt = dominant(recs)
+    # FP64 path first: every other form is compared against its full output
     out64 = torch.empty(2 ** 30, dtype=torch.float64, device=dev)
     ms64, recs64 = timed_steps(cq, torch, cm, ents, "fp64", out64, max(2, args.steps // 2), 1)
-    max_abs, tv = compare_outputs(torch, out, out64) if prec != "fp64" else (0.0, 0.0)
-
+    out = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
+    forms = {}
+    others = [f for f in args.forms.split(",") if f and f not in (prec, "fp64")]
+    for f in others + [prec]:
+        if f == "fp64":
+            continue
+        f_ms, f_recs = timed_steps(cq, torch, cm, ents, f, out, args.steps, args.warmup)
+        mx, tv = compare_outputs(torch, out, out64)
+        forms[f] = {"ms_per_step": round(f_ms, 4),
+                    "tflops": round(flops / (f_ms * 1e-3) / 1e12, 3),
+                    "speedup_vs_fp64_path": round(ms64 / f_ms, 3),
+                    "max_abs_vs_fp64": mx, "tv_vs_fp64": tv}
+        if f == prec:
+            ms, recs, max_abs, tv_h = f_ms, f_recs, mx, tv
+    if prec == "fp64":
+        out, ms, recs, max_abs, tv_h = out64, ms64, recs64, 0.0, 0.0
+    name, kfl, kms, kcnt = dominant(recs)
     tflops = flops / (ms * 1e-3) / 1e12
     achieved = kfl / (kms * 1e-3) / 1e12
     traffic = traffic_record(name)
@@ -212,7 +226,8 @@ def main():
                       "tflops": round(flops / (ms64 * 1e-3) / 1e12, 3),
                       "pct_peak": round(100.0 * flops / (ms64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"], 2)},
         "speedup_vs_fp64_path": round(ms64 / ms, 3),
-        "error_vs_fp64_gpu": {"max_abs": max_abs, "tv": tv},
+        "error_vs_fp64_gpu": {"max_abs": max_abs, "tv": tv_h},
+        "forms": forms,
         "kernels": {f"{n}@{fl:.3g}": round(t, 4) for n, t, fl in
                     [(k[0], v[1] / v[0], k[1]) for k, v in _groups(recs).items()]},
     }

@@ -64,9 +64,21 @@ struct ProfScope {
 bool valid_prec(cq_precision p) { return p >= CQ_FP64 && p <= CQ_FP16_SPLIT; }
 
 // Precisions whose kernels this build ships.
-bool prec_supported(cq_precision p) { return p == CQ_FP64 || p == CQ_FP32; }
+bool prec_supported(cq_precision p) { return p >= CQ_FP64 && p <= CQ_FP16_SPLIT; }
 
-int work_elem_bytes(cq_precision p) { return p == CQ_FP64 ? 8 : 4; }
+DType work_dtype(cq_precision p) {
+  switch (p) {
+    case CQ_FP64: return DType::F64;
+    case CQ_FP32: return DType::F32;
+    case CQ_BF16:
+    case CQ_FP16: return DType::H16;
+    default: return DType::H16X2;
+  }
+}
+
+int work_elem_bytes(cq_precision p) { return dtype_bytes(work_dtype(p)); }
+
+bool is_f16(cq_precision p) { return p == CQ_FP16 || p == CQ_FP16_SPLIT; }
 
 DType out_dtype(cq_precision p) { return p == CQ_FP64 ? DType::F64 : DType::F32; }
 
@@ -83,32 +95,48 @@ cq_status check_perm(const int32_t* out_perm, int n, std::vector<int>& perm) {
   return CQ_OK;
 }
 
-struct Resolved {
-  const void* p;
-  DType t;
-};
-
 // Runs a plan.  inputs[c]: FP64 device pointer of subcircuit c's tensor.
 cq_status execute(const Plan& plan, cq_precision prec, const double* const* inputs, void* out,
                   DType out_t, char* ws, hipStream_t stream) {
-  const DType wt = plan.work_elem_bytes == 8 ? DType::F64 : DType::F32;
-  auto res = [&](int tid) -> Resolved {
-    const TensorRef& t = plan.tensors[tid];
-    if (t.loc == Loc::Input) return {inputs[t.index], DType::F64};
-    if (t.loc == Loc::Out) return {out, out_t};
-    return {ws + plan.work_offset[t.index], wt};
+  const DType wt = work_dtype(prec);
+  const bool f16 = is_f16(prec);
+  auto planes = [&](char* base, int64_t elems) -> Operand {
+    Operand o;
+    o.p = base;
+    o.lo = wt == DType::H16X2 ? base + elems * 2 : nullptr;
+    o.t = wt;
+    return o;
   };
+  auto res = [&](int tid) -> Operand {
+    const TensorRef& t = plan.tensors[tid];
+    if (t.loc == Loc::Input) {
+      if (plan.input_offset[t.index] < 0) return Operand{inputs[t.index], nullptr, DType::F64};
+      return planes(ws + plan.input_offset[t.index], t.elems);
+    }
+    if (t.loc == Loc::Out) return Operand{out, nullptr, out_t};
+    return planes(ws + plan.work_offset[t.index], t.elems);
+  };
+  // operand preparation: FP64 entries -> the precision's storage format
+  for (size_t i = 0; i < plan.tensors.size(); ++i) {
+    const TensorRef& t = plan.tensors[i];
+    if (t.loc != Loc::Input || plan.input_offset[t.index] < 0) continue;
+    hipError_t e;
+    {
+      ProfScope ps("prep", 0.0, stream);
+      e = launch_prep(inputs[t.index], ws + plan.input_offset[t.index], t.elems, wt, f16, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "operand prep launch");
+  }
   for (const Step& s : plan.steps) {
     hipError_t e;
     if (s.is_gemm) {
       const GemmStep& g = s.g;
-      Resolved a = res(g.a), b = res(g.b), c = res(g.c);
+      Operand c = res(g.c);
       GemmLaunch L;
-      L.A = a.p;
-      L.ta = a.t;
-      L.B = b.p;
-      L.tb = b.t;
+      L.a = res(g.a);
+      L.b = res(g.b);
       L.C = const_cast<void*>(c.p);
+      L.C_lo = const_cast<void*>(c.lo);
       L.tc = c.t;
       L.Z = g.Z;
       L.M = g.M;
@@ -121,20 +149,24 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
       L.sCz = g.sCz;
       L.ldc = g.ldc;
       L.alpha = g.alpha;
+      L.nontemporal = plan.tensors[g.c].loc == Loc::Out;
       {
-        ProfScope ps(prec == CQ_FP64 ? "gemm_f64" : "gemm_f32", 2.0 * g.Z * g.M * g.N * g.K, stream);
+        static const char* kname[] = {"gemm_f64", "gemm_f32", "gemm_bf16", "gemm_bf16x3",
+                                      "gemm_f16", "gemm_f16x3"};
+        ProfScope ps(kname[prec], 2.0 * g.Z * g.M * g.N * g.K, stream);
         e = launch_gemm(prec, L, stream);
       }
       if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
     } else {
       const PermuteStep& p = s.p;
       if ((int)p.log2.size() > kMaxPermAxes) return fail(CQ_ERR_UNSUPPORTED, "permute has too many axes");
-      Resolved a = res(p.src), d = res(p.dst);
+      Operand d = res(p.dst);
       PermLaunch L;
-      L.src = a.p;
-      L.ts = a.t;
+      L.src = res(p.src);
       L.dst = const_cast<void*>(d.p);
+      L.dst_lo = const_cast<void*>(d.lo);
       L.td = d.t;
+      L.f16 = f16;
       L.naxes = (int)p.log2.size();
       for (int i = 0; i < L.naxes; ++i) {
         L.log2[i] = p.log2[i];
@@ -675,6 +707,8 @@ extern "C" cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_p
     js += (i ? ", " : "") + std::string("{\"loc\": \"") + loc + "\", \"index\": " +
           std::to_string(t.index) + ", \"elems\": " + std::to_string(t.elems);
     if (t.loc == Loc::Work) js += ", \"offset\": " + std::to_string(plan.work_offset[t.index]);
+    if (t.loc == Loc::Input && plan.input_offset[t.index] >= 0)
+      js += ", \"offset\": " + std::to_string(plan.input_offset[t.index]);
     js += "}";
   }
   js += "], \"steps\": [";

@@ -7,9 +7,14 @@ namespace cq {
 
 namespace {
 
+// Element kinds of a permute's source and destination.
+enum Kind { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
+
 struct PermArgs {
   const void* src;
+  const void* src_lo;  // lo plane of a split source, else null
   void* dst;
+  void* dst_lo;        // lo plane of a split destination, else null
   int64_t total;
   int naxes;
   int log2[kMaxPermAxes];
@@ -17,12 +22,18 @@ struct PermArgs {
   double alpha;
 };
 
+__device__ inline float h16_to_f(uint16_t x, bool f16) {
+  return f16 ? float(__builtin_bit_cast(_Float16, x)) : float(__builtin_bit_cast(__bf16, x));
+}
+__device__ inline uint16_t f_to_h16(float x, bool f16) {
+  return f16 ? __builtin_bit_cast(uint16_t, _Float16(x)) : __builtin_bit_cast(uint16_t, __bf16(x));
+}
+
 // Generic axis permutation with conversion: one destination element per
-// thread iteration, destination written contiguously.
-template <typename TS, typename TD>
+// thread iteration, destination written contiguously.  16-bit planes are
+// copied bit for bit when both sides use them.
+template <int SK, int DK>
 __global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
-  const TS* __restrict__ src = static_cast<const TS*>(p.src);
-  TD* __restrict__ dst = static_cast<TD*>(p.dst);
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.total; i += step) {
     int64_t r = i, off = 0;
@@ -31,7 +42,44 @@ __global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
       off += (r & (((int64_t)1 << l) - 1)) * p.sstride[a];
       r >>= l;
     }
-    dst[i] = TD(p.alpha * double(src[off]));
+    if constexpr (SK >= kBF16 && DK == SK) {
+      static_cast<uint16_t*>(p.dst)[i] = static_cast<const uint16_t*>(p.src)[off];
+      if (p.dst_lo) static_cast<uint16_t*>(p.dst_lo)[i] = static_cast<const uint16_t*>(p.src_lo)[off];
+    } else {
+      double v;
+      if constexpr (SK == kF64) v = static_cast<const double*>(p.src)[off];
+      else if constexpr (SK == kF32) v = static_cast<const float*>(p.src)[off];
+      else {
+        v = h16_to_f(static_cast<const uint16_t*>(p.src)[off], SK == kF16);
+        if (p.src_lo) v += h16_to_f(static_cast<const uint16_t*>(p.src_lo)[off], SK == kF16);
+      }
+      v *= p.alpha;
+      if constexpr (DK == kF64) static_cast<double*>(p.dst)[i] = v;
+      else if constexpr (DK == kF32) static_cast<float*>(p.dst)[i] = float(v);
+      else {
+        const float x = float(v);
+        const uint16_t h = f_to_h16(x, DK == kF16);
+        static_cast<uint16_t*>(p.dst)[i] = h;
+        if (p.dst_lo) static_cast<uint16_t*>(p.dst_lo)[i] = f_to_h16(x - h16_to_f(h, DK == kF16), DK == kF16);
+      }
+    }
+  }
+}
+
+// FP64 -> FP32 or 16-bit planes (hi = rn16(x), lo = rn16(x - hi)).
+template <int DK>
+__global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ src, void* dst,
+                                                   void* dst_lo, int64_t n) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const float x = float(src[i]);
+    if constexpr (DK == kF32) {
+      static_cast<float*>(dst)[i] = x;
+    } else {
+      const uint16_t h = f_to_h16(x, DK == kF16);
+      static_cast<uint16_t*>(dst)[i] = h;
+      if (dst_lo) static_cast<uint16_t*>(dst_lo)[i] = f_to_h16(x - h16_to_f(h, DK == kF16), DK == kF16);
+    }
   }
 }
 
@@ -146,12 +194,31 @@ unsigned grid_for(int64_t total) {
   return (unsigned)b;
 }
 
+
+int kind_of(DType t, bool f16) {
+  if (t == DType::F64) return kF64;
+  if (t == DType::F32) return kF32;
+  return f16 ? kF16 : kBF16;
+}
+
+template <int SK>
+void permute_dispatch_dst(int dk, dim3 grid, const PermArgs& a, hipStream_t s) {
+  switch (dk) {
+    case kF64: hipLaunchKernelGGL((permute_kernel<SK, kF64>), grid, dim3(256), 0, s, a); break;
+    case kF32: hipLaunchKernelGGL((permute_kernel<SK, kF32>), grid, dim3(256), 0, s, a); break;
+    case kBF16: hipLaunchKernelGGL((permute_kernel<SK, kBF16>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((permute_kernel<SK, kF16>), grid, dim3(256), 0, s, a); break;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
   PermArgs a;
-  a.src = p.src;
+  a.src = p.src.p;
+  a.src_lo = p.src.t == DType::H16X2 ? p.src.lo : nullptr;
   a.dst = p.dst;
+  a.dst_lo = p.td == DType::H16X2 ? p.dst_lo : nullptr;
   a.naxes = p.naxes;
   int bits = 0;
   for (int i = 0; i < p.naxes; ++i) {
@@ -161,12 +228,28 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
   }
   a.total = (int64_t)1 << bits;
   a.alpha = p.alpha;
-  const unsigned grid = grid_for(a.total);
-  const bool s64 = p.ts == DType::F64, d64 = p.td == DType::F64;
-  if (s64 && d64) hipLaunchKernelGGL((permute_kernel<double, double>), dim3(grid), dim3(256), 0, stream, a);
-  else if (s64) hipLaunchKernelGGL((permute_kernel<double, float>), dim3(grid), dim3(256), 0, stream, a);
-  else if (d64) hipLaunchKernelGGL((permute_kernel<float, double>), dim3(grid), dim3(256), 0, stream, a);
-  else hipLaunchKernelGGL((permute_kernel<float, float>), dim3(grid), dim3(256), 0, stream, a);
+  const dim3 grid(grid_for(a.total));
+  const int sk = kind_of(p.src.t, p.f16), dk = kind_of(p.td, p.f16);
+  switch (sk) {
+    case kF64: permute_dispatch_dst<kF64>(dk, grid, a, stream); break;
+    case kF32: permute_dispatch_dst<kF32>(dk, grid, a, stream); break;
+    case kBF16: permute_dispatch_dst<kBF16>(dk, grid, a, stream); break;
+    default: permute_dispatch_dst<kF16>(dk, grid, a, stream); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
+                       hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(grid_for(n));
+  void* lo = t == DType::H16X2 ? static_cast<char*>(dst) + n * 2 : nullptr;
+  if (t == DType::F32)
+    hipLaunchKernelGGL((prep_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n);
+  else if (f16)
+    hipLaunchKernelGGL((prep_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
+  else
+    hipLaunchKernelGGL((prep_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
   return hipGetLastError();
 }
 

@@ -2,15 +2,19 @@
 //
 //   C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
 //
-// Both operands keep the entry-tensor layout (labels slow, outputs fast), so
-// tiles load along M and N with full 128-byte lines and no operand transpose
-// pass is needed.  Matrix cores of gfx950 do the products:
-//   FP64: v_mfma_f64_16x16x4_f64, FP32: v_mfma_f32_32x32x2_f32.
-// Tiles: 128 x 128 per workgroup of 4 waves (64 x 64 each), K staged through
-// LDS 16 labels at a time with a register prefetch of the next stage.
-// Workgroups walk the tiles n-fastest so neighbours share A panels, and the
-// flat tile index is remapped so that each of the 8 XCDs (each with its own
-// L2) receives a contiguous range of tiles.
+// Operands keep the entry-tensor layout (labels slow, outputs fast), so tiles
+// load along M and N with full cache lines.  Matrix cores of gfx950:
+//   FP64:      v_mfma_f64_16x16x4_f64
+//   FP32:      v_mfma_f32_32x32x2_f32
+//   BF16/FP16: v_mfma_f32_32x32x16_{bf16,f16}, FP32 accumulation; operands
+//              arrive as 16-bit planes (hi, and lo for the split forms) and
+//              are transposed in registers on their way to LDS so that each
+//              LDS row holds 8 consecutive labels, the MFMA's k-contiguous
+//              operand.
+// Tiles are 128 x 128 per workgroup of 4 waves (64 x 64 each).  The flat tile
+// index is rastered along the dimension whose operand panel is the larger one
+// (so that panel is fetched from HBM once and reused from L2), and remapped so
+// that each of the 8 XCDs, each with its own L2, receives a contiguous range.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -21,14 +25,19 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
   const void* A;
+  const void* A_lo;
   const void* B;
+  const void* B_lo;
   void* C;
+  void* C_lo;
   int64_t M, N, K;
   int64_t sAz, sAk, sBz, sBk, sCz, ldc;
   int64_t tilesM, tilesN, tiles;
+  int m_fastest;
   double alpha;
 };
 
@@ -39,98 +48,141 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Loads 8 consecutive elements of row k (columns c0..c0+7) as double/float,
-// zero outside [0, K) x [0, ncols).
-template <typename T, typename R>
+struct TileCoord {
+  int64_t z, m0, n0;
+};
+
+template <int BM, int BN>
+__device__ inline TileCoord tile_coord(const GemmArgs& g) {
+  const int64_t t = xcd_tile(blockIdx.x, g.tiles);
+  TileCoord c;
+  if (g.m_fastest) {
+    const int64_t tm = t % g.tilesM, r = t / g.tilesM;
+    c.n0 = (r % g.tilesN) * BN;
+    c.z = r / g.tilesN;
+    c.m0 = tm * BM;
+  } else {
+    const int64_t tn = t % g.tilesN, r = t / g.tilesN;
+    c.m0 = (r % g.tilesM) * BM;
+    c.z = r / g.tilesM;
+    c.n0 = tn * BN;
+  }
+  return c;
+}
+
+// Loads 8 consecutive elements of row k (columns c0..c0+7), zero outside
+// [0, K) x [0, ncols).
+template <typename T>
 __device__ inline void load8(const T* __restrict__ P, int64_t k, int64_t sk, int64_t c0,
-                             int64_t ncols, int64_t K, R (&out)[8]) {
+                             int64_t ncols, int64_t K, T (&out)[8]) {
   if (k >= K) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) out[e] = R(0);
+    for (int e = 0; e < 8; ++e) out[e] = T(0);
     return;
   }
   const T* p = P + k * sk + c0;
   if (c0 + 8 <= ncols && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
-    if constexpr (sizeof(T) == 8) {
-      typedef double dv2 __attribute__((ext_vector_type(2)));
+    constexpr int W = 16 / sizeof(T);
+    typedef T v16 __attribute__((ext_vector_type(W)));
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        dv2 v = *reinterpret_cast<const dv2*>(p + e);
-        out[e] = R(v[0]);
-        out[e + 1] = R(v[1]);
-      }
-    } else {
-      typedef float fv4 __attribute__((ext_vector_type(4)));
+    for (int e = 0; e < 8; e += W) {
+      v16 v = *reinterpret_cast<const v16*>(p + e);
 #pragma unroll
-      for (int e = 0; e < 8; e += 4) {
-        fv4 v = *reinterpret_cast<const fv4*>(p + e);
-        out[e] = R(v[0]);
-        out[e + 1] = R(v[1]);
-        out[e + 2] = R(v[2]);
-        out[e + 3] = R(v[3]);
-      }
+      for (int q = 0; q < W; ++q) out[e + q] = v[q];
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) out[e] = (c0 + e < ncols) ? R(p[e]) : R(0);
+    for (int e = 0; e < 8; ++e) out[e] = (c0 + e < ncols) ? p[e] : T(0);
   }
 }
 
-template <typename TA, typename TB, typename TC>
-__global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
-  constexpr int BM = 128, BN = 128, BK = 16;
-  __shared__ double As[BK][BM];
-  __shared__ double Bs[BK][BN];
-  const int64_t tile = xcd_tile(blockIdx.x, g.tiles);
-  const int64_t tn = tile % g.tilesN;
-  const int64_t t2 = tile / g.tilesN;
-  const int64_t tm = t2 % g.tilesM;
-  const int64_t z = t2 / g.tilesM;
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const TA* A = static_cast<const TA*>(g.A) + z * g.sAz;
-  const TB* B = static_cast<const TB*>(g.B) + z * g.sBz;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int lr = tid >> 4, lc = (tid & 15) * 8;
-
-  d4_t acc[4][4];
+// Four consecutive doubles of row k (columns c0..c0+3), zero outside.
+__device__ inline void load4(const double* __restrict__ P, int64_t k, int64_t sk, int64_t c0,
+                             int64_t ncols, int64_t K, double (&out)[4]) {
+  if (k >= K) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int e = 0; e < 4; ++e) out[e] = 0.0;
+    return;
+  }
+  const double* p = P + k * sk + c0;
+  if (c0 + 4 <= ncols && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const dv2 x = *reinterpret_cast<const dv2*>(p), y = *reinterpret_cast<const dv2*>(p + 2);
+    out[0] = x[0];
+    out[1] = x[1];
+    out[2] = y[0];
+    out[3] = y[1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (c0 + e < ncols) ? p[e] : 0.0;
+  }
+}
+
+template <typename TC, bool NT>
+__device__ inline void store_out(TC* p, TC v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64
+// ---------------------------------------------------------------------------
+template <bool NT>
+__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs g) {
+  // 8 waves in a 4 x 2 grid, 32 x 64 outputs each: two waves per SIMD hide
+  // the load latency that one 64 x 64 wave per SIMD could not.
+  constexpr int BM = 128, BN = 128, BK = 16;
+  __shared__ __attribute__((aligned(16))) double As[BK][BM];
+  __shared__ __attribute__((aligned(16))) double Bs[BK][BN];
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const double* A = static_cast<const double*>(g.A) + tc.z * g.sAz;
+  const double* B = static_cast<const double*>(g.B) + tc.z * g.sBz;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  const int lr = tid >> 5, lc = (tid & 31) * 4;
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+
+  d4_t acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  double ra[8], rb[8];
-  load8(A, lr, g.sAk, m0 + lc, g.M, g.K, ra);
-  load8(B, lr, g.sBk, n0 + lc, g.N, g.K, rb);
+  double ra[4], rb[4];
+  load4(A, lr, g.sAk, m0 + lc, g.M, g.K, ra);
+  load4(B, lr, g.sBk, n0 + lc, g.N, g.K, rb);
   for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      As[lr][lc + e] = ra[e];
-      Bs[lr][lc + e] = rb[e];
+    for (int e = 0; e < 4; e += 2) {
+      *reinterpret_cast<dv2*>(&As[lr][lc + e]) = dv2{ra[e], ra[e + 1]};
+      *reinterpret_cast<dv2*>(&Bs[lr][lc + e]) = dv2{rb[e], rb[e + 1]};
     }
     __syncthreads();
     if (k0 + BK < g.K) {
-      load8(A, k0 + BK + lr, g.sAk, m0 + lc, g.M, g.K, ra);
-      load8(B, k0 + BK + lr, g.sBk, n0 + lc, g.N, g.K, rb);
+      load4(A, k0 + BK + lr, g.sAk, m0 + lc, g.M, g.K, ra);
+      load4(B, k0 + BK + lr, g.sBk, n0 + lc, g.N, g.K, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double a[4], b[4];
+      double a[2], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = Bs[kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  TC* C = static_cast<TC*>(g.C) + z * g.sCz;
+  double* C = static_cast<double*>(g.C) + tc.z * g.sCz;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -138,23 +190,22 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
         // f64 16x16x4 accumulators: item v of lane l is row l/16 + 4v, column l%16
         const int64_t row = m0 + wm + i * 16 + (lane >> 4) + 4 * v;
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
-        if (row < g.M && col < g.N) C[row * g.ldc + col] = TC(g.alpha * acc[i][j][v]);
+        if (row < g.M && col < g.N) store_out<double, NT>(&C[row * g.ldc + col], g.alpha * acc[i][j][v]);
       }
 }
 
-template <typename TA, typename TB, typename TC>
+// ---------------------------------------------------------------------------
+// FP32
+// ---------------------------------------------------------------------------
+template <bool NT>
 __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs g) {
   constexpr int BM = 128, BN = 128, BK = 16;
-  __shared__ float As[BK][BM];
-  __shared__ float Bs[BK][BN];
-  const int64_t tile = xcd_tile(blockIdx.x, g.tiles);
-  const int64_t tn = tile % g.tilesN;
-  const int64_t t2 = tile / g.tilesN;
-  const int64_t tm = t2 % g.tilesM;
-  const int64_t z = t2 / g.tilesM;
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const TA* A = static_cast<const TA*>(g.A) + z * g.sAz;
-  const TB* B = static_cast<const TB*>(g.B) + z * g.sBz;
+  __shared__ __attribute__((aligned(16))) float As[BK][BM];
+  __shared__ __attribute__((aligned(16))) float Bs[BK][BN];
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const float* A = static_cast<const float*>(g.A) + tc.z * g.sAz;
+  const float* B = static_cast<const float*>(g.B) + tc.z * g.sBz;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lr = tid >> 4, lc = (tid & 15) * 8;
@@ -173,10 +224,13 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs g) {
   load8(B, lr, g.sBk, n0 + lc, g.N, g.K, rb);
   for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
+    {
+      typedef float fv4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      As[lr][lc + e] = ra[e];
-      Bs[lr][lc + e] = rb[e];
+      for (int e = 0; e < 8; e += 4) {
+        *reinterpret_cast<fv4*>(&As[lr][lc + e]) = fv4{ra[e], ra[e + 1], ra[e + 2], ra[e + 3]};
+        *reinterpret_cast<fv4*>(&Bs[lr][lc + e]) = fv4{rb[e], rb[e + 1], rb[e + 2], rb[e + 3]};
+      }
     }
     __syncthreads();
     if (k0 + BK < g.K) {
@@ -197,7 +251,7 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  TC* C = static_cast<TC*>(g.C) + z * g.sCz;
+  float* C = static_cast<float*>(g.C) + tc.z * g.sCz;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -206,29 +260,448 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs g) {
       for (int v = 0; v < 16; ++v) {
         const int64_t row = m0 + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int64_t col = n0 + wn + j * 32 + (lane & 31);
-        if (row < g.M && col < g.N) C[row * g.ldc + col] = TC(alpha * acc[i][j][v]);
+        if (row < g.M && col < g.N) store_out<float, NT>(&C[row * g.ldc + col], alpha * acc[i][j][v]);
       }
 }
 
-template <typename TA, typename TB, typename TC>
-hipError_t run_f64(const GemmArgs& a, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+// ---------------------------------------------------------------------------
+// BF16 / FP16 with FP32 accumulation.  SPLIT = 3 issues hi*hi + hi*lo + lo*hi.
+// OUT: 0 = FP32, 1 = FP32 non-temporal, 2 = 16-bit planes (hi, and lo when split)
+// ---------------------------------------------------------------------------
+template <bool F16>
+struct Half;
+template <>
+struct Half<false> {
+  typedef __bf16 T;
+  typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+  static __device__ inline f16_t mfma(V8 a, V8 b, f16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Half<true> {
+  typedef _Float16 T;
+  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+  static __device__ inline f16_t mfma(V8 a, V8 b, f16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Row k, columns c0..c0+7 of a 16-bit plane, packed two per dword.
+__device__ inline u32x4 load_row8_h(const uint16_t* __restrict__ P, int64_t k, int64_t sk,
+                                    int64_t c0, int64_t ncols, int64_t K) {
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (k >= K) return v;
+  const uint16_t* p = P + k * sk + c0;
+  if (c0 + 8 <= ncols && ((reinterpret_cast<uintptr_t>(p) & 15) == 0))
+    return *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t lo = (c0 + 2 * j < ncols) ? p[2 * j] : 0u;
+    const uint32_t hi = (c0 + 2 * j + 1 < ncols) ? p[2 * j + 1] : 0u;
+    v[j] = lo | (hi << 16);
+  }
+  return v;
+}
+
+// r[e] holds row e (8 columns); o[c] receives column c (8 rows).
+__device__ inline void transpose8x8(const u32x4 (&r)[8], u32x4 (&o)[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t x = r[2 * i][c >> 1], y = r[2 * i + 1][c >> 1];
+      o[c][i] = (c & 1) ? ((x >> 16) | (y & 0xffff0000u)) : ((x & 0xffffu) | (y << 16));
+    }
+}
+
+template <bool F16>
+__device__ inline uint16_t to_h16(float x) {
+  return __builtin_bit_cast(uint16_t, typename Half<F16>::T(x));
+}
+
+template <bool F16>
+__device__ inline float from_h16(uint16_t x) {
+  return float(__builtin_bit_cast(typename Half<F16>::T, x));
+}
+
+template <int SPLIT, bool F16, int OUT>
+__global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs g) {
+  using H = Half<F16>;
+  using V8 = typename H::V8;
+  constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
+  constexpr int NP = SPLIT == 3 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t As[NP][BM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][BN][LDK];
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  // loader: waves 0-1 fetch A, waves 2-3 fetch B.  Each lane owns an
+  // 8 (label) x 8 (column) block; lanes 8j..8j+7 hold the 8 label groups of
+  // one column group, so the transposed LDS writes of 16 consecutive lanes
+  // fill two whole 128-byte rows (no bank conflicts) and every global load
+  // instruction reads 8 full 128-byte row segments.
+  const bool ldA = tid < 128;
+  const int lk = (lane & 7) * 8;
+  const int lc = ((lane >> 3) + 8 * ((tid >> 6) & 1)) * 8;
+  const int64_t zoff = tc.z * (ldA ? g.sAz : g.sBz);
+  const uint16_t* P[NP];
+  P[0] = static_cast<const uint16_t*>(ldA ? g.A : g.B) + zoff;
+  if constexpr (NP == 2) P[NP - 1] = static_cast<const uint16_t*>(ldA ? g.A_lo : g.B_lo) + zoff;
+  const int64_t lsk = ldA ? g.sAk : g.sBk;
+  const int64_t lcol = (ldA ? m0 : n0) + lc;
+  const int64_t lncols = ldA ? g.M : g.N;
+  uint16_t (*S)[BM][LDK] = ldA ? As : Bs;
+  // whole 8-column segment in range and 16-byte aligned for every row
+  bool vec_ok = lcol + 8 <= lncols && ((lsk & 7) == 0);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) vec_ok = vec_ok && ((reinterpret_cast<uintptr_t>(P[p] + lcol) & 15) == 0);
+
+  f16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  u32x4 rows[NP][8];
+  auto load = [&](int64_t k0) {
+    if (vec_ok && k0 + BK <= g.K) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const uint16_t* base = P[p] + (k0 + lk) * lsk + lcol;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rows[p][e] = *reinterpret_cast<const u32x4*>(base + e * lsk);
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rows[p][e] = load_row8_h(P[p], k0 + lk + e, lsk, lcol, lncols, g.K);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      u32x4 cols[8];
+      transpose8x8(rows[p], cols);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *reinterpret_cast<u32x4*>(&S[p][lc + c][lk]) = cols[c];
+    }
+  };
+
+  load(0);
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + BK < g.K) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kc = kk + 8 * (lane >> 5);
+      V8 a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[p][i] = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(&As[p][wm + i * 32 + (lane & 31)][kc]));
+          b[p][i] = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(&Bs[p][wn + i * 32 + (lane & 31)][kc]));
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = H::mfma(a[0][i], b[0][j], acc[i][j]);
+          if constexpr (SPLIT == 3) {
+            acc[i][j] = H::mfma(a[0][i], b[NP - 1][j], acc[i][j]);
+            acc[i][j] = H::mfma(a[NP - 1][i], b[0][j], acc[i][j]);
+          }
+        }
+    }
+  }
+  const float alpha = float(g.alpha);
+  const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+  const int64_t cbase = tc.z * g.sCz + (m0 + wm + 4 * (lane >> 5)) * g.ldc + n0 + wn + (lane & 31);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rr = i * 32 + 8 * (v >> 2) + (v & 3);
+        const int cc = j * 32;
+        if (full || (m0 + wm + 4 * (lane >> 5) + rr < g.M && n0 + wn + (lane & 31) + cc < g.N)) {
+          const int64_t idx = cbase + rr * g.ldc + cc;
+          const float x = alpha * acc[i][j][v];
+          if constexpr (OUT == 2) {
+            const uint16_t h = to_h16<F16>(x);
+            static_cast<uint16_t*>(g.C)[idx] = h;
+            if constexpr (SPLIT == 3) static_cast<uint16_t*>(g.C_lo)[idx] = to_h16<F16>(x - from_h16<F16>(h));
+          } else {
+            store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx, x);
+          }
+        }
+      }
+}
+
+
+// ---------------------------------------------------------------------------
+// 16-bit path, asynchronous form (used when every operand row is 16-byte
+// aligned and at least 8 columns wide).  Operand tiles go global -> LDS with
+// global_load_lds_dwordx4 (no register staging) into NS rotating stages in
+// the operands' own [label][column] layout; ds_read_b64_tr_b16 then returns
+// each lane's k-contiguous MFMA operand (within a group of 16 lanes, slot j of
+// lane i is word i%4 of the address given by lane 4j + i/4).  LDS rows are
+// 128 columns (256 B) whose 16-byte chunks are XOR-swizzled by 2*(row & 3),
+// so the 16 lanes of one transposed read touch 8 distinct chunks.  Results are
+// staged through LDS per wave so each global store instruction writes whole
+// 256-byte row segments.  The DMA is issued from asm: the compiler would
+// otherwise wait for every in-flight LDS DMA before each LDS read; completion
+// is tracked with explicit vmcnt waits instead (a wave's vector memory
+// operations retire in issue order).
+// ---------------------------------------------------------------------------
+#define CQ_GLOBAL __attribute__((address_space(1)))
+#define CQ_LDS __attribute__((address_space(3)))
+
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline int swz(int row, int chunk) { return chunk ^ ((row & 3) << 1); }
+
+// s_waitcnt vmcnt(N) lgkmcnt(0)
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+template <int SPLIT, bool F16, int OUT, int NS>
+__global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs g) {
+  using H = Half<F16>;
+  using V8 = typename H::V8;
+  constexpr int BM = 128, BN = 128, BK = 32;
+  constexpr int NP = SPLIT == 3 ? 2 : 1;
+  constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
+  constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
+  constexpr int LPW = 2 * 2 * NP;       // DMA instructions per wave per stage
+  constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
+  constexpr int EPI = 4 * 64 * EROW;
+  constexpr int SMEM = NS * STAGE > EPI ? NS * STAGE : EPI;
+  static_assert(NS >= 2 && NS <= 3, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+
+  const uint16_t* gbase[2][NP];
+  int64_t gsk[2], ccap[2];
+  {
+    const int64_t za = tc.z * g.sAz, zb = tc.z * g.sBz;
+    gbase[0][0] = static_cast<const uint16_t*>(g.A) + za + m0;
+    gbase[1][0] = static_cast<const uint16_t*>(g.B) + zb + n0;
+    if constexpr (NP == 2) {
+      gbase[0][NP - 1] = static_cast<const uint16_t*>(g.A_lo) + za + m0;
+      gbase[1][NP - 1] = static_cast<const uint16_t*>(g.B_lo) + zb + n0;
+    }
+    gsk[0] = g.sAk;
+    gsk[1] = g.sBk;
+    // last 8-column chunk that stays inside the operand (M, N >= 8)
+    ccap[0] = ((g.M - 8) & ~(int64_t)7) - m0;
+    ccap[1] = ((g.N - 8) & ~(int64_t)7) - n0;
+  }
+  // wave w, instruction q fill LDS rows 4*(2w+q) .. +3 of every operand plane
+  auto issue = [&](int s) {
+    const int64_t k0 = (int64_t)s * BK;
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int chunk0 = (wave * 2 + q) * 64;
+          const int pc = chunk0 + lane;
+          const int row = pc >> 4;
+          int64_t col = (int64_t)swz(row, pc & 15) * 8;
+          if (col > ccap[op]) col = ccap[op];
+          int64_t k = k0 + row;
+          if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+          const uint16_t* src = gbase[op][p] + k * gsk[op] + col;
+          const uint32_t dst = __builtin_amdgcn_readfirstlane(
+              (uint32_t)(uintptr_t)(lsm + (s % NS) * STAGE + (op * NP + p) * TILE + chunk0 * 16));
+          asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                       : "memory", "m0");
+        }
+  };
+
+  f16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  // transposed-read coordinates of this lane inside a 32-column operand block
+  const int grp = lane >> 4, r16 = lane & 15;
+  const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
+  const int krow = 8 * (grp >> 1) + (r16 >> 2);
+  auto frag = [&](int tile, int kk, int c0, int64_t kvalid) -> V8 {
+    const int col = c0 + col_in_blk;
+    const int r0 = kk + krow, r1 = r0 + 4;
+    const int o0 = tile + r0 * 256 + (swz(r0, col >> 3) << 4) + (col & 7) * 2;
+    const int o1 = tile + r1 * 256 + (swz(r1, col >> 3) << 4) + (col & 7) * 2;
+    s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
+    s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
+    if (kvalid < BK) {
+      // slot e of the two reads holds label kk + 8*(grp>>1) + e (+4)
+      const int kb = kk + 8 * (grp >> 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kvalid) lo[e] = 0;
+        if (kb + 4 + e >= kvalid) hi[e] = 0;
+      }
+    }
+    typedef short s8_t __attribute__((ext_vector_type(8)));
+    const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(V8, v);
+  };
+
+  for (int s = 0; s < NS - 1 && s < nstages; ++s) issue(s);
+  for (int s = 0; s < nstages; ++s) {
+    // this wave's loads of stage s have landed once at most `ahead` later
+    // stages are outstanding; the barrier then covers every wave's loads
+    const int ahead = (nstages - 1 - s) < (NS - 2) ? (nstages - 1 - s) : (NS - 2);
+    if (ahead >= 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (s + NS - 1 < nstages) issue(s + NS - 1);
+    const int sb = (s % NS) * STAGE;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      V8 a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[p][i] = frag(sb + (0 * NP + p) * TILE, kk, wm + 32 * i, kvalid);
+          b[p][i] = frag(sb + (1 * NP + p) * TILE, kk, wn + 32 * i, kvalid);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = H::mfma(a[0][i], b[0][j], acc[i][j]);
+          if constexpr (SPLIT == 3) {
+            acc[i][j] = H::mfma(a[0][i], b[NP - 1][j], acc[i][j]);
+            acc[i][j] = H::mfma(a[NP - 1][i], b[0][j], acc[i][j]);
+          }
+        }
+    }
+  }
+
+  // epilogue: each wave stages its 64 x 64 results in LDS, then every store
+  // instruction writes four whole rows of 64 values
+  const float alpha = float(g.alpha);
+  __syncthreads();
+  char* wbuf = smem + wave * 64 * EROW;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int c = 32 * j + (lane & 31);
+        *reinterpret_cast<float*>(wbuf + r * EROW + c * 4) = alpha * acc[i][j][v];
+      }
+  __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+  const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int r = 4 * s + (lane >> 4);
+    const int c = 4 * (lane & 15);
+    const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + r * EROW + c * 4);
+    const int64_t m = m0 + wm + r, n = n0 + wn + c;
+    const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+    if (full || (m < g.M && n + 3 < g.N)) {
+      if constexpr (OUT == 2) {
+        typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+        u16x4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          h[e] = to_h16<F16>(x[e]);
+          l[e] = to_h16<F16>(x[e] - from_h16<F16>(h[e]));
+        }
+        *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(g.C) + idx) = h;
+        if constexpr (SPLIT == 3) *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(g.C_lo) + idx) = l;
+      } else {
+        store_out<f4_t, OUT == 1>(reinterpret_cast<f4_t*>(static_cast<float*>(g.C) + idx), x);
+      }
+    } else if (m < g.M) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (n + e < g.N) {
+          if constexpr (OUT == 2) {
+            const uint16_t h = to_h16<F16>(x[e]);
+            static_cast<uint16_t*>(g.C)[idx + e] = h;
+            if constexpr (SPLIT == 3) static_cast<uint16_t*>(g.C_lo)[idx + e] = to_h16<F16>(x[e] - from_h16<F16>(h));
+          } else {
+            store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx + e, x[e]);
+          }
+        }
+    }
+  }
+}
+
+template <typename K>
+hipError_t launch(K kernel, const GemmArgs& a, hipStream_t s, int threads = 256) {
+  hipLaunchKernelGGL(kernel, dim3((unsigned)a.tiles), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename TA, typename TB, typename TC>
-hipError_t run_f32(const GemmArgs& a, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+// 16-byte aligned rows of at least 8 columns in every operand plane and in
+// the output: the asynchronous kernel applies
+bool h16_async_ok(const GemmArgs& a, DType tc) {
+  auto al = [](const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool sizes = a.M >= 8 && a.N >= 8 && a.M % 8 == 0 && a.N % 8 == 0 && a.ldc % 4 == 0 &&
+                     a.sAk % 8 == 0 && a.sBk % 8 == 0 && a.sAz % 8 == 0 && a.sBz % 8 == 0 && a.sCz % 4 == 0;
+  (void)tc;
+  return sizes && al(a.A) && al(a.A_lo) && al(a.B) && al(a.B_lo) && al(a.C) && al(a.C_lo);
+}
+
+template <int SPLIT, bool F16>
+hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s) {
+  constexpr int NS = SPLIT == 3 ? 2 : 3;
+  if (h16_async_ok(a, tc)) {
+    if (tc == DType::F32) {
+      if (nt) return launch(gemm_h16a_kernel<SPLIT, F16, 1, NS>, a, s);
+      return launch(gemm_h16a_kernel<SPLIT, F16, 0, NS>, a, s);
+    }
+    return launch(gemm_h16a_kernel<SPLIT, F16, 2, NS>, a, s);
+  }
+  if (tc == DType::F32) {
+    if (nt) return launch(gemm_h16_kernel<SPLIT, F16, 1>, a, s);
+    return launch(gemm_h16_kernel<SPLIT, F16, 0>, a, s);
+  }
+  return launch(gemm_h16_kernel<SPLIT, F16, 2>, a, s);
 }
 
 }  // namespace
 
 hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t stream) {
   GemmArgs a;
-  a.A = g.A;
-  a.B = g.B;
+  a.A = g.a.p;
+  a.A_lo = g.a.lo;
+  a.B = g.b.p;
+  a.B_lo = g.b.lo;
   a.C = g.C;
+  a.C_lo = g.C_lo;
   a.M = g.M;
   a.N = g.N;
   a.K = g.K;
@@ -242,19 +715,33 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.tilesM = (g.M + 127) / 128;
   a.tilesN = (g.N + 127) / 128;
   a.tiles = a.tilesM * a.tilesN * g.Z;
+  // walk the tiles along M when the B operand is the larger one (its panels
+  // are then shared by consecutive workgroups), else along N
+  const double a_elems = double(g.sAz ? g.Z : 1) * double(g.M) * double(g.K);
+  const double b_elems = double(g.sBz ? g.Z : 1) * double(g.N) * double(g.K);
+  a.m_fastest = b_elems > a_elems ? 1 : 0;
   if (a.tiles <= 0) return hipSuccess;
   if (a.tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool a64 = g.ta == DType::F64, b64 = g.tb == DType::F64, c64 = g.tc == DType::F64;
-  if (prec == CQ_FP64) {
-    if (!(a64 && b64 && c64)) return hipErrorInvalidValue;
-    return run_f64<double, double, double>(a, a.tiles, stream);
-  }
-  if (prec == CQ_FP32) {
-    if (c64) return hipErrorInvalidValue;
-    if (a64 && b64) return run_f32<double, double, float>(a, a.tiles, stream);
-    if (a64 && !b64) return run_f32<double, float, float>(a, a.tiles, stream);
-    if (!a64 && b64) return run_f32<float, double, float>(a, a.tiles, stream);
-    return run_f32<float, float, float>(a, a.tiles, stream);
+  const bool nt = g.nontemporal;
+  switch (prec) {
+    case CQ_FP64:
+      if (g.a.t != DType::F64 || g.b.t != DType::F64 || g.tc != DType::F64) return hipErrorInvalidValue;
+      return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
+    case CQ_FP32:
+      if (g.a.t != DType::F32 || g.b.t != DType::F32 || g.tc != DType::F32) return hipErrorInvalidValue;
+      return nt ? launch(gemm_f32_kernel<true>, a, stream) : launch(gemm_f32_kernel<false>, a, stream);
+    case CQ_BF16:
+    case CQ_FP16:
+      if (g.a.t != DType::H16 || g.b.t != DType::H16) return hipErrorInvalidValue;
+      if (g.tc != DType::F32 && g.tc != DType::H16) return hipErrorInvalidValue;
+      return prec == CQ_BF16 ? dispatch_h16<1, false>(a, g.tc, nt, stream)
+                             : dispatch_h16<1, true>(a, g.tc, nt, stream);
+    case CQ_BF16_SPLIT:
+    case CQ_FP16_SPLIT:
+      if (g.a.t != DType::H16X2 || g.b.t != DType::H16X2) return hipErrorInvalidValue;
+      if (g.tc != DType::F32 && g.tc != DType::H16X2) return hipErrorInvalidValue;
+      return prec == CQ_BF16_SPLIT ? dispatch_h16<3, false>(a, g.tc, nt, stream)
+                                   : dispatch_h16<3, true>(a, g.tc, nt, stream);
   }
   return hipErrorInvalidValue;
 }

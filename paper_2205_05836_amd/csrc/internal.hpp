@@ -101,8 +101,13 @@ struct Plan {
   std::vector<Step> steps;
   std::vector<int64_t> work_offset;  // byte offset of each workspace buffer
   std::vector<int64_t> work_bytes;
+  // byte offset of each input's converted copy in the workspace, or -1 when
+  // the contraction reads the caller's FP64 entries directly
+  std::vector<int64_t> input_offset;
   int64_t workspace_bytes = 0;
-  int work_elem_bytes = 8;  // 8 for FP64 intermediates, 4 otherwise
+  // bytes per element of every operand and intermediate: 8 (FP64), 4 (FP32 or
+  // two 16-bit planes), 2 (one 16-bit plane)
+  int work_elem_bytes = 8;
   double flops = 0.0;       // algorithmic flops of the GEMM steps
 };
 

@@ -10,29 +10,46 @@
 
 namespace cq {
 
-enum class DType { F64, F32 };
+// Storage formats of contraction operands.  H16: one plane of 16-bit values
+// (BF16 or FP16); H16X2: a hi plane followed by a lo plane of the same length
+// (x = hi + lo).
+enum class DType { F64, F32, H16, H16X2 };
+
+inline int dtype_bytes(DType t) {
+  return t == DType::F64 ? 8 : (t == DType::F32 || t == DType::H16X2 ? 4 : 2);
+}
+
+struct Operand {
+  const void* p = nullptr;   // values, or the hi plane
+  const void* lo = nullptr;  // lo plane (H16X2 only)
+  DType t = DType::F64;
+};
 
 struct GemmLaunch {
-  const void* A;
-  DType ta;
-  const void* B;
-  DType tb;
-  void* C;
-  DType tc;
+  Operand a, b;
+  void* C = nullptr;
+  void* C_lo = nullptr;  // lo plane of C (H16X2 only)
+  DType tc = DType::F64;
   int64_t Z, M, N, K;
   int64_t sAz, sAk, sBz, sBk, sCz, ldc;
   double alpha;
+  bool nontemporal = false;  // final output: stores bypass the caches
 };
 
 // C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
 hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t stream);
 
+// Converts n FP64 values to `t` (FP32, or BF16/FP16 planes when f16 is false/true).
+hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
+                       hipStream_t stream);
+
 constexpr int kMaxPermAxes = 48;
 struct PermLaunch {
-  const void* src;
-  DType ts;
+  Operand src;
   void* dst;
+  void* dst_lo;
   DType td;
+  bool f16;
   int naxes;
   int log2[kMaxPermAxes];
   int64_t sstride[kMaxPermAxes];
@@ -65,7 +82,7 @@ hipError_t launch_merge(const MergeLaunch& m, hipStream_t stream);
 
 struct TopkLaunch {
   const void* bins;
-  DType t;
+  DType t;                // F64 or F32
   int64_t count;
   int C;                  // candidates wanted, <= 64
   double* cand_val;       // workspace

@@ -339,6 +339,16 @@ cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work
     t.elems = pow2(t.log2_size());
     plan.tensors.push_back(t);
   }
+  // Every precision but FP64 contracts converted copies of the entries
+  // (FP32, or 16-bit hi/lo planes); they lead the workspace.
+  plan.input_offset.assign(n, -1);
+  if (work_elem_bytes != 8) {
+    for (int c = 0; c < n; ++c) {
+      plan.input_offset[c] = plan.workspace_bytes;
+      const int64_t bytes = plan.tensors[c].elems * work_elem_bytes;
+      plan.workspace_bytes += ((bytes + 255) / 256) * 256;
+    }
+  }
   // Exhaustive DP over subsets for the cheapest pairwise order.
   const unsigned full = (1u << n) - 1;
   std::vector<DPEntry> dp(full + 1);

@@ -238,3 +238,72 @@ def test_30_qubit_chain_full_size_sampled(prec, tol):
     tot = 2.0 ** -8 * float(rs[0] @ rs[1].reshape(256, 256) @ rs[2])
     got_tot = float(torch.sum(out, dtype=torch.float64).item())
     assert abs(got_tot - tot) < (1e-9 if prec == "fp64" else 1e-4)
+
+
+# --- 16-bit matrix-core forms ------------------------------------------------
+
+# Relative-to-scale bounds: one rounding of each operand to 8 significant bits
+# (BF16) or 11 (FP16) plus FP32 accumulation; the split forms keep 16 / 22
+# bits of each operand and drop only lo*lo.
+H16_REL = {"bf16": 3e-2, "bf16_split": 3e-4, "fp16": 4e-3, "fp16_split": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16", "fp16_split"])
+@pytest.mark.parametrize("bonds,ns", [([2, 1], [3, 5, 7]), ([1, 2], [7, 6, 7]), ([3], [9, 8])])
+def test_h16_integer_entries_exact(bonds, ns, prec):
+    # integer entries in [-4, 4] need no low part; every intermediate stays an
+    # integer below 2^11 (FP16) or is carried exactly by hi + lo (split forms)
+    print(f"h16 int case bonds={bonds} ns={ns} {prec}", flush=True)
+    rng = np.random.default_rng(sum(ns) * 7 + len(bonds))
+    cm = syn.chain_cutmap(bonds, ns)
+    ks = syn.chain_ks(bonds, len(ns))
+    E = [syn.integer_entries(rng, k, n, lo=-4, hi=4) for k, n in zip(ks, ns)]
+    ref = rc.fd_contract(cm, E)
+    if prec == "fp16" and np.abs(ref).max() * 2 ** sum(bonds) >= 2048:
+        pytest.skip("intermediate exceeds the FP16 integer range")
+    got = gpu_fd(cm, E, prec)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
+def test_h16_dirichlet_chain(prec):
+    cm, E = syn.chain_instance(12, [3, 2], [8, 6, 7])
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    err = np.abs(gpu_fd(cm, E, prec) - ref)
+    print(f"{prec}: max abs {err.max():.3e}")
+    # plain BF16 keeps 8 significant bits: on this small chain (2^21 outputs,
+    # probabilities up to ~1e-3) it cannot reach 1e-6; only its rounding bound
+    # is asserted.  The split form must meet 1e-6.
+    if prec == "bf16_split":
+        assert err.max() < 1e-6
+    assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
+
+
+def test_h16_chain_of_four_split():
+    cm, E = syn.chain_instance(15, [2, 1, 2], [5, 4, 5, 5])
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    err = np.abs(gpu_fd(cm, E, "bf16_split") - ref)
+    assert np.all(err <= H16_REL["bf16_split"] * scale + FP32_FLOOR)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
+def test_30_qubit_chain_full_size_h16(prec):
+    m = cq()
+    cm = syn.chain_cutmap(BONDS_30Q, NS_30Q)
+    ents = _entries_30q()
+    print(f"30q full size {prec}", flush=True)
+    out = m.cq_reconstruct_fd(cm, ents, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(32)
+    heavy = [np.argsort(syn.identity_row(SEED_30Q, c, 10))[-4:] for c in range(3)]
+    hb = [(a << 20) | (b << 10) | c for a in heavy[0] for b in heavy[1] for c in heavy[2]]
+    bins = np.concatenate([rng.integers(0, 2 ** 30, size=900), hb]).astype(np.int64)
+    got = out[torch.from_numpy(bins).to(DEV)].cpu().numpy().astype(np.float64)
+    ref = _sampled_reference(bins)
+    scale = _sampled_reference(bins, absolute=True)
+    err = np.abs(got - ref)
+    print(f"max abs err {err.max():.3e}, max err/scale {np.max(err / scale):.3e}", flush=True)
+    assert err.max() < 1e-6
+    assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
