@@ -185,9 +185,15 @@ typedef struct cq_dd_instance {
   const int32_t* max_active;     /* host, n_sub: outputs activated per zoom */
 } cq_dd_instance;
 
+typedef enum cq_dd_launch {
+  CQ_DD_GRAPH = 0,   /* the whole batch captured into one hipGraph, launched once */
+  CQ_DD_DIRECT = 1   /* the same launches issued directly on the stream */
+} cq_dd_launch;
+
 typedef struct cq_dd_params {
   cq_precision prec;  /* arithmetic of the bin contraction */
   int32_t R;          /* recursions and list capacity, 1..CQ_MAX_DD_R */
+  int32_t launch;     /* cq_dd_launch */
 } cq_dd_params;
 
 typedef struct cq_dd_record {  /* one recursion, written by the library */
@@ -204,16 +210,25 @@ typedef struct cq_dd_record {  /* one recursion, written by the library */
   int32_t popped;               /* 1 when a bin was popped */
 } cq_dd_record;
 
-/* Workspace for one instance at a time (instances run one after another).
- * bins_stored != 0 when the caller passes bin buffers (then no bin scratch is
- * counted). */
+/* Workspace: the buffers of the largest instance (instances run one after
+ * another and share them) plus a small control block per instance (device
+ * program, recursion state, launch descriptors, records).  bins_stored != 0
+ * when the caller passes a bin buffer for every recursion (then no bin
+ * scratch is counted). */
 cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
                                const cq_dd_params* params, int32_t bins_stored, size_t* bytes);
 
 /* records: host, n_inst * R records (instance-major).  bins: NULL, or a host
- * array of n_inst * R device pointers, each NULL or a buffer of 2^n_active
- * values (double for CQ_FP64 else float) that receives that recursion's bins.
- * recursions_done: host, n_inst. */
+ * array of n_inst * R device pointers, each NULL (bins go to workspace
+ * scratch) or a buffer of 2^A values (double for CQ_FP64 else float), A =
+ * sum_c max(#active_c at recursion 0, min(max_active[c], n_c)), the most bins
+ * a recursion can have; recursion r's 2^n_active bins are written at its
+ * start.  recursions_done: host, n_inst.
+ *
+ * Every recursion of every instance is enqueued without a host round trip:
+ * shapes that depend on the zoom are computed on the device.  The call
+ * returns after the records have been read back (it synchronises `stream`);
+ * all validation happens before the first launch. */
 cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params* params,
                             cq_dd_record* records, void* const* bins, int32_t* recursions_done,
                             void* workspace, size_t workspace_bytes, hipStream_t stream);

@@ -36,7 +36,10 @@ class cq_dd_instance(C.Structure):
 
 
 class cq_dd_params(C.Structure):
-    _fields_ = [("prec", C.c_int), ("R", C.c_int32)]
+    _fields_ = [("prec", C.c_int), ("R", C.c_int32), ("launch", C.c_int32)]
+
+
+DD_LAUNCH = {"graph": 0, "direct": 1}
 
 
 class cq_dd_record(C.Structure):

@@ -176,23 +176,25 @@ class _Instances:
 
 def cq_dd_workspace_size(instances, prec="fp64", R=4, bins_stored=False):
     ins = _Instances(instances)
-    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R))
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), 0)
     b = C.c_size_t()
     check(lib().cq_dd_workspace_size(len(instances), ins.arr, C.byref(par), int(bins_stored),
                                      C.byref(b)))
     return b.value
 
 
-def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, stream=None):
+def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, stream=None,
+                      launch="graph"):
     """Dynamic definition over a batch of instances.  Each instance is a dict
     with keys subs, entries (FP64 device tensors), active, merged, fixed,
     fixed_vals (recursion-0 masks, bit i = output i, i = 0 most significant)
     and max_active.  ``bins``: optional list (instance-major, R per instance)
-    of device tensors or None that receive each recursion's bins.
+    of device tensors that receive each recursion's bins (each sized for the
+    most bins a recursion can have).  ``launch``: "graph" (one hipGraph for
+    the batch) or "direct".
     Returns (records, recursions_done): records[i][r] is a dict."""
-    import torch
     ins = _Instances(instances)
-    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R))
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), _lib.DD_LAUNCH[launch])
     nbytes = cq_dd_workspace_size(instances, prec, R, bins is not None)
     dev = instances[0]["entries"][0].device
     ws = _workspace(nbytes, dev, workspace)

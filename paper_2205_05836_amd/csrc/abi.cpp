@@ -7,6 +7,7 @@
 #include <mutex>
 #include <cmath>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -288,6 +289,11 @@ extern "C" cq_status cq_reconstruct_fd(int32_t n_sub, const cq_subcircuit* subs,
 
 // ---------------------------------------------------------------------------
 // Dynamic definition
+//
+// Each recursion is a fixed sequence of launches whose sizes are read from
+// device memory (see kernels.hpp), so a whole batch -- every instance and
+// every recursion -- is enqueued without the host looking at a result, and
+// by default captured into one hipGraph and launched once.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -296,24 +302,6 @@ struct DDSub {
 };
 
 int popc(uint64_t x) { return __builtin_popcountll(x); }
-
-// output position i <-> flat bit n-1-i
-uint64_t to_flat(uint64_t m, int n) {
-  uint64_t f = 0;
-  for (int i = 0; i < n; ++i)
-    if ((m >> i) & 1) f |= (uint64_t)1 << (n - 1 - i);
-  return f;
-}
-
-struct DDLayout {
-  std::vector<int64_t> ep_off, rs_off;
-  int64_t plan_off = 0, plan_bytes = 0;
-  int64_t bins_off = 0, bins_bytes = 0;
-  int64_t cand_off = 0, cand_cap = 0;
-  int64_t small_off = 0;  // top-C out (val, idx), refine in/out, total
-  int64_t total = 0;
-  std::vector<int> amax;
-};
 
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
@@ -329,7 +317,7 @@ cq_status dd_validate(const cq_dd_instance& in, const cq_dd_params& p, CutMap& c
   for (int c = 0; c < cm.n_sub; ++c) {
     const int n = cm.subs[c].n();
     if (n > 63) return fail(CQ_ERR_SHAPE, "too many outputs in a subcircuit");
-    const uint64_t all = n == 64 ? ~(uint64_t)0 : (((uint64_t)1 << n) - 1);
+    const uint64_t all = ((uint64_t)1 << n) - 1;
     DDSub d{in.active[c], in.merged[c], in.fixed[c], in.fixed_vals[c]};
     if ((d.active | d.merged | d.fixed) != all || (d.active & d.merged) || (d.active & d.fixed) ||
         (d.merged & d.fixed) || (d.fixed_vals & ~d.fixed))
@@ -348,275 +336,338 @@ cq_status dd_validate(const cq_dd_instance& in, const cq_dd_params& p, CutMap& c
   return CQ_OK;
 }
 
-cq_status dd_layout(const cq_dd_instance& in, const cq_dd_params& p, const CutMap& cm,
-                    const std::vector<DDSub>& s0, bool bins_stored, DDLayout& L) {
-  L = DDLayout();
-  int64_t off = 0;
+// Per-instance plan and the layout of its buffers.  The big buffers (reduced
+// entries, contraction workspace, bin scratch, top-C candidates) are shared
+// by the instances, which run one after another; each instance has its own
+// control block (program, state, descriptors, records).
+struct DDInstancePlan {
+  CutMap cm;
+  std::vector<DDSub> s0;
+  std::vector<int> amax;
+  Plan plan;
+  SymPlan sp;
+  std::vector<int64_t> ep_off, rs_off;
+  int64_t plan_off = 0, bins_off = 0, bins_bytes = 0, cand_off = 0, cand_cap = 0;
+  int64_t big = 0;  // bytes of the shared region this instance needs
+  int64_t max_count = 0;
+  std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
+};
+
+struct DDCtrl {
+  int64_t prog = 0, state = 0, level = 0, recs = 0, bytes = 0;
+};
+
+DDCtrl dd_ctrl(int R) {
+  DDCtrl c;
+  c.prog = 0;
+  c.state = align256(c.prog + (int64_t)sizeof(DDProgram));
+  c.level = align256(c.state + (int64_t)sizeof(DDState));
+  c.recs = align256(c.level + (int64_t)sizeof(DDLevel));
+  c.bytes = align256(c.recs + (int64_t)R * (int64_t)sizeof(cq_dd_record));
+  return c;
+}
+
+cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool bins_stored,
+                           DDInstancePlan& D) {
+  cq_status st = dd_validate(in, p, D.cm, D.s0);
+  if (st != CQ_OK) return st;
+  const CutMap& cm = D.cm;
   int sum_a = 0;
+  D.amax.clear();
   for (int c = 0; c < cm.n_sub; ++c) {
-    const int a = std::max(popc(s0[c].active), std::min(in.max_active[c], cm.subs[c].n()));
-    L.amax.push_back(a);
+    const int a = std::max(popc(D.s0[c].active), std::min(in.max_active[c], cm.subs[c].n()));
+    D.amax.push_back(a);
     sum_a += a;
   }
+  st = make_sym_plan(cm, D.amax, work_elem_bytes(p.prec), D.plan, D.sp);
+  if (st != CQ_OK) return st;
+  if ((int)D.plan.steps.size() > kDDMaxSteps || (int)D.plan.tensors.size() > kDDMaxTensors)
+    return fail(CQ_ERR_UNSUPPORTED, "bin contraction plan too long for the device program");
+  for (const Step& s : D.plan.steps)
+    if (!s.is_gemm && (int)s.p.log2.size() > kDDMaxPermAxes)
+      return fail(CQ_ERR_UNSUPPORTED, "bin contraction permute has too many axes");
+  int64_t off = 0;
+  D.ep_off.clear();
+  D.rs_off.clear();
   for (int c = 0; c < cm.n_sub; ++c) {
-    L.ep_off.push_back(off);
-    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * ((int64_t)1 << L.amax[c]) * 8);
+    D.ep_off.push_back(off);
+    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * ((int64_t)1 << D.amax[c]) * 8);
   }
   for (int c = 0; c < cm.n_sub; ++c) {
-    L.rs_off.push_back(off);
+    D.rs_off.push_back(off);
     off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * 8);
   }
-  Plan plan;
-  cq_status st = make_plan(cm, L.amax, work_elem_bytes(p.prec), {}, plan);
-  if (st != CQ_OK) return st;
-  // smaller shapes may pick another order; leave room for a factor of 2
-  L.plan_off = off;
-  L.plan_bytes = align256(2 * plan.workspace_bytes);
-  off += L.plan_bytes;
-  const int64_t nbins = (int64_t)1 << sum_a;
-  L.bins_off = off;
-  L.bins_bytes = bins_stored ? 0 : align256(nbins * (p.prec == CQ_FP64 ? 8 : 4));
-  off += L.bins_bytes;
-  L.cand_off = off;
-  L.cand_cap = topk_candidate_capacity(nbins, 64);
-  off = align256(off + L.cand_cap * 16);
-  L.small_off = off;
-  off = align256(off + 64 * 8 * 4 + 256);
-  L.total = off;
+  D.plan_off = off;
+  off = align256(off + D.plan.workspace_bytes);
+  D.max_count = (int64_t)1 << sum_a;
+  D.bins_off = off;
+  D.bins_bytes = bins_stored ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
+  off += D.bins_bytes;
+  D.cand_off = off;
+  D.cand_cap = topk_indirect_capacity(D.max_count);
+  off = align256(off + D.cand_cap * 16);
+  D.big = off;
+  D.step_max.clear();
+  for (const Step& s : D.plan.steps) {
+    if (s.is_gemm) {
+      const GemmStep& g = s.g;
+      D.step_max.push_back(((g.M + 127) / 128) * ((g.N + 127) / 128) * g.Z);
+      if (D.step_max.back() > 0x7fffffffLL) return fail(CQ_ERR_SHAPE, "bin contraction too large");
+    } else {
+      int bits = 0;
+      for (int l : s.p.log2) bits += l;
+      D.step_max.push_back((int64_t)1 << bits);
+    }
+  }
   return CQ_OK;
 }
 
-struct ListEntry {
-  double v;
-  int rec;
-  uint64_t bin;
-  std::vector<DDSub> child;
-};
-
-bool list_less(const ListEntry& a, const ListEntry& b) {
-  if (a.v != b.v) return a.v > b.v;
-  if (a.rec != b.rec) return a.rec < b.rec;
-  return a.bin < b.bin;
+cq_status dd_plan_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
+                      bool bins_stored, std::vector<DDInstancePlan>& plans, int64_t& big,
+                      int64_t& total) {
+  plans.assign(n_inst, DDInstancePlan());
+  big = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    cq_status st = dd_plan_instance(inst[i], p, bins_stored, plans[i]);
+    if (st != CQ_OK) return st;
+    big = std::max(big, plans[i].big);
+  }
+  total = align256(big) + (int64_t)n_inst * dd_ctrl(p.R).bytes;
+  return CQ_OK;
 }
 
-cq_status dd_run_instance(const cq_dd_instance& in, const cq_dd_params& p, cq_dd_record* recs,
-                          void* const* bins_user, int32_t* done, char* ws, size_t ws_bytes,
-                          hipStream_t stream) {
-  CutMap cm;
-  std::vector<DDSub> state;
-  cq_status st = dd_validate(in, p, cm, state);
-  if (st != CQ_OK) return st;
-  DDLayout L;
-  st = dd_layout(in, p, cm, state, bins_user != nullptr, L);
-  if (st != CQ_OK) return st;
-  if ((int64_t)ws_bytes < L.total || !ws) return fail(CQ_ERR_WORKSPACE, "workspace too small");
-  const int n_sub = cm.n_sub;
-  const int R = p.R;
-  const double scale = std::ldexp(1.0, -cm.K);
-  std::vector<ListEntry> list;
-  double* small = reinterpret_cast<double*>(ws + L.small_off);
-  double* top_val = small;                                     // 64
-  uint64_t* top_idx = reinterpret_cast<uint64_t*>(small + 64);  // 64
-  double* ref_out = small + 128;                               // 64
-  uint64_t* zero_idx = reinterpret_cast<uint64_t*>(small + 192);  // 1
-  double* total_out = small + 193;                             // 1
-  hipError_t e = hipMemsetAsync(zero_idx, 0, sizeof(uint64_t), stream);
-  if (e != hipSuccess) return hip_fail(e, "memset");
-  *done = 0;
-  for (int r = 0; r < R; ++r) {
-    cq_dd_record& rec = recs[r];
-    std::memset(&rec, 0, sizeof(rec));
-    std::vector<int> na(n_sub), nm(n_sub);
-    int sum_a = 0;
-    bool any_merged = false;
-    std::vector<const double*> ep(n_sub), rs(n_sub);
-    for (int c = 0; c < n_sub; ++c) {
-      const int n = cm.subs[c].n();
-      const DDSub& d = state[c];
-      rec.active[c] = d.active;
-      rec.merged[c] = d.merged;
-      rec.fixed[c] = d.fixed;
-      rec.fixed_vals[c] = d.fixed_vals;
-      na[c] = popc(d.active);
-      nm[c] = popc(d.merged);
-      if (na[c] > L.amax[c]) return fail(CQ_ERR_WORKSPACE, "active count exceeds the planned maximum");
-      sum_a += na[c];
-      any_merged = any_merged || nm[c] > 0;
-      const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
-      double* Ep = reinterpret_cast<double*>(ws + L.ep_off[c]);
-      double* Rs = reinterpret_cast<double*>(ws + L.rs_off[c]);
-      MergeLaunch M;
-      M.E = in.entries[c];
-      M.Ep = Ep;
-      M.rows = rows;
-      M.n = n;
-      M.na = na[c];
-      M.nm = nm[c];
-      M.active_flat = to_flat(d.active, n);
-      M.merged_flat = to_flat(d.merged, n);
-      M.fixed_vals_flat = to_flat(d.fixed_vals, n);
-      {
-        ProfScope ps("dd_merge", 0.0, stream);
-        e = launch_merge(M, stream);
-      }
-      if (e != hipSuccess) return hip_fail(e, "merge launch");
-      // row sums of the reduced entries give the recursion total
-      MergeLaunch S;
-      S.E = Ep;
-      S.Ep = Rs;
-      S.rows = rows;
-      S.n = na[c];
-      S.na = 0;
-      S.nm = na[c];
-      S.active_flat = 0;
-      S.merged_flat = na[c] == 64 ? ~(uint64_t)0 : (((uint64_t)1 << na[c]) - 1);
-      S.fixed_vals_flat = 0;
-      e = launch_merge(S, stream);
-      if (e != hipSuccess) return hip_fail(e, "row-sum launch");
-      ep[c] = Ep;
-      rs[c] = Rs;
+SymPow to_dev(const SymQ& q) {
+  SymPow s;
+  s.c0 = q.c0;
+  s.mask = q.mask;
+  s.zero = q.zero ? 1 : 0;
+  s.pad = 0;
+  return s;
+}
+
+// Host image of an instance's device program; pointers refer to `ws`.
+void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_params& p, char* ws,
+                DDProgram& P) {
+  std::memset(&P, 0, sizeof(P));
+  const CutMap& cm = D.cm;
+  const Plan& plan = D.plan;
+  const DType wt = work_dtype(p.prec);
+  P.n_sub = cm.n_sub;
+  P.K = cm.K;
+  P.R = p.R;
+  P.n_steps = (int)plan.steps.size();
+  P.C_max = std::min(4 * p.R, kDDMaxC);
+  for (int c = 0; c < cm.n_sub; ++c) {
+    P.n_out[c] = cm.subs[c].n();
+    P.max_active[c] = in.max_active[c];
+    P.kc[c] = cm.subs[c].k();
+    for (int j = 0; j < P.kc[c]; ++j) P.cut[c][j] = cm.subs[c].cuts[j];
+    P.rows[c] = (int64_t)1 << (2 * cm.subs[c].k());
+    P.E[c] = in.entries[c];
+    P.Ep[c] = reinterpret_cast<double*>(ws + D.ep_off[c]);
+    P.Rs[c] = reinterpret_cast<double*>(ws + D.rs_off[c]);
+    P.prep_dst[c] = -1;
+  }
+  char* pw = ws + D.plan_off;
+  for (size_t t = 0; t < plan.tensors.size(); ++t) {
+    const TensorRef& T = plan.tensors[t];
+    DDTensor& d = P.tensor[t];
+    P.tensor_elems[t] = to_dev(D.sp.elems[t]);
+    if (T.loc == Loc::Out) {
+      d.is_out = 1;
+      continue;
     }
-    rec.n_active = sum_a;
-    RefineLaunch T;
-    std::memset(&T, 0, sizeof(T));
-    T.n_sub = n_sub;
-    T.K = cm.K;
-    for (int c = 0; c < n_sub; ++c) {
-      T.Ep[c] = rs[c];
-      T.ld[c] = 1;
-      T.na[c] = 0;
-      T.kc[c] = cm.subs[c].k();
-      for (int j = 0; j < T.kc[c]; ++j) T.cut[c][j] = cm.subs[c].cuts[j];
-    }
-    T.bins = zero_idx;
-    T.nbins = 1;
-    T.scale = scale;
-    T.out = total_out;
-    e = launch_refine(T, stream);
-    if (e != hipSuccess) return hip_fail(e, "total launch");
-    // bins
-    Plan plan;
-    st = make_plan(cm, na, work_elem_bytes(p.prec), {}, plan);
-    if (st != CQ_OK) return st;
-    if (plan.workspace_bytes > L.plan_bytes) return fail(CQ_ERR_WORKSPACE, "bin plan exceeds workspace");
-    void* bins = bins_user ? bins_user[r] : nullptr;
-    if (!bins) {
-      if (L.bins_bytes == 0) return fail(CQ_ERR_ARG, "null bin buffer");
-      bins = ws + L.bins_off;
-    }
-    st = execute(plan, p.prec, ep.data(), bins, out_dtype(p.prec), ws + L.plan_off, stream);
-    if (st != CQ_OK) return st;
-    const int64_t nbins = (int64_t)1 << sum_a;
-    int C = 0;
-    if (any_merged) {
-      C = (int)std::min<int64_t>(std::min(4 * R, 64), nbins);
-      TopkLaunch K;
-      K.bins = bins;
-      K.t = out_dtype(p.prec);
-      K.count = nbins;
-      K.C = C;
-      K.cand_val = reinterpret_cast<double*>(ws + L.cand_off);
-      K.cand_idx = reinterpret_cast<uint64_t*>(ws + L.cand_off + L.cand_cap * 8);
-      K.cand_capacity = L.cand_cap;
-      K.out_val = top_val;
-      K.out_idx = top_idx;
-      {
-        ProfScope ps("dd_topk", 0.0, stream);
-        e = launch_topk(K, stream);
+    char* base;
+    if (T.loc == Loc::Input) {
+      if (plan.input_offset[T.index] < 0) {
+        d.hi = P.Ep[T.index];
+        continue;
       }
-      if (e != hipSuccess) return hip_fail(e, "top-C launch");
-      RefineLaunch F;
-      std::memset(&F, 0, sizeof(F));
-      F.n_sub = n_sub;
-      F.K = cm.K;
-      for (int c = 0; c < n_sub; ++c) {
-        F.Ep[c] = ep[c];
-        F.ld[c] = (int64_t)1 << na[c];
-        F.na[c] = na[c];
-        F.kc[c] = cm.subs[c].k();
-        for (int j = 0; j < F.kc[c]; ++j) F.cut[c][j] = cm.subs[c].cuts[j];
-      }
-      F.bins = top_idx;
-      F.nbins = C;
-      F.scale = scale;
-      F.out = ref_out;
-      {
-        ProfScope ps("dd_refine", 0.0, stream);
-        e = launch_refine(F, stream);
-      }
-      if (e != hipSuccess) return hip_fail(e, "refine launch");
+      base = pw + plan.input_offset[T.index];
+      P.prep_dst[T.index] = (int)t;
+    } else {
+      base = pw + plan.work_offset[T.index];
     }
-    std::vector<uint64_t> h_idx(64);
-    std::vector<double> h_val(64);
-    double h_total = 0.0;
-    e = hipMemcpyAsync(&h_total, total_out, sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && C > 0)
-      e = hipMemcpyAsync(h_idx.data(), top_idx, C * sizeof(uint64_t), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && C > 0)
-      e = hipMemcpyAsync(h_val.data(), ref_out, C * sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "readback");
-    rec.total = h_total;
-    // list update (Algorithm 1): R largest new bins by FP64 value
-    std::vector<std::pair<double, uint64_t>> cand;
-    for (int i = 0; i < C; ++i) cand.push_back({h_val[i], h_idx[i]});
-    std::sort(cand.begin(), cand.end(), [](const std::pair<double, uint64_t>& a,
-                                           const std::pair<double, uint64_t>& b) {
-      if (a.first != b.first) return a.first > b.first;
-      return a.second < b.second;
-    });
-    for (int i = 0; i < (int)cand.size() && i < R; ++i) {
-      ListEntry le;
-      le.v = cand[i].first;
-      le.rec = r;
-      le.bin = cand[i].second;
-      int shift = sum_a;
-      for (int c = 0; c < n_sub; ++c) {
-        shift -= na[c];
-        const uint64_t bits = (le.bin >> shift) & ((na[c] == 64) ? ~(uint64_t)0 : (((uint64_t)1 << na[c]) - 1));
-        DDSub ch = state[c];
-        int t = 0;
-        for (int pos = 0; pos < 64; ++pos) {
-          if ((ch.active >> pos) & 1) {
-            if ((bits >> (na[c] - 1 - t)) & 1) ch.fixed_vals |= (uint64_t)1 << pos;
-            ++t;
-          }
-        }
-        ch.fixed |= ch.active;
-        ch.active = 0;
-        le.child.push_back(ch);
+    d.hi = base;
+    // split planes: lo follows hi at the largest size, whatever the recursion's size
+    d.lo = wt == DType::H16X2 ? base + T.elems * 2 : nullptr;
+  }
+  for (size_t si = 0; si < plan.steps.size(); ++si) {
+    const Step& s = plan.steps[si];
+    P.step_is_gemm[si] = s.is_gemm ? 1 : 0;
+    if (s.is_gemm) {
+      const SymGemm& q = D.sp.gemm[si];
+      DDGemmSym& g = P.gemm[si];
+      g.a = s.g.a;
+      g.b = s.g.b;
+      g.c = s.g.c;
+      g.Z = to_dev(q.Z);
+      g.M = to_dev(q.M);
+      g.N = to_dev(q.N);
+      g.K = to_dev(q.K);
+      g.sAz = to_dev(q.sAz);
+      g.sAk = to_dev(q.sAk);
+      g.sBz = to_dev(q.sBz);
+      g.sBk = to_dev(q.sBk);
+      g.sCz = to_dev(q.sCz);
+      g.ldc = to_dev(q.ldc);
+      g.alpha = s.g.alpha;
+    } else {
+      const SymPerm& q = D.sp.perm[si];
+      DDPermSym& m = P.perm[si];
+      m.src = s.p.src;
+      m.dst = s.p.dst;
+      m.naxes = (int)q.log2.size();
+      for (int i = 0; i < m.naxes; ++i) {
+        m.log2[i].c0 = q.log2[i].c0;
+        m.log2[i].mask = q.log2[i].mask;
+        m.sstride[i] = to_dev(q.sstride[i]);
       }
-      list.push_back(le);
-    }
-    std::sort(list.begin(), list.end(), list_less);
-    if ((int)list.size() > R) list.resize(R);
-    rec.n_list = (int)list.size();
-    for (int i = 0; i < rec.n_list; ++i) {
-      rec.list_val[i] = list[i].v;
-      rec.list_rec[i] = list[i].rec;
-      rec.list_bin[i] = list[i].bin;
-    }
-    *done = r + 1;
-    if (list.empty()) break;
-    rec.popped = 1;
-    ListEntry head = list.front();
-    list.erase(list.begin());
-    // zoom: activate the first max_active[c] merged outputs of the popped bin
-    for (int c = 0; c < n_sub; ++c) {
-      DDSub nx = head.child[c];
-      uint64_t act = 0, mer = nx.merged;
-      int taken = 0;
-      for (int pos = 0; pos < 64 && taken < in.max_active[c]; ++pos) {
-        if ((mer >> pos) & 1) {
-          act |= (uint64_t)1 << pos;
-          ++taken;
-        }
-      }
-      nx.active = act;
-      nx.merged = mer & ~act;
-      state[c] = nx;
+      m.alpha = s.p.alpha;
     }
   }
+}
+
+DType tensor_dtype(const Plan& plan, int t, cq_precision prec) {
+  const TensorRef& T = plan.tensors[t];
+  if (T.loc == Loc::Out) return out_dtype(prec);
+  if (T.loc == Loc::Input && plan.input_offset[T.index] < 0) return DType::F64;
+  return work_dtype(prec);
+}
+
+// Enqueues recursion r of one instance.
+cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char* ws, char* ctrl,
+                           int r, void* bins, hipStream_t stream) {
+  const DDCtrl L = dd_ctrl(p.R);
+  const DDProgram* prog = reinterpret_cast<const DDProgram*>(ctrl + L.prog);
+  DDState* st = reinterpret_cast<DDState*>(ctrl + L.state);
+  DDLevel* lv = reinterpret_cast<DDLevel*>(ctrl + L.level);
+  cq_dd_record* recs = reinterpret_cast<cq_dd_record*>(ctrl + L.recs);
+  const CutMap& cm = D.cm;
+  const int ns = cm.n_sub;
+  const cq_precision prec = p.prec;
+  hipError_t e = launch_dd_setup(prog, st, lv, recs, r, bins, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup launch");
+  int64_t merge_threads = 0, rs_threads = 0, prep_n = 0;
+  for (int c = 0; c < ns; ++c) {
+    const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
+    merge_threads = std::max(merge_threads, (rows << D.amax[c]) << 6);
+    rs_threads = std::max(rs_threads, rows << 6);
+    prep_n = std::max(prep_n, rows << D.amax[c]);
+  }
+  e = launch_merge_indirect(&lv->merge[0], ns, merge_threads, stream);
+  if (e != hipSuccess) return hip_fail(e, "merge launch");
+  e = launch_merge_indirect(&lv->rowsum[0], ns, rs_threads, stream);
+  if (e != hipSuccess) return hip_fail(e, "row-sum launch");
+  RefineLaunch T;
+  std::memset(&T, 0, sizeof(T));
+  T.n_sub = ns;
+  T.K = cm.K;
+  for (int c = 0; c < ns; ++c) {
+    T.Ep[c] = reinterpret_cast<const double*>(ws + D.rs_off[c]);
+    T.ld[c] = 1;
+    T.kc[c] = cm.subs[c].k();
+    for (int j = 0; j < T.kc[c]; ++j) T.cut[c][j] = cm.subs[c].cuts[j];
+  }
+  T.bins = &st->zero_idx;
+  T.nbins = 1;
+  T.scale = std::ldexp(1.0, -cm.K);
+  T.out = &st->total;
+  e = launch_refine(T, stream);
+  if (e != hipSuccess) return hip_fail(e, "total launch");
+  if (work_dtype(prec) != DType::F64) {
+    e = launch_prep_indirect(&lv->prep[0], ns, work_dtype(prec), is_f16(prec), prep_n, stream);
+    if (e != hipSuccess) return hip_fail(e, "operand prep launch");
+  }
+  for (size_t si = 0; si < D.plan.steps.size(); ++si) {
+    const Step& s = D.plan.steps[si];
+    if (s.is_gemm) {
+      e = launch_gemm_indirect(prec, &lv->gemm[si], D.step_max[si], tensor_dtype(D.plan, s.g.c, prec),
+                               false, stream);
+      if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
+    } else {
+      e = launch_permute_indirect(&lv->perm[si], tensor_dtype(D.plan, s.p.src, prec),
+                                  tensor_dtype(D.plan, s.p.dst, prec), is_f16(prec), D.step_max[si],
+                                  stream);
+      if (e != hipSuccess) return hip_fail(e, "permute launch");
+    }
+  }
+  e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, D.max_count,
+                           reinterpret_cast<double*>(ws + D.cand_off),
+                           reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8), D.cand_cap,
+                           st->top_val, st->top_idx, stream);
+  if (e != hipSuccess) return hip_fail(e, "top-C launch");
+  e = launch_refine_indirect(&lv->refine, std::min(4 * p.R, kDDMaxC), stream);
+  if (e != hipSuccess) return hip_fail(e, "refine launch");
+  e = launch_dd_update(prog, st, recs, r, stream);
+  if (e != hipSuccess) return hip_fail(e, "update launch");
+  return CQ_OK;
+}
+
+cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
+                         const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
+                         int64_t big, hipStream_t stream) {
+  const DDCtrl L = dd_ctrl(p.R);
+  for (int i = 0; i < n_inst; ++i) {
+    const DDInstancePlan& D = plans[i];
+    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
+    DDInit init;
+    std::memset(&init, 0, sizeof(init));
+    for (int c = 0; c < D.cm.n_sub; ++c) {
+      init.active[c] = D.s0[c].active;
+      init.merged[c] = D.s0[c].merged;
+      init.fixed[c] = D.s0[c].fixed;
+      init.fixed_vals[c] = D.s0[c].fixed_vals;
+    }
+    hipError_t e = launch_dd_init(reinterpret_cast<DDState*>(ctrl + L.state),
+                                  reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, init, stream);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    for (int r = 0; r < p.R; ++r) {
+      void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
+      if (!bins) bins = ws + D.bins_off;
+      cq_status st = dd_enqueue_level(D, p, ws, ctrl, r, bins, stream);
+      if (st != CQ_OK) return st;
+    }
+  }
+  return CQ_OK;
+}
+
+// Owns the captured graph; it is released only after `stream` has drained.
+struct DDGraph {
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool launched = false;
+  ~DDGraph() {
+    if (launched) (void)hipStreamSynchronize(stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// Captures the batch on a private stream and launches it once on `stream`.
+cq_status dd_run_graph(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
+                       const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
+                       int64_t big, hipStream_t stream, DDGraph& G) {
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "capture stream");
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "begin capture");
+  }
+  cq_status st = dd_enqueue_all(n_inst, inst, p, plans, bins_user, ws, big, cs);
+  e = hipStreamEndCapture(cs, &G.graph);
+  (void)hipStreamDestroy(cs);
+  if (st != CQ_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  G.stream = stream;
+  e = hipGraphLaunch(G.exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  G.launched = true;
   return CQ_OK;
 }
 
@@ -626,18 +677,11 @@ extern "C" cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* 
                                           const cq_dd_params* params, int32_t bins_stored,
                                           size_t* bytes) {
   if (n_inst < 1 || !inst || !params || !bytes) return fail(CQ_ERR_ARG, "null or empty argument");
-  int64_t need = 0;
-  for (int i = 0; i < n_inst; ++i) {
-    CutMap cm;
-    std::vector<DDSub> s0;
-    cq_status st = dd_validate(inst[i], *params, cm, s0);
-    if (st != CQ_OK) return st;
-    DDLayout L;
-    st = dd_layout(inst[i], *params, cm, s0, bins_stored != 0, L);
-    if (st != CQ_OK) return st;
-    need = std::max(need, L.total);
-  }
-  *bytes = (size_t)need;
+  std::vector<DDInstancePlan> plans;
+  int64_t big = 0, total = 0;
+  cq_status st = dd_plan_all(n_inst, inst, *params, bins_stored != 0, plans, big, total);
+  if (st != CQ_OK) return st;
+  *bytes = (size_t)total;
   return CQ_OK;
 }
 
@@ -648,25 +692,49 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   if (n_inst < 1 || !inst || !params || !records || !recursions_done)
     return fail(CQ_ERR_ARG, "null or empty argument");
   if (!prec_supported(params->prec)) return fail(CQ_ERR_UNSUPPORTED, "precision not built");
-  // validate everything before the first launch
-  for (int i = 0; i < n_inst; ++i) {
-    CutMap cm;
-    std::vector<DDSub> s0;
-    cq_status st = dd_validate(inst[i], *params, cm, s0);
-    if (st != CQ_OK) return st;
-    DDLayout L;
-    st = dd_layout(inst[i], *params, cm, s0, bins != nullptr, L);
-    if (st != CQ_OK) return st;
-    if (!workspace || (int64_t)workspace_bytes < L.total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
-  }
+  if (params->launch != CQ_DD_GRAPH && params->launch != CQ_DD_DIRECT)
+    return fail(CQ_ERR_ARG, "unknown launch mode");
+  // validate and plan everything before the first launch
+  std::vector<DDInstancePlan> plans;
+  int64_t big = 0, total = 0;
+  cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, plans, big, total);
+  if (st != CQ_OK) return st;
+  if (!workspace || (int64_t)workspace_bytes < total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
+  if (bins)
+    for (int i = 0; i < n_inst; ++i)
+      for (int r = 0; r < params->R; ++r)
+        if (!bins[(size_t)i * params->R + r] && plans[i].bins_bytes == 0)
+          return fail(CQ_ERR_ARG, "null bin buffer");
   if (fault_injected("dd")) return fail(CQ_ERR_HIP, "injected fault before launch");
+  char* ws = static_cast<char*>(workspace);
+  const DDCtrl L = dd_ctrl(params->R);
+  // device programs (host images stay alive until the final synchronisation)
+  std::vector<DDProgram> progs(n_inst);
   for (int i = 0; i < n_inst; ++i) {
-    cq_status st = dd_run_instance(inst[i], *params, records + (size_t)i * params->R,
-                                   bins ? bins + (size_t)i * params->R : nullptr,
-                                   recursions_done + i, static_cast<char*>(workspace),
-                                   workspace_bytes, stream);
-    if (st != CQ_OK) return st;
+    dd_program(plans[i], inst[i], *params, ws, progs[i]);
+    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
+    hipError_t e = hipMemcpyAsync(ctrl + L.prog, &progs[i], sizeof(DDProgram), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "program upload");
   }
+  DDGraph graph;
+  if (params->launch == CQ_DD_GRAPH)
+    st = dd_run_graph(n_inst, inst, *params, plans, bins, ws, big, stream, graph);
+  else
+    st = dd_enqueue_all(n_inst, inst, *params, plans, bins, ws, big, stream);
+  if (st != CQ_OK) return st;
+  std::vector<int32_t> done(n_inst, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
+    hipError_t e = hipMemcpyAsync(records + (size_t)i * params->R, ctrl + L.recs,
+                                  sizeof(cq_dd_record) * params->R, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&done[i], ctrl + L.state + offsetof(DDState, done), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "record readback");
+  }
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "synchronise");
+  for (int i = 0; i < n_inst; ++i) recursions_done[i] = done[i];
   return CQ_OK;
 }
 

@@ -10,17 +10,6 @@ namespace {
 // Element kinds of a permute's source and destination.
 enum Kind { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
 
-struct PermArgs {
-  const void* src;
-  const void* src_lo;  // lo plane of a split source, else null
-  void* dst;
-  void* dst_lo;        // lo plane of a split destination, else null
-  int64_t total;
-  int naxes;
-  int log2[kMaxPermAxes];
-  int64_t sstride[kMaxPermAxes];
-  double alpha;
-};
 
 __device__ inline float h16_to_f(uint16_t x, bool f16) {
   return f16 ? float(__builtin_bit_cast(_Float16, x)) : float(__builtin_bit_cast(__bf16, x));
@@ -33,7 +22,7 @@ __device__ inline uint16_t f_to_h16(float x, bool f16) {
 // thread iteration, destination written contiguously.  16-bit planes are
 // copied bit for bit when both sides use them.
 template <int SK, int DK>
-__global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
+__device__ inline void permute_body(const PermArgs& p) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.total; i += step) {
     int64_t r = i, off = 0;
@@ -66,10 +55,19 @@ __global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
   }
 }
 
+template <int SK, int DK>
+__global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
+  permute_body<SK, DK>(p);
+}
+
+template <int SK, int DK>
+__global__ void __launch_bounds__(256) permute_ind_kernel(const PermArgs* __restrict__ p) {
+  permute_body<SK, DK>(*p);
+}
+
 // FP64 -> FP32 or 16-bit planes (hi = rn16(x), lo = rn16(x - hi)).
 template <int DK>
-__global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ src, void* dst,
-                                                   void* dst_lo, int64_t n) {
+__device__ inline void prep_body(const double* __restrict__ src, void* dst, void* dst_lo, int64_t n) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
     const float x = float(src[i]);
@@ -81,6 +79,19 @@ __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ sr
       if (dst_lo) static_cast<uint16_t*>(dst_lo)[i] = f_to_h16(x - h16_to_f(h, DK == kF16), DK == kF16);
     }
   }
+}
+
+template <int DK>
+__global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ src, void* dst,
+                                                   void* dst_lo, int64_t n) {
+  prep_body<DK>(src, dst, dst_lo, n);
+}
+
+// blockIdx.y selects the argument block
+template <int DK>
+__global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a) {
+  const PrepArgs p = a[blockIdx.y];
+  prep_body<DK>(p.src, p.dst, p.dst_lo, p.n);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,6 +198,15 @@ __global__ void __launch_bounds__(256) attr_init_kernel(AttrArgs a) {
   }
 }
 
+// Indirect launches size their grid for the largest shape and loop; a
+// moderate cap keeps the empty workgroups of smaller shapes cheap.
+unsigned grid_ind(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
 unsigned grid_for(int64_t total) {
   int64_t b = (total + 255) / 256;
   if (b > 1 << 20) b = 1 << 20;
@@ -211,7 +231,44 @@ void permute_dispatch_dst(int dk, dim3 grid, const PermArgs& a, hipStream_t s) {
   }
 }
 
+template <int SK>
+void permute_ind_dispatch_dst(int dk, dim3 grid, const PermArgs* a, hipStream_t s) {
+  switch (dk) {
+    case kF64: hipLaunchKernelGGL((permute_ind_kernel<SK, kF64>), grid, dim3(256), 0, s, a); break;
+    case kF32: hipLaunchKernelGGL((permute_ind_kernel<SK, kF32>), grid, dim3(256), 0, s, a); break;
+    case kBF16: hipLaunchKernelGGL((permute_ind_kernel<SK, kBF16>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((permute_ind_kernel<SK, kF16>), grid, dim3(256), 0, s, a); break;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_permute_indirect(const PermArgs* dev, DType ts, DType td, bool f16,
+                                   int64_t max_total, hipStream_t stream) {
+  if (max_total <= 0) return hipSuccess;
+  const dim3 grid(grid_ind(max_total));
+  const int sk = kind_of(ts, f16), dk = kind_of(td, f16);
+  switch (sk) {
+    case kF64: permute_ind_dispatch_dst<kF64>(dk, grid, dev, stream); break;
+    case kF32: permute_ind_dispatch_dst<kF32>(dk, grid, dev, stream); break;
+    case kBF16: permute_ind_dispatch_dst<kBF16>(dk, grid, dev, stream); break;
+    default: permute_ind_dispatch_dst<kF16>(dk, grid, dev, stream); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_indirect(const PrepArgs* dev, int count, DType t, bool f16, int64_t max_n,
+                                hipStream_t stream) {
+  if (max_n <= 0 || count <= 0) return hipSuccess;
+  const dim3 grid(grid_ind(max_n), (unsigned)count);
+  if (t == DType::F32)
+    hipLaunchKernelGGL((prep_ind_kernel<kF32>), grid, dim3(256), 0, stream, dev);
+  else if (f16)
+    hipLaunchKernelGGL((prep_ind_kernel<kF16>), grid, dim3(256), 0, stream, dev);
+  else
+    hipLaunchKernelGGL((prep_ind_kernel<kBF16>), grid, dim3(256), 0, stream, dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
   PermArgs a;

@@ -25,34 +25,38 @@ __device__ inline uint64_t deposit(uint64_t x, uint64_t mask) {
   return r;
 }
 
-struct MergeArgs {
-  const double* E;
-  double* Ep;
-  int64_t outputs;  // rows << na
-  int n, na, tpo_log2;
-  int64_t iters;    // 2^(nm - tpo_log2)
-  uint64_t active_flat, merged_lo, merged_hi, fixed_vals_flat;
-};
 
 // A group of 2^tpo_log2 lanes sums one reduced entry; lanes stride the merged
-// index, then a fixed xor-butterfly combines them (deterministic order).
-__global__ void __launch_bounds__(256) merge_kernel(MergeArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t out = g >> a.tpo_log2;
-  const int sub = (int)(g & ((1 << a.tpo_log2) - 1));
-  if (out >= a.outputs) return;
-  const int64_t row = out >> a.na;
-  const uint64_t av = (uint64_t)(out & (((int64_t)1 << a.na) - 1));
-  const double* Er = a.E + (row << a.n);
-  const uint64_t base = a.fixed_vals_flat | deposit(av, a.active_flat) | deposit((uint64_t)sub, a.merged_lo);
-  double acc = 0.0;
-  uint64_t d = 0;
-  for (int64_t t = 0; t < a.iters; ++t) {
-    acc += Er[base | d];
-    d = ((d | ~a.merged_hi) + 1) & a.merged_hi;
+// index, then a fixed xor-butterfly combines them (deterministic order).  The
+// lanes of a group share their loop trip count, so the butterfly only reads
+// active lanes.
+__device__ inline void merge_body(const MergeArgs& a) {
+  const int64_t total = a.outputs << a.tpo_log2;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += step) {
+    const int64_t out = g >> a.tpo_log2;
+    const int sub = (int)(g & ((1 << a.tpo_log2) - 1));
+    const int64_t row = out >> a.na;
+    const uint64_t av = (uint64_t)(out & (((int64_t)1 << a.na) - 1));
+    const double* Er = a.E + (row << a.n);
+    const uint64_t base = a.fixed_vals_flat | deposit(av, a.active_flat) | deposit((uint64_t)sub, a.merged_lo);
+    double acc = 0.0;
+    uint64_t d = 0;
+    for (int64_t t = 0; t < a.iters; ++t) {
+      acc += Er[base | d];
+      d = ((d | ~a.merged_hi) + 1) & a.merged_hi;
+    }
+    for (int s = (1 << a.tpo_log2) >> 1; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
+    if (sub == 0) a.Ep[out] = acc;
   }
-  for (int s = (1 << a.tpo_log2) >> 1; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
-  if (sub == 0) a.Ep[out] = acc;
+}
+
+__global__ void __launch_bounds__(256) merge_kernel(MergeArgs a) { merge_body(a); }
+
+// blockIdx.y selects the argument block
+__global__ void __launch_bounds__(256) merge_ind_kernel(const MergeArgs* __restrict__ a) {
+  const MergeArgs m = a[blockIdx.y];
+  merge_body(m);
 }
 
 // ---------------------------------------------------------------------------
@@ -95,15 +99,27 @@ __device__ void bitonic_sort(Key* buf) {
   }
 }
 
+// count_dev / C_dev, when given, replace count (the chunk then follows the
+// grid) and C.  Each workgroup writes out_stride keys, the worst key past its
+// survivors.
 template <typename T, bool kExplicit>
 __global__ void __launch_bounds__(256) topk_kernel(const T* __restrict__ vals,
                                                    const uint64_t* __restrict__ idxs,
                                                    int64_t count, int64_t chunk, int C,
                                                    double* __restrict__ out_v,
-                                                   uint64_t* __restrict__ out_i) {
+                                                   uint64_t* __restrict__ out_i,
+                                                   const int64_t* __restrict__ count_dev,
+                                                   const int32_t* __restrict__ C_dev,
+                                                   int out_stride) {
   __shared__ Key buf[kTopS];
   __shared__ int cnt;
   __shared__ Key thr;
+  if (C_dev) C = *C_dev;
+  if (C <= 0) return;
+  if (count_dev) {
+    count = *count_dev;
+    chunk = (count + gridDim.x - 1) / gridDim.x;
+  }
   const int64_t begin = (int64_t)blockIdx.x * chunk;
   int64_t end = begin + chunk;
   if (end > count) end = count;
@@ -140,10 +156,10 @@ __global__ void __launch_bounds__(256) topk_kernel(const T* __restrict__ vals,
     if (cnt > kTopS - round) trim();
   }
   trim();
-  for (int t = threadIdx.x; t < C; t += blockDim.x) {
+  for (int t = threadIdx.x; t < out_stride; t += blockDim.x) {
     const Key k = (t < cnt) ? buf[t] : worst_key();
-    out_v[(int64_t)blockIdx.x * C + t] = k.v;
-    out_i[(int64_t)blockIdx.x * C + t] = k.i;
+    out_v[(int64_t)blockIdx.x * out_stride + t] = k.v;
+    out_i[(int64_t)blockIdx.x * out_stride + t] = k.i;
   }
 }
 
@@ -157,20 +173,9 @@ int64_t topk_blocks(int64_t count) {
 // ---------------------------------------------------------------------------
 // Refine: one workgroup per bin, threads over the 4^K global labels.
 // ---------------------------------------------------------------------------
-struct RefineArgs {
-  int n_sub, K;
-  const double* Ep[CQ_MAX_SUBCIRCUITS];
-  int64_t ld[CQ_MAX_SUBCIRCUITS];
-  int na[CQ_MAX_SUBCIRCUITS];
-  int kc[CQ_MAX_SUBCIRCUITS];
-  int cut[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];
-  const uint64_t* bins;
-  double scale;
-  double* out;
-};
 
-__global__ void __launch_bounds__(256) refine_kernel(RefineArgs a) {
-  __shared__ double red[256];
+__device__ inline void refine_body(const RefineArgs& a, double* red) {
+  if ((int)blockIdx.x >= a.nbins) return;
   const uint64_t bin = a.bins[blockIdx.x];
   int64_t col[CQ_MAX_SUBCIRCUITS];
   int shift = 0;
@@ -197,6 +202,16 @@ __global__ void __launch_bounds__(256) refine_kernel(RefineArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) a.out[blockIdx.x] = a.scale * red[0];
+}
+
+__global__ void __launch_bounds__(256) refine_kernel(RefineArgs a) {
+  __shared__ double red[256];
+  refine_body(a, red);
+}
+
+__global__ void __launch_bounds__(256) refine_ind_kernel(const RefineArgs* __restrict__ a) {
+  __shared__ double red[256];
+  refine_body(*a, red);
 }
 
 }  // namespace
@@ -239,17 +254,17 @@ hipError_t launch_topk(const TopkLaunch& t, hipStream_t stream) {
   if (t.t == DType::F64)
     hipLaunchKernelGGL((topk_kernel<double, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
                        static_cast<const double*>(t.bins), nullptr, t.count, chunk, t.C, t.cand_val,
-                       t.cand_idx);
+                       t.cand_idx, nullptr, nullptr, t.C);
   else
     hipLaunchKernelGGL((topk_kernel<float, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
                        static_cast<const float*>(t.bins), nullptr, t.count, chunk, t.C, t.cand_val,
-                       t.cand_idx);
+                       t.cand_idx, nullptr, nullptr, t.C);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nc = blocks * t.C;
   hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
                      (const double*)t.cand_val, (const uint64_t*)t.cand_idx, nc, nc, t.C, t.out_val,
-                     t.out_idx);
+                     t.out_idx, nullptr, nullptr, t.C);
   return hipGetLastError();
 }
 
@@ -265,10 +280,361 @@ hipError_t launch_refine(const RefineLaunch& r, hipStream_t stream) {
     for (int j = 0; j < CQ_MAX_LOCAL_CUTS; ++j) a.cut[c][j] = r.cut[c][j];
   }
   a.bins = r.bins;
+  a.nbins = r.nbins;
   a.scale = r.scale;
   a.out = r.out;
   if (r.nbins <= 0) return hipSuccess;
   hipLaunchKernelGGL(refine_kernel, dim3((unsigned)r.nbins), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_indirect(const MergeArgs* dev, int count, int64_t max_threads,
+                                 hipStream_t stream) {
+  if (count <= 0 || max_threads <= 0) return hipSuccess;
+  int64_t b = (max_threads + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(merge_ind_kernel, dim3((unsigned)b, (unsigned)count), dim3(256), 0, stream, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream) {
+  if (max_bins <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_ind_kernel, dim3((unsigned)max_bins), dim3(256), 0, stream, dev);
+  return hipGetLastError();
+}
+
+int64_t topk_indirect_capacity(int64_t max_count) { return topk_blocks(max_count) * kDDMaxC; }
+
+hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_dev,
+                                const int32_t* C_dev, int64_t max_count, double* cand_val,
+                                uint64_t* cand_idx, int64_t cand_capacity, double* out_val,
+                                uint64_t* out_idx, hipStream_t stream) {
+  const int64_t blocks = topk_blocks(max_count);
+  if (blocks * kDDMaxC > cand_capacity) return hipErrorInvalidValue;
+  if (t == DType::F64)
+    hipLaunchKernelGGL((topk_kernel<double, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                       static_cast<const double*>(bins), nullptr, (int64_t)0, (int64_t)0, 0,
+                       cand_val, cand_idx, count_dev, C_dev, kDDMaxC);
+  else
+    hipLaunchKernelGGL((topk_kernel<float, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                       static_cast<const float*>(bins), nullptr, (int64_t)0, (int64_t)0, 0,
+                       cand_val, cand_idx, count_dev, C_dev, kDDMaxC);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nc = blocks * kDDMaxC;
+  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
+                     (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
+                     out_idx, nullptr, C_dev, kDDMaxC);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device-driven recursion control.  These kernels run on one thread: they
+// handle a few hundred words per recursion.
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ inline int64_t sym_pow(const SymPow& s, const int32_t* na) {
+  if (s.zero) return 0;
+  int e = s.c0;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c)
+    if ((s.mask >> c) & 1u) e += na[c];
+  return (int64_t)1 << e;
+}
+
+__device__ inline int sym_log(const SymLog& s, const int32_t* na) {
+  int e = s.c0;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c)
+    if ((s.mask >> c) & 1u) e += na[c];
+  return e;
+}
+
+// output position i <-> flat bit n-1-i
+__device__ inline uint64_t pos_to_flat(uint64_t m, int n) {
+  uint64_t f = 0;
+  for (int i = 0; i < n; ++i)
+    if ((m >> i) & 1) f |= (uint64_t)1 << (n - 1 - i);
+  return f;
+}
+
+__device__ inline uint64_t low_bits(int k) { return k >= 64 ? ~(uint64_t)0 : (((uint64_t)1 << k) - 1); }
+
+// Merge descriptor: lanes take the lowest tpo merged flat bits, the loop the rest.
+__device__ inline void set_merge(MergeArgs& m, const double* E, double* Ep, int64_t rows, int n,
+                                 int na, uint64_t active_flat, uint64_t merged_flat,
+                                 uint64_t fixed_vals_flat) {
+  const int nm = __popcll(merged_flat);
+  const int tpo = nm < 6 ? nm : 6;
+  uint64_t lo = 0, rest = merged_flat;
+  for (int i = 0; i < tpo; ++i) {
+    const uint64_t low = rest & (~rest + 1);
+    lo |= low;
+    rest ^= low;
+  }
+  m.E = E;
+  m.Ep = Ep;
+  m.outputs = rows << na;
+  m.n = n;
+  m.na = na;
+  m.tpo_log2 = tpo;
+  m.iters = (int64_t)1 << (nm - tpo);
+  m.active_flat = active_flat;
+  m.merged_lo = lo;
+  m.merged_hi = rest;
+  m.fixed_vals_flat = fixed_vals_flat;
+}
+
+__global__ void dd_init_kernel(DDState* st, cq_dd_record* recs, int R, DDInit init) {
+  uint64_t* w = reinterpret_cast<uint64_t*>(recs);
+  const int64_t words = (int64_t)R * (int64_t)(sizeof(cq_dd_record) / 8);
+  for (int64_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
+    st->active[c] = init.active[c];
+    st->merged[c] = init.merged[c];
+    st->fixed[c] = init.fixed[c];
+    st->fixed_vals[c] = init.fixed_vals[c];
+    st->na[c] = 0;
+  }
+  st->n_active = 0;
+  st->stop = 0;
+  st->done = 0;
+  st->n_list = 0;
+  st->C = 0;
+  st->count = 0;
+  st->zero_idx = 0;
+  st->total = 0.0;
+}
+
+__global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DDLevel* lv,
+                                cq_dd_record* recs, int r, void* bins) {
+  if (threadIdx.x != 0) return;
+  const int ns = P->n_sub;
+  if (st->stop) {
+    for (int c = 0; c < ns; ++c) {
+      lv->merge[c].outputs = 0;
+      lv->rowsum[c].outputs = 0;
+      lv->prep[c].n = 0;
+    }
+    for (int s = 0; s < P->n_steps; ++s) {
+      lv->gemm[s].tiles = 0;
+      lv->perm[s].total = 0;
+    }
+    lv->refine.nbins = 0;
+    st->C = 0;
+    st->count = 0;
+    return;
+  }
+  cq_dd_record& rec = recs[r];
+  int32_t na[CQ_MAX_SUBCIRCUITS];
+  int sum = 0;
+  bool any_merged = false;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) na[c] = 0;
+  for (int c = 0; c < ns; ++c) {
+    const int n = P->n_out[c];
+    const uint64_t act = st->active[c], mer = st->merged[c], fv = st->fixed_vals[c];
+    na[c] = __popcll(act);
+    st->na[c] = na[c];
+    sum += na[c];
+    any_merged = any_merged || mer != 0;
+    rec.active[c] = act;
+    rec.merged[c] = mer;
+    rec.fixed[c] = st->fixed[c];
+    rec.fixed_vals[c] = fv;
+    set_merge(lv->merge[c], P->E[c], P->Ep[c], P->rows[c], n, na[c], pos_to_flat(act, n),
+              pos_to_flat(mer, n), pos_to_flat(fv, n));
+    // row sums of the reduced entries give the recursion total
+    set_merge(lv->rowsum[c], P->Ep[c], P->Rs[c], P->rows[c], na[c], 0, 0, low_bits(na[c]), 0);
+    const int t = P->prep_dst[c];
+    PrepArgs& pa = lv->prep[c];
+    pa.src = P->Ep[c];
+    pa.dst = t >= 0 ? P->tensor[t].hi : nullptr;
+    pa.dst_lo = t >= 0 ? P->tensor[t].lo : nullptr;
+    pa.n = t >= 0 ? sym_pow(P->tensor_elems[t], na) : 0;
+  }
+  rec.n_active = sum;
+  st->n_active = sum;
+  const int64_t count = (int64_t)1 << sum;
+  st->count = count;
+  st->C = any_merged ? (int)(count < P->C_max ? count : P->C_max) : 0;
+  for (int s = 0; s < P->n_steps; ++s) {
+    if (P->step_is_gemm[s]) {
+      const DDGemmSym& G = P->gemm[s];
+      const DDTensor& ta = P->tensor[G.a];
+      const DDTensor& tb = P->tensor[G.b];
+      const DDTensor& tc = P->tensor[G.c];
+      GemmArgs& g = lv->gemm[s];
+      const int64_t Z = sym_pow(G.Z, na), M = sym_pow(G.M, na), N = sym_pow(G.N, na);
+      const int64_t K = sym_pow(G.K, na);
+      g.A = ta.hi;
+      g.A_lo = ta.lo;
+      g.B = tb.hi;
+      g.B_lo = tb.lo;
+      g.C = tc.is_out ? bins : tc.hi;
+      g.C_lo = tc.is_out ? nullptr : tc.lo;
+      g.M = M;
+      g.N = N;
+      g.K = K;
+      g.sAz = sym_pow(G.sAz, na);
+      g.sAk = sym_pow(G.sAk, na);
+      g.sBz = sym_pow(G.sBz, na);
+      g.sBk = sym_pow(G.sBk, na);
+      g.sCz = sym_pow(G.sCz, na);
+      g.ldc = sym_pow(G.ldc, na);
+      g.alpha = G.alpha;
+      g.tilesM = (M + 127) / 128;
+      g.tilesN = (N + 127) / 128;
+      g.tiles = g.tilesM * g.tilesN * Z;
+      const double a_elems = double(g.sAz ? Z : 1) * double(M) * double(K);
+      const double b_elems = double(g.sBz ? Z : 1) * double(N) * double(K);
+      g.m_fastest = b_elems > a_elems ? 1 : 0;
+    } else {
+      const DDPermSym& Q = P->perm[s];
+      const DDTensor& ts = P->tensor[Q.src];
+      const DDTensor& td = P->tensor[Q.dst];
+      PermArgs& p = lv->perm[s];
+      p.src = ts.hi;
+      p.src_lo = ts.lo;
+      p.dst = td.is_out ? bins : td.hi;
+      p.dst_lo = td.is_out ? nullptr : td.lo;
+      p.naxes = Q.naxes;
+      int bits = 0;
+      for (int i = 0; i < Q.naxes; ++i) {
+        const int l = sym_log(Q.log2[i], na);
+        p.log2[i] = l;
+        p.sstride[i] = sym_pow(Q.sstride[i], na);
+        bits += l;
+      }
+      p.total = (int64_t)1 << bits;
+      p.alpha = Q.alpha;
+    }
+  }
+  RefineArgs& f = lv->refine;
+  f.n_sub = ns;
+  f.K = P->K;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
+    f.Ep[c] = c < ns ? P->Ep[c] : nullptr;
+    f.ld[c] = (int64_t)1 << na[c];
+    f.na[c] = na[c];
+    f.kc[c] = c < ns ? P->kc[c] : 0;
+    for (int j = 0; j < CQ_MAX_LOCAL_CUTS; ++j) f.cut[c][j] = P->cut[c][j];
+  }
+  f.bins = st->top_idx;
+  f.nbins = st->C;
+  f.scale = ldexp(1.0, -P->K);
+  f.out = st->ref_val;
+}
+
+__device__ inline bool entry_before(double v1, int r1, uint64_t b1, double v2, int r2, uint64_t b2) {
+  if (v1 != v2) return v1 > v2;
+  if (r1 != r2) return r1 < r2;
+  return b1 < b2;
+}
+
+__global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* st, cq_dd_record* recs,
+                                 int r) {
+  if (threadIdx.x != 0) return;
+  if (st->stop) return;
+  cq_dd_record& rec = recs[r];
+  rec.total = st->total;
+  const int ns = P->n_sub, R = P->R, C = st->C;
+  // candidates by (FP64 value desc, bin asc)
+  int order[kDDMaxC];
+  for (int i = 0; i < C; ++i) {
+    int j = i;
+    const double v = st->ref_val[i];
+    const uint64_t b = st->top_idx[i];
+    while (j > 0 && entry_before(v, 0, b, st->ref_val[order[j - 1]], 0, st->top_idx[order[j - 1]])) {
+      order[j] = order[j - 1];
+      --j;
+    }
+    order[j] = i;
+  }
+  int nl = st->n_list;
+  const int take = C < R ? C : R;
+  for (int i = 0; i < take; ++i) {
+    const double v = st->ref_val[order[i]];
+    const uint64_t bin = st->top_idx[order[i]];
+    // sorted insertion into L, keeping at most R entries
+    int pos = nl;
+    while (pos > 0 && entry_before(v, r, bin, st->list[pos - 1].v, st->list[pos - 1].rec,
+                                   st->list[pos - 1].bin))
+      --pos;
+    if (pos >= R) continue;
+    const int last = nl < R ? nl : R - 1;
+    for (int q = last; q > pos; --q) st->list[q] = st->list[q - 1];
+    if (nl < R) ++nl;
+    DDEntry& e = st->list[pos];
+    e.v = v;
+    e.rec = r;
+    e.bin = bin;
+    int shift = st->n_active;
+    for (int c = 0; c < ns; ++c) {
+      const int a = st->na[c];
+      shift -= a;
+      const uint64_t bits = (bin >> shift) & low_bits(a);
+      const uint64_t act = st->active[c];
+      uint64_t fv = st->fixed_vals[c];
+      int t = 0;
+      for (int p = 0; p < 64; ++p)
+        if ((act >> p) & 1) {
+          if ((bits >> (a - 1 - t)) & 1) fv |= (uint64_t)1 << p;
+          ++t;
+        }
+      e.fixed[c] = st->fixed[c] | act;
+      e.fixed_vals[c] = fv;
+      e.merged[c] = st->merged[c];
+    }
+  }
+  st->n_list = nl;
+  rec.n_list = nl;
+  for (int i = 0; i < nl; ++i) {
+    rec.list_val[i] = st->list[i].v;
+    rec.list_rec[i] = st->list[i].rec;
+    rec.list_bin[i] = st->list[i].bin;
+  }
+  st->done = r + 1;
+  if (nl == 0) {
+    st->stop = 1;
+    return;
+  }
+  rec.popped = 1;
+  // zoom: the first max_active[c] merged outputs of the popped bin become active
+  for (int c = 0; c < ns; ++c) {
+    const uint64_t mer = st->list[0].merged[c];
+    uint64_t act = 0;
+    int taken = 0;
+    for (int p = 0; p < 64 && taken < P->max_active[c]; ++p)
+      if ((mer >> p) & 1) {
+        act |= (uint64_t)1 << p;
+        ++taken;
+      }
+    st->active[c] = act;
+    st->merged[c] = mer & ~act;
+    st->fixed[c] = st->list[0].fixed[c];
+    st->fixed_vals[c] = st->list[0].fixed_vals[c];
+  }
+  for (int q = 0; q + 1 < nl; ++q) st->list[q] = st->list[q + 1];
+  st->n_list = nl - 1;
+}
+
+}  // namespace
+
+hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(dd_init_kernel, dim3(1), dim3(256), 0, stream, st, recs, R, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_dd_record* recs,
+                           int r, void* bins, hipStream_t stream) {
+  hipLaunchKernelGGL(dd_setup_kernel, dim3(1), dim3(64), 0, stream, prog, st, lv, recs, r, bins);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(64), 0, stream, prog, st, recs, r);
   return hipGetLastError();
 }
 

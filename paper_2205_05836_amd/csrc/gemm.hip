@@ -27,19 +27,6 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-struct GemmArgs {
-  const void* A;
-  const void* A_lo;
-  const void* B;
-  const void* B_lo;
-  void* C;
-  void* C_lo;
-  int64_t M, N, K;
-  int64_t sAz, sAk, sBz, sBk, sCz, ldc;
-  int64_t tilesM, tilesN, tiles;
-  int m_fastest;
-  double alpha;
-};
 
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous block of tiles.
 __device__ inline int64_t xcd_tile(int64_t b, int64_t total) {
@@ -47,6 +34,13 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total) {
   const int64_t xcd = b % 8, local = b / 8;
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
+
+// Kernels take their arguments by value, or -- for shapes decided on the
+// device -- from device memory through `gp`; workgroups beyond the tile count
+// of an indirect launch exit at once.
+#define CQ_LOAD_GEMM_ARGS                                       \
+  const GemmArgs g = gp ? *gp : gv;                             \
+  if (gp && (int64_t)blockIdx.x >= g.tiles) return;
 
 struct TileCoord {
   int64_t z, m0, n0;
@@ -130,7 +124,8 @@ __device__ inline void store_out(TC* p, TC v) {
 // FP64
 // ---------------------------------------------------------------------------
 template <bool NT>
-__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_LOAD_GEMM_ARGS
   // 8 waves in a 4 x 2 grid, 32 x 64 outputs each: two waves per SIMD hide
   // the load latency that one 64 x 64 wave per SIMD could not.
   constexpr int BM = 128, BN = 128, BK = 16;
@@ -198,7 +193,8 @@ __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs g) {
 // FP32
 // ---------------------------------------------------------------------------
 template <bool NT>
-__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_LOAD_GEMM_ARGS
   constexpr int BM = 128, BN = 128, BK = 16;
   __shared__ __attribute__((aligned(16))) float As[BK][BM];
   __shared__ __attribute__((aligned(16))) float Bs[BK][BN];
@@ -326,7 +322,8 @@ __device__ inline float from_h16(uint16_t x) {
 }
 
 template <int SPLIT, bool F16, int OUT>
-__global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_LOAD_GEMM_ARGS
   using H = Half<F16>;
   using V8 = typename H::V8;
   constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
@@ -478,7 +475,8 @@ __device__ inline void wait_vm() {
 }
 
 template <int SPLIT, bool F16, int OUT, int NS>
-__global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_LOAD_GEMM_ARGS
   using H = Half<F16>;
   using V8 = typename H::V8;
   constexpr int BM = 128, BN = 128, BK = 32;
@@ -661,7 +659,18 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs g) {
 
 template <typename K>
 hipError_t launch(K kernel, const GemmArgs& a, hipStream_t s, int threads = 256) {
-  hipLaunchKernelGGL(kernel, dim3((unsigned)a.tiles), dim3(threads), 0, s, a);
+  hipLaunchKernelGGL(kernel, dim3((unsigned)a.tiles), dim3(threads), 0, s, a,
+                     static_cast<const GemmArgs*>(nullptr));
+  return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_ind(K kernel, const GemmArgs* dev, int64_t max_tiles, hipStream_t s,
+                      int threads = 256) {
+  if (max_tiles <= 0) return hipSuccess;
+  if (max_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  GemmArgs dummy{};
+  hipLaunchKernelGGL(kernel, dim3((unsigned)max_tiles), dim3(threads), 0, s, dummy, dev);
   return hipGetLastError();
 }
 
@@ -742,6 +751,31 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
       if (g.tc != DType::F32 && g.tc != DType::H16X2) return hipErrorInvalidValue;
       return prec == CQ_BF16_SPLIT ? dispatch_h16<3, false>(a, g.tc, nt, stream)
                                    : dispatch_h16<3, true>(a, g.tc, nt, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
+                                DType tc, bool nontemporal, hipStream_t stream) {
+  switch (prec) {
+    case CQ_FP64:
+      return nontemporal ? launch_ind(gemm_f64_kernel<true>, dev, max_tiles, stream, 512)
+                         : launch_ind(gemm_f64_kernel<false>, dev, max_tiles, stream, 512);
+    case CQ_FP32:
+      return nontemporal ? launch_ind(gemm_f32_kernel<true>, dev, max_tiles, stream)
+                         : launch_ind(gemm_f32_kernel<false>, dev, max_tiles, stream);
+    case CQ_BF16:
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, false, 0>, dev, max_tiles, stream);
+      return launch_ind(gemm_h16_kernel<1, false, 2>, dev, max_tiles, stream);
+    case CQ_BF16_SPLIT:
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, false, 0>, dev, max_tiles, stream);
+      return launch_ind(gemm_h16_kernel<3, false, 2>, dev, max_tiles, stream);
+    case CQ_FP16:
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, true, 0>, dev, max_tiles, stream);
+      return launch_ind(gemm_h16_kernel<1, true, 2>, dev, max_tiles, stream);
+    case CQ_FP16_SPLIT:
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, true, 0>, dev, max_tiles, stream);
+      return launch_ind(gemm_h16_kernel<3, true, 2>, dev, max_tiles, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -114,7 +114,42 @@ struct Plan {
 // `out_log2` per subcircuit = number of outputs taking part (n_c for FD, the
 // active count for DD bins).  `out_perm` (may be empty): bit permutation to
 // apply to the final concatenated order.
+// keep_empty: subcircuits with no outputs taking part still carry a size-1
+// output axis (the dynamic-definition plans re-evaluate sizes per recursion).
 cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work_elem_bytes,
-                    const std::vector<int>& out_perm, Plan& plan);
+                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty = false);
+
+// ---------------------------------------------------------------------------
+// Plans with symbolic sizes.  Every size and stride of a plan is a product of
+// axis sizes: 4 per cut label and 2^{na_c} for the outputs of subcircuit c.
+// A SymQ is 2^(c0 + sum_{c in mask} na_c) (or 0 when `zero`); as a log2 it
+// is c0 + sum_{c in mask} na_c.
+// ---------------------------------------------------------------------------
+struct SymQ {
+  int c0 = 0;
+  uint32_t mask = 0;
+  bool zero = false;
+};
+int64_t sym_value(const SymQ& q, const std::vector<int>& na);
+int sym_log2(const SymQ& q, const std::vector<int>& na);
+
+struct SymGemm {
+  SymQ Z, M, N, K, sAz, sAk, sBz, sBk, sCz, ldc;
+};
+struct SymPerm {
+  std::vector<SymQ> log2;     // read as log2 values
+  std::vector<SymQ> sstride;  // read as powers
+};
+struct SymPlan {
+  std::vector<SymQ> elems;    // per tensor
+  std::vector<SymGemm> gemm;  // per step (GEMM steps)
+  std::vector<SymPerm> perm;  // per step (permute steps)
+};
+
+// Plan for the largest active counts `amax` (every output axis kept) and its
+// symbolic form, checked to reproduce the plan at `amax`.  Any active counts
+// na_c <= amax_c fit the plan's buffers.
+cq_status make_sym_plan(const CutMap& cm, const std::vector<int>& amax, int work_elem_bytes,
+                        Plan& plan, SymPlan& sp);
 
 }  // namespace cq

@@ -39,6 +39,30 @@ struct GemmLaunch {
 // C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
 hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t stream);
 
+// Kernel-side GEMM description (also written by device code for shapes that
+// are only known on the device).  tiles = tilesM * tilesN * Z with 128 x 128
+// tiles; m_fastest selects the raster order.
+struct GemmArgs {
+  const void* A;
+  const void* A_lo;
+  const void* B;
+  const void* B_lo;
+  void* C;
+  void* C_lo;
+  int64_t M, N, K;
+  int64_t sAz, sAk, sBz, sBk, sCz, ldc;
+  int64_t tilesM, tilesN, tiles;
+  int m_fastest;
+  double alpha;
+};
+
+// Launches `max_tiles` workgroups of the precision's GEMM kernel reading its
+// arguments from device memory (`dev`); surplus workgroups exit.  Operands and
+// output are in the precision's storage format (tc: F32/F64 output or the
+// precision's own planes); the register-path 16-bit kernel is used.
+hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
+                                DType tc, bool nontemporal, hipStream_t stream);
+
 // Converts n FP64 values to `t` (FP32, or BF16/FP16 planes when f16 is false/true).
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
                        hipStream_t stream);
@@ -109,5 +133,186 @@ struct RefineLaunch {
 };
 // FP64 value of chosen bins: scale * sum over all 4^K labels of prod_c Ep[c][row][a_c].
 hipError_t launch_refine(const RefineLaunch& r, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks.  Host launchers fill them; the device-driven
+// dynamic definition writes them from device code, for shapes that depend on
+// which bin a recursion zooms into, and launches the same kernels on them.
+// ---------------------------------------------------------------------------
+struct PermArgs {
+  const void* src;
+  const void* src_lo;  // lo plane of a split source, else null
+  void* dst;
+  void* dst_lo;        // lo plane of a split destination, else null
+  int64_t total;
+  int naxes;
+  int log2[kMaxPermAxes];
+  int64_t sstride[kMaxPermAxes];
+  double alpha;
+};
+
+struct PrepArgs {
+  const double* src;
+  void* dst;
+  void* dst_lo;
+  int64_t n;
+};
+
+struct MergeArgs {
+  const double* E;
+  double* Ep;
+  int64_t outputs;  // rows << na
+  int n, na, tpo_log2;
+  int64_t iters;    // 2^(nm - tpo_log2)
+  uint64_t active_flat, merged_lo, merged_hi, fixed_vals_flat;
+};
+
+struct RefineArgs {
+  int n_sub, K;
+  const double* Ep[CQ_MAX_SUBCIRCUITS];
+  int64_t ld[CQ_MAX_SUBCIRCUITS];
+  int na[CQ_MAX_SUBCIRCUITS];
+  int kc[CQ_MAX_SUBCIRCUITS];
+  int cut[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];
+  const uint64_t* bins;
+  int nbins;
+  double scale;
+  double* out;
+};
+
+// Indirect launches: `max_*` bounds the grid; the kernels read their
+// arguments from device memory and skip work beyond the stored sizes.
+hipError_t launch_permute_indirect(const PermArgs* dev, DType ts, DType td, bool f16,
+                                   int64_t max_total, hipStream_t stream);
+hipError_t launch_prep_indirect(const PrepArgs* dev, int count, DType t, bool f16,
+                                int64_t max_n, hipStream_t stream);
+hipError_t launch_merge_indirect(const MergeArgs* dev, int count, int64_t max_threads,
+                                 hipStream_t stream);
+hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream);
+// Top-C of *count bins with C = *C_dev (nothing when C <= 0); pass one
+// writes 64 keys per workgroup into the candidate buffers.
+hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_dev,
+                                const int32_t* C_dev, int64_t max_count, double* cand_val,
+                                uint64_t* cand_idx, int64_t cand_capacity, double* out_val,
+                                uint64_t* out_idx, hipStream_t stream);
+int64_t topk_indirect_capacity(int64_t max_count);
+
+// ---------------------------------------------------------------------------
+// Device-driven dynamic definition (Algorithm 1).  One recursion is a fixed
+// sequence of launches: setup (descriptors from the current masks), merge,
+// row sums, FP64 total, operand preparation, the bin contraction, top-C,
+// FP64 refinement and the list update / zoom.  Sizes are products of powers
+// of two, 2^(c0 + sum of the active counts of the subcircuits in `mask`), so
+// the contraction plan made for the largest active counts is re-evaluated on
+// the device for the current ones.
+// ---------------------------------------------------------------------------
+constexpr int kDDMaxSteps = 16;
+constexpr int kDDMaxTensors = 48;
+constexpr int kDDMaxPermAxes = 24;
+constexpr int kDDMaxC = 64;
+
+struct SymPow {   // 0 when zero != 0, else 2^(c0 + sum_{c in mask} na[c])
+  int32_t c0;
+  uint32_t mask;
+  int32_t zero;
+  int32_t pad;
+};
+struct SymLog {   // c0 + sum_{c in mask} na[c]
+  int32_t c0;
+  uint32_t mask;
+};
+
+struct DDTensor {
+  void* hi;        // values or hi plane (null for the recursion's bin buffer)
+  void* lo;        // lo plane of split operands
+  int32_t is_out;  // the recursion's bin buffer
+  int32_t pad;
+};
+
+struct DDGemmSym {
+  int32_t a, b, c, pad;
+  SymPow Z, M, N, K, sAz, sAk, sBz, sBk, sCz, ldc;
+  double alpha;
+};
+
+struct DDPermSym {
+  int32_t src, dst, naxes, pad;
+  SymLog log2[kDDMaxPermAxes];
+  SymPow sstride[kDDMaxPermAxes];
+  double alpha;
+};
+
+struct DDProgram {
+  int32_t n_sub, K, R, n_steps;
+  int32_t C_max;                             // min(4R, 64)
+  int32_t pad;
+  int32_t n_out[CQ_MAX_SUBCIRCUITS];
+  int32_t max_active[CQ_MAX_SUBCIRCUITS];
+  int32_t kc[CQ_MAX_SUBCIRCUITS];
+  int32_t cut[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];
+  int64_t rows[CQ_MAX_SUBCIRCUITS];
+  const double* E[CQ_MAX_SUBCIRCUITS];       // FP64 entries
+  double* Ep[CQ_MAX_SUBCIRCUITS];            // reduced entries
+  double* Rs[CQ_MAX_SUBCIRCUITS];            // their row sums
+  int32_t prep_dst[CQ_MAX_SUBCIRCUITS];      // tensor receiving the converted copy, or -1
+  DDTensor tensor[kDDMaxTensors];
+  SymPow tensor_elems[kDDMaxTensors];
+  int32_t step_is_gemm[kDDMaxSteps];
+  DDGemmSym gemm[kDDMaxSteps];
+  DDPermSym perm[kDDMaxSteps];
+};
+
+struct DDEntry {  // one entry of the list L with the masks of its bin
+  double v;
+  int32_t rec;
+  int32_t pad;
+  uint64_t bin;
+  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
+  uint64_t merged[CQ_MAX_SUBCIRCUITS];
+};
+
+struct DDState {
+  uint64_t active[CQ_MAX_SUBCIRCUITS];
+  uint64_t merged[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
+  int32_t na[CQ_MAX_SUBCIRCUITS];
+  int32_t n_active, stop, done, n_list;
+  int32_t C, pad;
+  int64_t count;                 // bins of the recursion
+  uint64_t zero_idx;             // 0: the single bin of the total
+  double total;
+  double top_val[kDDMaxC];
+  uint64_t top_idx[kDDMaxC];
+  double ref_val[kDDMaxC];
+  DDEntry list[CQ_MAX_DD_R];
+};
+
+struct DDLevel {  // descriptors of the current recursion
+  MergeArgs merge[CQ_MAX_SUBCIRCUITS];
+  MergeArgs rowsum[CQ_MAX_SUBCIRCUITS];
+  PrepArgs prep[CQ_MAX_SUBCIRCUITS];
+  GemmArgs gemm[kDDMaxSteps];
+  PermArgs perm[kDDMaxSteps];
+  RefineArgs refine;
+};
+
+struct DDInit {
+  uint64_t active[CQ_MAX_SUBCIRCUITS];
+  uint64_t merged[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
+};
+
+// State <- recursion-0 masks, list empty, records zeroed.
+hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
+                          hipStream_t stream);
+// Descriptors of recursion r from the state; `bins` receives its bins.
+hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_dd_record* recs,
+                           int r, void* bins, hipStream_t stream);
+// List update, record r and zoom into the popped bin.
+hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
+                            hipStream_t stream);
 
 }  // namespace cq

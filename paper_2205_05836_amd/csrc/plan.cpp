@@ -324,7 +324,7 @@ struct Builder {
 cq_status check_plan_bounds(const Plan& plan);
 
 cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work_elem_bytes,
-                    const std::vector<int>& out_perm, Plan& plan) {
+                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty) {
   plan = Plan();
   plan.work_elem_bytes = work_elem_bytes;
   const int n = cm.n_sub;
@@ -335,7 +335,7 @@ cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work
     t.loc = Loc::Input;
     t.index = c;
     for (int id : cm.subs[c].cuts) t.axes.push_back(Axis{0, id, 2});
-    if (out_log2[c] > 0) t.axes.push_back(Axis{1, c, out_log2[c]});
+    if (out_log2[c] > 0 || keep_empty) t.axes.push_back(Axis{1, c, out_log2[c]});
     t.elems = pow2(t.log2_size());
     plan.tensors.push_back(t);
   }
@@ -474,6 +474,155 @@ cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work
     s.is_gemm = false;
     s.p = p;
     plan.steps.push_back(s);
+  }
+  return check_plan_bounds(plan);
+}
+
+int64_t sym_value(const SymQ& q, const std::vector<int>& na) {
+  return q.zero ? 0 : pow2(sym_log2(q, na));
+}
+
+int sym_log2(const SymQ& q, const std::vector<int>& na) {
+  int e = q.c0;
+  for (size_t c = 0; c < na.size(); ++c)
+    if ((q.mask >> c) & 1u) e += na[c];
+  return e;
+}
+
+namespace {
+
+SymQ sym_axis(const Axis& a) {
+  SymQ q;
+  if (a.kind == 0) q.c0 = a.log2;
+  else q.mask = 1u << a.id;
+  return q;
+}
+
+SymQ sym_size(const std::vector<Axis>& ax, size_t b, size_t e) {
+  SymQ q;
+  for (size_t i = b; i < e; ++i) {
+    const SymQ s = sym_axis(ax[i]);
+    q.c0 += s.c0;
+    q.mask |= s.mask;
+  }
+  return q;
+}
+
+SymQ sym_mul(SymQ a, const SymQ& b) {
+  a.c0 += b.c0;
+  a.mask |= b.mask;
+  a.zero = a.zero || b.zero;
+  return a;
+}
+
+SymQ sym_zero() {
+  SymQ q;
+  q.zero = true;
+  return q;
+}
+
+// Permute from `src` axes to `dst` axes (every dst axis present in src).
+bool sym_permute(const std::vector<Axis>& src, const std::vector<Axis>& dst, SymPerm& sp,
+                 PermuteStep& num, const std::vector<int>& amax) {
+  sp = SymPerm();
+  num.log2.clear();
+  num.sstride.clear();
+  for (const Axis& a : dst) {
+    int i = (int)src.size() - 1;
+    while (i >= 0 && !(src[i] == a)) --i;
+    if (i < 0) return false;
+    sp.log2.push_back(sym_axis(a));
+    sp.sstride.push_back(sym_size(src, i + 1, src.size()));
+    num.log2.push_back(sym_log2(sp.log2.back(), amax));
+    num.sstride.push_back(sym_value(sp.sstride.back(), amax));
+  }
+  return true;
+}
+
+// Source offset of each destination bit (least significant first).
+std::vector<int64_t> unit_offsets(const PermuteStep& p) {
+  std::vector<int64_t> off;
+  for (int a = (int)p.log2.size() - 1; a >= 0; --a)
+    for (int b = 0; b < p.log2[a]; ++b) off.push_back(p.sstride[a] << b);
+  return off;
+}
+
+}  // namespace
+
+cq_status make_sym_plan(const CutMap& cm, const std::vector<int>& amax, int work_elem_bytes,
+                        Plan& plan, SymPlan& sp) {
+  cq_status st = make_plan(cm, amax, work_elem_bytes, {}, plan, true);
+  if (st != CQ_OK) return st;
+  sp = SymPlan();
+  std::vector<Axis> all_out;
+  for (int c = 0; c < cm.n_sub; ++c) all_out.push_back(Axis{1, c, amax[c]});
+  for (const TensorRef& t : plan.tensors) {
+    // the final permute's destination carries no axes: it holds every output
+    const bool bare_out = t.loc == Loc::Out && t.axes.empty();
+    const std::vector<Axis>& ax = bare_out ? all_out : t.axes;
+    sp.elems.push_back(sym_size(ax, 0, ax.size()));
+    if (sym_value(sp.elems.back(), amax) != t.elems)
+      return fail(CQ_ERR_UNSUPPORTED, "internal: symbolic tensor size mismatch");
+  }
+  sp.gemm.resize(plan.steps.size());
+  sp.perm.resize(plan.steps.size());
+  auto bad = [] { return fail(CQ_ERR_UNSUPPORTED, "internal: symbolic plan mismatch"); };
+  for (size_t si = 0; si < plan.steps.size(); ++si) {
+    Step& s = plan.steps[si];
+    if (s.is_gemm) {
+      const GemmStep& g = s.g;
+      const std::vector<Axis>& A = plan.tensors[g.a].axes;
+      const std::vector<Axis>& B = plan.tensors[g.b].axes;
+      std::vector<Axis> sh;
+      for (const Axis& a : A)
+        if (is_label(a) && std::find(B.begin(), B.end(), a) != B.end()) sh.push_back(a);
+      const size_t ns = sh.size();
+      size_t ba = 0, bb = 0;
+      if (!find_run(A, sh, ba) || !find_run(B, sh, bb)) return bad();
+      const SymQ PA = sym_size(A, 0, ns ? ba : 0), QA = sym_size(A, ns ? ba + ns : 0, A.size());
+      const SymQ PB = sym_size(B, 0, ns ? bb : 0), QB = sym_size(B, ns ? bb + ns : 0, B.size());
+      const bool pb_empty = ns == 0 || bb == 0;
+      const bool pa_empty = ns == 0 || ba == 0;
+      SymGemm q;
+      q.K = sym_size(sh, 0, ns);
+      q.M = QA;
+      q.N = QB;
+      if (pb_empty) {
+        q.Z = PA;
+        q.sAz = sym_mul(q.K, q.M);
+        q.sBz = sym_zero();
+      } else {
+        if (!pa_empty) return bad();
+        q.Z = PB;
+        q.sAz = sym_zero();
+        q.sBz = sym_mul(q.K, q.N);
+      }
+      q.sAk = q.M;
+      q.sBk = q.N;
+      q.sCz = sym_mul(q.M, q.N);
+      q.ldc = q.N;
+      const int64_t want[10] = {g.Z, g.M, g.N, g.K, g.sAz, g.sAk, g.sBz, g.sBk, g.sCz, g.ldc};
+      const SymQ* got[10] = {&q.Z, &q.M, &q.N, &q.K, &q.sAz, &q.sAk, &q.sBz, &q.sBk, &q.sCz, &q.ldc};
+      for (int i = 0; i < 10; ++i)
+        if (sym_value(*got[i], amax) != want[i]) return bad();
+      sp.gemm[si] = q;
+    } else {
+      PermuteStep& p = s.p;
+      const TensorRef& td = plan.tensors[p.dst];
+      const std::vector<Axis>& src = plan.tensors[p.src].axes;
+      const bool bare_out = td.loc == Loc::Out && td.axes.empty();
+      PermuteStep num = p;
+      if (!sym_permute(src, bare_out ? all_out : td.axes, sp.perm[si], num, amax)) return bad();
+      if (bare_out) {
+        // the bit-level final permute becomes an axis-level one; both must
+        // send every destination bit to the same source bit
+        if (unit_offsets(num) != unit_offsets(p)) return bad();
+        p.log2 = num.log2;
+        p.sstride = num.sstride;
+      } else if (num.log2 != p.log2 || num.sstride != p.sstride) {
+        return bad();
+      }
+    }
   }
   return check_plan_bounds(plan);
 }

@@ -45,12 +45,17 @@ def instance(cm, E, states, max_active):
                 max_active=list(max_active))
 
 
-def run_gpu(cm, E, states, max_active, R, prec):
+def max_bins_log2(cm, states, max_active):
     ns = [len(cutmap.outputs(s)) for s in cm]
-    A = max(sum(len(s.active) for s in states), sum(min(m, n) for m, n in zip(max_active, ns)))
+    return sum(max(len(s.active), min(m, n)) for s, m, n in zip(states, max_active, ns))
+
+
+def run_gpu(cm, E, states, max_active, R, prec, launch="graph"):
+    A = max_bins_log2(cm, states, max_active)
     dt = torch.float64 if prec == "fp64" else torch.float32
     bins = [torch.full((2 ** A,), float("nan"), dtype=dt, device=DEV) for _ in range(R)]
-    recs, done = cq().cq_reconstruct_dd([instance(cm, E, states, max_active)], prec, R, bins=bins)
+    recs, done = cq().cq_reconstruct_dd([instance(cm, E, states, max_active)], prec, R, bins=bins,
+                                        launch=launch)
     torch.cuda.synchronize()
     return recs[0], done[0], bins
 
@@ -67,14 +72,14 @@ def _unique_positions(vals, gap):
     return out
 
 
-def compare(cm, E, states, max_active, R, prec, tol):
+def compare(cm, E, states, max_active, R, prec, tol, launch="graph"):
     """Walks the recursions of both runs.  Labels, bins and list values must
     agree; list identities must agree wherever the order is fixed by values
     more than `gap` apart (ties up to rounding may rank either way, Algorithm 1
     admits both); the comparison stops after a pop that was such a tie, since
     both zoom paths are then correct."""
     ref = dd.run(cm, E, states, max_active, R)
-    got, done, bins = run_gpu(cm, E, states, max_active, R, prec)
+    got, done, bins = run_gpu(cm, E, states, max_active, R, prec, launch)
     gap = 0.0 if tol == 0 else 1e-10
     for r, (g, o) in enumerate(zip(got, ref)):
         st = o["states"]
@@ -109,17 +114,18 @@ def compare(cm, E, states, max_active, R, prec, tol):
     assert done == len(ref)
 
 
+@pytest.mark.parametrize("launch", ["graph", "direct"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", range(4))
-def test_integer_entries_exact(case, prec):
+def test_integer_entries_exact(case, prec, launch):
     rng = np.random.default_rng(50 + case)
     bonds = [[1, 1], [2, 1], [0, 2], [1, 2, 1]][case]
     ns = [[4, 4, 4], [5, 3, 6], [3, 4, 5], [3, 3, 4, 3]][case]
     cm = syn.chain_cutmap(bonds, ns)
     E = [syn.integer_entries(rng, k, n, lo=-3, hi=6) for k, n in zip(syn.chain_ks(bonds, len(ns)), ns)]
     M = [1 + (case % 2)] * len(ns)
-    print(f"dd int case {case} {prec}", flush=True)
-    compare(cm, E, dd.initial_states(cm, M), M, R=4, prec=prec, tol=0)
+    print(f"dd int case {case} {prec} {launch}", flush=True)
+    compare(cm, E, dd.initial_states(cm, M), M, R=4, prec=prec, tol=0, launch=launch)
 
 
 def test_physical_circuit_fp64():
@@ -130,7 +136,8 @@ def test_physical_circuit_fp64():
     compare(subs, E, dd.initial_states(subs, M), M, R=5, prec="fp64", tol=1e-12)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("bf16_split", 1e-6),
+                                      ("fp16_split", 1e-6), ("fp16", 1e-3), ("bf16", 2e-2)])
 def test_dirichlet_chain(prec, tol):
     cm, E = syn.chain_instance(61, [2, 2], [7, 6, 7])
     M = [2, 2, 2]
@@ -184,3 +191,28 @@ def test_hidden_string_found():
     nb = 2 ** got[r]["n_active"]
     assert bins[r][:nb].cpu().numpy().max() == pytest.approx(1.0, abs=1e-12)
     compare(subs, E, dd.initial_states(subs, M), M, R, "fp64", 1e-12)
+
+
+def test_graph_and_direct_launches_agree():
+    """The captured graph replays exactly the launches of the direct mode."""
+    m = cq()
+    insts = []
+    for i, (bonds, ns) in enumerate([([2, 1], [5, 6, 4]), ([1, 1, 1], [4, 3, 4, 3])]):
+        cm, E = syn.chain_instance(90 + i, bonds, ns)
+        M = [2] * len(ns)
+        insts.append(instance(cm, E, dd.initial_states(cm, M), M))
+    R = 4
+    out = {}
+    for launch in ("graph", "direct"):
+        bins = []
+        for inst in insts:
+            A = max_bins_log2(inst["subs"], dd.initial_states(inst["subs"], inst["max_active"]),
+                              inst["max_active"])
+            bins += [torch.full((2 ** A,), float("nan"), dtype=torch.float32, device=DEV) for _ in range(R)]
+        recs, done = m.cq_reconstruct_dd(insts, "fp32", R, bins=bins, launch=launch)
+        out[launch] = (recs, done, [b.cpu().numpy() for b in bins])
+    (rg, dg, bg), (rd, ddn, bd) = out["graph"], out["direct"]
+    assert dg == ddn
+    assert rg == rd
+    for x, y in zip(bg, bd):
+        assert np.array_equal(x, y, equal_nan=True)
