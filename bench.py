@@ -52,6 +52,9 @@ def parse():
                     help="other precisions timed beside the headline and FP64")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--dd-forms", default="fp32,bf16_split,fp64",
+                    help="precisions of the batched dynamic-definition leg ('' skips it)")
+    ap.add_argument("--dd-runs", type=int, default=3)
     return ap.parse_args()
 
 
@@ -157,6 +160,69 @@ def cpu_baseline_leg(torch, ents, out_fp, budget_s):
     return cpu, {"max_abs_vs_oracle_slice": slice_err, "max_abs_vs_oracle_sampled_1000": samp_err}
 
 
+DD_SEED, DD_INST, DD_NOUT, DD_ACT, DD_R = 400, 16, 20, 8, 4
+DD_WORKLOAD = ("batched DD: 16 chain instances x 4 subcircuits x 20 outputs (80 qubits), "
+               "K uniform in 2..6 (<= 4 cuts per subcircuit), entries (4^k, 2^20) FP64 as in the "
+               "30-qubit workload (instance i seed 400+i), 8 active per subcircuit (2^32 bins), "
+               "R = 4 recursions, one hipGraph per batch")
+
+
+def dd_leg(torch, cq, forms, runs):
+    """Times the whole batch (16 instances x R recursions, one call, graph
+    launch) per precision; flops are the planner's per recursion shape."""
+    from workloads import synthetic as syn
+    bonds_all = syn.dd_batch_bonds(DD_SEED, n_inst=DD_INST, n_sub=4, k_range=(2, 6),
+                                   max_k_per_sub=4)
+    insts = []
+    entry_bytes = 0
+    for i, bonds in enumerate(bonds_all):
+        ks = syn.chain_ks(bonds, 4)
+        cm = syn.chain_cutmap(list(bonds), [DD_NOUT] * 4)
+        ents = [syn.entries_torch(DD_SEED + i, c, ks[c], DD_NOUT, "cuda:0") for c in range(4)]
+        entry_bytes += sum(e.numel() * 8 for e in ents)
+        act = (1 << DD_ACT) - 1
+        insts.append(dict(subs=cm, entries=ents, active=[act] * 4,
+                          merged=[((1 << DD_NOUT) - 1) ^ act] * 4, fixed=[0] * 4,
+                          fixed_vals=[0] * 4, max_active=[DD_ACT] * 4))
+    torch.cuda.synchronize()
+    out = {"workload": DD_WORKLOAD, "entry_bytes": entry_bytes, "forms": {}}
+    ref_lists = None
+    for f in forms:
+        ws = torch.empty(cq.cq_dd_workspace_size(insts, f, DD_R), dtype=torch.uint8,
+                         device="cuda:0")
+        recs, done = cq.cq_reconstruct_dd(insts, f, DD_R, workspace=ws)  # warm-up
+        times = []
+        for _ in range(runs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            recs, done = cq.cq_reconstruct_dd(insts, f, DD_R, workspace=ws)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        del ws
+        ms = sorted(times)[len(times) // 2]
+        flops, bins = 0.0, 0
+        plans = {}
+        for inst, rr in zip(insts, recs):
+            for rec in rr:
+                na = [bin(x).count("1") for x in rec["active"]]
+                key = (id(inst), tuple(na))
+                if key not in plans:
+                    plans[key] = cq.cq_plan_json(inst["subs"], f, out_bits=na)["flops"]
+                flops += plans[key]
+                bins += 2 ** rec["n_active"]
+        lists = [[(e[1], e[2]) for e in rr[-1]["list"]] for rr in recs]
+        if ref_lists is None:
+            ref_lists = lists
+        out["forms"][f] = {"ms_per_batch": round(ms, 3), "recursions": int(sum(done)),
+                           "bins": bins, "bins_per_s": bins / (ms * 1e-3),
+                           "algorithmic_flops": flops,
+                           "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                           "same_zoom_path_as_first_form": lists == ref_lists}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -232,6 +298,14 @@ def main():
                     [(k[0], v[1] / v[0], k[1]) for k, v in _groups(recs).items()]},
     }
     del out64
+    dd_forms = [f for f in args.dd_forms.split(",") if f]
+    if dd_forms:
+        del out
+        out = None
+        torch.cuda.empty_cache()
+        result["dd"] = dd_leg(torch, cq, dd_forms, args.dd_runs)
+        out = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
+        cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
     if not args.skip_cpu:
         cpu, err = cpu_baseline_leg(torch, ents, out, args.cpu_seconds)
         result["cpu_baseline"] = cpu

@@ -404,7 +404,7 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   D.bins_bytes = bins_stored ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
   off += D.bins_bytes;
   D.cand_off = off;
-  D.cand_cap = topk_indirect_capacity(D.max_count);
+  D.cand_cap = topk_indirect_capacity(D.max_count, std::min(4 * p.R, kDDMaxC));
   off = align256(off + D.cand_cap * 16);
   D.big = off;
   D.step_max.clear();
@@ -592,7 +592,8 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
       if (e != hipSuccess) return hip_fail(e, "permute launch");
     }
   }
-  e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, D.max_count,
+  e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, std::min(4 * p.R, kDDMaxC),
+                           D.max_count,
                            reinterpret_cast<double*>(ws + D.cand_off),
                            reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8), D.cand_cap,
                            st->top_val, st->top_idx, stream);

@@ -51,8 +51,6 @@ __device__ inline void merge_body(const MergeArgs& a) {
   }
 }
 
-__global__ void __launch_bounds__(256) merge_kernel(MergeArgs a) { merge_body(a); }
-
 // blockIdx.y selects the argument block
 __global__ void __launch_bounds__(256) merge_ind_kernel(const MergeArgs* __restrict__ a) {
   const MergeArgs m = a[blockIdx.y];
@@ -163,6 +161,144 @@ __global__ void __launch_bounds__(256) topk_kernel(const T* __restrict__ vals,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Top-C pass one over the bins, bandwidth-shaped: every thread streams 16-byte
+// vectors (the next round is loaded while the current one is filtered), keys
+// in LDS are (value, 32-bit offset in the chunk), and the running threshold
+// is the workgroup's C-th best so far, so after the first rounds almost no
+// value enters the buffer.  A round is filtered in two halves with a
+// capacity check between them, which keeps the buffer from overflowing
+// whatever the order of the values.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CKey {
+  T v;
+  uint32_t i;
+};
+
+template <typename T>
+__device__ inline bool cbetter(const CKey<T>& a, const CKey<T>& b) {
+  return a.v > b.v || (a.v == b.v && a.i < b.i);
+}
+
+template <typename T>
+__device__ inline CKey<T> cworst() {
+  return CKey<T>{T(-DBL_MAX), 0xffffffffu};
+}
+
+template <>
+__device__ inline CKey<float> cworst<float>() {
+  return CKey<float>{-FLT_MAX, 0xffffffffu};
+}
+
+constexpr int kScanS = 4096;  // LDS keys
+
+template <typename T>
+__device__ void cbitonic_sort(CKey<T>* buf) {
+  for (int k = 2; k <= kScanS; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < kScanS / 2; t += blockDim.x) {
+        const int i = 2 * j * (t / j) + (t % j);
+        const int p = i + j;
+        const bool asc = (i & k) == 0;
+        CKey<T> x = buf[i], y = buf[p];
+        const bool swap = asc ? cbetter(y, x) : cbetter(x, y);
+        if (swap) {
+          buf[i] = y;
+          buf[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) topk_scan_kernel(const T* __restrict__ vals,
+                                                        const int64_t* __restrict__ count_dev,
+                                                        const int32_t* __restrict__ C_dev,
+                                                        double* __restrict__ out_v,
+                                                        uint64_t* __restrict__ out_i,
+                                                        int out_stride) {
+  constexpr int EPV = 16 / (int)sizeof(T);  // values per 16-byte vector
+  constexpr int NV = 4;                     // vectors per thread per round
+  constexpr int VPT = EPV * NV;
+  constexpr int HALF = 256 * VPT / 2;       // most keys one half-round can add
+  static_assert(HALF + 64 <= kScanS, "buffer too small for a half round");
+  typedef T V __attribute__((ext_vector_type(EPV)));
+  __shared__ CKey<T> buf[kScanS];
+  __shared__ int cnt;
+  __shared__ CKey<T> thr;
+  const int C = *C_dev;
+  if (C <= 0) return;
+  const int64_t count = *count_dev;
+  const int64_t round = 256 * VPT;
+  // chunks are whole rounds, so every vector start is a multiple of EPV
+  const int64_t per = ((count + gridDim.x - 1) / gridDim.x + round - 1) / round * round;
+  const int64_t begin = (int64_t)blockIdx.x * per;
+  int64_t end = begin + per;
+  if (end > count) end = count;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    thr = cworst<T>();
+  }
+  __syncthreads();
+  auto trim = [&]() {
+    for (int t = cnt + threadIdx.x; t < kScanS; t += blockDim.x) buf[t] = cworst<T>();
+    __syncthreads();
+    cbitonic_sort(buf);
+    if (threadIdx.x == 0) {
+      if (cnt > C) cnt = C;
+      thr = (cnt == C) ? buf[C - 1] : cworst<T>();
+    }
+    __syncthreads();
+  };
+  const bool vec = (reinterpret_cast<uintptr_t>(vals) & 15) == 0;
+  auto load = [&](int64_t r0, V (&x)[NV]) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int64_t e0 = r0 + ((int64_t)j * 256 + threadIdx.x) * EPV;
+      if (vec && e0 + EPV <= end) {
+        x[j] = *reinterpret_cast<const V*>(vals + e0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPV; ++e) x[j][e] = (e0 + e < end) ? vals[e0 + e] : T(0);
+      }
+    }
+  };
+  V cur[NV], nxt[NV];
+  if (begin < end) load(begin, cur);
+  for (int64_t r0 = begin; r0 < end; r0 += round) {
+    if (r0 + round < end) load(r0 + round, nxt);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const CKey<T> th = thr;
+#pragma unroll
+      for (int j = h * NV / 2; j < (h + 1) * NV / 2; ++j) {
+        const int64_t e0 = r0 + ((int64_t)j * 256 + threadIdx.x) * EPV;
+#pragma unroll
+        for (int e = 0; e < EPV; ++e) {
+          const CKey<T> key{cur[j][e], (uint32_t)(e0 + e - begin)};
+          if (e0 + e < end && cbetter(key, th)) {
+            const int pos = atomicAdd(&cnt, 1);
+            buf[pos] = key;
+          }
+        }
+      }
+      __syncthreads();
+      if (cnt > kScanS - HALF) trim();
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) cur[j] = nxt[j];
+  }
+  trim();
+  for (int t = threadIdx.x; t < out_stride; t += blockDim.x) {
+    const bool ok = t < cnt;
+    out_v[(int64_t)blockIdx.x * out_stride + t] = ok ? double(buf[t].v) : -DBL_MAX;
+    out_i[(int64_t)blockIdx.x * out_stride + t] = ok ? (uint64_t)begin + buf[t].i : ~(uint64_t)0;
+  }
+}
+
 int64_t topk_blocks(int64_t count) {
   int64_t b = (count + 65535) / 65536;
   if (b > 2048) b = 2048;
@@ -216,58 +352,6 @@ __global__ void __launch_bounds__(256) refine_ind_kernel(const RefineArgs* __res
 
 }  // namespace
 
-hipError_t launch_merge(const MergeLaunch& m, hipStream_t stream) {
-  MergeArgs a;
-  a.E = m.E;
-  a.Ep = m.Ep;
-  a.n = m.n;
-  a.na = m.na;
-  a.outputs = m.rows << m.na;
-  a.tpo_log2 = m.nm < 6 ? m.nm : 6;
-  a.iters = (int64_t)1 << (m.nm - a.tpo_log2);
-  a.active_flat = m.active_flat;
-  a.fixed_vals_flat = m.fixed_vals_flat;
-  // lowest tpo_log2 merged bits go to the lanes, the rest to the loop
-  uint64_t lo = 0, rest = m.merged_flat;
-  for (int i = 0; i < a.tpo_log2; ++i) {
-    const uint64_t low = rest & (~rest + 1);
-    lo |= low;
-    rest ^= low;
-  }
-  a.merged_lo = lo;
-  a.merged_hi = rest;
-  const int64_t threads = a.outputs << a.tpo_log2;
-  const int64_t blocks = (threads + 255) / 256;
-  if (blocks <= 0) return hipSuccess;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a);
-  return hipGetLastError();
-}
-
-int64_t topk_candidate_capacity(int64_t count, int C) { return topk_blocks(count) * C; }
-
-hipError_t launch_topk(const TopkLaunch& t, hipStream_t stream) {
-  if (t.C < 1 || t.C > 64) return hipErrorInvalidValue;
-  const int64_t blocks = topk_blocks(t.count);
-  if (blocks * t.C > t.cand_capacity) return hipErrorInvalidValue;
-  const int64_t chunk = (t.count + blocks - 1) / blocks;
-  if (t.t == DType::F64)
-    hipLaunchKernelGGL((topk_kernel<double, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
-                       static_cast<const double*>(t.bins), nullptr, t.count, chunk, t.C, t.cand_val,
-                       t.cand_idx, nullptr, nullptr, t.C);
-  else
-    hipLaunchKernelGGL((topk_kernel<float, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
-                       static_cast<const float*>(t.bins), nullptr, t.count, chunk, t.C, t.cand_val,
-                       t.cand_idx, nullptr, nullptr, t.C);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t nc = blocks * t.C;
-  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
-                     (const double*)t.cand_val, (const uint64_t*)t.cand_idx, nc, nc, t.C, t.out_val,
-                     t.out_idx, nullptr, nullptr, t.C);
-  return hipGetLastError();
-}
-
 hipError_t launch_refine(const RefineLaunch& r, hipStream_t stream) {
   RefineArgs a;
   a.n_sub = r.n_sub;
@@ -303,28 +387,29 @@ hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream
   return hipGetLastError();
 }
 
-int64_t topk_indirect_capacity(int64_t max_count) { return topk_blocks(max_count) * kDDMaxC; }
+int64_t topk_indirect_capacity(int64_t max_count, int C_max) {
+  return topk_blocks(max_count) * C_max;
+}
 
 hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_dev,
-                                const int32_t* C_dev, int64_t max_count, double* cand_val,
-                                uint64_t* cand_idx, int64_t cand_capacity, double* out_val,
-                                uint64_t* out_idx, hipStream_t stream) {
+                                const int32_t* C_dev, int C_max, int64_t max_count,
+                                double* cand_val, uint64_t* cand_idx, int64_t cand_capacity,
+                                double* out_val, uint64_t* out_idx, hipStream_t stream) {
+  if (C_max < 1 || C_max > kDDMaxC) return hipErrorInvalidValue;
   const int64_t blocks = topk_blocks(max_count);
-  if (blocks * kDDMaxC > cand_capacity) return hipErrorInvalidValue;
+  if (blocks * C_max > cand_capacity) return hipErrorInvalidValue;
   if (t == DType::F64)
-    hipLaunchKernelGGL((topk_kernel<double, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
-                       static_cast<const double*>(bins), nullptr, (int64_t)0, (int64_t)0, 0,
-                       cand_val, cand_idx, count_dev, C_dev, kDDMaxC);
+    hipLaunchKernelGGL((topk_scan_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                       static_cast<const double*>(bins), count_dev, C_dev, cand_val, cand_idx, C_max);
   else
-    hipLaunchKernelGGL((topk_kernel<float, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
-                       static_cast<const float*>(bins), nullptr, (int64_t)0, (int64_t)0, 0,
-                       cand_val, cand_idx, count_dev, C_dev, kDDMaxC);
+    hipLaunchKernelGGL((topk_scan_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                       static_cast<const float*>(bins), count_dev, C_dev, cand_val, cand_idx, C_max);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t nc = blocks * kDDMaxC;
+  const int64_t nc = blocks * C_max;
   hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
                      (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
-                     out_idx, nullptr, C_dev, kDDMaxC);
+                     out_idx, nullptr, C_dev, C_max);
   return hipGetLastError();
 }
 

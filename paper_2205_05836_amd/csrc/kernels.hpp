@@ -95,30 +95,6 @@ struct AttrLaunch {
 hipError_t launch_attribute(const AttrLaunch& a, hipStream_t stream);
 
 // Dynamic definition helpers.
-struct MergeLaunch {
-  const double* E;   // (rows, 2^n)
-  double* Ep;        // (rows, 2^na)
-  int64_t rows;
-  int n, na, nm;
-  uint64_t active_flat, merged_flat, fixed_vals_flat;  // masks over flat bit positions
-};
-hipError_t launch_merge(const MergeLaunch& m, hipStream_t stream);
-
-struct TopkLaunch {
-  const void* bins;
-  DType t;                // F64 or F32
-  int64_t count;
-  int C;                  // candidates wanted, <= 64
-  double* cand_val;       // workspace
-  uint64_t* cand_idx;     // workspace
-  int64_t cand_capacity;  // entries of cand_val / cand_idx
-  double* out_val;        // C values (working precision widened to double)
-  uint64_t* out_idx;      // C bin indices
-};
-// Exact top-C by (value desc, index asc).
-hipError_t launch_topk(const TopkLaunch& t, hipStream_t stream);
-int64_t topk_candidate_capacity(int64_t count, int C);
-
 struct RefineLaunch {
   int n_sub, K;
   const double* Ep[CQ_MAX_SUBCIRCUITS];
@@ -189,13 +165,14 @@ hipError_t launch_prep_indirect(const PrepArgs* dev, int count, DType t, bool f1
 hipError_t launch_merge_indirect(const MergeArgs* dev, int count, int64_t max_threads,
                                  hipStream_t stream);
 hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream);
-// Top-C of *count bins with C = *C_dev (nothing when C <= 0); pass one
-// writes 64 keys per workgroup into the candidate buffers.
+// Top-C of *count bins (value desc, index asc) with C = *C_dev <= C_max
+// (nothing when C <= 0): pass one keeps C_max keys per workgroup in the
+// candidate buffers, pass two selects from them.
 hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_dev,
-                                const int32_t* C_dev, int64_t max_count, double* cand_val,
-                                uint64_t* cand_idx, int64_t cand_capacity, double* out_val,
-                                uint64_t* out_idx, hipStream_t stream);
-int64_t topk_indirect_capacity(int64_t max_count);
+                                const int32_t* C_dev, int C_max, int64_t max_count,
+                                double* cand_val, uint64_t* cand_idx, int64_t cand_capacity,
+                                double* out_val, uint64_t* out_idx, hipStream_t stream);
+int64_t topk_indirect_capacity(int64_t max_count, int C_max);
 
 // ---------------------------------------------------------------------------
 // Device-driven dynamic definition (Algorithm 1).  One recursion is a fixed

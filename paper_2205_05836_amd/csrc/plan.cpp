@@ -50,6 +50,13 @@ int shared_cuts(const CutMap& cm, unsigned m1, unsigned m2) {
 
 int64_t pow2(int e) { return (int64_t)1 << e; }
 
+// One run of consecutive subcircuit ids.
+bool contiguous(unsigned m) {
+  if (m == 0) return true;
+  while (!(m & 1u)) m >>= 1;
+  return (m & (m + 1)) == 0;
+}
+
 int64_t axes_size(const std::vector<Axis>& ax, size_t b, size_t e) {
   int s = 0;
   for (size_t i = b; i < e; ++i) s += ax[i].log2;
@@ -364,6 +371,11 @@ cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work
       double flops = 2.0 * std::pow(2.0, l2r + 2.0 * sh);
       double bytes = work_elem_bytes * (std::pow(2.0, l2a) + std::pow(2.0, l2b) + std::pow(2.0, l2r));
       double cost = dp[a].cost + dp[b].cost + flops + 20.0 * bytes;
+      // the root's result is in concatenated order only when each side is a
+      // contiguous range of subcircuits; otherwise a final permute reads and
+      // writes the whole output once more
+      if (m == full && !(contiguous(a) && contiguous(b)))
+        cost += 20.0 * 2.0 * work_elem_bytes * std::pow(2.0, l2r);
       if (cost < dp[m].cost) {
         dp[m].cost = cost;
         dp[m].left = a;
