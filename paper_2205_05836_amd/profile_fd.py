@@ -1,0 +1,49 @@
+"""Profiling driver: the 30-qubit full-definition workload (chain of three
+10-output subcircuits, 4 + 4 cuts, seed 2) reconstructed ``reps`` times in
+one precision, then one device-to-device copy of 1 GiB.
+
+Inputs are generated on the host and copied in, so the only kernels that run
+are the library's and the runtime's copy kernel; the copy moves a known
+number of bytes and calibrates the HBM traffic counters (FETCH_SIZE,
+WRITE_SIZE) read for the reconstruction kernels.
+
+    python -m paper_2205_05836_amd.profile_fd bf16_split 3
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+COPY_BYTES = 1 << 30
+
+
+def main(argv):
+    prec = argv[1] if len(argv) > 1 else "bf16_split"
+    reps = int(argv[2]) if len(argv) > 2 else 3
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+
+    import paper_2205_05836_amd as cq
+    from workloads import synthetic as syn
+
+    cm, E = syn.chain_instance(2, [4, 4], [10, 10, 10])
+    ents = [torch.from_numpy(e).to("cuda:0") for e in E]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    out = torch.empty(2 ** 30, dtype=dt, device="cuda:0")
+    torch.cuda.synchronize()
+    for i in range(reps):
+        cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
+        torch.cuda.synchronize()
+        print(f"step {i} done", flush=True)
+    del out
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy of {COPY_BYTES} bytes done", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv)
