@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16_split", help="headline precision")
-    ap.add_argument("--forms", default="fp32,bf16",
+    ap.add_argument("--forms", default="fp32,bf16,fp16_split",
                     help="other precisions timed beside the headline and FP64")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

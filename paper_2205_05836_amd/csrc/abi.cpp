@@ -117,6 +117,7 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
     if (t.loc == Loc::Out) return Operand{out, nullptr, out_t};
     return planes(ws + plan.work_offset[t.index], t.elems);
   };
+  auto colmax = [&](int c) { return reinterpret_cast<uint64_t*>(ws + plan.colmax_offset[c]); };
   // operand preparation: FP64 entries -> the precision's storage format
   for (size_t i = 0; i < plan.tensors.size(); ++i) {
     const TensorRef& t = plan.tensors[i];
@@ -124,9 +125,41 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
     hipError_t e;
     {
       ProfScope ps("prep", 0.0, stream);
-      e = launch_prep(inputs[t.index], ws + plan.input_offset[t.index], t.elems, wt, f16, stream);
+      if (plan.scaled) {
+        const int nb = t.axes.empty() || t.axes.back().kind != 1 ? 0 : t.axes.back().log2;
+        const int64_t rows = t.elems >> nb;
+        e = launch_colmax(inputs[t.index], rows, nb, colmax(t.index), stream);
+        if (e == hipSuccess)
+          e = launch_prep_scaled(inputs[t.index], ws + plan.input_offset[t.index], t.elems, nb,
+                                 colmax(t.index), wt, f16, stream);
+      } else {
+        e = launch_prep(inputs[t.index], ws + plan.input_offset[t.index], t.elems, wt, f16, stream);
+      }
     }
     if (e != hipSuccess) return hip_fail(e, "operand prep launch");
+  }
+  int32_t* rowexp = nullptr;
+  int32_t* colexp = nullptr;
+  if (plan.scaled && plan.rowexp_offset >= 0) {
+    rowexp = reinterpret_cast<int32_t*>(ws + plan.rowexp_offset);
+    colexp = reinterpret_cast<int32_t*>(ws + plan.colexp_offset);
+    const Plan::FacGroup* gr[2] = {&plan.row_fac, &plan.col_fac};
+    int32_t* outs[2] = {rowexp, colexp};
+    const int64_t counts[2] = {plan.rowexp_count, plan.colexp_count};
+    for (int q = 0; q < 2; ++q) {
+      ExpSumLaunch x;
+      std::memset(&x, 0, sizeof(x));
+      x.out = outs[q];
+      x.count = counts[q];
+      x.n = (int)gr[q]->sub.size();
+      for (int i = 0; i < x.n; ++i) {
+        x.colmax[i] = colmax(gr[q]->sub[i]);
+        x.shift[i] = gr[q]->shift[i];
+        x.bits[i] = gr[q]->bits[i];
+      }
+      hipError_t e = launch_expsum(x, stream);
+      if (e != hipSuccess) return hip_fail(e, "scale exponent launch");
+    }
   }
   for (const Step& s : plan.steps) {
     hipError_t e;
@@ -151,6 +184,10 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
       L.ldc = g.ldc;
       L.alpha = g.alpha;
       L.nontemporal = plan.tensors[g.c].loc == Loc::Out;
+      if (rowexp && plan.tensors[g.c].loc == Loc::Out) {
+        L.rowexp = rowexp;
+        L.colexp = colexp;
+      }
       {
         static const char* kname[] = {"gemm_f64", "gemm_f32", "gemm_bf16", "gemm_bf16x3",
                                       "gemm_f16", "gemm_f16x3"};
@@ -174,6 +211,14 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
         L.sstride[i] = p.sstride[i];
       }
       L.alpha = p.alpha;
+      if (plan.scaled && plan.tensors[p.dst].loc == Loc::Out) {
+        L.nfac = (int)plan.perm_fac.sub.size();
+        for (int i = 0; i < L.nfac; ++i) {
+          L.colmax[i] = colmax(plan.perm_fac.sub[i]);
+          L.fac_shift[i] = plan.perm_fac.shift[i];
+          L.fac_bits[i] = plan.perm_fac.bits[i];
+        }
+      }
       {
         ProfScope ps("permute", 0.0, stream);
         e = launch_permute(L, stream);
@@ -195,7 +240,7 @@ cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec
   if (st != CQ_OK) return st;
   std::vector<int> ol;
   for (auto& s : cm.subs) ol.push_back(s.n());
-  return make_plan(cm, ol, work_elem_bytes(prec), perm, plan);
+  return make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
 }
 
 }  // namespace
@@ -765,7 +810,7 @@ extern "C" cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_p
   st = check_perm(out_perm, n_bits, perm);
   if (st != CQ_OK) return st;
   Plan plan;
-  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan);
+  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
   if (st != CQ_OK) return st;
   std::string js = "{\"workspace_bytes\": " + std::to_string(plan.workspace_bytes) +
                    ", \"work_elem_bytes\": " + std::to_string(plan.work_elem_bytes) +

@@ -18,6 +18,19 @@ __device__ inline uint16_t f_to_h16(float x, bool f16) {
   return f16 ? __builtin_bit_cast(uint16_t, _Float16(x)) : __builtin_bit_cast(uint16_t, __bf16(x));
 }
 
+// Binary exponent e of a column maximum m = f * 2^e, f in [0.5, 1) (0 for 0).
+__device__ inline int colmax_exp(uint64_t bits) {
+  const int be = (int)((bits >> 52) & 0x7ff);
+  return be == 0 ? 0 : be - 1022;
+}
+
+__device__ inline int fac_exp(const PermArgs& p, int64_t off) {
+  int e = 0;
+  for (int c = 0; c < p.nfac; ++c)
+    e += colmax_exp(p.colmax[c][(off >> p.fac_shift[c]) & ((1ll << p.fac_bits[c]) - 1)]);
+  return e;
+}
+
 // Generic axis permutation with conversion: one destination element per
 // thread iteration, destination written contiguously.  16-bit planes are
 // copied bit for bit when both sides use them.
@@ -43,6 +56,7 @@ __device__ inline void permute_body(const PermArgs& p) {
         if (p.src_lo) v += h16_to_f(static_cast<const uint16_t*>(p.src_lo)[off], SK == kF16);
       }
       v *= p.alpha;
+      if (p.nfac) v = ldexp(v, fac_exp(p, off));
       if constexpr (DK == kF64) static_cast<double*>(p.dst)[i] = v;
       else if constexpr (DK == kF32) static_cast<float*>(p.dst)[i] = float(v);
       else {
@@ -92,6 +106,58 @@ template <int DK>
 __global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a) {
   const PrepArgs p = a[blockIdx.y];
   prep_body<DK>(p.src, p.dst, p.dst_lo, p.n);
+}
+
+// Column maxima of |E| (rows x 2^cols_log2, FP64): each thread folds a run of
+// rows of one column, then one atomic max per thread.
+__global__ void __launch_bounds__(256) colmax_kernel(const double* __restrict__ E, int64_t rows,
+                                                     int cols_log2, int rows_per_thread,
+                                                     uint64_t* colmax) {
+  const int64_t cols = (int64_t)1 << cols_log2;
+  const int64_t chunks = (rows + rows_per_thread - 1) / rows_per_thread;
+  const int64_t total = chunks * cols;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += step) {
+    const int64_t col = t & (cols - 1), r0 = (t >> cols_log2) * rows_per_thread;
+    int64_t r1 = r0 + rows_per_thread;
+    if (r1 > rows) r1 = rows;
+    double m = 0.0;
+    for (int64_t r = r0; r < r1; ++r) m = fmax(m, fabs(E[(r << cols_log2) + col]));
+    atomicMax(reinterpret_cast<unsigned long long*>(colmax + col),
+              (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) p[i] = v;
+}
+
+template <int DK>
+__global__ void __launch_bounds__(256) prep_scaled_kernel(const double* __restrict__ src, void* dst,
+                                                          void* dst_lo, int64_t n, int cols_log2,
+                                                          const uint64_t* __restrict__ colmax) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t mask = ((int64_t)1 << cols_log2) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const float x = float(ldexp(src[i], -colmax_exp(colmax[i & mask])));
+    if constexpr (DK == kF32) {
+      static_cast<float*>(dst)[i] = x;
+    } else {
+      const uint16_t h = f_to_h16(x, DK == kF16);
+      static_cast<uint16_t*>(dst)[i] = h;
+      if (dst_lo) static_cast<uint16_t*>(dst_lo)[i] = f_to_h16(x - h16_to_f(h, DK == kF16), DK == kF16);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) expsum_kernel(ExpSumLaunch x) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < x.count; r += step) {
+    int e = 0;
+    for (int c = 0; c < x.n; ++c) e += colmax_exp(x.colmax[c][(r >> x.shift[c]) & ((1ll << x.bits[c]) - 1)]);
+    x.out[r] = e;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -285,6 +351,12 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
   }
   a.total = (int64_t)1 << bits;
   a.alpha = p.alpha;
+  a.nfac = p.nfac;
+  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
+    a.colmax[c] = p.colmax[c];
+    a.fac_shift[c] = p.fac_shift[c];
+    a.fac_bits[c] = p.fac_bits[c];
+  }
   const dim3 grid(grid_for(a.total));
   const int sk = kind_of(p.src.t, p.f16), dk = kind_of(p.td, p.f16);
   switch (sk) {
@@ -307,6 +379,43 @@ hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f1
     hipLaunchKernelGGL((prep_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
   else
     hipLaunchKernelGGL((prep_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_colmax(const double* E, int64_t rows, int cols_log2, uint64_t* colmax,
+                         hipStream_t stream) {
+  const int64_t cols = (int64_t)1 << cols_log2;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cols)), dim3(256), 0, stream, colmax, cols,
+                     (uint64_t)0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rpt = 64;
+  const int64_t total = (rows + rpt - 1) / rpt * cols;
+  hipLaunchKernelGGL(colmax_kernel, dim3(grid_for(total)), dim3(256), 0, stream, E, rows, cols_log2,
+                     rpt, colmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_scaled(const double* src, void* dst, int64_t n, int cols_log2,
+                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(grid_for(n));
+  void* lo = t == DType::H16X2 ? static_cast<char*>(dst) + n * 2 : nullptr;
+  if (t == DType::F32)
+    hipLaunchKernelGGL((prep_scaled_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n,
+                       cols_log2, colmax);
+  else if (f16)
+    hipLaunchKernelGGL((prep_scaled_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n,
+                       cols_log2, colmax);
+  else
+    hipLaunchKernelGGL((prep_scaled_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n,
+                       cols_log2, colmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_expsum(const ExpSumLaunch& x, hipStream_t stream) {
+  if (x.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(expsum_kernel, dim3(grid_for(x.count)), dim3(256), 0, stream, x);
   return hipGetLastError();
 }
 

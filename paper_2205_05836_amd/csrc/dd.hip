@@ -567,6 +567,8 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.sCz = sym_pow(G.sCz, na);
       g.ldc = sym_pow(G.ldc, na);
       g.alpha = G.alpha;
+      g.rowexp = nullptr;
+      g.colexp = nullptr;
       g.tilesM = (M + 127) / 128;
       g.tilesN = (N + 127) / 128;
       g.tiles = g.tilesM * g.tilesN * Z;
@@ -592,6 +594,7 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       }
       p.total = (int64_t)1 << bits;
       p.alpha = Q.alpha;
+      p.nfac = 0;
     }
   }
   RefineArgs& f = lv->refine;

@@ -431,7 +431,12 @@ __global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs gv, const Gem
         const int cc = j * 32;
         if (full || (m0 + wm + 4 * (lane >> 5) + rr < g.M && n0 + wn + (lane & 31) + cc < g.N)) {
           const int64_t idx = cbase + rr * g.ldc + cc;
-          const float x = alpha * acc[i][j][v];
+          float x = alpha * acc[i][j][v];
+          if constexpr (OUT != 2) {
+            if (g.rowexp)
+              x = __builtin_ldexpf(x, g.rowexp[tc.z * g.M + m0 + wm + 4 * (lane >> 5) + rr] +
+                                          g.colexp[n0 + wn + (lane & 31) + cc]);
+          }
           if constexpr (OUT == 2) {
             const uint16_t h = to_h16<F16>(x);
             static_cast<uint16_t*>(g.C)[idx] = h;
@@ -624,9 +629,17 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
   for (int s = 0; s < 16; ++s) {
     const int r = 4 * s + (lane >> 4);
     const int c = 4 * (lane & 15);
-    const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + r * EROW + c * 4);
+    f4_t x = *reinterpret_cast<const f4_t*>(wbuf + r * EROW + c * 4);
     const int64_t m = m0 + wm + r, n = n0 + wn + c;
     const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+    if constexpr (OUT != 2) {
+      if (g.rowexp && m < g.M) {
+        const int32_t re = g.rowexp[tc.z * g.M + m];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < g.N) x[e] = __builtin_ldexpf(x[e], re + g.colexp[n + e]);
+      }
+    }
     if (full || (m < g.M && n + 3 < g.N)) {
       if constexpr (OUT == 2) {
         typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
@@ -721,6 +734,8 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.sCz = g.sCz;
   a.ldc = g.ldc;
   a.alpha = g.alpha;
+  a.rowexp = g.rowexp;
+  a.colexp = g.colexp;
   a.tilesM = (g.M + 127) / 128;
   a.tilesN = (g.N + 127) / 128;
   a.tiles = a.tilesM * a.tilesN * g.Z;

@@ -109,6 +109,21 @@ struct Plan {
   // two 16-bit planes), 2 (one 16-bit plane)
   int work_elem_bytes = 8;
   double flops = 0.0;       // algorithmic flops of the GEMM steps
+
+  // Column scaling (FP16 operands): inputs are scaled per output column by
+  // powers of two before conversion, and the final step adds the exponents
+  // back.  A factor group lists, per subcircuit, where its output digit sits
+  // in the index the exponents are summed over (bits 0: a subcircuit without
+  // outputs, digit always 0).
+  struct FacGroup {
+    std::vector<int> sub, shift, bits;
+  };
+  bool scaled = false;
+  std::vector<int64_t> colmax_offset;   // per input: 2^{n_c} uint64 column maxima
+  int64_t rowexp_offset = -1, colexp_offset = -1;  // final GEMM: Z*M and N int32 exponents
+  int64_t rowexp_count = 0, colexp_count = 0;
+  FacGroup row_fac, col_fac;            // final GEMM: over z*M + m, and over n
+  FacGroup perm_fac;                    // final permute: over the source offset
 };
 
 // `out_log2` per subcircuit = number of outputs taking part (n_c for FD, the
@@ -116,8 +131,11 @@ struct Plan {
 // apply to the final concatenated order.
 // keep_empty: subcircuits with no outputs taking part still carry a size-1
 // output axis (the dynamic-definition plans re-evaluate sizes per recursion).
+// column_scaling: reserve and describe the column scaling of the operands
+// (the 16-bit FP16 forms).
 cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work_elem_bytes,
-                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty = false);
+                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty = false,
+                    bool column_scaling = false);
 
 // ---------------------------------------------------------------------------
 // Plans with symbolic sizes.  Every size and stride of a plan is a product of

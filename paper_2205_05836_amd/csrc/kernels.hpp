@@ -34,6 +34,10 @@ struct GemmLaunch {
   int64_t sAz, sAk, sBz, sBk, sCz, ldc;
   double alpha;
   bool nontemporal = false;  // final output: stores bypass the caches
+  // FP32 output scaled by 2^(rowexp[z*M + m] + colexp[n]) when set (16-bit
+  // forms with column-scaled operands)
+  const int32_t* rowexp = nullptr;
+  const int32_t* colexp = nullptr;
 };
 
 // C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
@@ -54,6 +58,8 @@ struct GemmArgs {
   int64_t tilesM, tilesN, tiles;
   int m_fastest;
   double alpha;
+  const int32_t* rowexp;  // optional output exponents (see GemmLaunch)
+  const int32_t* colexp;
 };
 
 // Launches `max_tiles` workgroups of the precision's GEMM kernel reading its
@@ -67,6 +73,26 @@ hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t 
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
                        hipStream_t stream);
 
+// Column scaling by powers of two (16-bit operands).  colmax[b] receives the
+// bit pattern of max_l |E[l][b]| (FP64, so the unsigned order is the value
+// order); column b is then scaled by 2^-e, e the binary exponent with
+// max = f * 2^e, f in [0.5, 1).  Scaling is exact, and the result's
+// per-subcircuit exponents are added back at the end.
+hipError_t launch_colmax(const double* E, int64_t rows, int cols_log2, uint64_t* colmax,
+                         hipStream_t stream);
+hipError_t launch_prep_scaled(const double* src, void* dst, int64_t n, int cols_log2,
+                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream);
+// out[r] = sum_c e_c(colmax[c][(r >> shift[c]) & (2^bits[c] - 1)]) for r < count.
+struct ExpSumLaunch {
+  int32_t* out;
+  int64_t count;
+  int n;
+  const uint64_t* colmax[CQ_MAX_SUBCIRCUITS];
+  int shift[CQ_MAX_SUBCIRCUITS];
+  int bits[CQ_MAX_SUBCIRCUITS];
+};
+hipError_t launch_expsum(const ExpSumLaunch& x, hipStream_t stream);
+
 constexpr int kMaxPermAxes = 48;
 struct PermLaunch {
   Operand src;
@@ -78,6 +104,10 @@ struct PermLaunch {
   int log2[kMaxPermAxes];
   int64_t sstride[kMaxPermAxes];
   double alpha;
+  int nfac = 0;  // column-scale undo (PermArgs)
+  const uint64_t* colmax[CQ_MAX_SUBCIRCUITS] = {};
+  int fac_shift[CQ_MAX_SUBCIRCUITS] = {};
+  int fac_bits[CQ_MAX_SUBCIRCUITS] = {};
 };
 // dst[i] = alpha * src[sum_a idx_a(i) * sstride[a]]; i spans prod 2^log2[a].
 hipError_t launch_permute(const PermLaunch& p, hipStream_t stream);
@@ -125,6 +155,12 @@ struct PermArgs {
   int log2[kMaxPermAxes];
   int64_t sstride[kMaxPermAxes];
   double alpha;
+  // optional column-scale undo: value *= 2^(sum_c e_c) with e_c the exponent
+  // of colmax[c][(src offset >> fac_shift[c]) & (2^fac_bits[c] - 1)]
+  int nfac;
+  const uint64_t* colmax[CQ_MAX_SUBCIRCUITS];
+  int fac_shift[CQ_MAX_SUBCIRCUITS];
+  int fac_bits[CQ_MAX_SUBCIRCUITS];
 };
 
 struct PrepArgs {

@@ -330,8 +330,11 @@ struct Builder {
 
 cq_status check_plan_bounds(const Plan& plan);
 
+cq_status add_column_scaling(const CutMap& cm, const std::vector<int>& out_log2, Plan& plan);
+
 cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work_elem_bytes,
-                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty) {
+                    const std::vector<int>& out_perm, Plan& plan, bool keep_empty,
+                    bool column_scaling) {
   plan = Plan();
   plan.work_elem_bytes = work_elem_bytes;
   const int n = cm.n_sub;
@@ -487,7 +490,72 @@ cq_status make_plan(const CutMap& cm, const std::vector<int>& out_log2, int work
     s.p = p;
     plan.steps.push_back(s);
   }
+  if (column_scaling) {
+    cq_status st = add_column_scaling(cm, out_log2, plan);
+    if (st != CQ_OK) return st;
+  }
   return check_plan_bounds(plan);
+}
+
+cq_status add_column_scaling(const CutMap& cm, const std::vector<int>& out_log2, Plan& plan) {
+  auto reserve = [&](int64_t bytes) {
+    const int64_t off = plan.workspace_bytes;
+    plan.workspace_bytes = off + (bytes + 255) / 256 * 256;
+    return off;
+  };
+  plan.scaled = true;
+  plan.colmax_offset.clear();
+  for (int c = 0; c < cm.n_sub; ++c) plan.colmax_offset.push_back(reserve(pow2(out_log2[c]) * 8));
+  // subcircuits whose outputs take no part: one column, digit always 0
+  std::vector<bool> seen(cm.n_sub, false);
+  auto add = [&](Plan::FacGroup& g, const std::vector<Axis>& ax, size_t b, size_t e) {
+    int shift = 0;
+    for (size_t i = e; i-- > b;) {
+      if (ax[i].kind == 1) {
+        g.sub.push_back(ax[i].id);
+        g.shift.push_back(shift);
+        g.bits.push_back(ax[i].log2);
+        seen[ax[i].id] = true;
+      }
+      shift += ax[i].log2;
+    }
+  };
+  const Step& last = plan.steps.back();
+  Plan::FacGroup* rest = nullptr;
+  if (last.is_gemm && plan.tensors[last.g.c].loc == Loc::Out) {
+    const GemmStep& g = last.g;
+    const std::vector<Axis>& ax = plan.tensors[g.c].axes;
+    int row_bits = 0;
+    while ((pow2(row_bits)) < g.Z * g.M) ++row_bits;
+    size_t split = 0;
+    for (int acc = 0; split < ax.size() && acc < row_bits; ++split) acc += ax[split].log2;
+    while (split < ax.size() && ax[split].log2 == 0) ++split;
+    int acc = 0;
+    for (size_t i = 0; i < split; ++i) acc += ax[i].log2;
+    if (acc != row_bits) return fail(CQ_ERR_UNSUPPORTED, "internal: final GEMM rows do not split at an axis");
+    add(plan.row_fac, ax, 0, split);
+    add(plan.col_fac, ax, split, ax.size());
+    plan.rowexp_count = g.Z * g.M;
+    plan.colexp_count = g.N;
+    plan.rowexp_offset = reserve(plan.rowexp_count * 4);
+    plan.colexp_offset = reserve(plan.colexp_count * 4);
+    rest = &plan.row_fac;
+  } else if (!last.is_gemm) {
+    const std::vector<Axis>& ax = plan.tensors[last.p.src].axes;
+    add(plan.perm_fac, ax, 0, ax.size());
+    rest = &plan.perm_fac;
+  } else {
+    return fail(CQ_ERR_UNSUPPORTED, "internal: plan ends without writing the output");
+  }
+  for (int c = 0; c < cm.n_sub; ++c)
+    if (!seen[c]) {
+      rest->sub.push_back(c);
+      rest->shift.push_back(0);
+      rest->bits.push_back(0);
+    }
+  if ((int)plan.perm_fac.sub.size() > CQ_MAX_SUBCIRCUITS || (int)plan.row_fac.sub.size() > CQ_MAX_SUBCIRCUITS)
+    return fail(CQ_ERR_UNSUPPORTED, "internal: too many scale factors");
+  return CQ_OK;
 }
 
 int64_t sym_value(const SymQ& q, const std::vector<int>& na) {

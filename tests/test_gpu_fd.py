@@ -233,9 +233,11 @@ def test_30_qubit_chain_full_size_sampled(prec, tol):
         assert np.max(err / scale) < 1e-13
     else:
         assert np.all(err <= 1e-5 * scale + FP32_FLOOR)
-    # closed form of the total (sum over all bins): 2^-K sum_l prod_c rowsum_c(l_c)
-    rs = [e.sum(dim=1).cpu().numpy() for e in ents]
-    tot = 2.0 ** -8 * float(rs[0] @ rs[1].reshape(256, 256) @ rs[2])
+    # closed form of the total (sum over all bins): 2^-K sum_l prod_c rowsum_c(l_c),
+    # row sums of the host-built entries contracted by the oracle
+    ks = syn.chain_ks(BONDS_30Q, 3)
+    rs = [syn.dirichlet_entries(SEED_30Q, c, ks[c], 10).sum(axis=1)[:, None] for c in range(3)]
+    tot = float(rc.fd_contract(cm, rs)[0])
     got_tot = float(torch.sum(out, dtype=torch.float64).item())
     assert abs(got_tot - tot) < (1e-9 if prec == "fp64" else 1e-4)
 
@@ -307,3 +309,68 @@ def test_30_qubit_chain_full_size_h16(prec):
     print(f"max abs err {err.max():.3e}, max err/scale {np.max(err / scale):.3e}", flush=True)
     assert err.max() < 1e-6
     assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
+
+
+# --- 32-qubit chain of four: the mixed-precision accuracy matrix -------------
+
+SEED_32Q = 3
+BONDS_32Q = [3, 2, 3]        # K = 8; label rows 64, 1024, 1024, 64
+NS_32Q = [8, 8, 8, 8]        # 2^32 outputs
+
+
+def _full_vs(out, ref_out, chunk=1 << 27):
+    """max |a - b| and total variation over all outputs (device, float64)."""
+    mx, tv = 0.0, 0.0
+    for i in range(0, out.numel(), chunk):
+        d = (out[i:i + chunk].double() - ref_out[i:i + chunk].double()).abs()
+        mx = max(mx, float(d.max()))
+        tv += float(d.sum())
+    return mx, 0.5 * tv
+
+
+_FP64_32Q = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_split", "fp16_split", "bf16", "fp16"])
+def test_32_qubit_chain_of_four_accuracy_matrix(prec):
+    """2^32 outputs in every precision against the oracle on 10^5 sampled
+    bins (seed 31), and against the FP64 GPU output over all bins."""
+    m = cq()
+    cm, E = syn.chain_instance(SEED_32Q, BONDS_32Q, NS_32Q)
+    ents = [to_dev(e) for e in E]
+    print(f"32q chain of four {prec}", flush=True)
+    out = m.cq_reconstruct_fd(cm, ents, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    bins = rng.integers(0, 2 ** 32, size=100_000).astype(np.int64)
+    got = out[torch.from_numpy(bins).to(DEV)].cpu().numpy().astype(np.float64)
+    ref = rc.fd_per_bin(cm, E, bins)
+    scale = rc.fd_per_bin(cm, [np.abs(e) for e in E], bins)
+    err = np.abs(got - ref)
+    rel = err / np.maximum(scale, 1e-300)
+    line = (f"{prec}: sampled max abs {err.max():.3e}, TV estimate {2.0 ** 31 * err.mean():.3e}, "
+            f"max err/scale {rel.max():.3e}, median err/scale {np.median(rel):.3e}")
+    if prec == "fp64":
+        _FP64_32Q["out"] = out
+    elif "out" in _FP64_32Q:
+        mx, tv = _full_vs(out, _FP64_32Q["out"])
+        line += f"; vs FP64 GPU over 2^32: max abs {mx:.3e}, TV {tv:.3e}"
+    print(line, flush=True)
+    if prec == "fp64":
+        assert err.max() < 1e-10
+        assert np.all(err <= 1e-13 * scale + 1e-300)
+    elif prec == "fp32":
+        assert err.max() < 1e-6
+        assert np.all(err <= 1e-5 * scale + FP32_FLOOR)
+    elif prec == "bf16_split":
+        assert err.max() < 1e-6
+        assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
+    elif prec == "fp16_split":
+        # columns are scaled by powers of two before the FP16 conversion, so
+        # hi + lo keeps 22 bits of every entry whatever its magnitude
+        assert err.max() < 1e-6
+        assert np.all(err <= 1e-5 * scale + FP32_FLOOR)
+    else:
+        assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
+    if prec == "fp16":
+        _FP64_32Q.clear()
