@@ -393,6 +393,7 @@ struct DDInstancePlan {
   SymPlan sp;
   std::vector<int64_t> ep_off, rs_off;
   int64_t plan_off = 0, bins_off = 0, bins_bytes = 0, cand_off = 0, cand_cap = 0;
+  int topc_step = -1;  // the GEMM that selects top-C instead of storing bins, or -1
   int64_t big = 0;  // bytes of the shared region this instance needs
   int64_t max_count = 0;
   std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
@@ -445,13 +446,6 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   D.plan_off = off;
   off = align256(off + D.plan.workspace_bytes);
   D.max_count = (int64_t)1 << sum_a;
-  D.bins_off = off;
-  D.bins_bytes = bins_stored ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
-  off += D.bins_bytes;
-  D.cand_off = off;
-  D.cand_cap = topk_indirect_capacity(D.max_count, std::min(4 * p.R, kDDMaxC));
-  off = align256(off + D.cand_cap * 16);
-  D.big = off;
   D.step_max.clear();
   for (const Step& s : D.plan.steps) {
     if (s.is_gemm) {
@@ -464,6 +458,21 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
       D.step_max.push_back((int64_t)1 << bits);
     }
   }
+  const int C_max = std::min(4 * p.R, kDDMaxC);
+  // Without bin buffers from the caller and with a GEMM writing the bins, the
+  // bins are never stored: that GEMM selects top-C candidates itself.
+  const Step& last = D.plan.steps.back();
+  D.topc_step = -1;
+  if (!bins_stored && last.is_gemm && D.plan.tensors[last.g.c].loc == Loc::Out)
+    D.topc_step = (int)D.plan.steps.size() - 1;
+  D.bins_off = off;
+  D.bins_bytes = (bins_stored || D.topc_step >= 0) ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
+  off += D.bins_bytes;
+  D.cand_off = off;
+  D.cand_cap = D.topc_step >= 0 ? D.step_max[D.topc_step] * C_max
+                                : topk_indirect_capacity(D.max_count, C_max);
+  off = align256(off + D.cand_cap * 16);
+  D.big = off;
   return CQ_OK;
 }
 
@@ -513,6 +522,9 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
     P.Rs[c] = reinterpret_cast<double*>(ws + D.rs_off[c]);
     P.prep_dst[c] = -1;
   }
+  P.topc_step = D.topc_step;
+  P.cand_v = reinterpret_cast<double*>(ws + D.cand_off);
+  P.cand_i = reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8);
   char* pw = ws + D.plan_off;
   for (size_t t = 0; t < plan.tensors.size(); ++t) {
     const TensorRef& T = plan.tensors[t];
@@ -628,7 +640,7 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
     const Step& s = D.plan.steps[si];
     if (s.is_gemm) {
       e = launch_gemm_indirect(prec, &lv->gemm[si], D.step_max[si], tensor_dtype(D.plan, s.g.c, prec),
-                               false, stream);
+                               false, (int)si == D.topc_step, stream);
       if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
     } else {
       e = launch_permute_indirect(&lv->perm[si], tensor_dtype(D.plan, s.p.src, prec),
@@ -637,11 +649,16 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
       if (e != hipSuccess) return hip_fail(e, "permute launch");
     }
   }
-  e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, std::min(4 * p.R, kDDMaxC),
-                           D.max_count,
-                           reinterpret_cast<double*>(ws + D.cand_off),
-                           reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8), D.cand_cap,
-                           st->top_val, st->top_idx, stream);
+  if (D.topc_step >= 0)
+    e = launch_topk_candidates(reinterpret_cast<const double*>(ws + D.cand_off),
+                               reinterpret_cast<const uint64_t*>(ws + D.cand_off + D.cand_cap * 8),
+                               reinterpret_cast<const int64_t*>(&st->topc_count), &st->C,
+                               std::min(4 * p.R, kDDMaxC), st->top_val, st->top_idx, stream);
+  else
+    e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, std::min(4 * p.R, kDDMaxC),
+                             D.max_count, reinterpret_cast<double*>(ws + D.cand_off),
+                             reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8),
+                             D.cand_cap, st->top_val, st->top_idx, stream);
   if (e != hipSuccess) return hip_fail(e, "top-C launch");
   e = launch_refine_indirect(&lv->refine, std::min(4 * p.R, kDDMaxC), stream);
   if (e != hipSuccess) return hip_fail(e, "refine launch");
@@ -670,7 +687,7 @@ cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd
     if (e != hipSuccess) return hip_fail(e, "init launch");
     for (int r = 0; r < p.R; ++r) {
       void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
-      if (!bins) bins = ws + D.bins_off;
+      if (!bins && D.topc_step < 0) bins = ws + D.bins_off;
       cq_status st = dd_enqueue_level(D, p, ws, ctrl, r, bins, stream);
       if (st != CQ_OK) return st;
     }

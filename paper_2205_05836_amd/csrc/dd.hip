@@ -413,6 +413,15 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
   return hipGetLastError();
 }
 
+hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
+                                  const int64_t* count_dev, const int32_t* C_dev, int C_max,
+                                  double* out_val, uint64_t* out_idx, hipStream_t stream) {
+  if (C_max < 1 || C_max > kDDMaxC) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream, cand_val, cand_idx,
+                     (int64_t)0, (int64_t)0, 0, out_val, out_idx, count_dev, C_dev, C_max);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Device-driven recursion control.  These kernels run on one thread: they
 // handle a few hundred words per recursion.
@@ -542,6 +551,14 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
   const int64_t count = (int64_t)1 << sum;
   st->count = count;
   st->C = any_merged ? (int)(count < P->C_max ? count : P->C_max) : 0;
+  // without stored bins and with nothing to select, the bins are not needed
+  const bool skip = P->topc_step >= 0 && st->C == 0;
+  if (P->topc_step >= 0) {
+    st->topc_thr = 0x000fffffffffffffull;  // order-preserving key of -infinity
+    st->topc_count = 0;
+  }
+  if (skip)
+    for (int c = 0; c < ns; ++c) lv->prep[c].n = 0;
   for (int s = 0; s < P->n_steps; ++s) {
     if (P->step_is_gemm[s]) {
       const DDGemmSym& G = P->gemm[s];
@@ -569,9 +586,15 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.alpha = G.alpha;
       g.rowexp = nullptr;
       g.colexp = nullptr;
+      const bool tc_here = s == P->topc_step;
+      g.topc_thr = tc_here ? &st->topc_thr : nullptr;
+      g.topc_count = tc_here ? &st->topc_count : nullptr;
+      g.topc_C = tc_here ? &st->C : nullptr;
+      g.topc_v = tc_here ? P->cand_v : nullptr;
+      g.topc_i = tc_here ? P->cand_i : nullptr;
       g.tilesM = (M + 127) / 128;
       g.tilesN = (N + 127) / 128;
-      g.tiles = g.tilesM * g.tilesN * Z;
+      g.tiles = skip ? 0 : g.tilesM * g.tilesN * Z;
       const double a_elems = double(g.sAz ? Z : 1) * double(M) * double(K);
       const double b_elems = double(g.sBz ? Z : 1) * double(N) * double(K);
       g.m_fastest = b_elems > a_elems ? 1 : 0;
@@ -592,7 +615,7 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
         p.sstride[i] = sym_pow(Q.sstride[i], na);
         bits += l;
       }
-      p.total = (int64_t)1 << bits;
+      p.total = skip ? 0 : (int64_t)1 << bits;
       p.alpha = Q.alpha;
       p.nfac = 0;
     }

@@ -17,6 +17,7 @@
 // that each of the 8 XCDs, each with its own L2, receives a contiguous range.
 #include <hip/hip_runtime.h>
 
+
 #include "kernels.hpp"
 
 namespace cq {
@@ -121,9 +122,152 @@ __device__ inline void store_out(TC* p, TC v) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused top-C epilogue (dynamic definition without stored bins).  A tile
+// first compares its values with the running threshold tau, a lower bound on
+// the C-th best bin value (it only ever holds the C-th best value of some
+// tile).  Tiles with nothing at or above tau end there -- after the first
+// tiles almost all of them.  Otherwise the tile selects its own C best keys
+// (value desc, index asc) above tau in an LDS buffer, appends them to the
+// candidate list and, holding C of them, raises tau to the C-th.  Every key of
+// the global top C is at or above tau and among its tile's C best, so the
+// candidates contain the global top C exactly.
+// ---------------------------------------------------------------------------
+__device__ inline unsigned long long ord_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+__device__ inline double ord_val(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+template <typename T>
+struct TcKey {
+  T v;
+  uint32_t i;  // r * 128 + c inside the tile
+};
+
+template <typename T>
+__device__ inline bool tc_better(const TcKey<T>& a, const TcKey<T>& b) {
+  return a.v > b.v || (a.v == b.v && a.i < b.i);
+}
+
+template <typename T>
+__device__ inline TcKey<T> tc_worst() {
+  return TcKey<T>{T(-INFINITY), 0xffffffffu};
+}
+
+// Best key of the wave (every lane gets it).
+template <typename T>
+__device__ inline TcKey<T> wave_best(TcKey<T> k) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    const TcKey<T> o{__shfl_xor(k.v, s), (uint32_t)__shfl_xor((int)k.i, s)};
+    if (tc_better(o, k)) k = o;
+  }
+  return k;
+}
+
+// get(e) -> (value, r * 128 + c, or 0xffffffff outside M x N) for e < V.
+// Each wave takes its C best keys at or above tau by C rounds of a wave
+// arg-max over the values its lanes hold (the owner retires the winner);
+// wave 0 then merges the waves' lists the same way.  Every loop over e is
+// unrolled, so the accumulators behind get() are indexed statically.
+template <typename T, int V, int NTHR, typename Get, typename Raw>
+__device__ __forceinline__ void topc_tile(const GemmArgs& g, int64_t z, int64_t m0, int64_t n0, bool full,
+                                          Get get, Raw raw) {
+  constexpr int NW = NTHR / 64;
+  static_assert(V <= 64, "one live bit per value");
+  __shared__ TcKey<T> wk[NW][kDDMaxC];
+  __shared__ TcKey<T> outk[kDDMaxC];
+  __shared__ int wn[NW];
+  __shared__ int nout;
+  __shared__ unsigned long long base;
+  const int C = *g.topc_C;
+  if (C <= 0) return;
+  const double tau = ord_val(*g.topc_thr);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // fast test on full tiles: the largest value against tau
+  if (full) {
+    T mx = raw(0);
+#pragma unroll
+    for (int e = 1; e < V; ++e) mx = raw(e) > mx ? raw(e) : mx;
+    if (__syncthreads_count(double(mx) >= tau) == 0) return;
+  }
+  uint64_t live = 0;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const TcKey<T> k = get(e);
+    if (k.i != 0xffffffffu && double(k.v) >= tau) live |= 1ull << e;
+  }
+  if (__syncthreads_count(live != 0) == 0) return;
+  int got = 0;
+  for (int round = 0; round < C; ++round) {
+    if (__ballot(live != 0) == 0) break;
+    TcKey<T> best = tc_worst<T>();
+    int be = -1;
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      if ((live >> e) & 1) {
+        const TcKey<T> k = get(e);
+        if (tc_better(k, best)) {
+          best = k;
+          be = e;
+        }
+      }
+    const TcKey<T> w = wave_best(best);
+    if (lane == 0) wk[wave][got] = w;
+    if (be >= 0 && best.i == w.i) live &= ~(1ull << be);
+    ++got;
+  }
+  if (lane == 0) wn[wave] = got;
+  __syncthreads();
+  if (wave == 0) {
+    // lane l holds key l of every wave's list
+    uint32_t hl = 0;
+    TcKey<T> h[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      h[w] = tc_worst<T>();
+      if (lane < wn[w]) {
+        h[w] = wk[w][lane];
+        hl |= 1u << w;
+      }
+    }
+    int n = 0;
+    for (; n < C; ++n) {
+      if (__ballot(hl != 0) == 0) break;
+      TcKey<T> best = tc_worst<T>();
+      int bw = -1;
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        if (((hl >> w) & 1) && tc_better(h[w], best)) {
+          best = h[w];
+          bw = w;
+        }
+      const TcKey<T> win = wave_best(best);
+      if (lane == 0) outk[n] = win;
+      if (bw >= 0 && best.i == win.i) hl &= ~(1u << bw);
+    }
+    if (lane == 0) {
+      nout = n;
+      if (n == C) atomicMax(g.topc_thr, ord_key(double(outk[C - 1].v)));
+      base = atomicAdd(g.topc_count, (unsigned long long)n);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nout; t += NTHR) {
+    const TcKey<T> k = outk[t];
+    g.topc_v[base + t] = double(k.v);
+    g.topc_i[base + t] = (uint64_t)(z * g.sCz + (m0 + (k.i >> 7)) * g.ldc + n0 + (k.i & 127));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64
 // ---------------------------------------------------------------------------
-template <bool NT>
+template <bool NT, bool TC = false>
 __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
   CQ_LOAD_GEMM_ARGS
   // 8 waves in a 4 x 2 grid, 32 x 64 outputs each: two waves per SIMD hide
@@ -163,6 +307,7 @@ __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmAr
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      if (kk >= g.K - k0) break;  // short K (outer products): skip all-zero steps
       double a[2], b[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
@@ -174,6 +319,18 @@ __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmAr
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  }
+  if constexpr (TC) {
+    const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+    auto get = [&](int e) -> TcKey<double> {
+      const int i = e >> 4, j = (e >> 2) & 3, v = e & 3;
+      const int r = wm + i * 16 + (lane >> 4) + 4 * v, c = wn + j * 16 + (lane & 15);
+      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
+      return TcKey<double>{g.alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+    };
+    auto raw = [&](int e) -> double { return g.alpha * acc[e >> 4][(e >> 2) & 3][e & 3]; };
+    topc_tile<double, 32, 512>(g, tc.z, m0, n0, full, get, raw);
+    return;
   }
   double* C = static_cast<double*>(g.C) + tc.z * g.sCz;
 #pragma unroll
@@ -192,7 +349,7 @@ __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmAr
 // ---------------------------------------------------------------------------
 // FP32
 // ---------------------------------------------------------------------------
-template <bool NT>
+template <bool NT, bool TC = false>
 __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
   CQ_LOAD_GEMM_ARGS
   constexpr int BM = 128, BN = 128, BK = 16;
@@ -235,6 +392,7 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmAr
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
+      if (kk >= g.K - k0) break;  // short K (outer products): skip all-zero steps
       float a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 5)][wm + i * 32 + (lane & 31)];
@@ -246,6 +404,19 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmAr
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  }
+  if constexpr (TC) {
+    const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+    auto get = [&](int e) -> TcKey<float> {
+      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
+      const int r = wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int c = wn + j * 32 + (lane & 31);
+      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
+      return TcKey<float>{alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+    };
+    auto raw = [&](int e) -> float { return alpha * acc[e >> 5][(e >> 4) & 1][e & 15]; };
+    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, get, raw);
+    return;
   }
   float* C = static_cast<float*>(g.C) + tc.z * g.sCz;
 #pragma unroll
@@ -262,7 +433,8 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmAr
 
 // ---------------------------------------------------------------------------
 // BF16 / FP16 with FP32 accumulation.  SPLIT = 3 issues hi*hi + hi*lo + lo*hi.
-// OUT: 0 = FP32, 1 = FP32 non-temporal, 2 = 16-bit planes (hi, and lo when split)
+// OUT: 0 = FP32, 1 = FP32 non-temporal, 2 = 16-bit planes (hi, and lo when
+// split), 3 = fused top-C (no store)
 // ---------------------------------------------------------------------------
 template <bool F16>
 struct Half;
@@ -322,7 +494,8 @@ __device__ inline float from_h16(uint16_t x) {
 }
 
 template <int SPLIT, bool F16, int OUT>
-__global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+__global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmArgs gv,
+                                                                           const GemmArgs* __restrict__ gp) {
   CQ_LOAD_GEMM_ARGS
   using H = Half<F16>;
   using V8 = typename H::V8;
@@ -397,6 +570,7 @@ __global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs gv, const Gem
     if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
+      if (kk >= g.K - k0) break;  // short K (outer products): skip all-zero steps
       const int kc = kk + 8 * (lane >> 5);
       V8 a[NP][2], b[NP][2];
 #pragma unroll
@@ -419,6 +593,19 @@ __global__ void __launch_bounds__(256, 2) gemm_h16_kernel(GemmArgs gv, const Gem
     }
   }
   const float alpha = float(g.alpha);
+  if constexpr (OUT == 3) {
+    const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+    auto get = [&](int e) -> TcKey<float> {
+      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
+      const int r = wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int c = wn + j * 32 + (lane & 31);
+      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
+      return TcKey<float>{alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+    };
+    auto raw = [&](int e) -> float { return alpha * acc[e >> 5][(e >> 4) & 1][e & 15]; };
+    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, get, raw);
+    return;
+  }
   const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
   const int64_t cbase = tc.z * g.sCz + (m0 + wm + 4 * (lane >> 5)) * g.ldc + n0 + wn + (lane & 31);
 #pragma unroll
@@ -736,6 +923,11 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.alpha = g.alpha;
   a.rowexp = g.rowexp;
   a.colexp = g.colexp;
+  a.topc_thr = nullptr;
+  a.topc_count = nullptr;
+  a.topc_C = nullptr;
+  a.topc_v = nullptr;
+  a.topc_i = nullptr;
   a.tilesM = (g.M + 127) / 128;
   a.tilesN = (g.N + 127) / 128;
   a.tiles = a.tilesM * a.tilesN * g.Z;
@@ -771,7 +963,18 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
 }
 
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
-                                DType tc, bool nontemporal, hipStream_t stream) {
+                                DType tc, bool nontemporal, bool topc, hipStream_t stream) {
+  if (topc) {
+    switch (prec) {
+      case CQ_FP64: return launch_ind(gemm_f64_kernel<false, true>, dev, max_tiles, stream, 512);
+      case CQ_FP32: return launch_ind(gemm_f32_kernel<false, true>, dev, max_tiles, stream);
+      case CQ_BF16: return launch_ind(gemm_h16_kernel<1, false, 3>, dev, max_tiles, stream);
+      case CQ_BF16_SPLIT: return launch_ind(gemm_h16_kernel<3, false, 3>, dev, max_tiles, stream);
+      case CQ_FP16: return launch_ind(gemm_h16_kernel<1, true, 3>, dev, max_tiles, stream);
+      case CQ_FP16_SPLIT: return launch_ind(gemm_h16_kernel<3, true, 3>, dev, max_tiles, stream);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (prec) {
     case CQ_FP64:
       return nontemporal ? launch_ind(gemm_f64_kernel<true>, dev, max_tiles, stream, 512)

@@ -60,6 +60,14 @@ struct GemmArgs {
   double alpha;
   const int32_t* rowexp;  // optional output exponents (see GemmLaunch)
   const int32_t* colexp;
+  // Top-C instead of the store (launch_gemm_indirect with topc): each tile
+  // appends its C best (value, index) keys not below the running threshold
+  // and raises the threshold to its C-th best value when it has C of them.
+  unsigned long long* topc_thr;    // order-preserving key of the threshold value
+  unsigned long long* topc_count;  // candidates appended
+  const int32_t* topc_C;
+  double* topc_v;
+  uint64_t* topc_i;
 };
 
 // Launches `max_tiles` workgroups of the precision's GEMM kernel reading its
@@ -67,7 +75,7 @@ struct GemmArgs {
 // output are in the precision's storage format (tc: F32/F64 output or the
 // precision's own planes); the register-path 16-bit kernel is used.
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
-                                DType tc, bool nontemporal, hipStream_t stream);
+                                DType tc, bool nontemporal, bool topc, hipStream_t stream);
 
 // Converts n FP64 values to `t` (FP32, or BF16/FP16 planes when f16 is false/true).
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
@@ -209,6 +217,10 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
                                 double* cand_val, uint64_t* cand_idx, int64_t cand_capacity,
                                 double* out_val, uint64_t* out_idx, hipStream_t stream);
 int64_t topk_indirect_capacity(int64_t max_count, int C_max);
+// Top-C (C = *C_dev) of *count_dev explicit candidate keys.
+hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
+                                  const int64_t* count_dev, const int32_t* C_dev, int C_max,
+                                  double* out_val, uint64_t* out_idx, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Device-driven dynamic definition (Algorithm 1).  One recursion is a fixed
@@ -268,6 +280,10 @@ struct DDProgram {
   double* Ep[CQ_MAX_SUBCIRCUITS];            // reduced entries
   double* Rs[CQ_MAX_SUBCIRCUITS];            // their row sums
   int32_t prep_dst[CQ_MAX_SUBCIRCUITS];      // tensor receiving the converted copy, or -1
+  int32_t topc_step;                         // GEMM step that selects top-C instead of storing, or -1
+  int32_t pad2;
+  double* cand_v;                            // its candidate buffers
+  uint64_t* cand_i;
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -294,6 +310,8 @@ struct DDState {
   int32_t n_active, stop, done, n_list;
   int32_t C, pad;
   int64_t count;                 // bins of the recursion
+  unsigned long long topc_thr;   // fused top-C: running threshold (order-preserving key)
+  unsigned long long topc_count; // fused top-C: candidates appended
   uint64_t zero_idx;             // 0: the single bin of the total
   double total;
   double top_val[kDDMaxC];

@@ -216,3 +216,31 @@ def test_graph_and_direct_launches_agree():
     assert rg == rd
     for x, y in zip(bg, bd):
         assert np.array_equal(x, y, equal_nan=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_split"])
+def test_fused_top_c_matches_stored_bins(prec):
+    """Without bin buffers the last GEMM selects the top-C candidates itself
+    (nothing stored); the records must equal those of the stored-bin path
+    exactly, ties (integer entries) included."""
+    m = cq()
+    rng = np.random.default_rng(5)
+    insts = []
+    cm, E = syn.chain_instance(81, [2, 1], [6, 7, 5])
+    insts.append(instance(cm, E, dd.initial_states(cm, [3, 2, 2]), [3, 2, 2]))
+    cm = syn.chain_cutmap([1, 2], [5, 5, 6])
+    E = [syn.integer_entries(rng, k, n, lo=-2, hi=3) for k, n in zip(syn.chain_ks([1, 2], 3), [5, 5, 6])]
+    insts.append(instance(cm, E, dd.initial_states(cm, [2, 2, 2]), [2, 2, 2]))
+    cm, E = syn.chain_instance(82, [0, 2, 1], [4, 5, 4, 5])
+    insts.append(instance(cm, E, dd.initial_states(cm, [2, 1, 2, 1]), [2, 1, 2, 1]))
+    R = 5
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    bins = []
+    for inst in insts:
+        A = max_bins_log2(inst["subs"], dd.initial_states(inst["subs"], inst["max_active"]),
+                          inst["max_active"])
+        bins += [torch.empty(2 ** A, dtype=dt, device=DEV) for _ in range(R)]
+    stored, done_s = m.cq_reconstruct_dd(insts, prec, R, bins=bins)
+    fused, done_f = m.cq_reconstruct_dd(insts, prec, R)
+    assert done_s == done_f
+    assert stored == fused
