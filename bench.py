@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--dd-forms", default="fp32,bf16_split,fp64",
                     help="precisions of the batched dynamic-definition leg ('' skips it)")
     ap.add_argument("--dd-runs", type=int, default=3)
+    ap.add_argument("--skip-attribution", action="store_true",
+                    help="skip the entry-attribution leg")
     return ap.parse_args()
 
 
@@ -266,6 +268,39 @@ def dd_leg(torch, cq, forms, runs):
     return out
 
 
+ATTR_WORKLOAD = ("entry attribution at the DD subcircuit shape: 22 register slots, 2 initialised "
+                 "and 2 measured cut ends (k = 4), 20 outputs; variants (16, 9, 2^22) FP64 uniform "
+                 "random -> entries (256, 2^20) FP64")
+
+
+def attribution_leg(torch, cq, runs=3):
+    """Times cq_attribute (two FP64 passes through an intermediate U of
+    4^r x 4^o x 2^n) at the shape of one DD subcircuit."""
+    sub = (22, [0, 1] + [-1] * 20, [-1] * 20 + [2, 3])
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(5)
+    V = torch.rand((16, 9, 2 ** 22), dtype=torch.float64, device="cuda:0", generator=gen)
+    E = torch.empty((256, 2 ** 20), dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(cq.cq_attribute_workspace_size(sub), dtype=torch.uint8, device="cuda:0")
+    cq.cq_attribute(sub, V, E, workspace=ws)
+    times = []
+    for _ in range(runs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        cq.cq_attribute(sub, V, E, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = sorted(times)[len(times) // 2]
+    alg = (V.numel() + E.numel()) * 8
+    inter = 2 * 16 * 16 * 2 ** 20 * 8  # U written once and read once
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"workload": ATTR_WORKLOAD, "ms": round(ms, 3), "algorithmic_bytes": alg,
+            "achieved_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+            "achieved_GBps_with_intermediate": round((alg + inter) / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -344,6 +379,9 @@ def main():
         result["dd"] = dd_leg(torch, cq, dd_forms, args.dd_runs)
         out = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
         cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
+    if not args.skip_attribution:
+        result["attribution"] = attribution_leg(torch, cq)
+        torch.cuda.empty_cache()
     if not args.skip_cpu:
         cpu, err = cpu_baseline_leg(torch, ents, out, args.cpu_seconds)
         result["cpu_baseline"] = cpu

@@ -394,6 +394,7 @@ struct DDInstancePlan {
   std::vector<int64_t> ep_off, rs_off;
   int64_t plan_off = 0, bins_off = 0, bins_bytes = 0, cand_off = 0, cand_cap = 0;
   int topc_step = -1;  // the GEMM that selects top-C instead of storing bins, or -1
+  int64_t stage_off = 0;
   int64_t big = 0;  // bytes of the shared region this instance needs
   int64_t max_count = 0;
   std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
@@ -472,6 +473,8 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   D.cand_cap = D.topc_step >= 0 ? D.step_max[D.topc_step] * C_max
                                 : topk_indirect_capacity(D.max_count, C_max);
   off = align256(off + D.cand_cap * 16);
+  D.stage_off = off;  // fused top-C: keys staged between the two selection passes
+  off = align256(off + (int64_t)kTopcStage * kDDMaxC * 16);  // values, then indices
   D.big = off;
   return CQ_OK;
 }
@@ -653,7 +656,9 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
     e = launch_topk_candidates(reinterpret_cast<const double*>(ws + D.cand_off),
                                reinterpret_cast<const uint64_t*>(ws + D.cand_off + D.cand_cap * 8),
                                reinterpret_cast<const int64_t*>(&st->topc_count), &st->C,
-                               std::min(4 * p.R, kDDMaxC), st->top_val, st->top_idx, stream);
+                               std::min(4 * p.R, kDDMaxC), reinterpret_cast<double*>(ws + D.stage_off),
+                               reinterpret_cast<uint64_t*>(ws + D.stage_off + (int64_t)kTopcStage * kDDMaxC * 8),
+                               st->top_val, st->top_idx, stream);
   else
     e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, std::min(4 * p.R, kDDMaxC),
                              D.max_count, reinterpret_cast<double*>(ws + D.cand_off),

@@ -264,6 +264,96 @@ __global__ void __launch_bounds__(256) attr_init_kernel(AttrArgs a) {
   }
 }
 
+// Register forms of the two passes for few cut ends (the common case): a
+// thread owns one (j, b) -- or one (lm, b) -- reads each input element once
+// and produces every label of its group by butterflies in registers, so V and
+// U each cross HBM once.
+//  * measured ends, O <= 2: the 3^O x 2^O values V[j][beta][compose(b, m)]
+//    give all 4^O labels lm;
+//  * initialised ends, R <= 3: per init digit, (|0>, |1>, |+>, |+i>) ->
+//    (I, X, Y, Z) = (d0 + d1, -d0 - d1 + 2 d2, -d0 - d1 + 2 d3, d0 - d1).
+template <int O>
+__global__ void __launch_bounds__(256) attr_meas_reg_kernel(AttrArgs a) {
+  constexpr int NB = O == 0 ? 1 : (O == 1 ? 3 : 9);   // 3^O bases
+  constexpr int NM = 1 << O;                          // outcomes of the measured bits
+  constexpr int NL = 1 << (2 * O);                    // labels
+  const int64_t nb = (int64_t)1 << a.n;
+  const int64_t total = ((int64_t)1 << (2 * a.r)) * nb;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+    const int64_t b = i & (nb - 1);
+    const int64_t j = i >> a.n;
+    int64_t x0 = 0;
+    for (int q = 0; q < a.n; ++q)
+      if ((b >> (a.n - 1 - q)) & 1) x0 |= (int64_t)1 << a.out_pos[q];
+    double v[NB][NM];
+#pragma unroll
+    for (int beta = 0; beta < NB; ++beta)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        int64_t x = x0;
+#pragma unroll
+        for (int u = 0; u < O; ++u)
+          if ((m >> (O - 1 - u)) & 1) x |= (int64_t)1 << a.meas_pos[u];
+        v[beta][m] = a.V[((j * NB + beta) << a.w) + x];
+      }
+#pragma unroll
+    for (int lm = 0; lm < NL; ++lm) {
+      int beta = 0;
+#pragma unroll
+      for (int u = 0; u < O; ++u) beta = 3 * beta + basis_of((lm >> (2 * (O - 1 - u))) & 3);
+      double sum = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        bool neg = false;
+#pragma unroll
+        for (int u = 0; u < O; ++u)
+          if (((m >> (O - 1 - u)) & 1) && ((lm >> (2 * (O - 1 - u))) & 3) != 0) neg = !neg;
+        sum += neg ? -v[beta][m] : v[beta][m];
+      }
+      a.U[(j * NL + lm) * nb + b] = sum;
+    }
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) attr_init_reg_kernel(AttrArgs a) {
+  constexpr int NJ = 1 << (2 * R);
+  const int64_t nb = (int64_t)1 << a.n;
+  const int64_t nlm = (int64_t)1 << (2 * a.o);
+  const int64_t total = nlm * nb;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+    const int64_t b = i & (nb - 1);
+    const int64_t lm = i >> a.n;
+    double u[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) u[j] = a.U[(j * nlm + lm) * nb + b];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int sd = 1 << (2 * (R - 1 - t));  // stride of init digit t
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if ((j / sd) % 4 != 0) continue;
+        const double d0 = u[j], d1 = u[j + sd], d2 = u[j + 2 * sd], d3 = u[j + 3 * sd];
+        u[j] = d0 + d1;                       // I
+        u[j + sd] = 2.0 * d2 - d0 - d1;       // X
+        u[j + 2 * sd] = 2.0 * d3 - d0 - d1;   // Y
+        u[j + 3 * sd] = d0 - d1;              // Z
+      }
+    }
+    int64_t mrow = 0;
+    for (int q = 0; q < a.o; ++q) mrow += ((lm >> (2 * (a.o - 1 - q))) & 3) * a.meas_w[q];
+#pragma unroll
+    for (int li = 0; li < NJ; ++li) {
+      int64_t row = mrow;
+#pragma unroll
+      for (int t = 0; t < R; ++t) row += ((li >> (2 * (R - 1 - t))) & 3) * a.init_w[t];
+      a.E[row * nb + b] = u[li];
+    }
+  }
+}
+
 // Indirect launches size their grid for the largest shape and loop; a
 // moderate cap keeps the empty workgroups of smaller shapes cheap.
 unsigned grid_ind(int64_t total) {
@@ -437,10 +527,22 @@ hipError_t launch_attribute(const AttrLaunch& l, hipStream_t stream) {
   }
   const int64_t total = ((int64_t)1 << (2 * (l.r + l.o))) << l.n;
   const unsigned grid = grid_for(total);
-  hipLaunchKernelGGL(attr_meas_kernel, dim3(grid), dim3(256), 0, stream, a);
+  const dim3 gm(grid_for(((int64_t)1 << (2 * l.r)) << l.n)), gi(grid_for(((int64_t)1 << (2 * l.o)) << l.n));
+  switch (l.o) {
+    case 0: hipLaunchKernelGGL(attr_meas_reg_kernel<0>, gm, dim3(256), 0, stream, a); break;
+    case 1: hipLaunchKernelGGL(attr_meas_reg_kernel<1>, gm, dim3(256), 0, stream, a); break;
+    case 2: hipLaunchKernelGGL(attr_meas_reg_kernel<2>, gm, dim3(256), 0, stream, a); break;
+    default: hipLaunchKernelGGL(attr_meas_kernel, dim3(grid), dim3(256), 0, stream, a); break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(attr_init_kernel, dim3(grid), dim3(256), 0, stream, a);
+  switch (l.r) {
+    case 0: hipLaunchKernelGGL(attr_init_reg_kernel<0>, gi, dim3(256), 0, stream, a); break;
+    case 1: hipLaunchKernelGGL(attr_init_reg_kernel<1>, gi, dim3(256), 0, stream, a); break;
+    case 2: hipLaunchKernelGGL(attr_init_reg_kernel<2>, gi, dim3(256), 0, stream, a); break;
+    case 3: hipLaunchKernelGGL(attr_init_reg_kernel<3>, gi, dim3(256), 0, stream, a); break;
+    default: hipLaunchKernelGGL(attr_init_kernel, dim3(grid), dim3(256), 0, stream, a); break;
+  }
   return hipGetLastError();
 }
 

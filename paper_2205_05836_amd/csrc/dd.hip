@@ -415,10 +415,17 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
 
 hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
                                   const int64_t* count_dev, const int32_t* C_dev, int C_max,
-                                  double* out_val, uint64_t* out_idx, hipStream_t stream) {
+                                  double* stage_val, uint64_t* stage_idx, double* out_val,
+                                  uint64_t* out_idx, hipStream_t stream) {
   if (C_max < 1 || C_max > kDDMaxC) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream, cand_val, cand_idx,
-                     (int64_t)0, (int64_t)0, 0, out_val, out_idx, count_dev, C_dev, C_max);
+  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(kTopcStage), dim3(256), 0, stream, cand_val,
+                     cand_idx, (int64_t)0, (int64_t)0, 0, stage_val, stage_idx, count_dev, C_dev, C_max);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nc = (int64_t)kTopcStage * C_max;
+  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
+                     (const double*)stage_val, (const uint64_t*)stage_idx, nc, nc, 0, out_val, out_idx,
+                     nullptr, C_dev, C_max);
   return hipGetLastError();
 }
 

@@ -217,10 +217,13 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
                                 double* cand_val, uint64_t* cand_idx, int64_t cand_capacity,
                                 double* out_val, uint64_t* out_idx, hipStream_t stream);
 int64_t topk_indirect_capacity(int64_t max_count, int C_max);
-// Top-C (C = *C_dev) of *count_dev explicit candidate keys.
+// Top-C (C = *C_dev) of *count_dev explicit candidate keys, in two passes
+// through kTopcStage * C_max staged keys.
+constexpr int kTopcStage = 256;
 hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
                                   const int64_t* count_dev, const int32_t* C_dev, int C_max,
-                                  double* out_val, uint64_t* out_idx, hipStream_t stream);
+                                  double* stage_val, uint64_t* stage_idx, double* out_val,
+                                  uint64_t* out_idx, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Device-driven dynamic definition (Algorithm 1).  One recursion is a fixed

@@ -374,3 +374,33 @@ def test_32_qubit_chain_of_four_accuracy_matrix(prec):
         assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR)
     if prec == "fp16":
         _FP64_32Q.clear()
+
+
+# --- attribution: register-butterfly and general kernels ---------------------
+
+@pytest.mark.parametrize("r,o", [(0, 0), (0, 2), (1, 1), (2, 2), (3, 1), (3, 2), (4, 1), (1, 3), (2, 4)])
+def test_attribution_all_pass_shapes(r, o):
+    """Random (non-physical) variant tensors through every attribution kernel
+    shape: measured ends <= 2 and initialised ends <= 3 take the register
+    butterflies, larger counts the general kernels.  Slots interleave init,
+    output and measured roles, and cut ids are not in slot order."""
+    rng = np.random.default_rng(100 + 10 * r + o)
+    n = 3
+    w = r + o + n
+    roles = ["i"] * r + ["m"] * o + ["o"] * n
+    rng.shuffle(roles)
+    # an init slot may also be an output: make the first init slot one
+    cuts = list(rng.permutation(r + o))
+    init_cut, meas_cut = [-1] * w, [-1] * w
+    ci = iter(cuts)
+    for s, role in enumerate(roles):
+        if role == "i":
+            init_cut[s] = int(next(ci))
+        elif role == "m":
+            meas_cut[s] = int(next(ci))
+    sub = (w, init_cut, meas_cut)
+    V = rng.random((4 ** r, 3 ** o, 2 ** w))
+    ref = at.attribute(sub, V)
+    got = gpu_attribute(sub, V)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
