@@ -479,17 +479,25 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   return CQ_OK;
 }
 
+// Instances run on `lanes` parallel streams (graph branches) when none of
+// them stores bins: each lane then has its own copy of the shared region,
+// which is small without bin scratch.  Otherwise they run one after another.
+constexpr int kDDLanes = 4;
+
 cq_status dd_plan_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
                       bool bins_stored, std::vector<DDInstancePlan>& plans, int64_t& big,
-                      int64_t& total) {
+                      int& lanes, int64_t& total) {
   plans.assign(n_inst, DDInstancePlan());
   big = 0;
+  bool all_fused = true;
   for (int i = 0; i < n_inst; ++i) {
     cq_status st = dd_plan_instance(inst[i], p, bins_stored, plans[i]);
     if (st != CQ_OK) return st;
     big = std::max(big, plans[i].big);
+    all_fused = all_fused && plans[i].topc_step >= 0;
   }
-  total = align256(big) + (int64_t)n_inst * dd_ctrl(p.R).bytes;
+  lanes = all_fused ? std::min<int>(n_inst, kDDLanes) : 1;
+  total = (int64_t)lanes * align256(big) + (int64_t)n_inst * dd_ctrl(p.R).bytes;
   return CQ_OK;
 }
 
@@ -672,30 +680,79 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
   return CQ_OK;
 }
 
-cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
-                         const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                         int64_t big, hipStream_t stream) {
+// Streams and events of the parallel lanes; released after the call's final
+// synchronisation.
+struct DDLaneSet {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  ~DDLaneSet() {
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+};
+
+cq_status dd_enqueue_instance(int i, const cq_dd_params& p, const DDInstancePlan& D,
+                              void* const* bins_user, char* region, char* ctrl, hipStream_t stream) {
   const DDCtrl L = dd_ctrl(p.R);
-  for (int i = 0; i < n_inst; ++i) {
-    const DDInstancePlan& D = plans[i];
-    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
-    DDInit init;
-    std::memset(&init, 0, sizeof(init));
-    for (int c = 0; c < D.cm.n_sub; ++c) {
-      init.active[c] = D.s0[c].active;
-      init.merged[c] = D.s0[c].merged;
-      init.fixed[c] = D.s0[c].fixed;
-      init.fixed_vals[c] = D.s0[c].fixed_vals;
-    }
-    hipError_t e = launch_dd_init(reinterpret_cast<DDState*>(ctrl + L.state),
-                                  reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, init, stream);
-    if (e != hipSuccess) return hip_fail(e, "init launch");
-    for (int r = 0; r < p.R; ++r) {
-      void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
-      if (!bins && D.topc_step < 0) bins = ws + D.bins_off;
-      cq_status st = dd_enqueue_level(D, p, ws, ctrl, r, bins, stream);
+  DDInit init;
+  std::memset(&init, 0, sizeof(init));
+  for (int c = 0; c < D.cm.n_sub; ++c) {
+    init.active[c] = D.s0[c].active;
+    init.merged[c] = D.s0[c].merged;
+    init.fixed[c] = D.s0[c].fixed;
+    init.fixed_vals[c] = D.s0[c].fixed_vals;
+  }
+  hipError_t e = launch_dd_init(reinterpret_cast<DDState*>(ctrl + L.state),
+                                reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, init, stream);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  for (int r = 0; r < p.R; ++r) {
+    void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
+    if (!bins && D.topc_step < 0) bins = region + D.bins_off;
+    cq_status st = dd_enqueue_level(D, p, region, ctrl, r, bins, stream);
+    if (st != CQ_OK) return st;
+  }
+  return CQ_OK;
+}
+
+// Enqueues the batch behind `stream`: lane l runs instances l, l + lanes, ...
+// on a stream of its own forked from and joined back into `stream`.
+cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p,
+                         const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
+                         int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
+  const DDCtrl L = dd_ctrl(p.R);
+  char* ctrl0 = ws + (int64_t)lanes * align256(big);
+  if (lanes <= 1) {
+    for (int i = 0; i < n_inst; ++i) {
+      cq_status st = dd_enqueue_instance(i, p, plans[i], bins_user, ws, ctrl0 + (int64_t)i * L.bytes, stream);
       if (st != CQ_OK) return st;
     }
+    return CQ_OK;
+  }
+  hipEvent_t fork = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "lane event");
+  ls.events.push_back(fork);
+  e = hipEventRecord(fork, stream);
+  if (e != hipSuccess) return hip_fail(e, "lane fork");
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "lane stream");
+    ls.streams.push_back(s);
+    e = hipStreamWaitEvent(s, fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "lane wait");
+    char* region = ws + (int64_t)l * align256(big);
+    for (int i = l; i < n_inst; i += lanes) {
+      cq_status st = dd_enqueue_instance(i, p, plans[i], bins_user, region, ctrl0 + (int64_t)i * L.bytes, s);
+      if (st != CQ_OK) return st;
+    }
+    hipEvent_t join = nullptr;
+    e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "lane event");
+    ls.events.push_back(join);
+    e = hipEventRecord(join, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
+    if (e != hipSuccess) return hip_fail(e, "lane join");
   }
   return CQ_OK;
 }
@@ -714,9 +771,9 @@ struct DDGraph {
 };
 
 // Captures the batch on a private stream and launches it once on `stream`.
-cq_status dd_run_graph(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
+cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p,
                        const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                       int64_t big, hipStream_t stream, DDGraph& G) {
+                       int64_t big, int lanes, hipStream_t stream, DDGraph& G, DDLaneSet& ls) {
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "capture stream");
@@ -725,7 +782,7 @@ cq_status dd_run_graph(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_p
     (void)hipStreamDestroy(cs);
     return hip_fail(e, "begin capture");
   }
-  cq_status st = dd_enqueue_all(n_inst, inst, p, plans, bins_user, ws, big, cs);
+  cq_status st = dd_enqueue_all(n_inst, p, plans, bins_user, ws, big, lanes, cs, ls);
   e = hipStreamEndCapture(cs, &G.graph);
   (void)hipStreamDestroy(cs);
   if (st != CQ_OK) return st;
@@ -747,7 +804,8 @@ extern "C" cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* 
   if (n_inst < 1 || !inst || !params || !bytes) return fail(CQ_ERR_ARG, "null or empty argument");
   std::vector<DDInstancePlan> plans;
   int64_t big = 0, total = 0;
-  cq_status st = dd_plan_all(n_inst, inst, *params, bins_stored != 0, plans, big, total);
+  int lanes = 1;
+  cq_status st = dd_plan_all(n_inst, inst, *params, bins_stored != 0, plans, big, lanes, total);
   if (st != CQ_OK) return st;
   *bytes = (size_t)total;
   return CQ_OK;
@@ -765,7 +823,8 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   // validate and plan everything before the first launch
   std::vector<DDInstancePlan> plans;
   int64_t big = 0, total = 0;
-  cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, plans, big, total);
+  int lanes = 1;
+  cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, plans, big, lanes, total);
   if (st != CQ_OK) return st;
   if (!workspace || (int64_t)workspace_bytes < total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
   if (bins)
@@ -777,22 +836,24 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   char* ws = static_cast<char*>(workspace);
   const DDCtrl L = dd_ctrl(params->R);
   // device programs (host images stay alive until the final synchronisation)
+  char* ctrl0 = ws + (int64_t)lanes * align256(big);
   std::vector<DDProgram> progs(n_inst);
   for (int i = 0; i < n_inst; ++i) {
-    dd_program(plans[i], inst[i], *params, ws, progs[i]);
-    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
+    dd_program(plans[i], inst[i], *params, ws + (int64_t)(i % lanes) * align256(big), progs[i]);
+    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
     hipError_t e = hipMemcpyAsync(ctrl + L.prog, &progs[i], sizeof(DDProgram), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "program upload");
   }
+  DDLaneSet lane_set;  // destroyed after the graph (declared first)
   DDGraph graph;
   if (params->launch == CQ_DD_GRAPH)
-    st = dd_run_graph(n_inst, inst, *params, plans, bins, ws, big, stream, graph);
+    st = dd_run_graph(n_inst, *params, plans, bins, ws, big, lanes, stream, graph, lane_set);
   else
-    st = dd_enqueue_all(n_inst, inst, *params, plans, bins, ws, big, stream);
+    st = dd_enqueue_all(n_inst, *params, plans, bins, ws, big, lanes, stream, lane_set);
   if (st != CQ_OK) return st;
   std::vector<int32_t> done(n_inst, 0);
   for (int i = 0; i < n_inst; ++i) {
-    char* ctrl = ws + align256(big) + (int64_t)i * L.bytes;
+    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
     hipError_t e = hipMemcpyAsync(records + (size_t)i * params->R, ctrl + L.recs,
                                   sizeof(cq_dd_record) * params->R, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess)

@@ -244,3 +244,22 @@ def test_fused_top_c_matches_stored_bins(prec):
     fused, done_f = m.cq_reconstruct_dd(insts, prec, R)
     assert done_s == done_f
     assert stored == fused
+
+
+def test_parallel_lanes_graph_and_direct_agree_with_single_instances():
+    """Without bin buffers the instances of a batch run on parallel lanes
+    (graph branches): both launch modes must reproduce, record for record,
+    each instance run on its own."""
+    m = cq()
+    insts = []
+    for i, (bonds, ns) in enumerate([([2, 1], [5, 6, 4]), ([1, 1, 1], [4, 3, 4, 3]), ([0, 2], [4, 5, 5]),
+                                     ([1, 2], [5, 4, 5]), ([2, 2], [4, 5, 4]), ([1, 0, 1], [3, 4, 4, 3])]):
+        cm, E = syn.chain_instance(120 + i, bonds, ns)
+        M = [2] * len(ns)
+        insts.append(instance(cm, E, dd.initial_states(cm, M), M))
+    R = 4
+    alone = [m.cq_reconstruct_dd([x], "fp32", R) for x in insts]
+    for launch in ("graph", "direct"):
+        recs, done = m.cq_reconstruct_dd(insts, "fp32", R, launch=launch)
+        assert done == [d[1][0] for d in alone]
+        assert recs == [d[0][0] for d in alone]
