@@ -395,6 +395,8 @@ struct DDInstancePlan {
   int64_t plan_off = 0, bins_off = 0, bins_bytes = 0, cand_off = 0, cand_cap = 0;
   int topc_step = -1;  // the GEMM that selects top-C instead of storing bins, or -1
   int64_t stage_off = 0;
+  int64_t seg_a = 0, seg_b = 0, bound_a_off = 0, bound_b_off = 0, bound_u_off = 0, list_off = 0;
+  int64_t warm_out_off = 0;
   int64_t big = 0;  // bytes of the shared region this instance needs
   int64_t max_count = 0;
   std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
@@ -475,6 +477,23 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   off = align256(off + D.cand_cap * 16);
   D.stage_off = off;  // fused top-C: keys staged between the two selection passes
   off = align256(off + (int64_t)kTopcStage * kDDMaxC * 16);  // values, then indices
+  if (D.topc_step >= 0) {
+    // tile pruning buffers of the top-C GEMM, sized for the largest shape
+    const GemmStep& g = D.plan.steps[D.topc_step].g;
+    D.seg_a = (g.sAz ? g.Z : 1) * g.K * ((g.M + 127) / 128);
+    D.seg_b = (g.sBz ? g.Z : 1) * g.K * ((g.N + 127) / 128);
+    const int64_t tiles = D.step_max[D.topc_step];
+    D.bound_a_off = off;
+    off = align256(off + D.seg_a * 4);
+    D.bound_b_off = off;
+    off = align256(off + D.seg_b * 4);
+    D.bound_u_off = off;
+    off = align256(off + tiles * 4);
+    D.list_off = off;
+    off = align256(off + tiles * 8);
+    D.warm_out_off = off;
+    off = align256(off + kDDMaxC * 16);
+  }
   D.big = off;
   return CQ_OK;
 }
@@ -536,6 +555,14 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
   P.topc_step = D.topc_step;
   P.cand_v = reinterpret_cast<double*>(ws + D.cand_off);
   P.cand_i = reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8);
+  if (D.topc_step >= 0) {
+    P.bound_a = reinterpret_cast<float*>(ws + D.bound_a_off);
+    P.bound_b = reinterpret_cast<float*>(ws + D.bound_b_off);
+    P.bound_u = reinterpret_cast<float*>(ws + D.bound_u_off);
+    P.tile_list = reinterpret_cast<uint64_t*>(ws + D.list_off);
+    P.warm_v = reinterpret_cast<double*>(ws + D.warm_out_off);
+    P.warm_i = reinterpret_cast<uint64_t*>(ws + D.warm_out_off + kDDMaxC * 8);
+  }
   char* pw = ws + D.plan_off;
   for (size_t t = 0; t < plan.tensors.size(); ++t) {
     const TensorRef& T = plan.tensors[t];
@@ -649,9 +676,32 @@ cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char*
   }
   for (size_t si = 0; si < D.plan.steps.size(); ++si) {
     const Step& s = D.plan.steps[si];
-    if (s.is_gemm) {
+    if (s.is_gemm && (int)si == D.topc_step) {
+      // fused top-C with tile pruning (see launch_tile_bounds)
+      const int64_t tiles = D.step_max[si];
+      e = launch_tile_bounds(&lv->gemm[si], tensor_dtype(D.plan, s.g.a, prec), is_f16(prec),
+                             reinterpret_cast<float*>((ws + D.bound_a_off)),
+                             reinterpret_cast<float*>((ws + D.bound_b_off)),
+                             reinterpret_cast<float*>(ws + D.bound_u_off), D.seg_a, D.seg_b,
+                             tiles, stream);
+      if (e == hipSuccess)
+        e = launch_tile_warm(reinterpret_cast<const float*>(ws + D.bound_u_off), &st->n_tiles,
+                             &st->warm_count, reinterpret_cast<uint64_t*>(ws + D.warm_out_off + kDDMaxC * 8),
+                             (int)std::min<int64_t>(tiles, kDDMaxC), stream);
+      if (e == hipSuccess)
+        e = launch_gemm_indirect(prec, &lv->topc_warm, std::min<int64_t>(tiles, kDDMaxC),
+                                 tensor_dtype(D.plan, s.g.c, prec), false, true, stream);
+      if (e == hipSuccess)
+        e = launch_tile_compact(reinterpret_cast<const float*>(ws + D.bound_u_off), &st->n_tiles,
+                                &st->topc_thr, reinterpret_cast<uint64_t*>(ws + D.list_off),
+                                &st->list_count, tiles, stream);
+      if (e == hipSuccess)
+        e = launch_gemm_indirect(prec, &lv->gemm[si], tiles, tensor_dtype(D.plan, s.g.c, prec), false,
+                                 true, stream);
+      if (e != hipSuccess) return hip_fail(e, "top-C GEMM launch");
+    } else if (s.is_gemm) {
       e = launch_gemm_indirect(prec, &lv->gemm[si], D.step_max[si], tensor_dtype(D.plan, s.g.c, prec),
-                               false, (int)si == D.topc_step, stream);
+                               false, false, stream);
       if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
     } else {
       e = launch_permute_indirect(&lv->perm[si], tensor_dtype(D.plan, s.p.src, prec),

@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) topk_scan_kernel(const T* __restrict__ va
 }
 
 int64_t topk_blocks(int64_t count) {
-  int64_t b = (count + 65535) / 65536;
+  int64_t b = (count + 8191) / 8192;
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   return b;
@@ -387,6 +387,92 @@ hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream
   return hipGetLastError();
 }
 
+// Second pass for small key sets (count <= kSelCap): one workgroup; each
+// thread holds up to 64 keys in registers, each wave takes its C best by C
+// rounds of a wave arg-max, wave 0 merges the four lists the same way.
+constexpr int kSelCap = 256 * 64;
+
+__device__ inline Key wave_best_key(Key k) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    const Key o{__shfl_xor(k.v, s), (uint64_t)__shfl_xor((long long)k.i, s)};
+    if (better(o, k)) k = o;
+  }
+  return k;
+}
+
+__global__ void __launch_bounds__(256) select_small_kernel(const double* __restrict__ vals,
+                                                           const uint64_t* __restrict__ idxs,
+                                                           int64_t count, const int32_t* __restrict__ C_dev,
+                                                           double* __restrict__ out_v,
+                                                           uint64_t* __restrict__ out_i) {
+  __shared__ Key wk[4][kDDMaxC];
+  __shared__ int wn[4];
+  const int C = *C_dev;
+  if (C <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  Key h[64];
+  uint64_t live = 0;
+  // clamped, unconditional loads: all 128 of a thread are in flight together
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    const int64_t x = (int64_t)j * 256 + threadIdx.x;
+    const int64_t xc = x < count ? x : 0;
+    h[j] = Key{vals[xc], idxs[xc]};
+  }
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    const int64_t x = (int64_t)j * 256 + threadIdx.x;
+    if (x >= count) h[j] = worst_key();
+    if (better(h[j], worst_key())) live |= 1ull << j;
+  }
+  int got = 0;
+  for (int round = 0; round < C; ++round) {
+    if (__ballot(live != 0) == 0) break;
+    Key best = worst_key();
+    int bj = -1;
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (((live >> j) & 1) && better(h[j], best)) {
+        best = h[j];
+        bj = j;
+      }
+    const Key w = wave_best_key(best);
+    if (lane == 0) wk[wave][got] = w;
+    if (bj >= 0 && best.i == w.i && best.v == w.v) live &= ~(1ull << bj);
+    ++got;
+  }
+  if (lane == 0) wn[wave] = got;
+  __syncthreads();
+  if (wave != 0) return;
+  Key m[4];
+  uint32_t ml = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    m[w] = worst_key();
+    if (lane < wn[w]) {
+      m[w] = wk[w][lane];
+      ml |= 1u << w;
+    }
+  }
+  for (int n = 0; n < C; ++n) {
+    Key best = worst_key();
+    int bw = -1;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      if (((ml >> w) & 1) && better(m[w], best)) {
+        best = m[w];
+        bw = w;
+      }
+    const Key win = wave_best_key(best);
+    if (lane == 0) {
+      out_v[n] = win.v;
+      out_i[n] = win.i;
+    }
+    if (bw >= 0 && best.i == win.i && best.v == win.v) ml &= ~(1u << bw);
+  }
+}
+
 int64_t topk_indirect_capacity(int64_t max_count, int C_max) {
   return topk_blocks(max_count) * C_max;
 }
@@ -407,9 +493,13 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nc = blocks * C_max;
-  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
-                     (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
-                     out_idx, nullptr, C_dev, C_max);
+  if (nc <= kSelCap)
+    hipLaunchKernelGGL(select_small_kernel, dim3(1), dim3(256), 0, stream, (const double*)cand_val,
+                       (const uint64_t*)cand_idx, nc, C_dev, out_val, out_idx);
+  else
+    hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
+                       (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
+                       out_idx, nullptr, C_dev, C_max);
   return hipGetLastError();
 }
 
@@ -422,10 +512,9 @@ hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_i
                      cand_idx, (int64_t)0, (int64_t)0, 0, stage_val, stage_idx, count_dev, C_dev, C_max);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t nc = (int64_t)kTopcStage * C_max;
-  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
-                     (const double*)stage_val, (const uint64_t*)stage_idx, nc, nc, 0, out_val, out_idx,
-                     nullptr, C_dev, C_max);
+  const int64_t nc = (int64_t)kTopcStage * C_max;  // <= kSelCap
+  hipLaunchKernelGGL(select_small_kernel, dim3(1), dim3(256), 0, stream, (const double*)stage_val,
+                     (const uint64_t*)stage_idx, nc, C_dev, out_val, out_idx);
   return hipGetLastError();
 }
 
@@ -594,6 +683,9 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.rowexp = nullptr;
       g.colexp = nullptr;
       const bool tc_here = s == P->topc_step;
+      g.topc_publish_only = 0;
+      g.tile_list = tc_here ? P->tile_list : nullptr;
+      g.tile_count = tc_here ? &st->list_count : nullptr;
       g.topc_thr = tc_here ? &st->topc_thr : nullptr;
       g.topc_count = tc_here ? &st->topc_count : nullptr;
       g.topc_C = tc_here ? &st->C : nullptr;
@@ -626,6 +718,20 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       p.alpha = Q.alpha;
       p.nfac = 0;
     }
+  }
+  if (P->topc_step >= 0) {
+    // tile pruning: the 64 tiles with the largest bounds raise the threshold
+    // first, then only tiles whose bound reaches it are multiplied
+    const GemmArgs& gm = lv->gemm[P->topc_step];
+    st->n_tiles = gm.tiles;
+    st->warm_C = (int)(gm.tiles < 64 ? gm.tiles : 64);
+    st->warm_count = st->warm_C;
+    st->list_count = 0;
+    GemmArgs& w = lv->topc_warm;
+    w = gm;
+    w.tile_list = P->warm_i;
+    w.tile_count = &st->warm_count;
+    w.topc_publish_only = 1;
   }
   RefineArgs& f = lv->refine;
   f.n_sub = ns;

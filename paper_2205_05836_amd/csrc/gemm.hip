@@ -39,17 +39,17 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total) {
 // Kernels take their arguments by value, or -- for shapes decided on the
 // device -- from device memory through `gp`; workgroups beyond the tile count
 // of an indirect launch exit at once.
-#define CQ_LOAD_GEMM_ARGS                                       \
-  const GemmArgs g = gp ? *gp : gv;                             \
-  if (gp && (int64_t)blockIdx.x >= g.tiles) return;
+#define CQ_LOAD_GEMM_ARGS                                                        \
+  const GemmArgs g = gp ? *gp : gv;                                              \
+  if (gp && (int64_t)blockIdx.x >= (g.tile_list ? *g.tile_count : g.tiles)) return; \
+  if (gp && g.tile_list && g.tile_list[blockIdx.x] >= (uint64_t)g.tiles) return;
 
 struct TileCoord {
   int64_t z, m0, n0;
 };
 
 template <int BM, int BN>
-__device__ inline TileCoord tile_coord(const GemmArgs& g) {
-  const int64_t t = xcd_tile(blockIdx.x, g.tiles);
+__device__ inline TileCoord tile_coord_of(const GemmArgs& g, int64_t t) {
   TileCoord c;
   if (g.m_fastest) {
     const int64_t tm = t % g.tilesM, r = t / g.tilesM;
@@ -63,6 +63,12 @@ __device__ inline TileCoord tile_coord(const GemmArgs& g) {
     c.n0 = tn * BN;
   }
   return c;
+}
+
+template <int BM, int BN>
+__device__ inline TileCoord tile_coord(const GemmArgs& g) {
+  return tile_coord_of<BM, BN>(g, g.tile_list ? (int64_t)g.tile_list[blockIdx.x]
+                                              : xcd_tile(blockIdx.x, g.tiles));
 }
 
 // Loads 8 consecutive elements of row k (columns c0..c0+7), zero outside
@@ -251,9 +257,9 @@ __device__ __forceinline__ void topc_tile(const GemmArgs& g, int64_t z, int64_t 
       if (bw >= 0 && best.i == win.i) hl &= ~(1u << bw);
     }
     if (lane == 0) {
-      nout = n;
       if (n == C) atomicMax(g.topc_thr, ord_key(double(outk[C - 1].v)));
-      base = atomicAdd(g.topc_count, (unsigned long long)n);
+      nout = g.topc_publish_only ? 0 : n;
+      base = g.topc_publish_only ? 0 : atomicAdd(g.topc_count, (unsigned long long)n);
     }
   }
   __syncthreads();
@@ -928,6 +934,9 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.topc_C = nullptr;
   a.topc_v = nullptr;
   a.topc_i = nullptr;
+  a.topc_publish_only = 0;
+  a.tile_list = nullptr;
+  a.tile_count = nullptr;
   a.tilesM = (g.M + 127) / 128;
   a.tilesN = (g.N + 127) / 128;
   a.tiles = a.tilesM * a.tilesN * g.Z;
@@ -960,6 +969,162 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
                                    : dispatch_h16<3, true>(a, g.tc, nt, stream);
   }
   return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <int KIND>  // 0 FP64, 1 FP32, 2 BF16 planes, 3 FP16 planes
+__device__ inline double operand_at(const void* hi, const void* lo, int64_t i) {
+  if constexpr (KIND == 0) return static_cast<const double*>(hi)[i];
+  else if constexpr (KIND == 1) return static_cast<const float*>(hi)[i];
+  else {
+    const uint16_t* h = static_cast<const uint16_t*>(hi);
+    const uint16_t* l = static_cast<const uint16_t*>(lo);
+    double v = double(from_h16<KIND == 3>(h[i]));
+    if (l) v += double(from_h16<KIND == 3>(l[i]));
+    return v;
+  }
+}
+
+// One wave per 128-element row segment of A (then of B): its max |value|.
+template <int KIND>
+__global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __restrict__ gp, float* amax,
+                                                          float* bmax) {
+  const GemmArgs g = *gp;
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t Z = g.tilesM * g.tilesN > 0 ? g.tiles / (g.tilesM * g.tilesN) : 0;
+  const int64_t za_n = g.sAz ? Z : 1, zb_n = g.sBz ? Z : 1;
+  const int64_t na = za_n * g.K * g.tilesM, nb = zb_n * g.K * g.tilesN;
+  if (seg >= na + nb) return;  // whole waves exit together
+  const bool isA = seg < na;
+  const int64_t s = isA ? seg : seg - na;
+  const int64_t tl = isA ? g.tilesM : g.tilesN;
+  const int64_t t = s % tl, zk = s / tl, k = zk % g.K, z = zk / g.K;
+  const int64_t base = isA ? z * g.sAz + k * g.sAk : z * g.sBz + k * g.sBk;
+  const int64_t lim = isA ? g.M : g.N;
+  const void* hi = isA ? g.A : g.B;
+  const void* lo = isA ? g.A_lo : g.B_lo;
+  double m = 0.0;
+  for (int e = lane; e < 128; e += 64) {
+    const int64_t c = t * 128 + e;
+    if (c < lim) m = fmax(m, fabs(operand_at<KIND>(hi, lo, base + c)));
+  }
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) (isA ? amax : bmax)[s] = __double2float_ru(m);
+}
+
+__global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restrict__ gp,
+                                                         const float* __restrict__ amax,
+                                                         const float* __restrict__ bmax, float* U) {
+  const GemmArgs g = *gp;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.tiles) return;
+  const TileCoord c = tile_coord_of<128, 128>(g, t);
+  const int64_t mt = c.m0 / 128, nt = c.n0 / 128;
+  const int64_t za = g.sAz ? c.z : 0, zb = g.sBz ? c.z : 0;
+  double u = 0.0;
+  for (int64_t k = 0; k < g.K; ++k)
+    u += double(amax[(za * g.K + k) * g.tilesM + mt]) * double(bmax[(zb * g.K + k) * g.tilesN + nt]);
+  // the kernels accumulate in FP32 (or FP64): allow K roundings of 2^-24
+  u *= g.alpha * (1.0 + double(g.K + 4) * 0x1p-23);
+  U[t] = __double2float_ru(u);
+}
+
+// Warm-up tiles: block b of `warm` takes the tile with the largest bound in
+// slice b of the tiles (any tiles would do: they only raise the threshold).
+__global__ void __launch_bounds__(256) tile_warm_kernel(const float* __restrict__ U,
+                                                        const int64_t* __restrict__ n_tiles,
+                                                        const int64_t* __restrict__ warm,
+                                                        uint64_t* list) {
+  __shared__ float bv[4];
+  __shared__ uint64_t bi[4];
+  const int64_t n = *n_tiles, w = *warm;
+  if ((int64_t)blockIdx.x >= w) return;
+  const int64_t chunk = n / w;
+  const int64_t begin = blockIdx.x * chunk;
+  const int64_t end = (int64_t)blockIdx.x == w - 1 ? n : begin + chunk;
+  float v = -INFINITY;
+  uint64_t id = (uint64_t)begin;
+  for (int64_t t = begin + threadIdx.x; t < end; t += blockDim.x)
+    if (U[t] > v) {
+      v = U[t];
+      id = (uint64_t)t;
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float ov = __shfl_xor(v, o);
+    const uint64_t oi = (uint64_t)__shfl_xor((long long)id, o);
+    if (ov > v || (ov == v && oi < id)) {
+      v = ov;
+      id = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    bv[wave] = v;
+    bi[wave] = id;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k)
+      if (bv[k] > v || (bv[k] == v && bi[k] < id)) {
+        v = bv[k];
+        id = bi[k];
+      }
+    list[blockIdx.x] = id;
+  }
+}
+
+__global__ void __launch_bounds__(256) tile_compact_kernel(const float* __restrict__ U,
+                                                           const int64_t* __restrict__ n_tiles,
+                                                           const unsigned long long* __restrict__ thr,
+                                                           uint64_t* list, int64_t* count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *n_tiles) return;
+  if (double(U[t]) >= ord_val(*thr)) {
+    const unsigned long long p = atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
+    list[p] = (uint64_t)t;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tile_bounds(const GemmArgs* dev, DType t, bool f16, float* amax, float* bmax,
+                              float* U, int64_t max_seg_a, int64_t max_seg_b, int64_t max_tiles,
+                              hipStream_t stream) {
+  const int64_t segs = max_seg_a + max_seg_b;
+  if (segs <= 0 || max_tiles <= 0) return hipSuccess;
+  const dim3 g1((unsigned)((segs * 64 + 255) / 256));
+  switch (t) {
+    case DType::F64: hipLaunchKernelGGL(tile_rowmax_kernel<0>, g1, dim3(256), 0, stream, dev, amax, bmax); break;
+    case DType::F32: hipLaunchKernelGGL(tile_rowmax_kernel<1>, g1, dim3(256), 0, stream, dev, amax, bmax); break;
+    default:
+      if (f16) hipLaunchKernelGGL(tile_rowmax_kernel<3>, g1, dim3(256), 0, stream, dev, amax, bmax);
+      else hipLaunchKernelGGL(tile_rowmax_kernel<2>, g1, dim3(256), 0, stream, dev, amax, bmax);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tile_bound_kernel, dim3((unsigned)((max_tiles + 255) / 256)), dim3(256), 0, stream,
+                     dev, (const float*)amax, (const float*)bmax, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_warm(const float* U, const int64_t* n_tiles, const int64_t* warm,
+                            uint64_t* list, int max_warm, hipStream_t stream) {
+  if (max_warm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_warm_kernel, dim3((unsigned)max_warm), dim3(256), 0, stream, U, n_tiles, warm,
+                     list);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_compact(const float* U, const int64_t* n_tiles,
+                               const unsigned long long* thr_key, uint64_t* list,
+                               int64_t* count, int64_t max_tiles, hipStream_t stream) {
+  if (max_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_compact_kernel, dim3((unsigned)((max_tiles + 255) / 256)), dim3(256), 0,
+                     stream, U, n_tiles, thr_key, list, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,

@@ -68,7 +68,26 @@ struct GemmArgs {
   const int32_t* topc_C;
   double* topc_v;
   uint64_t* topc_i;
+  int topc_publish_only;           // raise the threshold only, append nothing
+  // Optional tile list: workgroup b takes tile tile_list[b] if b < *tile_count.
+  const uint64_t* tile_list;
+  const int64_t* tile_count;
 };
+
+// Tile pruning for the fused top-C (dynamic definition).  For the GEMM at
+// `dev`: amax[(za * K + k) * tilesM + mt] = max |A| over the rows of tile mt
+// (likewise bmax), then U[t] >= alpha * sum_k amax * bmax, an upper bound on
+// every output of tile t (inflated for FP32 accumulation, rounded up).
+hipError_t launch_tile_bounds(const GemmArgs* dev, DType t, bool f16, float* amax, float* bmax,
+                              float* U, int64_t max_seg_a, int64_t max_seg_b, int64_t max_tiles,
+                              hipStream_t stream);
+// list[b] <- the tile with the largest bound in slice b of *warm slices.
+hipError_t launch_tile_warm(const float* U, const int64_t* n_tiles, const int64_t* warm,
+                            uint64_t* list, int max_warm, hipStream_t stream);
+// list <- the tiles t < *n_tiles with U[t] >= the threshold, *count their number.
+hipError_t launch_tile_compact(const float* U, const int64_t* n_tiles,
+                               const unsigned long long* thr_key, uint64_t* list,
+                               int64_t* count, int64_t max_tiles, hipStream_t stream);
 
 // Launches `max_tiles` workgroups of the precision's GEMM kernel reading its
 // arguments from device memory (`dev`); surplus workgroups exit.  Operands and
@@ -287,6 +306,13 @@ struct DDProgram {
   int32_t pad2;
   double* cand_v;                            // its candidate buffers
   uint64_t* cand_i;
+  // tile pruning of that GEMM (see launch_tile_bounds)
+  float* bound_a;
+  float* bound_b;
+  float* bound_u;
+  uint64_t* tile_list;
+  double* warm_v;                            // the 64 tiles with the largest bounds
+  uint64_t* warm_i;
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -315,6 +341,10 @@ struct DDState {
   int64_t count;                 // bins of the recursion
   unsigned long long topc_thr;   // fused top-C: running threshold (order-preserving key)
   unsigned long long topc_count; // fused top-C: candidates appended
+  int64_t n_tiles;               // fused top-C: tiles of the GEMM
+  int64_t warm_count;            // tiles evaluated first (largest bounds)
+  int64_t list_count;            // tiles whose bound reaches the threshold
+  int32_t warm_C, pad4;
   uint64_t zero_idx;             // 0: the single bin of the total
   double total;
   double top_val[kDDMaxC];
@@ -328,6 +358,7 @@ struct DDLevel {  // descriptors of the current recursion
   MergeArgs rowsum[CQ_MAX_SUBCIRCUITS];
   PrepArgs prep[CQ_MAX_SUBCIRCUITS];
   GemmArgs gemm[kDDMaxSteps];
+  GemmArgs topc_warm;            // the top-C GEMM over the warm-up tiles
   PermArgs perm[kDDMaxSteps];
   RefineArgs refine;
 };
