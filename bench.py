@@ -379,6 +379,7 @@ def main():
         result["dd"] = dd_leg(torch, cq, dd_forms, args.dd_runs)
         out = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
         cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
+    result["autotune"] = cq.cq_autotune_json()
     if not args.skip_attribution:
         result["attribution"] = attribution_leg(torch, cq)
         torch.cuda.empty_cache()

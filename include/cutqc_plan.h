@@ -49,6 +49,29 @@ cq_status cq_profile_enable(int32_t on);
  * ms, flops: host, cap entries each.  *count = records that were pending. */
 cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap, int32_t* count);
 
+/* GEMM autotuner for the full-definition label GEMMs.  The first launch of
+ * each GEMM shape (outside stream capture, at least 64 output tiles) times
+ * every kernel variant twice on the caller's stream and keeps the fastest for
+ * that shape; that call synchronises the stream.  Variant v: bit 0 flips the
+ * tile raster order (M- or N-fastest); v >> 1 picks, for the 16-bit forms,
+ * the asynchronous LDS-staged kernel with its default ring depth (0), with
+ * the other depth (1), or the register-path kernel (2).  FP32 and FP64 have
+ * variants 0 and 1; 16-bit forms 0..5 (2..5 only where the asynchronous
+ * kernel's alignment holds).  Every variant computes the same sums.
+ *
+ * mode: 0 = variant 0 always (cached choices ignored); 1 = tune (the
+ * default, also set by the environment variable CQ_AUTOTUNE unless it starts
+ * with '0'); 2 + v = variant v always where it applies, else 0 (for tests).
+ * Negative modes act as 0.  Process-wide; the cache is guarded by a mutex.
+ * Always returns CQ_OK. */
+cq_status cq_autotune_enable(int32_t mode);
+
+/* The cached choices as JSON:
+ *   [{"prec": ..., "M", "N", "K", "Z", "variant": v, "ms": [[v, ms], ...]}, ...]
+ * *needed receives the length including the terminating NUL; with buf null
+ * or buf_bytes below it, nothing is written and CQ_ERR_ARG is returned. */
+cq_status cq_autotune_json(char* buf, size_t buf_bytes, size_t* needed);
+
 #ifdef __cplusplus
 }
 #endif

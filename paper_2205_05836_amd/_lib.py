@@ -16,7 +16,8 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_split": 3, "fp16": 4, "fp16_
 MAX_SUBCIRCUITS = 8
 MAX_DD_R = 16
 
-EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json",
+EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
+            "cq_autotune_json",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
             "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd"]
@@ -95,6 +96,10 @@ def lib():
                                C.POINTER(C.c_size_t)]
     L.cq_profile_enable.restype = st
     L.cq_profile_enable.argtypes = [C.c_int32]
+    L.cq_autotune_enable.restype = st
+    L.cq_autotune_enable.argtypes = [C.c_int32]
+    L.cq_autotune_json.restype = st
+    L.cq_autotune_json.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.cq_profile_read.restype = st
     L.cq_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.c_int32, C.POINTER(C.c_int32)]

@@ -237,6 +237,22 @@ def cq_plan_json(subs, prec="fp64", out_bits=None, out_perm=None):
     return json.loads(buf.value.decode())
 
 
+def cq_autotune_enable(on=True, variant=None):
+    """Turn GEMM autotuning on or off; ``variant=v`` forces variant v."""
+    mode = 2 + int(variant) if variant is not None else (1 if on else 0)
+    check(lib().cq_autotune_enable(mode))
+
+
+def cq_autotune_json():
+    """The autotuner's cached choices (list of dicts)."""
+    import json
+    need = C.c_size_t()
+    lib().cq_autotune_json(None, 0, C.byref(need))
+    buf = C.create_string_buffer(need.value)
+    check(lib().cq_autotune_json(buf, need.value, C.byref(need)))
+    return json.loads(buf.value.decode())
+
+
 def cq_profile_enable(on=True):
     check(lib().cq_profile_enable(1 if on else 0))
 

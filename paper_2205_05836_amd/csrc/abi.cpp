@@ -1023,3 +1023,17 @@ extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int
   }
   return st;
 }
+
+extern "C" cq_status cq_autotune_enable(int32_t mode) {
+  autotune_set(mode);
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_autotune_json(char* buf, size_t buf_bytes, size_t* needed) {
+  if (!needed) return fail(CQ_ERR_ARG, "null argument");
+  const std::string js = autotune_json();
+  *needed = js.size() + 1;
+  if (!buf || buf_bytes < js.size() + 1) return fail(CQ_ERR_ARG, "buffer too small");
+  std::memcpy(buf, js.c_str(), js.size() + 1);
+  return CQ_OK;
+}

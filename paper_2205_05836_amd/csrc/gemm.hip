@@ -17,6 +17,12 @@
 // that each of the 8 XCDs, each with its own L2, receives a contiguous range.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "kernels.hpp"
 
@@ -890,10 +896,20 @@ bool h16_async_ok(const GemmArgs& a, DType tc) {
   return sizes && al(a.A) && al(a.A_lo) && al(a.B) && al(a.B_lo) && al(a.C) && al(a.C_lo);
 }
 
+// Variant `impl` of the 16-bit launch: 0 = asynchronous kernel with its
+// default ring depth, 1 = the other depth, 2 = register-path kernel.
 template <int SPLIT, bool F16>
-hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s) {
+hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int impl = 0) {
   constexpr int NS = SPLIT == 3 ? 2 : 3;
-  if (h16_async_ok(a, tc)) {
+  constexpr int NS2 = SPLIT == 3 ? 3 : 2;
+  if (impl == 1 && h16_async_ok(a, tc)) {
+    if (tc == DType::F32) {
+      if (nt) return launch(gemm_h16a_kernel<SPLIT, F16, 1, NS2>, a, s);
+      return launch(gemm_h16a_kernel<SPLIT, F16, 0, NS2>, a, s);
+    }
+    return launch(gemm_h16a_kernel<SPLIT, F16, 2, NS2>, a, s);
+  }
+  if (impl != 2 && h16_async_ok(a, tc)) {
     if (tc == DType::F32) {
       if (nt) return launch(gemm_h16a_kernel<SPLIT, F16, 1, NS>, a, s);
       return launch(gemm_h16a_kernel<SPLIT, F16, 0, NS>, a, s);
@@ -905,6 +921,71 @@ hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s) {
     return launch(gemm_h16_kernel<SPLIT, F16, 0>, a, s);
   }
   return launch(gemm_h16_kernel<SPLIT, F16, 2>, a, s);
+}
+
+}  // namespace
+
+namespace {
+
+// One launch of variant v: bit 0 flips the raster order, v >> 1 selects the
+// 16-bit implementation (dispatch_h16).
+hipError_t launch_variant(cq_precision prec, GemmArgs a, DType tc, bool nt, int v, hipStream_t stream) {
+  if (v & 1) a.m_fastest ^= 1;
+  const int impl = v >> 1;
+  switch (prec) {
+    case CQ_FP64:
+      return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
+    case CQ_FP32:
+      return nt ? launch(gemm_f32_kernel<true>, a, stream) : launch(gemm_f32_kernel<false>, a, stream);
+    case CQ_BF16: return dispatch_h16<1, false>(a, tc, nt, stream, impl);
+    case CQ_FP16: return dispatch_h16<1, true>(a, tc, nt, stream, impl);
+    case CQ_BF16_SPLIT: return dispatch_h16<3, false>(a, tc, nt, stream, impl);
+    case CQ_FP16_SPLIT: return dispatch_h16<3, true>(a, tc, nt, stream, impl);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner.  The first time a GEMM shape is launched (outside stream
+// capture) every variant runs twice on the caller's stream and the fastest
+// second run is kept for that shape; later launches use it.  Each variant
+// computes the whole result, so the output is valid whichever ran last.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int prec, tc, nt, za, zb, aligned;
+  int64_t M, N, K, Z;
+  bool operator<(const TuneKey& o) const {
+    const int64_t x[10] = {prec, tc, nt, za, zb, aligned, M, N, K, Z};
+    const int64_t y[10] = {o.prec, o.tc, o.nt, o.za, o.zb, o.aligned, o.M, o.N, o.K, o.Z};
+    for (int i = 0; i < 10; ++i)
+      if (x[i] != y[i]) return x[i] < y[i];
+    return false;
+  }
+};
+
+struct TuneEntry {
+  int variant;
+  float ms[6];
+  int tried;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+std::atomic<int> g_tune_on{-1};  // -1: not yet read from CQ_AUTOTUNE
+
+// 0: variant 0 always, 1: tune, 2 + v: variant v always (where it applies)
+int tune_mode() {
+  int on = g_tune_on.load();
+  if (on < 0) {
+    const char* e = std::getenv("CQ_AUTOTUNE");
+    on = (e && e[0] == '0') ? 0 : 1;
+    g_tune_on.store(on);
+  }
+  return on;
+}
+
+int variant_count(cq_precision prec) {
+  return (prec == CQ_FP64 || prec == CQ_FP32) ? 2 : 6;
 }
 
 }  // namespace
@@ -951,24 +1032,109 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   switch (prec) {
     case CQ_FP64:
       if (g.a.t != DType::F64 || g.b.t != DType::F64 || g.tc != DType::F64) return hipErrorInvalidValue;
-      return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
+      break;
     case CQ_FP32:
       if (g.a.t != DType::F32 || g.b.t != DType::F32 || g.tc != DType::F32) return hipErrorInvalidValue;
-      return nt ? launch(gemm_f32_kernel<true>, a, stream) : launch(gemm_f32_kernel<false>, a, stream);
+      break;
     case CQ_BF16:
     case CQ_FP16:
       if (g.a.t != DType::H16 || g.b.t != DType::H16) return hipErrorInvalidValue;
       if (g.tc != DType::F32 && g.tc != DType::H16) return hipErrorInvalidValue;
-      return prec == CQ_BF16 ? dispatch_h16<1, false>(a, g.tc, nt, stream)
-                             : dispatch_h16<1, true>(a, g.tc, nt, stream);
+      break;
     case CQ_BF16_SPLIT:
     case CQ_FP16_SPLIT:
       if (g.a.t != DType::H16X2 || g.b.t != DType::H16X2) return hipErrorInvalidValue;
       if (g.tc != DType::F32 && g.tc != DType::H16X2) return hipErrorInvalidValue;
-      return prec == CQ_BF16_SPLIT ? dispatch_h16<3, false>(a, g.tc, nt, stream)
-                                   : dispatch_h16<3, true>(a, g.tc, nt, stream);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
+  // tune only shapes worth it (a few microseconds of work or more), never
+  // inside a capture
+  const int mode = tune_mode();
+  if (mode >= 2) {
+    const int v = mode - 2;
+    const bool ok = v < variant_count(prec) && ((v >> 1) == 0 || h16_async_ok(a, g.tc));
+    return launch_variant(prec, a, g.tc, nt, ok ? v : 0, stream);
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (mode == 0 || a.tiles < 64 || hipStreamIsCapturing(stream, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone)
+    return launch_variant(prec, a, g.tc, nt, 0, stream);
+  const TuneKey key{(int)prec, (int)g.tc, nt ? 1 : 0, g.sAz ? 1 : 0, g.sBz ? 1 : 0,
+                    h16_async_ok(a, g.tc) ? 1 : 0, g.M, g.N, g.K, g.Z};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return launch_variant(prec, a, g.tc, nt, it->second.variant, stream);
+  }
+  TuneEntry te{0, {0, 0, 0, 0, 0, 0}, 0};
+  hipEvent_t ev[3];
+  for (int i = 0; i < 3; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return launch_variant(prec, a, g.tc, nt, 0, stream);
+  hipError_t err = hipSuccess;
+  float best = 0.0f;
+  for (int v = 0; v < variant_count(prec) && err == hipSuccess; ++v) {
+    // the register path only when the asynchronous one applies too (else
+    // variants 0 and 4 are the same kernel)
+    if ((v >> 1) == 2 && !h16_async_ok(a, g.tc)) continue;
+    if ((v >> 1) == 1 && !h16_async_ok(a, g.tc)) continue;
+    err = hipEventRecord(ev[0], stream);
+    if (err == hipSuccess) err = launch_variant(prec, a, g.tc, nt, v, stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[1], stream);
+    if (err == hipSuccess) err = launch_variant(prec, a, g.tc, nt, v, stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[2], stream);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+    float t1 = 0.0f, t2 = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t1, ev[0], ev[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&t2, ev[1], ev[2]);
+    const float t = t1 < t2 ? t1 : t2;
+    te.ms[v] = t;
+    te.tried |= 1 << v;
+    if (err == hipSuccess && (v == 0 || t < best)) {
+      best = t;
+      te.variant = v;
+    }
+  }
+  for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  if (err != hipSuccess) return err;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = te;
+  }
+  // the output comes from the chosen variant, as on every later call
+  return launch_variant(prec, a, g.tc, nt, te.variant, stream);
+}
+
+void autotune_set(int mode) { g_tune_on.store(mode < 0 ? 0 : mode); }
+
+std::string autotune_json() {
+  static const char* pname[] = {"fp64", "fp32", "bf16", "bf16_split", "fp16", "fp16_split"};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string s = "[";
+  bool first = true;
+  for (const auto& kv : g_tune) {
+    const TuneKey& k = kv.first;
+    const TuneEntry& e = kv.second;
+    char buf[512];
+    int n = std::snprintf(buf, sizeof(buf),
+                          "%s{\"prec\": \"%s\", \"M\": %lld, \"N\": %lld, \"K\": %lld, \"Z\": %lld, "
+                          "\"variant\": %d, \"ms\": [",
+                          first ? "" : ", ", pname[k.prec], (long long)k.M, (long long)k.N,
+                          (long long)k.K, (long long)k.Z, e.variant);
+    s.append(buf, n);
+    bool f2 = true;
+    for (int v = 0; v < 6; ++v)
+      if ((e.tried >> v) & 1) {
+        n = std::snprintf(buf, sizeof(buf), "%s[%d, %.4f]", f2 ? "" : ", ", v, e.ms[v]);
+        s.append(buf, n);
+        f2 = false;
+      }
+    s += "]}";
+    first = false;
+  }
+  s += "]";
+  return s;
 }
 
 namespace {

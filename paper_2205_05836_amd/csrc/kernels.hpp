@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "cutqc.h"
 
@@ -41,7 +42,10 @@ struct GemmLaunch {
 };
 
 // C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]
+// (kernel variant chosen by the autotuner, see gemm.hip)
 hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t stream);
+void autotune_set(int mode);
+std::string autotune_json();
 
 // Kernel-side GEMM description (also written by device code for shapes that
 // are only known on the device).  tiles = tilesM * tilesN * Z with 128 x 128

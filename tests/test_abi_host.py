@@ -286,3 +286,15 @@ def test_plans_of_benchmark_workloads_need_no_permute():
         assert p["tensors"][p["steps"][-1]["c"]]["loc"] == "out"
     p = plan_json(syn.chain_cutmap([4, 4], [10, 10, 10]), "fp32")
     assert p["flops"] == pytest.approx(2 * (2 ** 10 * 2 ** 18 * 2 ** 8 + 2 ** 20 * 2 ** 10 * 2 ** 8))
+
+
+def test_autotune_json_and_modes_without_gpu():
+    import paper_2205_05836_amd as cq
+    L = lib()
+    need = C.c_size_t()
+    assert L.cq_autotune_json(None, 0, C.byref(need)) == -1  # CQ_ERR_ARG: buffer too small
+    assert need.value >= 3
+    assert cq.cq_autotune_json() == []  # nothing tuned on a host without launches
+    for mode in (0, 1, 2, 7, -3):
+        assert L.cq_autotune_enable(mode) == 0
+    cq.cq_autotune_enable(True)

@@ -156,6 +156,39 @@ def test_deterministic_repeat():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 2), ("bf16_split", 6),
+                                            ("fp16", 6)])
+def test_every_gemm_variant_matches_oracle(prec, variants):
+    """Each autotuner variant forced in turn; 2^24 outputs give every GEMM
+    hundreds of tiles, so all variants apply.  Raster order changes no sum,
+    so the two rasters of one implementation agree bit for bit."""
+    m = cq()
+    cm, E = syn.chain_instance(14, [4, 4], [8, 8, 8])
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    tol = {"fp64": 1e-13, "fp32": 1e-5, **H16_REL}[prec]
+    outs = []
+    try:
+        for v in range(variants):
+            m.cq_autotune_enable(variant=v)
+            print(f"{prec} variant {v}", flush=True)
+            out = gpu_fd(cm, E, prec)
+            err = np.abs(out - ref)
+            assert np.all(err <= tol * scale + FP32_FLOOR), (prec, v, float(err.max()))
+            outs.append(out)
+        for v in range(0, variants, 2):
+            assert np.array_equal(outs[v], outs[v + 1]), (prec, v)
+        m.cq_autotune_enable(True)
+        tuned = gpu_fd(cm, E, prec)
+        again = gpu_fd(cm, E, prec)
+        assert np.array_equal(tuned, again)
+        assert any(np.array_equal(tuned, o) for o in outs)
+        shapes = [e for e in m.cq_autotune_json() if e["prec"] == prec]
+        assert shapes and all(0 <= e["variant"] < variants for e in shapes)
+    finally:
+        m.cq_autotune_enable(True)
+
+
 def test_workspace_too_small_writes_nothing():
     m = cq()
     cm, E = syn.chain_instance(14, [4, 4], [6, 6, 6])
