@@ -678,6 +678,21 @@ __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
 }
 
+// s_waitcnt vmcnt(n) for a wave-uniform n (above 63: 63, which waits longer).
+// An asm statement with a memory clobber, so no memory access moves across it.
+__device__ inline void wait_vm_n(int n) {
+#define CQ_W4(b)                                                       \
+  case b: asm volatile("s_waitcnt vmcnt(" #b ")" ::: "memory"); break; \
+  case b + 1: asm volatile("s_waitcnt vmcnt(" #b " + 1)" ::: "memory"); break; \
+  case b + 2: asm volatile("s_waitcnt vmcnt(" #b " + 2)" ::: "memory"); break; \
+  case b + 3: asm volatile("s_waitcnt vmcnt(" #b " + 3)" ::: "memory"); break;
+  switch (n < 0 ? 0 : (n > 63 ? 63 : n)) {
+    CQ_W4(0) CQ_W4(4) CQ_W4(8) CQ_W4(12) CQ_W4(16) CQ_W4(20) CQ_W4(24) CQ_W4(28)
+    CQ_W4(32) CQ_W4(36) CQ_W4(40) CQ_W4(44) CQ_W4(48) CQ_W4(52) CQ_W4(56) CQ_W4(60)
+  }
+#undef CQ_W4
+}
+
 template <int SPLIT, bool F16, int OUT, int NS>
 __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
   CQ_LOAD_GEMM_ARGS
@@ -869,6 +884,257 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
   }
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit path, persistent form (FP32 output, no output exponents).  Same
+// operand ring, transposed LDS reads and MFMAs as gemm_h16a_kernel, but each
+// workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
+// on across tile boundaries.  A finished tile's results stay in registers and
+// are written out in eight row slabs spread over the next tile's stages, so
+// the output stream is steady instead of one burst per tile (a burst of
+// stores stalls the issuing wave while HBM drains writes from every CU).
+// Slab u of a wave holds rows 32*(u>>2) + 8*(u&3) .. +7 of its 64 x 64
+// block; it goes through an 8-row LDS buffer of the wave so that each store
+// instruction writes whole 256-byte row segments.  A wave's vector memory
+// operations retire in issue order, so the wait for a stage's operands also
+// waits for every store issued before those loads; each iteration issues its
+// stores first and its loads last, and the wait counts exactly the
+// operations issued after the awaited loads, so stores get NS - 1 stages to
+// drain before anything waits on them.
+// ---------------------------------------------------------------------------
+template <int SPLIT, bool F16, int OUT, int NS>
+__global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
+  using H = Half<F16>;
+  using V8 = typename H::V8;
+  constexpr int BM = 128, BN = 128, BK = 32;
+  constexpr int NP = SPLIT == 3 ? 2 : 1;
+  constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
+  constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
+  constexpr int LPW = 2 * 2 * NP;       // DMA instructions per wave per stage
+  constexpr int RING = NS * STAGE;
+  constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
+  static_assert(NS >= 2 && NS <= 5, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[RING + 4 * 8 * EROW];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  char* const wbuf = smem + RING + wave * 8 * EROW;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+  const int64_t my_tiles = (g.tiles - (int64_t)blockIdx.x + gridDim.x - 1) / gridDim.x;
+  const int64_t total = my_tiles * nstages;
+  // tile coordinates in 32-bit arithmetic (tiles < 2^31): workgroup b's i-th
+  // tile is virtual block b + i * gridDim.x, placed like xcd_tile/tile_coord_of
+  auto tile_of = [&](int64_t i) -> TileCoord {
+    const uint32_t vb = blockIdx.x + (uint32_t)i * gridDim.x;
+    const uint32_t T = (uint32_t)g.tiles, per = T / 8, rem = T % 8;
+    const uint32_t x = vb % 8, loc = vb / 8;
+    const uint32_t t = x < rem ? x * (per + 1) + loc : rem * (per + 1) + (x - rem) * per + loc;
+    const uint32_t tM = (uint32_t)g.tilesM, tN = (uint32_t)g.tilesN;
+    TileCoord c;
+    if (g.m_fastest) {
+      const uint32_t r = t / tM;
+      c.m0 = (int64_t)(t - r * tM) * BM;
+      c.z = r / tN;
+      c.n0 = (int64_t)(r - (uint32_t)c.z * tN) * BN;
+    } else {
+      const uint32_t r = t / tN;
+      c.n0 = (int64_t)(t - r * tN) * BN;
+      c.z = r / tM;
+      c.m0 = (int64_t)(r - (uint32_t)c.z * tM) * BM;
+    }
+    return c;
+  };
+  // operand loads run ahead of the multiplies; their state advances one
+  // stage per issue: tile index, stage in the tile, ring slot, and each
+  // plane's source row base for this lane in the current tile
+  const int64_t ccapM = (g.M - 8) & ~(int64_t)7, ccapN = (g.N - 8) & ~(int64_t)7;
+  const int lrow = lane >> 4;                                  // row inside a 4-row chunk
+  const int64_t lcol = (int64_t)swz(lrow, lane & 15) * 8;     // swizzled column of this lane
+  int64_t is_i = 0;
+  int is_s = 0, is_slot = 0;
+  const uint16_t* isrc[2][NP];
+  auto issue_next = [&]() {
+    if (is_s == 0) {
+      const TileCoord tc = tile_of(is_i);
+#pragma unroll
+      for (int op = 0; op < 2; ++op) {
+        int64_t col = (op ? tc.n0 : tc.m0) + lcol;
+        const int64_t cap = op ? ccapN : ccapM;  // last 8-column chunk inside the operand
+        if (col > cap) col = cap;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          isrc[op][p] = static_cast<const uint16_t*>(op ? (p ? g.B_lo : g.B) : (p ? g.A_lo : g.A)) +
+                        tc.z * (op ? g.sBz : g.sAz) + col;
+      }
+    }
+    const int64_t k0 = (int64_t)is_s * BK;
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+          const int chunk0 = (wave * 2 + qq) * 64;
+          int64_t k = k0 + (wave * 2 + qq) * 4 + lrow;
+          if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+          const uint16_t* src = isrc[op][p] + k * (op ? g.sBk : g.sAk);
+          const uint32_t dst = __builtin_amdgcn_readfirstlane(
+              (uint32_t)(uintptr_t)(lsm + is_slot * STAGE + (op * NP + p) * TILE + chunk0 * 16));
+          asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                       : "memory", "m0");
+        }
+    if (++is_s == nstages) {
+      is_s = 0;
+      ++is_i;
+    }
+    if (++is_slot == NS) is_slot = 0;
+  };
+  const int grp = lane >> 4, r16 = lane & 15;
+  const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
+  const int krow = 8 * (grp >> 1) + (r16 >> 2);
+  auto frag = [&](int tile, int kk, int c0, int64_t kvalid) -> V8 {
+    const int col = c0 + col_in_blk;
+    const int r0 = kk + krow, r1 = r0 + 4;
+    const int o0 = tile + r0 * 256 + (swz(r0, col >> 3) << 4) + (col & 7) * 2;
+    const int o1 = tile + r1 * 256 + (swz(r1, col >> 3) << 4) + (col & 7) * 2;
+    s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
+    s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
+    if (kvalid < BK) {
+      const int kb = kk + 8 * (grp >> 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kvalid) lo[e] = 0;
+        if (kb + 4 + e >= kvalid) hi[e] = 0;
+      }
+    }
+    typedef short s8_t __attribute__((ext_vector_type(8)));
+    const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(V8, v);
+  };
+
+  f16_t acc[2][2], prev[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = prev[i][j][v] = 0.0f;
+  TileCoord pt{0, 0, 0};  // tile held in prev
+  // slab u of prev (already scaled by alpha): rows 32*(u>>2) + 8*(u&3) .. +7
+  auto slab = [&](const int u) {
+    const int i = u >> 2, vg = u & 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 4 * (lane >> 5) + e;  // row inside the slab
+        const int c = 32 * j + (lane & 31);
+        *reinterpret_cast<float*>(wbuf + r * EROW + c * 4) = prev[i][j][4 * vg + e];
+      }
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+    const bool full = pt.m0 + BM <= g.M && pt.n0 + BN <= g.N;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rl = 4 * h + (lane >> 4);
+      const int c = 4 * (lane & 15);
+      const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + c * 4);
+      const int64_t m = pt.m0 + wm + 32 * i + 8 * vg + rl, n = pt.n0 + wn + c;
+      const int64_t idx = pt.z * g.sCz + m * g.ldc + n;
+      if (full || (m < g.M && n + 3 < g.N)) {
+        store_out<f4_t, OUT == 1>(reinterpret_cast<f4_t*>(static_cast<float*>(g.C) + idx), x);
+      } else if (m < g.M) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < g.N) store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx + e, x[e]);
+      }
+    }
+  };
+  const float alpha = float(g.alpha);
+  for (int64_t q = 0; q < NS - 1 && q < total; ++q) issue_next();
+  // hist[k]: vector memory instructions issued by iteration q - 1 - k (the
+  // prologue's loads count as iterations -NS+1 .. -1, one stage each).  The
+  // loads of stage q were issued last in iteration q - NS + 1, so exactly
+  // hist[0] + ... + hist[NS-3] instructions were issued after them; waiting
+  // until no more are outstanding completes them and nothing issued later.
+  // Stores of tiles with a ragged edge are not counted, which only makes the
+  // wait longer.
+  int hist[NS - 1];
+  const int pro = total < NS - 1 ? (int)total : NS - 1;
+#pragma unroll
+  for (int k = 0; k < NS - 1; ++k) hist[k] = (NS - 2 - k) < pro ? LPW : 0;
+  int s = 0, slot = 0;
+  int64_t i = 0;
+  for (int64_t q = 0; q < total; ++q) {
+    int after = 0;
+#pragma unroll
+    for (int k = 0; k < NS - 2; ++k) after += hist[k];
+    wait_vm_n(after);
+    // stage q landed for every wave; the slot of stage q - 1 is free.  A bare
+    // barrier: a fence here would also wait for this wave's output stores.
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    // slabs of the previous tile due at this stage (two stores each), then
+    // the loads of stage q + NS - 1
+    int ops = 0;
+    if (i > 0) {
+      const bool pfull = pt.m0 + BM <= g.M && pt.n0 + BN <= g.N;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if ((u * nstages) / 8 == s) {
+          slab(u);
+          if (pfull) ops += 2;
+        }
+    }
+    if (q + NS - 1 < total) {
+      issue_next();
+      ops += LPW;
+    }
+#pragma unroll
+    for (int k = NS - 2; k > 0; --k) hist[k] = hist[k - 1];
+    hist[0] = ops;
+    const int sb = slot * STAGE;
+    if (++slot == NS) slot = 0;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      V8 a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+          a[p][ii] = frag(sb + (0 * NP + p) * TILE, kk, wm + 32 * ii, kvalid);
+          b[p][ii] = frag(sb + (1 * NP + p) * TILE, kk, wn + 32 * ii, kvalid);
+        }
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[ii][j] = H::mfma(a[0][ii], b[0][j], acc[ii][j]);
+          if constexpr (SPLIT == 3) {
+            acc[ii][j] = H::mfma(a[0][ii], b[NP - 1][j], acc[ii][j]);
+            acc[ii][j] = H::mfma(a[NP - 1][ii], b[0][j], acc[ii][j]);
+          }
+        }
+    }
+    if (++s == nstages) {
+      s = 0;
+      pt = tile_of(i);
+      ++i;
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            prev[ii][j][v] = alpha * acc[ii][j][v];
+            acc[ii][j][v] = 0.0f;
+          }
+    }
+  }
+  if (i > 0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) slab(u);
+  }
+}
+
 template <typename K>
 hipError_t launch(K kernel, const GemmArgs& a, hipStream_t s, int threads = 256) {
   hipLaunchKernelGGL(kernel, dim3((unsigned)a.tiles), dim3(threads), 0, s, a,
@@ -897,11 +1163,40 @@ bool h16_async_ok(const GemmArgs& a, DType tc) {
 }
 
 // Variant `impl` of the 16-bit launch: 0 = asynchronous kernel with its
-// default ring depth, 1 = the other depth, 2 = register-path kernel.
+// default ring depth, 1 = the other depth, 2 = register-path kernel,
+// 3 = persistent kernel.
+// Persistent grid: two workgroups per compute unit, a multiple of 8 so that
+// workgroup b stays on XCD b % 8 for every tile it takes.
+int64_t persistent_grid(int64_t tiles) {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  int64_t grid = 2 * (int64_t)cus[dev];
+  grid -= grid % 8;
+  return tiles < grid ? tiles : grid;
+}
+
+// the persistent kernel applies: FP32 output without exponents, K >= 1
+bool h16p_ok(const GemmArgs& a, DType tc) {
+  return tc == DType::F32 && a.rowexp == nullptr && a.K >= 1 && h16_async_ok(a, tc);
+}
+
 template <int SPLIT, bool F16>
 hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int impl = 0) {
   constexpr int NS = SPLIT == 3 ? 2 : 3;
   constexpr int NS2 = SPLIT == 3 ? 3 : 2;
+  constexpr int NSP = SPLIT == 3 ? 2 : 4;
+  if (impl == 3 && h16p_ok(a, tc)) {
+    const int64_t grid = persistent_grid(a.tiles);
+    if (nt) hipLaunchKernelGGL((gemm_h16p_kernel<SPLIT, F16, 1, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((gemm_h16p_kernel<SPLIT, F16, 0, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (impl == 1 && h16_async_ok(a, tc)) {
     if (tc == DType::F32) {
       if (nt) return launch(gemm_h16a_kernel<SPLIT, F16, 1, NS2>, a, s);
@@ -965,7 +1260,7 @@ struct TuneKey {
 
 struct TuneEntry {
   int variant;
-  float ms[6];
+  float ms[8];
   int tried;
 };
 
@@ -985,7 +1280,7 @@ int tune_mode() {
 }
 
 int variant_count(cq_precision prec) {
-  return (prec == CQ_FP64 || prec == CQ_FP32) ? 2 : 6;
+  return (prec == CQ_FP64 || prec == CQ_FP32) ? 2 : 8;
 }
 
 }  // namespace
@@ -1054,7 +1349,9 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   const int mode = tune_mode();
   if (mode >= 2) {
     const int v = mode - 2;
-    const bool ok = v < variant_count(prec) && ((v >> 1) == 0 || h16_async_ok(a, g.tc));
+    const int impl = v >> 1;
+    const bool ok = v < variant_count(prec) &&
+                    (impl == 0 || (impl == 3 ? h16p_ok(a, g.tc) : h16_async_ok(a, g.tc)));
     return launch_variant(prec, a, g.tc, nt, ok ? v : 0, stream);
   }
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1068,7 +1365,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return launch_variant(prec, a, g.tc, nt, it->second.variant, stream);
   }
-  TuneEntry te{0, {0, 0, 0, 0, 0, 0}, 0};
+  TuneEntry te{0, {0, 0, 0, 0, 0, 0, 0, 0}, 0};
   hipEvent_t ev[3];
   for (int i = 0; i < 3; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return launch_variant(prec, a, g.tc, nt, 0, stream);
@@ -1079,6 +1376,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     // variants 0 and 4 are the same kernel)
     if ((v >> 1) == 2 && !h16_async_ok(a, g.tc)) continue;
     if ((v >> 1) == 1 && !h16_async_ok(a, g.tc)) continue;
+    if ((v >> 1) == 3 && !h16p_ok(a, g.tc)) continue;
     err = hipEventRecord(ev[0], stream);
     if (err == hipSuccess) err = launch_variant(prec, a, g.tc, nt, v, stream);
     if (err == hipSuccess) err = hipEventRecord(ev[1], stream);
@@ -1124,7 +1422,7 @@ std::string autotune_json() {
                           (long long)k.K, (long long)k.Z, e.variant);
     s.append(buf, n);
     bool f2 = true;
-    for (int v = 0; v < 6; ++v)
+    for (int v = 0; v < 8; ++v)
       if ((e.tried >> v) & 1) {
         n = std::snprintf(buf, sizeof(buf), "%s[%d, %.4f]", f2 ? "" : ", ", v, e.ms[v]);
         s.append(buf, n);

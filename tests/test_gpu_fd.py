@@ -156,8 +156,8 @@ def test_deterministic_repeat():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 2), ("bf16_split", 6),
-                                            ("fp16", 6)])
+@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 2), ("bf16_split", 8),
+                                            ("fp16", 8)])
 def test_every_gemm_variant_matches_oracle(prec, variants):
     """Each autotuner variant forced in turn; 2^24 outputs give every GEMM
     hundreds of tiles, so all variants apply.  Raster order changes no sum,
@@ -187,6 +187,34 @@ def test_every_gemm_variant_matches_oracle(prec, variants):
         assert shapes and all(0 <= e["variant"] < variants for e in shapes)
     finally:
         m.cq_autotune_enable(True)
+
+
+# final GEMMs with ragged tiles (M or N below 128) and 8192 tiles, so every
+# workgroup of the persistent kernel takes many tiles; K = 256, 64 and 16
+RAGGED = [(22, [4, 4], [10, 4, 10]), (23, [3, 3], [10, 3, 10]), (24, [5, 2], [10, 10, 4])]
+
+
+@pytest.mark.parametrize("seed,bonds,ns", RAGGED)
+@pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
+def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
+    """Variants 6 and 7 (persistent kernel, both rasters) against variant 0
+    bit for bit -- same products, same order -- and against the oracle."""
+    m = cq()
+    cm, E = syn.chain_instance(seed, bonds, ns)
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    outs = {}
+    try:
+        for v in (0, 6, 7):
+            m.cq_autotune_enable(variant=v)
+            print(f"{prec} {bonds} {ns} variant {v}", flush=True)
+            outs[v] = gpu_fd(cm, E, prec)
+    finally:
+        m.cq_autotune_enable(True)
+    err = np.abs(outs[0] - ref)
+    assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR), float(err.max())
+    assert np.array_equal(outs[6], outs[0])
+    assert np.array_equal(outs[7], outs[0])
 
 
 def test_workspace_too_small_writes_nothing():
