@@ -210,11 +210,15 @@ typedef struct cq_dd_record {  /* one recursion, written by the library */
   int32_t popped;               /* 1 when a bin was popped */
 } cq_dd_record;
 
-/* Workspace: the buffers of the largest instance (instances run one after
- * another and share them) plus a small control block per instance (device
- * program, recursion state, launch descriptors, records).  bins_stored != 0
- * when the caller passes a bin buffer for every recursion (then no bin
- * scratch is counted). */
+/* Workspace: the buffers of the largest instance plus a small control block
+ * per instance (device program, recursion state, launch descriptors,
+ * records).  Instances share those buffers: with stored bins they run one
+ * after another; without (bins_stored == 0, the bins never leave the last
+ * GEMM's epilogue) they run on up to four parallel lanes -- streams forked
+ * from and joined back into `stream` -- and each lane gets its own copy of
+ * the buffers, instance i on lane i % 4.  bins_stored != 0 when the caller
+ * passes a bin buffer for every recursion (then no bin scratch is
+ * counted). */
 cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
                                const cq_dd_params* params, int32_t bins_stored, size_t* bytes);
 
