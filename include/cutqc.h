@@ -212,11 +212,12 @@ typedef struct cq_dd_record {  /* one recursion, written by the library */
 
 /* Workspace: the buffers of the largest instance plus a small control block
  * per instance (device program, recursion state, launch descriptors,
- * records).  Instances share those buffers: with stored bins they run one
- * after another; without (bins_stored == 0, the bins never leave the last
- * GEMM's epilogue) they run on up to four parallel lanes -- streams forked
- * from and joined back into `stream` -- and each lane gets its own copy of
- * the buffers, instance i on lane i % 4.  bins_stored != 0 when the caller
+ * records).  Instances share those buffers and run one after another, except
+ * when no bins are stored (bins_stored == 0) and every instance's contraction
+ * ends in a GEMM, so its bins never leave that GEMM's epilogue: then they run
+ * on min(n_inst, 4) parallel lanes -- streams forked from and joined back
+ * into `stream` -- each with its own copy of the buffers, instance i on lane
+ * i % lanes.  bins_stored != 0 when the caller
  * passes a bin buffer for every recursion (then no bin scratch is
  * counted). */
 cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
