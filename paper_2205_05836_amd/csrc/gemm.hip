@@ -885,8 +885,8 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
 }
 
 // ---------------------------------------------------------------------------
-// 16-bit path, persistent form (FP32 output, no output exponents).  Same
-// operand ring, transposed LDS reads and MFMAs as gemm_h16a_kernel, but each
+// Persistent form (FP32 output, no output exponents), for 16-bit and FP32
+// operands.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
 // workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
 // on across tile boundaries.  A finished tile's results stay in registers and
 // are written out in eight row slabs spread over the next tile's stages, so
@@ -900,19 +900,122 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
 // stores first and its loads last, and the wait counts exactly the
 // operations issued after the awaited loads, so stores get NS - 1 stages to
 // drain before anything waits on them.
+//
+// The operand policy P fixes the element type.  A stage holds BK labels of
+// each operand plane, 8 KB: rows of 128 elements, one DMA instruction (64
+// lanes x 16 bytes) filling RPI rows; wave w's instruction q fills rows
+// (2w + q) * RPI .. +RPI-1.  P::chunk gives the 16-byte chunk of its row
+// that a lane's load lands in (a swizzle against LDS bank conflicts) and
+// P::mma runs the stage's MFMAs for one wave's 64 x 64 block.
 // ---------------------------------------------------------------------------
-template <int SPLIT, bool F16, int OUT, int NS>
-__global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
+
+// 16-bit planes (hi, and lo for the split forms): rows of 256 bytes, read
+// back k-contiguous with ds_read_b64_tr_b16 as in gemm_h16a_kernel.
+template <int SPLIT, bool F16>
+struct PersistH16 {
   using H = Half<F16>;
   using V8 = typename H::V8;
-  constexpr int BM = 128, BN = 128, BK = 32;
-  constexpr int NP = SPLIT == 3 ? 2 : 1;
-  constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
+  static constexpr int BK = 32, NP = SPLIT == 3 ? 2 : 1, RPI = 4, CW = 8;
+  typedef uint16_t E;
+  static __device__ int lrow(int lane) { return lane >> 4; }
+  static __device__ int chunk(int lane) { return swz(lane >> 4, lane & 15); }
+  static __device__ const E* plane(const GemmArgs& g, int op, int p) {
+    return static_cast<const E*>(op ? (p ? g.B_lo : g.B) : (p ? g.A_lo : g.A));
+  }
+  static __device__ void mma(f16_t (&acc)[2][2], CQ_LDS char* lsm, int sb, int64_t kvalid, int wm, int wn,
+                             int lane) {
+    constexpr int TILE = BK * 256;
+    const int grp = lane >> 4, r16 = lane & 15;
+    const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
+    const int krow = 8 * (grp >> 1) + (r16 >> 2);
+    auto frag = [&](int tile, int kk, int c0) -> V8 {
+      const int col = c0 + col_in_blk;
+      const int r0 = kk + krow, r1 = r0 + 4;
+      const int o0 = tile + r0 * 256 + (swz(r0, col >> 3) << 4) + (col & 7) * 2;
+      const int o1 = tile + r1 * 256 + (swz(r1, col >> 3) << 4) + (col & 7) * 2;
+      s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
+      s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
+      if (kvalid < BK) {
+        const int kb = kk + 8 * (grp >> 1);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (kb + e >= kvalid) lo[e] = 0;
+          if (kb + 4 + e >= kvalid) hi[e] = 0;
+        }
+      }
+      typedef short s8_t __attribute__((ext_vector_type(8)));
+      const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      return __builtin_bit_cast(V8, v);
+    };
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      V8 a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+          a[p][ii] = frag(sb + (0 * NP + p) * TILE, kk, wm + 32 * ii);
+          b[p][ii] = frag(sb + (1 * NP + p) * TILE, kk, wn + 32 * ii);
+        }
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[ii][j] = H::mfma(a[0][ii], b[0][j], acc[ii][j]);
+          if constexpr (SPLIT == 3) {
+            acc[ii][j] = H::mfma(a[0][ii], b[NP - 1][j], acc[ii][j]);
+            acc[ii][j] = H::mfma(a[NP - 1][ii], b[0][j], acc[ii][j]);
+          }
+        }
+    }
+  }
+};
+
+// FP32: rows of 512 bytes.  Odd rows have their 16-byte chunks swapped by
+// halves (chunk ^ 8), so the MFMA operand reads -- 32 consecutive floats of
+// rows k and k + 1 -- fall into different banks.
+struct PersistF32 {
+  static constexpr int BK = 16, NP = 1, RPI = 2, CW = 4;
+  typedef float E;
+  static __device__ int lrow(int lane) { return lane >> 5; }
+  static __device__ int chunk(int lane) { return (lane & 31) ^ (8 * (lane >> 5)); }
+  static __device__ const E* plane(const GemmArgs& g, int op, int) {
+    return static_cast<const E*>(op ? g.B : g.A);
+  }
+  static __device__ void mma(f16_t (&acc)[2][2], CQ_LDS char* lsm, int sb, int64_t kvalid, int wm, int wn,
+                             int lane) {
+    constexpr int TILE = BK * 512;
+    const int r = lane >> 5, c = lane & 31;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      if (kk >= kvalid) break;  // short K (outer products): skip all-zero steps
+      const int row = kk + r;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int ca = wm + 32 * i + c, cb = wn + 32 * i + c;
+        a[i] = *(const CQ_LDS float*)(lsm + sb + row * 512 + (((ca >> 2) ^ (8 * r)) << 4) + (ca & 3) * 4);
+        b[i] = *(const CQ_LDS float*)(lsm + sb + TILE + row * 512 + (((cb >> 2) ^ (8 * r)) << 4) + (cb & 3) * 4);
+        if (row >= kvalid) a[i] = 0.0f;  // rows past K hold a clamped copy of row K - 1
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+};
+
+template <class P, int OUT, int NS>
+__global__ void __launch_bounds__(256, 2) gemm_persist_kernel(GemmArgs g) {
+  constexpr int BM = 128, BN = 128, BK = P::BK, NP = P::NP, RPI = P::RPI, CW = P::CW;
+  constexpr int TILE = 8192;            // bytes of one operand-plane stage
   constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
   constexpr int LPW = 2 * 2 * NP;       // DMA instructions per wave per stage
   constexpr int RING = NS * STAGE;
   constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
   static_assert(NS >= 2 && NS <= 5, "stage count");
+  static_assert(BK * 128 * sizeof(typename P::E) == TILE && RPI * 8 == BK, "stage layout");
   __shared__ __attribute__((aligned(16))) char smem[RING + 4 * 8 * EROW];
   CQ_LDS char* const lsm = (CQ_LDS char*)smem;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -946,24 +1049,22 @@ __global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
   // operand loads run ahead of the multiplies; their state advances one
   // stage per issue: tile index, stage in the tile, ring slot, and each
   // plane's source row base for this lane in the current tile
-  const int64_t ccapM = (g.M - 8) & ~(int64_t)7, ccapN = (g.N - 8) & ~(int64_t)7;
-  const int lrow = lane >> 4;                                  // row inside a 4-row chunk
-  const int64_t lcol = (int64_t)swz(lrow, lane & 15) * 8;     // swizzled column of this lane
+  const int64_t ccapM = (g.M - CW) & ~(int64_t)(CW - 1), ccapN = (g.N - CW) & ~(int64_t)(CW - 1);
+  const int lrow = P::lrow(lane);                      // row inside an instruction's rows
+  const int64_t lcol = (int64_t)P::chunk(lane) * CW;  // column this lane's 16 bytes start at
   int64_t is_i = 0;
   int is_s = 0, is_slot = 0;
-  const uint16_t* isrc[2][NP];
+  const typename P::E* isrc[2][NP];
   auto issue_next = [&]() {
     if (is_s == 0) {
       const TileCoord tc = tile_of(is_i);
 #pragma unroll
       for (int op = 0; op < 2; ++op) {
         int64_t col = (op ? tc.n0 : tc.m0) + lcol;
-        const int64_t cap = op ? ccapN : ccapM;  // last 8-column chunk inside the operand
+        const int64_t cap = op ? ccapN : ccapM;  // last 16-byte chunk inside the operand
         if (col > cap) col = cap;
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          isrc[op][p] = static_cast<const uint16_t*>(op ? (p ? g.B_lo : g.B) : (p ? g.A_lo : g.A)) +
-                        tc.z * (op ? g.sBz : g.sAz) + col;
+        for (int p = 0; p < NP; ++p) isrc[op][p] = P::plane(g, op, p) + tc.z * (op ? g.sBz : g.sAz) + col;
       }
     }
     const int64_t k0 = (int64_t)is_s * BK;
@@ -974,9 +1075,9 @@ __global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
 #pragma unroll
         for (int qq = 0; qq < 2; ++qq) {
           const int chunk0 = (wave * 2 + qq) * 64;
-          int64_t k = k0 + (wave * 2 + qq) * 4 + lrow;
+          int64_t k = k0 + (wave * 2 + qq) * RPI + lrow;
           if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
-          const uint16_t* src = isrc[op][p] + k * (op ? g.sBk : g.sAk);
+          const typename P::E* src = isrc[op][p] + k * (op ? g.sBk : g.sAk);
           const uint32_t dst = __builtin_amdgcn_readfirstlane(
               (uint32_t)(uintptr_t)(lsm + is_slot * STAGE + (op * NP + p) * TILE + chunk0 * 16));
           asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
@@ -987,28 +1088,6 @@ __global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
       ++is_i;
     }
     if (++is_slot == NS) is_slot = 0;
-  };
-  const int grp = lane >> 4, r16 = lane & 15;
-  const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
-  const int krow = 8 * (grp >> 1) + (r16 >> 2);
-  auto frag = [&](int tile, int kk, int c0, int64_t kvalid) -> V8 {
-    const int col = c0 + col_in_blk;
-    const int r0 = kk + krow, r1 = r0 + 4;
-    const int o0 = tile + r0 * 256 + (swz(r0, col >> 3) << 4) + (col & 7) * 2;
-    const int o1 = tile + r1 * 256 + (swz(r1, col >> 3) << 4) + (col & 7) * 2;
-    s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
-    s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
-    if (kvalid < BK) {
-      const int kb = kk + 8 * (grp >> 1);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (kb + e >= kvalid) lo[e] = 0;
-        if (kb + 4 + e >= kvalid) hi[e] = 0;
-      }
-    }
-    typedef short s8_t __attribute__((ext_vector_type(8)));
-    const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    return __builtin_bit_cast(V8, v);
   };
 
   f16_t acc[2][2], prev[2][2];
@@ -1092,28 +1171,7 @@ __global__ void __launch_bounds__(256, 2) gemm_h16p_kernel(GemmArgs g) {
     hist[0] = ops;
     const int sb = slot * STAGE;
     if (++slot == NS) slot = 0;
-    const int64_t kvalid = g.K - (int64_t)s * BK;
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      V8 a[NP][2], b[NP][2];
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int ii = 0; ii < 2; ++ii) {
-          a[p][ii] = frag(sb + (0 * NP + p) * TILE, kk, wm + 32 * ii, kvalid);
-          b[p][ii] = frag(sb + (1 * NP + p) * TILE, kk, wn + 32 * ii, kvalid);
-        }
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[ii][j] = H::mfma(a[0][ii], b[0][j], acc[ii][j]);
-          if constexpr (SPLIT == 3) {
-            acc[ii][j] = H::mfma(a[0][ii], b[NP - 1][j], acc[ii][j]);
-            acc[ii][j] = H::mfma(a[NP - 1][ii], b[0][j], acc[ii][j]);
-          }
-        }
-    }
+    P::mma(acc, lsm, sb, g.K - (int64_t)s * BK, wm, wn, lane);
     if (++s == nstages) {
       s = 0;
       pt = tile_of(i);
@@ -1186,6 +1244,15 @@ bool h16p_ok(const GemmArgs& a, DType tc) {
   return tc == DType::F32 && a.rowexp == nullptr && a.K >= 1 && h16_async_ok(a, tc);
 }
 
+// FP32 operands for the persistent kernel: 16-byte aligned rows of at least
+// 4 columns, and an output whose rows take 16-byte stores
+bool f32p_ok(const GemmArgs& a) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return a.rowexp == nullptr && a.K >= 1 && a.M >= 4 && a.N >= 4 && a.M % 4 == 0 && a.N % 4 == 0 &&
+         a.sAk % 4 == 0 && a.sBk % 4 == 0 && a.sAz % 4 == 0 && a.sBz % 4 == 0 && a.ldc % 4 == 0 &&
+         a.sCz % 4 == 0 && al(a.A) && al(a.B) && al(a.C);
+}
+
 template <int SPLIT, bool F16>
 hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int impl = 0) {
   constexpr int NS = SPLIT == 3 ? 2 : 3;
@@ -1193,8 +1260,9 @@ hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int
   constexpr int NSP = SPLIT == 3 ? 2 : 4;
   if (impl == 3 && h16p_ok(a, tc)) {
     const int64_t grid = persistent_grid(a.tiles);
-    if (nt) hipLaunchKernelGGL((gemm_h16p_kernel<SPLIT, F16, 1, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((gemm_h16p_kernel<SPLIT, F16, 0, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    using P = PersistH16<SPLIT, F16>;
+    if (nt) hipLaunchKernelGGL((gemm_persist_kernel<P, 1, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((gemm_persist_kernel<P, 0, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
     return hipGetLastError();
   }
   if (impl == 1 && h16_async_ok(a, tc)) {
@@ -1231,6 +1299,12 @@ hipError_t launch_variant(cq_precision prec, GemmArgs a, DType tc, bool nt, int 
     case CQ_FP64:
       return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
     case CQ_FP32:
+      if (impl == 3 && f32p_ok(a)) {
+        const int64_t grid = persistent_grid(a.tiles);
+        if (nt) hipLaunchKernelGGL((gemm_persist_kernel<PersistF32, 1, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
+        else hipLaunchKernelGGL((gemm_persist_kernel<PersistF32, 0, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
+        return hipGetLastError();
+      }
       return nt ? launch(gemm_f32_kernel<true>, a, stream) : launch(gemm_f32_kernel<false>, a, stream);
     case CQ_BF16: return dispatch_h16<1, false>(a, tc, nt, stream, impl);
     case CQ_FP16: return dispatch_h16<1, true>(a, tc, nt, stream, impl);
@@ -1280,7 +1354,17 @@ int tune_mode() {
 }
 
 int variant_count(cq_precision prec) {
-  return (prec == CQ_FP64 || prec == CQ_FP32) ? 2 : 8;
+  return prec == CQ_FP64 ? 2 : 8;
+}
+
+// whether variant v has a kernel of its own for this launch (else it would
+// repeat variant v & 1)
+bool variant_applies(cq_precision prec, const GemmArgs& a, DType tc, int v) {
+  const int impl = v >> 1;
+  if (impl == 0) return true;
+  if (v >= variant_count(prec)) return false;
+  if (prec == CQ_FP32) return impl == 3 && f32p_ok(a);
+  return impl == 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
 }
 
 }  // namespace
@@ -1349,10 +1433,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   const int mode = tune_mode();
   if (mode >= 2) {
     const int v = mode - 2;
-    const int impl = v >> 1;
-    const bool ok = v < variant_count(prec) &&
-                    (impl == 0 || (impl == 3 ? h16p_ok(a, g.tc) : h16_async_ok(a, g.tc)));
-    return launch_variant(prec, a, g.tc, nt, ok ? v : 0, stream);
+    return launch_variant(prec, a, g.tc, nt, variant_applies(prec, a, g.tc, v) ? v : 0, stream);
   }
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (mode == 0 || a.tiles < 64 || hipStreamIsCapturing(stream, &cap) != hipSuccess ||
@@ -1372,11 +1453,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   hipError_t err = hipSuccess;
   float best = 0.0f;
   for (int v = 0; v < variant_count(prec) && err == hipSuccess; ++v) {
-    // the register path only when the asynchronous one applies too (else
-    // variants 0 and 4 are the same kernel)
-    if ((v >> 1) == 2 && !h16_async_ok(a, g.tc)) continue;
-    if ((v >> 1) == 1 && !h16_async_ok(a, g.tc)) continue;
-    if ((v >> 1) == 3 && !h16p_ok(a, g.tc)) continue;
+    if (!variant_applies(prec, a, g.tc, v)) continue;
     err = hipEventRecord(ev[0], stream);
     if (err == hipSuccess) err = launch_variant(prec, a, g.tc, nt, v, stream);
     if (err == hipSuccess) err = hipEventRecord(ev[1], stream);

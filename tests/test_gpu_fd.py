@@ -156,7 +156,7 @@ def test_deterministic_repeat():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 2), ("bf16_split", 8),
+@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 8), ("bf16_split", 8),
                                             ("fp16", 8)])
 def test_every_gemm_variant_matches_oracle(prec, variants):
     """Each autotuner variant forced in turn; 2^24 outputs give every GEMM
@@ -195,7 +195,7 @@ RAGGED = [(22, [4, 4], [10, 4, 10]), (23, [3, 3], [10, 3, 10]), (24, [5, 2], [10
 
 
 @pytest.mark.parametrize("seed,bonds,ns", RAGGED)
-@pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_split"])
 def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
     """Variants 6 and 7 (persistent kernel, both rasters) against variant 0
     bit for bit -- same products, same order -- and against the oracle."""
@@ -212,7 +212,7 @@ def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
     finally:
         m.cq_autotune_enable(True)
     err = np.abs(outs[0] - ref)
-    assert np.all(err <= H16_REL[prec] * scale + FP32_FLOOR), float(err.max())
+    assert np.all(err <= {"fp32": 1e-5, **H16_REL}[prec] * scale + FP32_FLOOR), float(err.max())
     assert np.array_equal(outs[6], outs[0])
     assert np.array_equal(outs[7], outs[0])
 
