@@ -132,6 +132,29 @@ def step_bytes(plan, step, prec):
     return tb(step["a"]) + tb(step["b"]) + tb(step["c"])
 
 
+def step_roofline(plan, prec, ms):
+    """Whole-step binding roofline of one form: the larger of the time to
+    issue its MFMAs at the dtype's dense peak (split forms issue three per
+    product) and the time to move its algorithmic bytes at HBM peak: FP64
+    entries read once, the output written once and every intermediate
+    written and read once in the form's storage format."""
+    issue = 3 if prec.endswith("_split") else 1
+    t_mfma = issue * plan["flops"] / (PEAK_TFLOPS[prec] * 1e12)
+    eb = plan["work_elem_bytes"]
+    nbytes = 0
+    for T in plan["tensors"]:
+        if T["loc"] == "input":
+            nbytes += T["elems"] * 8
+        elif T["loc"] == "out":
+            nbytes += T["elems"] * (8 if prec == "fp64" else 4)
+        else:
+            nbytes += 2 * T["elems"] * eb
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t = max(t_mfma, t_hbm)
+    return {"bound": "mfma" if t_mfma >= t_hbm else "hbm", "time_at_roof_ms": round(t * 1e3, 4),
+            "algorithmic_bytes": nbytes, "frac": round(t * 1e3 / ms, 4)}
+
+
 def roofline(plan, prec, name, kfl, kms, kcnt):
     """Binding roofline of the dominant kernel: the larger of its time at the
     dtype's dense MFMA peak (algorithmic flops) and at HBM peak (algorithmic
@@ -334,6 +357,8 @@ def main():
         mx, tv = compare_outputs(torch, out, out64)
         forms[f] = {"ms_per_step": round(f_ms, 4),
                     "tflops": round(flops / (f_ms * 1e-3) / 1e12, 3),
+                    "pct_peak": round(100.0 * flops / (f_ms * 1e-3) / 1e12 / PEAK_TFLOPS[f], 2),
+                    "step_roofline": step_roofline(cq.cq_plan_json(cm, f), f, f_ms),
                     "speedup_vs_fp64_path": round(ms64 / f_ms, 3),
                     "max_abs_vs_fp64": mx, "tv_vs_fp64": tv}
         if f == prec:
@@ -363,10 +388,15 @@ def main():
         "roofline": roof,
         "fp64_path": {"ms_per_step": round(ms64, 4),
                       "tflops": round(flops / (ms64 * 1e-3) / 1e12, 3),
-                      "pct_peak": round(100.0 * flops / (ms64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"], 2)},
+                      "pct_peak": round(100.0 * flops / (ms64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"], 2),
+                      "step_roofline": step_roofline(cq.cq_plan_json(cm, "fp64"), "fp64", ms64)},
         "speedup_vs_fp64_path": round(ms64 / ms, 3),
         "error_vs_fp64_gpu": {"max_abs": max_abs, "tv": tv_h},
         "forms": forms,
+        # the accuracy/speed gate per form: max-abs error below 1e-6 against
+        # the FP64 GPU output and at least twice the FP64 path's speed; the
+        # passing form closest to its own step roofline is named
+        "gate": gate(forms),
         "kernels": {f"{n}@{fl:.3g}": round(t, 4) for n, t, fl in
                     [(k[0], v[1] / v[0], k[1]) for k, v in _groups(recs).items()]},
     }
@@ -388,6 +418,17 @@ def main():
         result["cpu_baseline"] = cpu
         result["error_vs_oracle"] = err
     print(json.dumps(result), flush=True)
+
+
+def gate(forms):
+    ok = {f: v for f, v in forms.items()
+          if v["max_abs_vs_fp64"] < 1e-6 and v["speedup_vs_fp64_path"] >= 2.0}
+    if not ok:
+        return None
+    f = max(ok, key=lambda k: ok[k]["step_roofline"]["frac"])
+    v = ok[f]
+    return {"form": f, "step_roofline_frac": v["step_roofline"]["frac"],
+            "speedup_vs_fp64_path": v["speedup_vs_fp64_path"], "max_abs_vs_fp64": v["max_abs_vs_fp64"]}
 
 
 def _groups(recs):
