@@ -77,11 +77,12 @@ __device__ inline bool better(const Key& a, const Key& b) {
 
 __device__ inline Key worst_key() { return Key{-DBL_MAX, ~(uint64_t)0}; }
 
-// Sorts buf[0..kTopS) best-first; all threads of the workgroup call it.
-__device__ void bitonic_sort(Key* buf) {
-  for (int k = 2; k <= kTopS; k <<= 1) {
+// Sorts buf[0..n) best-first (n a power of two, 2..kTopS); all threads of
+// the workgroup call it with the same n.
+__device__ void bitonic_sort(Key* buf, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < kTopS / 2; t += blockDim.x) {
+      for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
         const int i = 2 * j * (t / j) + (t % j);
         const int p = i + j;
         const bool asc = (i & k) == 0;  // "ascending" = best first
@@ -126,10 +127,14 @@ __global__ void __launch_bounds__(256) topk_kernel(const T* __restrict__ vals,
     thr = worst_key();
   }
   __syncthreads();
+  // sorts only the filled prefix, rounded up to a power of two: after a
+  // selective scan most workgroups hold a handful of keys
   auto trim = [&]() {
-    for (int t = cnt + threadIdx.x; t < kTopS; t += blockDim.x) buf[t] = worst_key();
+    int n = 2;
+    while (n < cnt) n <<= 1;
+    for (int t = cnt + threadIdx.x; t < n; t += blockDim.x) buf[t] = worst_key();
     __syncthreads();
-    bitonic_sort(buf);
+    bitonic_sort(buf, n);
     if (threadIdx.x == 0) {
       if (cnt > C) cnt = C;
       thr = (cnt == C) ? buf[C - 1] : worst_key();
@@ -401,6 +406,7 @@ __device__ inline Key wave_best_key(Key k) {
   return k;
 }
 
+template <int KPT>
 __global__ void __launch_bounds__(256) select_small_kernel(const double* __restrict__ vals,
                                                            const uint64_t* __restrict__ idxs,
                                                            int64_t count, const int32_t* __restrict__ C_dev,
@@ -411,17 +417,18 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
   const int C = *C_dev;
   if (C <= 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Key h[64];
+  static_assert(KPT >= 1 && KPT <= 64, "keys per thread");
+  Key h[KPT];
   uint64_t live = 0;
-  // clamped, unconditional loads: all 128 of a thread are in flight together
+  // clamped, unconditional loads: all of a thread's loads are in flight together
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < KPT; ++j) {
     const int64_t x = (int64_t)j * 256 + threadIdx.x;
     const int64_t xc = x < count ? x : 0;
     h[j] = Key{vals[xc], idxs[xc]};
   }
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < KPT; ++j) {
     const int64_t x = (int64_t)j * 256 + threadIdx.x;
     if (x >= count) h[j] = worst_key();
     if (better(h[j], worst_key())) live |= 1ull << j;
@@ -432,7 +439,7 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
     Key best = worst_key();
     int bj = -1;
 #pragma unroll
-    for (int j = 0; j < 64; ++j)
+    for (int j = 0; j < KPT; ++j)
       if (((live >> j) & 1) && better(h[j], best)) {
         best = h[j];
         bj = j;
@@ -473,6 +480,18 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
   }
 }
 
+// one workgroup selects the C best of `count` <= kSelCap keys; the keys per
+// thread follow the count (fewer registers, all loads in flight)
+void launch_select_small(const double* vals, const uint64_t* idxs, int64_t count, const int32_t* C_dev,
+                         double* out_v, uint64_t* out_i, hipStream_t stream) {
+  if (count <= 256 * 4)
+    hipLaunchKernelGGL(select_small_kernel<4>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+  else if (count <= 256 * 16)
+    hipLaunchKernelGGL(select_small_kernel<16>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+  else
+    hipLaunchKernelGGL(select_small_kernel<64>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+}
+
 int64_t topk_indirect_capacity(int64_t max_count, int C_max) {
   return topk_blocks(max_count) * C_max;
 }
@@ -494,8 +513,7 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
   if (e != hipSuccess) return e;
   const int64_t nc = blocks * C_max;
   if (nc <= kSelCap)
-    hipLaunchKernelGGL(select_small_kernel, dim3(1), dim3(256), 0, stream, (const double*)cand_val,
-                       (const uint64_t*)cand_idx, nc, C_dev, out_val, out_idx);
+    launch_select_small((const double*)cand_val, (const uint64_t*)cand_idx, nc, C_dev, out_val, out_idx, stream);
   else
     hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
                        (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
@@ -513,8 +531,7 @@ hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nc = (int64_t)kTopcStage * C_max;  // <= kSelCap
-  hipLaunchKernelGGL(select_small_kernel, dim3(1), dim3(256), 0, stream, (const double*)stage_val,
-                     (const uint64_t*)stage_idx, nc, C_dev, out_val, out_idx);
+  launch_select_small((const double*)stage_val, (const uint64_t*)stage_idx, nc, C_dev, out_val, out_idx, stream);
   return hipGetLastError();
 }
 
