@@ -77,6 +77,33 @@ __device__ inline TileCoord tile_coord(const GemmArgs& g) {
                                               : xcd_tile(blockIdx.x, g.tiles));
 }
 
+// Tile of virtual block vb (a workgroup may take several, see CQ_TILE_LOOP).
+template <int BM, int BN>
+__device__ inline TileCoord tile_coord_v(const GemmArgs& g, int64_t vb) {
+  return tile_coord_of<BM, BN>(g, g.tile_list ? (int64_t)g.tile_list[vb] : xcd_tile(vb, g.tiles));
+}
+
+// Kernels that also serve indirect launches run their tile body for virtual
+// blocks blockIdx.x, +gridDim.x, ... up to the device-side count (the tile
+// list's length, or the tile count), so a launch over a pruned tile list
+// needs no grid sized for every tile; a direct launch (one workgroup per
+// tile) runs the body once.
+#define CQ_TILE_LOOP(BODY)                                                                      \
+  int64_t nvb = (int64_t)gridDim.x;                                                             \
+  if (gp) {                                                                                     \
+    const GemmArgs* q = gp;                                                                     \
+    nvb = q->tile_list ? *q->tile_count : q->tiles;                                             \
+  }                                                                                             \
+  _Pragma("nounroll")                                                                           \
+  for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {                                    \
+    /* reload the arguments per tile: nothing of the previous tile stays live */                \
+    asm volatile("" ::: "memory");                                                              \
+    const GemmArgs g = gp ? *gp : gv;                                                           \
+    if (g.tile_list && g.tile_list[vb] >= (uint64_t)g.tiles) continue;                          \
+    BODY;                                                                                       \
+    __syncthreads();                                                                            \
+  }
+
 // Loads 8 consecutive elements of row k (columns c0..c0+7), zero outside
 // [0, K) x [0, ncols).
 template <typename T>
@@ -279,15 +306,14 @@ __device__ __forceinline__ void topc_tile(const GemmArgs& g, int64_t z, int64_t 
 // ---------------------------------------------------------------------------
 // FP64
 // ---------------------------------------------------------------------------
-template <bool NT, bool TC = false>
-__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
-  CQ_LOAD_GEMM_ARGS
+template <bool NT, bool TC>
+__device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, int64_t vb) {
   // 8 waves in a 4 x 2 grid, 32 x 64 outputs each: two waves per SIMD hide
   // the load latency that one 64 x 64 wave per SIMD could not.
   constexpr int BM = 128, BN = 128, BK = 16;
   __shared__ __attribute__((aligned(16))) double As[BK][BM];
   __shared__ __attribute__((aligned(16))) double Bs[BK][BN];
-  const TileCoord tc = tile_coord<BM, BN>(g);
+  const TileCoord tc = tile_coord_v<BM, BN>(g, vb);
   const int64_t m0 = tc.m0, n0 = tc.n0;
   const double* A = static_cast<const double*>(g.A) + tc.z * g.sAz;
   const double* B = static_cast<const double*>(g.B) + tc.z * g.sBz;
@@ -358,16 +384,20 @@ __global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmAr
       }
 }
 
+template <bool NT, bool TC = false>
+__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_TILE_LOOP((gemm_f64_tile<NT, TC>(g, vb)))
+}
+
 // ---------------------------------------------------------------------------
 // FP32
 // ---------------------------------------------------------------------------
-template <bool NT, bool TC = false>
-__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
-  CQ_LOAD_GEMM_ARGS
+template <bool NT, bool TC>
+__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int64_t vb) {
   constexpr int BM = 128, BN = 128, BK = 16;
   __shared__ __attribute__((aligned(16))) float As[BK][BM];
   __shared__ __attribute__((aligned(16))) float Bs[BK][BN];
-  const TileCoord tc = tile_coord<BM, BN>(g);
+  const TileCoord tc = tile_coord_v<BM, BN>(g, vb);
   const int64_t m0 = tc.m0, n0 = tc.n0;
   const float* A = static_cast<const float*>(g.A) + tc.z * g.sAz;
   const float* B = static_cast<const float*>(g.B) + tc.z * g.sBz;
@@ -443,6 +473,11 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmAr
       }
 }
 
+template <bool NT, bool TC = false>
+__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+  CQ_TILE_LOOP((gemm_f32_tile<NT, TC>(g, vb)))
+}
+
 // ---------------------------------------------------------------------------
 // BF16 / FP16 with FP32 accumulation.  SPLIT = 3 issues hi*hi + hi*lo + lo*hi.
 // OUT: 0 = FP32, 1 = FP32 non-temporal, 2 = 16-bit planes (hi, and lo when
@@ -506,16 +541,14 @@ __device__ inline float from_h16(uint16_t x) {
 }
 
 template <int SPLIT, bool F16, int OUT>
-__global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmArgs gv,
-                                                                           const GemmArgs* __restrict__ gp) {
-  CQ_LOAD_GEMM_ARGS
+__device__ __forceinline__ void gemm_h16_tile(const GemmArgs& g, int64_t vb) {
   using H = Half<F16>;
   using V8 = typename H::V8;
   constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
   constexpr int NP = SPLIT == 3 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t As[NP][BM][LDK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][BN][LDK];
-  const TileCoord tc = tile_coord<BM, BN>(g);
+  const TileCoord tc = tile_coord_v<BM, BN>(g, vb);
   const int64_t m0 = tc.m0, n0 = tc.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -645,6 +678,12 @@ __global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmA
           }
         }
       }
+}
+
+template <int SPLIT, bool F16, int OUT>
+__global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmArgs gv,
+                                                                           const GemmArgs* __restrict__ gp) {
+  CQ_TILE_LOOP((gemm_h16_tile<SPLIT, F16, OUT>(g, vb)))
 }
 
 
@@ -1668,16 +1707,22 @@ hipError_t launch_tile_compact(const float* U, const int64_t* n_tiles,
   return hipGetLastError();
 }
 
+constexpr int64_t kTopcGrid = 1024;
+
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
                                 DType tc, bool nontemporal, bool topc, hipStream_t stream) {
   if (topc) {
+    // the tiles come from a pruned list whose length only the device knows:
+    // a few workgroups per CU walk it instead of one per possible tile (a
+    // grid of 2^18 workgroups that mostly exit costs 0.4-0.8 ms by itself)
+    const int64_t grid = max_tiles < kTopcGrid ? max_tiles : kTopcGrid;
     switch (prec) {
-      case CQ_FP64: return launch_ind(gemm_f64_kernel<false, true>, dev, max_tiles, stream, 512);
-      case CQ_FP32: return launch_ind(gemm_f32_kernel<false, true>, dev, max_tiles, stream);
-      case CQ_BF16: return launch_ind(gemm_h16_kernel<1, false, 3>, dev, max_tiles, stream);
-      case CQ_BF16_SPLIT: return launch_ind(gemm_h16_kernel<3, false, 3>, dev, max_tiles, stream);
-      case CQ_FP16: return launch_ind(gemm_h16_kernel<1, true, 3>, dev, max_tiles, stream);
-      case CQ_FP16_SPLIT: return launch_ind(gemm_h16_kernel<3, true, 3>, dev, max_tiles, stream);
+      case CQ_FP64: return launch_ind(gemm_f64_kernel<false, true>, dev, grid, stream, 512);
+      case CQ_FP32: return launch_ind(gemm_f32_kernel<false, true>, dev, grid, stream);
+      case CQ_BF16: return launch_ind(gemm_h16_kernel<1, false, 3>, dev, grid, stream);
+      case CQ_BF16_SPLIT: return launch_ind(gemm_h16_kernel<3, false, 3>, dev, grid, stream);
+      case CQ_FP16: return launch_ind(gemm_h16_kernel<1, true, 3>, dev, grid, stream);
+      case CQ_FP16_SPLIT: return launch_ind(gemm_h16_kernel<3, true, 3>, dev, grid, stream);
     }
     return hipErrorInvalidValue;
   }
