@@ -924,8 +924,8 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form (FP32 output, no output exponents), for 16-bit and FP32
-// operands.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
+// Persistent form (no output exponents), for 16-bit and FP32 operands, with
+// FP32 output or -- 16-bit operands -- 16-bit hi (and lo) output planes.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
 // workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
 // on across tile boundaries.  A finished tile's results stay in registers and
 // are written out in eight row slabs spread over the next tile's stages, so
@@ -955,6 +955,7 @@ struct PersistH16 {
   using H = Half<F16>;
   using V8 = typename H::V8;
   static constexpr int BK = 32, NP = SPLIT == 3 ? 2 : 1, RPI = 4, CW = 8;
+  static constexpr bool kF16 = F16;
   typedef uint16_t E;
   static __device__ int lrow(int lane) { return lane >> 4; }
   static __device__ int chunk(int lane) { return swz(lane >> 4, lane & 15); }
@@ -1015,6 +1016,7 @@ struct PersistH16 {
 // rows k and k + 1 -- fall into different banks.
 struct PersistF32 {
   static constexpr int BK = 16, NP = 1, RPI = 2, CW = 4;
+  static constexpr bool kF16 = false;
   typedef float E;
   static __device__ int lrow(int lane) { return lane >> 5; }
   static __device__ int chunk(int lane) { return (lane & 31) ^ (8 * (lane >> 5)); }
@@ -1157,7 +1159,29 @@ __global__ void __launch_bounds__(256, 2) gemm_persist_kernel(GemmArgs g) {
       const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + c * 4);
       const int64_t m = pt.m0 + wm + 32 * i + 8 * vg + rl, n = pt.n0 + wn + c;
       const int64_t idx = pt.z * g.sCz + m * g.ldc + n;
-      if (full || (m < g.M && n + 3 < g.N)) {
+      if constexpr (OUT == 2) {
+        // 16-bit planes: hi = rn16(x), and lo = rn16(x - hi) when C_lo is given
+        typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+        u16x4 hh, ll;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hh[e] = to_h16<P::kF16>(x[e]);
+          ll[e] = to_h16<P::kF16>(x[e] - from_h16<P::kF16>(hh[e]));
+        }
+        uint16_t* const ch = static_cast<uint16_t*>(g.C);
+        uint16_t* const cl = static_cast<uint16_t*>(g.C_lo);
+        if (full || (m < g.M && n + 3 < g.N)) {
+          *reinterpret_cast<u16x4*>(ch + idx) = hh;
+          if (cl) *reinterpret_cast<u16x4*>(cl + idx) = ll;
+        } else if (m < g.M) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (n + e < g.N) {
+              ch[idx + e] = hh[e];
+              if (cl) cl[idx + e] = ll[e];
+            }
+        }
+      } else if (full || (m < g.M && n + 3 < g.N)) {
         store_out<f4_t, OUT == 1>(reinterpret_cast<f4_t*>(static_cast<float*>(g.C) + idx), x);
       } else if (m < g.M) {
 #pragma unroll
@@ -1194,11 +1218,14 @@ __global__ void __launch_bounds__(256, 2) gemm_persist_kernel(GemmArgs g) {
     int ops = 0;
     if (i > 0) {
       const bool pfull = pt.m0 + BM <= g.M && pt.n0 + BN <= g.N;
+      // store instructions of a full slab: two rows of 16 bytes per lane, or
+      // of 8 bytes per plane for 16-bit output
+      const int per_slab = OUT == 2 ? (g.C_lo ? 4 : 2) : 2;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if ((u * nstages) / 8 == s) {
           slab(u);
-          if (pfull) ops += 2;
+          if (pfull) ops += per_slab;
         }
     }
     if (q + NS - 1 < total) {
@@ -1278,9 +1305,9 @@ int64_t persistent_grid(int64_t tiles) {
   return tiles < grid ? tiles : grid;
 }
 
-// the persistent kernel applies: FP32 output without exponents, K >= 1
+// the persistent kernel applies: no output exponents, K >= 1, aligned rows
 bool h16p_ok(const GemmArgs& a, DType tc) {
-  return tc == DType::F32 && a.rowexp == nullptr && a.K >= 1 && h16_async_ok(a, tc);
+  return a.rowexp == nullptr && a.K >= 1 && h16_async_ok(a, tc);
 }
 
 // FP32 operands for the persistent kernel: 16-byte aligned rows of at least
@@ -1300,7 +1327,8 @@ hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int
   if (impl == 3 && h16p_ok(a, tc)) {
     const int64_t grid = persistent_grid(a.tiles);
     using P = PersistH16<SPLIT, F16>;
-    if (nt) hipLaunchKernelGGL((gemm_persist_kernel<P, 1, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    if (tc != DType::F32) hipLaunchKernelGGL((gemm_persist_kernel<P, 2, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    else if (nt) hipLaunchKernelGGL((gemm_persist_kernel<P, 1, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((gemm_persist_kernel<P, 0, NSP>), dim3((unsigned)grid), dim3(256), 0, s, a);
     return hipGetLastError();
   }
