@@ -354,6 +354,90 @@ __global__ void __launch_bounds__(256) attr_init_reg_kernel(AttrArgs a) {
   }
 }
 
+// Both passes in one kernel for up to two measured and two initialised cut
+// ends (the dynamic-definition subcircuits): a thread owns one output column
+// b and walks the 3^O measurement bases; for each basis it loads the
+// 4^R x 2^O variant values V[j][basis][compose(b, m)] it needs (each element
+// of V is read once overall), forms U[j][lm] for the labels lm measured in
+// that basis, runs the init butterflies over j in registers and writes the
+// 4^R entries of each such lm.  U never reaches memory, so HBM sees V once
+// and E once.  Same operations in the same order as the two register passes.
+template <int R, int O>
+__global__ void __launch_bounds__(256) attr_fused_kernel(AttrArgs a) {
+  constexpr int NJ = 1 << (2 * R);                   // init digit strings
+  constexpr int NB = O == 0 ? 1 : (O == 1 ? 3 : 9);  // 3^O bases
+  constexpr int NM = 1 << O;                         // outcomes of the measured bits
+  constexpr int NL = 1 << (2 * O);                   // measured labels
+  const int64_t nb = (int64_t)1 << a.n;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += step) {
+    int64_t x0 = 0;
+    for (int q = 0; q < a.n; ++q)
+      if ((b >> (a.n - 1 - q)) & 1) x0 |= (int64_t)1 << a.out_pos[q];
+    int64_t xm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      int64_t x = x0;
+#pragma unroll
+      for (int u = 0; u < O; ++u)
+        if ((m >> (O - 1 - u)) & 1) x |= (int64_t)1 << a.meas_pos[u];
+      xm[m] = x;
+    }
+#pragma unroll
+    for (int beta = 0; beta < NB; ++beta) {
+      double v[NJ][NM];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) v[j][m] = a.V[(((int64_t)j * NB + beta) << a.w) + xm[m]];
+#pragma unroll
+      for (int lm = 0; lm < NL; ++lm) {
+        int bl = 0;
+#pragma unroll
+        for (int u = 0; u < O; ++u) bl = 3 * bl + basis_of((lm >> (2 * (O - 1 - u))) & 3);
+        if (bl != beta) continue;
+        double uj[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          double sum = 0.0;
+#pragma unroll
+          for (int m = 0; m < NM; ++m) {
+            bool neg = false;
+#pragma unroll
+            for (int u = 0; u < O; ++u)
+              if (((m >> (O - 1 - u)) & 1) && ((lm >> (2 * (O - 1 - u))) & 3) != 0) neg = !neg;
+            sum += neg ? -v[j][m] : v[j][m];
+          }
+          uj[j] = sum;
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int sd = 1 << (2 * (R - 1 - t));  // stride of init digit t
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            if ((j / sd) % 4 != 0) continue;
+            const double d0 = uj[j], d1 = uj[j + sd], d2 = uj[j + 2 * sd], d3 = uj[j + 3 * sd];
+            uj[j] = d0 + d1;                       // I
+            uj[j + sd] = 2.0 * d2 - d0 - d1;       // X
+            uj[j + 2 * sd] = 2.0 * d3 - d0 - d1;   // Y
+            uj[j + 3 * sd] = d0 - d1;              // Z
+          }
+        }
+        int64_t mrow = 0;
+#pragma unroll
+        for (int q = 0; q < O; ++q) mrow += ((lm >> (2 * (O - 1 - q))) & 3) * a.meas_w[q];
+#pragma unroll
+        for (int li = 0; li < NJ; ++li) {
+          int64_t row = mrow;
+#pragma unroll
+          for (int t = 0; t < R; ++t) row += ((li >> (2 * (R - 1 - t))) & 3) * a.init_w[t];
+          a.E[row * nb + b] = uj[li];
+        }
+      }
+    }
+  }
+}
+
 // Indirect launches size their grid for the largest shape and loop; a
 // moderate cap keeps the empty workgroups of smaller shapes cheap.
 unsigned grid_ind(int64_t total) {
@@ -527,6 +611,18 @@ hipError_t launch_attribute(const AttrLaunch& l, hipStream_t stream) {
   }
   const int64_t total = ((int64_t)1 << (2 * (l.r + l.o))) << l.n;
   const unsigned grid = grid_for(total);
+  if (l.r <= 2 && l.o <= 2) {
+    const dim3 gf(grid_for((int64_t)1 << l.n));
+#define CQ_ATTR_FUSED(R, O)                                                          \
+  if (l.r == R && l.o == O) {                                                        \
+    hipLaunchKernelGGL((attr_fused_kernel<R, O>), gf, dim3(256), 0, stream, a);     \
+    return hipGetLastError();                                                        \
+  }
+    CQ_ATTR_FUSED(0, 0) CQ_ATTR_FUSED(0, 1) CQ_ATTR_FUSED(0, 2)
+    CQ_ATTR_FUSED(1, 0) CQ_ATTR_FUSED(1, 1) CQ_ATTR_FUSED(1, 2)
+    CQ_ATTR_FUSED(2, 0) CQ_ATTR_FUSED(2, 1) CQ_ATTR_FUSED(2, 2)
+#undef CQ_ATTR_FUSED
+  }
   const dim3 gm(grid_for(((int64_t)1 << (2 * l.r)) << l.n)), gi(grid_for(((int64_t)1 << (2 * l.o)) << l.n));
   switch (l.o) {
     case 0: hipLaunchKernelGGL(attr_meas_reg_kernel<0>, gm, dim3(256), 0, stream, a); break;

@@ -439,6 +439,33 @@ def test_32_qubit_chain_of_four_accuracy_matrix(prec):
 
 # --- attribution: register-butterfly and general kernels ---------------------
 
+def test_attribution_full_dd_shape_sampled_columns():
+    """The DD subcircuit shape (22 slots: init slots 0, 1 for cuts 0, 1;
+    measured slots 20, 21 for cuts 2, 3; 20 outputs), variants (16, 9, 2^22)
+    uniform random on the device.  The oracle attributes a reduced subcircuit
+    with the same cut slots and 8 outputs whose variant columns are gathered
+    from 256 sampled output values b: its column s equals column b_s of the
+    full result (the measured bits are the two least significant slots in
+    both, so outcome(b, m) = 4 b + m)."""
+    m = cq()
+    sub = (22, [0, 1] + [-1] * 20, [-1] * 20 + [2, 3])
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(7)
+    V = torch.rand((16, 9, 2 ** 22), dtype=torch.float64, device=DEV, generator=gen)
+    print("attribution at the DD shape", flush=True)
+    E = m.cq_attribute(sub, V)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    bs = np.sort(rng.choice(2 ** 20, size=256, replace=False)).astype(np.int64)
+    cols = (4 * bs[:, None] + np.arange(4)[None, :]).ravel()  # sample s, outcome m -> 4 s + m
+    Vs = V[:, :, torch.from_numpy(cols).to(DEV)].cpu().numpy()
+    small = (10, [0, 1] + [-1] * 8, [-1] * 8 + [2, 3])
+    ref = at.attribute(small, Vs)
+    got = E[:, torch.from_numpy(bs).to(DEV)].cpu().numpy()
+    assert got.shape == ref.shape == (256, 256)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("r,o", [(0, 0), (0, 2), (1, 1), (2, 2), (3, 1), (3, 2), (4, 1), (1, 3), (2, 4)])
 def test_attribution_all_pass_shapes(r, o):
     """Random (non-physical) variant tensors through every attribution kernel
