@@ -1292,15 +1292,15 @@ bool h16_async_ok(const GemmArgs& a, DType tc) {
 // Persistent grid: two workgroups per compute unit, a multiple of 8 so that
 // workgroup b stays on XCD b % 8 for every tile it takes.
 int64_t persistent_grid(int64_t tiles) {
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64];  // compute units per device, 0 until asked
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cus[dev] <= 0) {
-    int n = 0;
+  int n = cus[dev].load(std::memory_order_relaxed);
+  if (n <= 0) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cus[dev] = n;
+    cus[dev].store(n, std::memory_order_relaxed);
   }
-  int64_t grid = 2 * (int64_t)cus[dev];
+  int64_t grid = 2 * (int64_t)n;
   grid -= grid % 8;
   return tiles < grid ? tiles : grid;
 }
