@@ -613,37 +613,51 @@ __global__ void dd_init_kernel(DDState* st, cq_dd_record* recs, int R, DDInit in
   st->total = 0.0;
 }
 
+// One workgroup of 64 threads: every thread derives the active counts (a
+// few words), thread c < n_sub writes subcircuit c's descriptors, thread
+// 32 + s step s's, and thread 0 the recursion-wide fields -- the descriptor
+// writes are independent, so they no longer run one after another.
 __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DDLevel* lv,
                                 cq_dd_record* recs, int r, void* bins) {
-  if (threadIdx.x != 0) return;
-  const int ns = P->n_sub;
+  const int tid = threadIdx.x;
+  const int ns = P->n_sub, nsteps = P->n_steps;
+  const int step = tid - 32;  // the step this thread describes, if in range
   if (st->stop) {
-    for (int c = 0; c < ns; ++c) {
-      lv->merge[c].outputs = 0;
-      lv->rowsum[c].outputs = 0;
-      lv->prep[c].n = 0;
+    if (tid < ns) {
+      lv->merge[tid].outputs = 0;
+      lv->rowsum[tid].outputs = 0;
+      lv->prep[tid].n = 0;
     }
-    for (int s = 0; s < P->n_steps; ++s) {
-      lv->gemm[s].tiles = 0;
-      lv->perm[s].total = 0;
+    if (step >= 0 && step < nsteps) {
+      lv->gemm[step].tiles = 0;
+      lv->perm[step].total = 0;
     }
-    lv->refine.nbins = 0;
-    st->C = 0;
-    st->count = 0;
+    if (tid == 0) {
+      lv->refine.nbins = 0;
+      st->C = 0;
+      st->count = 0;
+    }
     return;
   }
-  cq_dd_record& rec = recs[r];
   int32_t na[CQ_MAX_SUBCIRCUITS];
   int sum = 0;
   bool any_merged = false;
   for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) na[c] = 0;
   for (int c = 0; c < ns; ++c) {
+    na[c] = __popcll(st->active[c]);
+    sum += na[c];
+    any_merged = any_merged || st->merged[c] != 0;
+  }
+  const int64_t count = (int64_t)1 << sum;
+  const int C = any_merged ? (int)(count < P->C_max ? count : P->C_max) : 0;
+  // without stored bins and with nothing to select, the bins are not needed
+  const bool skip = P->topc_step >= 0 && C == 0;
+  cq_dd_record& rec = recs[r];
+  if (tid < ns) {
+    const int c = tid;
     const int n = P->n_out[c];
     const uint64_t act = st->active[c], mer = st->merged[c], fv = st->fixed_vals[c];
-    na[c] = __popcll(act);
     st->na[c] = na[c];
-    sum += na[c];
-    any_merged = any_merged || mer != 0;
     rec.active[c] = act;
     rec.merged[c] = mer;
     rec.fixed[c] = st->fixed[c];
@@ -657,28 +671,16 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
     pa.src = P->Ep[c];
     pa.dst = t >= 0 ? P->tensor[t].hi : nullptr;
     pa.dst_lo = t >= 0 ? P->tensor[t].lo : nullptr;
-    pa.n = t >= 0 ? sym_pow(P->tensor_elems[t], na) : 0;
+    pa.n = (t >= 0 && !skip) ? sym_pow(P->tensor_elems[t], na) : 0;
   }
-  rec.n_active = sum;
-  st->n_active = sum;
-  const int64_t count = (int64_t)1 << sum;
-  st->count = count;
-  st->C = any_merged ? (int)(count < P->C_max ? count : P->C_max) : 0;
-  // without stored bins and with nothing to select, the bins are not needed
-  const bool skip = P->topc_step >= 0 && st->C == 0;
-  if (P->topc_step >= 0) {
-    st->topc_thr = 0x000fffffffffffffull;  // order-preserving key of -infinity
-    st->topc_count = 0;
-  }
-  if (skip)
-    for (int c = 0; c < ns; ++c) lv->prep[c].n = 0;
-  for (int s = 0; s < P->n_steps; ++s) {
+  if (step >= 0 && step < nsteps) {
+    const int s = step;
     if (P->step_is_gemm[s]) {
       const DDGemmSym& G = P->gemm[s];
       const DDTensor& ta = P->tensor[G.a];
       const DDTensor& tb = P->tensor[G.b];
       const DDTensor& tc = P->tensor[G.c];
-      GemmArgs& g = lv->gemm[s];
+      GemmArgs g;
       const int64_t Z = sym_pow(G.Z, na), M = sym_pow(G.M, na), N = sym_pow(G.N, na);
       const int64_t K = sym_pow(G.K, na);
       g.A = ta.hi;
@@ -714,6 +716,21 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       const double a_elems = double(g.sAz ? Z : 1) * double(M) * double(K);
       const double b_elems = double(g.sBz ? Z : 1) * double(N) * double(K);
       g.m_fastest = b_elems > a_elems ? 1 : 0;
+      lv->gemm[s] = g;
+      if (tc_here) {
+        // tile pruning: the 64 tiles with the largest bounds raise the
+        // threshold first, then only tiles whose bound reaches it are
+        // multiplied
+        st->n_tiles = g.tiles;
+        st->warm_C = (int)(g.tiles < 64 ? g.tiles : 64);
+        st->warm_count = st->warm_C;
+        st->list_count = 0;
+        GemmArgs w = g;
+        w.tile_list = P->warm_i;
+        w.tile_count = &st->warm_count;
+        w.topc_publish_only = 1;
+        lv->topc_warm = w;
+      }
     } else {
       const DDPermSym& Q = P->perm[s];
       const DDTensor& ts = P->tensor[Q.src];
@@ -736,34 +753,30 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       p.nfac = 0;
     }
   }
-  if (P->topc_step >= 0) {
-    // tile pruning: the 64 tiles with the largest bounds raise the threshold
-    // first, then only tiles whose bound reaches it are multiplied
-    const GemmArgs& gm = lv->gemm[P->topc_step];
-    st->n_tiles = gm.tiles;
-    st->warm_C = (int)(gm.tiles < 64 ? gm.tiles : 64);
-    st->warm_count = st->warm_C;
-    st->list_count = 0;
-    GemmArgs& w = lv->topc_warm;
-    w = gm;
-    w.tile_list = P->warm_i;
-    w.tile_count = &st->warm_count;
-    w.topc_publish_only = 1;
+  if (tid == 0) {
+    rec.n_active = sum;
+    st->n_active = sum;
+    st->count = count;
+    st->C = C;
+    if (P->topc_step >= 0) {
+      st->topc_thr = 0x000fffffffffffffull;  // order-preserving key of -infinity
+      st->topc_count = 0;
+    }
+    RefineArgs& f = lv->refine;
+    f.n_sub = ns;
+    f.K = P->K;
+    for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
+      f.Ep[c] = c < ns ? P->Ep[c] : nullptr;
+      f.ld[c] = (int64_t)1 << na[c];
+      f.na[c] = na[c];
+      f.kc[c] = c < ns ? P->kc[c] : 0;
+      for (int j = 0; j < CQ_MAX_LOCAL_CUTS; ++j) f.cut[c][j] = P->cut[c][j];
+    }
+    f.bins = st->top_idx;
+    f.nbins = C;
+    f.scale = ldexp(1.0, -P->K);
+    f.out = st->ref_val;
   }
-  RefineArgs& f = lv->refine;
-  f.n_sub = ns;
-  f.K = P->K;
-  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
-    f.Ep[c] = c < ns ? P->Ep[c] : nullptr;
-    f.ld[c] = (int64_t)1 << na[c];
-    f.na[c] = na[c];
-    f.kc[c] = c < ns ? P->kc[c] : 0;
-    for (int j = 0; j < CQ_MAX_LOCAL_CUTS; ++j) f.cut[c][j] = P->cut[c][j];
-  }
-  f.bins = st->top_idx;
-  f.nbins = st->C;
-  f.scale = ldexp(1.0, -P->K);
-  f.out = st->ref_val;
 }
 
 __device__ inline bool entry_before(double v1, int r1, uint64_t b1, double v2, int r2, uint64_t b2) {
@@ -772,10 +785,10 @@ __device__ inline bool entry_before(double v1, int r1, uint64_t b1, double v2, i
   return b1 < b2;
 }
 
-__global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* st, cq_dd_record* recs,
-                                 int r) {
-  if (threadIdx.x != 0) return;
-  if (st->stop) return;
+// The list update reads and rewrites a few kilobytes of state in a long
+// dependent chain; one thread runs it on a copy of the state in LDS (the 64
+// threads copy it in and out), not through global memory.
+__device__ void dd_update_body(const DDProgram* __restrict__ P, DDState* st, cq_dd_record* recs, int r) {
   cq_dd_record& rec = recs[r];
   rec.total = st->total;
   const int ns = P->n_sub, R = P->R, C = st->C;
@@ -857,6 +870,22 @@ __global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* st, c
   }
   for (int q = 0; q + 1 < nl; ++q) st->list[q] = st->list[q + 1];
   st->n_list = nl - 1;
+}
+
+__global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* gst, cq_dd_record* recs,
+                                 int r) {
+  __shared__ DDState S;
+  static_assert(sizeof(DDState) % 8 == 0, "state copied in 8-byte words");
+  constexpr int W = (int)(sizeof(DDState) / 8);
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(gst);
+  uint64_t* lds = reinterpret_cast<uint64_t*>(&S);
+  for (int i = threadIdx.x; i < W; i += blockDim.x) lds[i] = src[i];
+  __syncthreads();
+  if (S.stop) return;
+  if (threadIdx.x == 0) dd_update_body(P, &S, recs, r);
+  __syncthreads();
+  uint64_t* dst = reinterpret_cast<uint64_t*>(gst);
+  for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = lds[i];
 }
 
 }  // namespace
