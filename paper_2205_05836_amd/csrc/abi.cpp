@@ -888,12 +888,12 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   // device programs (host images stay alive until the final synchronisation)
   char* ctrl0 = ws + (int64_t)lanes * align256(big);
   std::vector<DDProgram> progs(n_inst);
-  for (int i = 0; i < n_inst; ++i)
+  for (int i = 0; i < n_inst; ++i) {
     dd_program(plans[i], inst[i], *params, ws + (int64_t)(i % lanes) * align256(big), progs[i]);
-  // one strided copy for all instances' programs (control blocks L.bytes apart)
-  hipError_t e = hipMemcpy2DAsync(ctrl0 + L.prog, (size_t)L.bytes, progs.data(), sizeof(DDProgram),
-                                  sizeof(DDProgram), (size_t)n_inst, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "program upload");
+    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
+    hipError_t e = hipMemcpyAsync(ctrl + L.prog, &progs[i], sizeof(DDProgram), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "program upload");
+  }
   DDLaneSet lane_set;  // destroyed after the graph (declared first)
   DDGraph graph;
   if (params->launch == CQ_DD_GRAPH)
@@ -901,16 +901,17 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   else
     st = dd_enqueue_all(n_inst, *params, plans, bins, ws, big, lanes, stream, lane_set);
   if (st != CQ_OK) return st;
-  // records and recursion counts of all instances, one strided copy each
   std::vector<int32_t> done(n_inst, 0);
-  const size_t rec_bytes = sizeof(cq_dd_record) * (size_t)params->R;
-  e = hipMemcpy2DAsync(records, rec_bytes, ctrl0 + L.recs, (size_t)L.bytes, rec_bytes, (size_t)n_inst,
-                       hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpy2DAsync(done.data(), sizeof(int32_t), ctrl0 + L.state + offsetof(DDState, done),
-                         (size_t)L.bytes, sizeof(int32_t), (size_t)n_inst, hipMemcpyDeviceToHost, stream);
-  if (e != hipSuccess) return hip_fail(e, "record readback");
-  e = hipStreamSynchronize(stream);
+  for (int i = 0; i < n_inst; ++i) {
+    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
+    hipError_t e = hipMemcpyAsync(records + (size_t)i * params->R, ctrl + L.recs,
+                                  sizeof(cq_dd_record) * params->R, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&done[i], ctrl + L.state + offsetof(DDState, done), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "record readback");
+  }
+  hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "synchronise");
   for (int i = 0; i < n_inst; ++i) recursions_done[i] = done[i];
   return CQ_OK;
