@@ -351,6 +351,31 @@ def test_h16_chain_of_four_split():
     assert np.all(err <= H16_REL["bf16_split"] * scale + FP32_FLOOR)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_30_qubit_chain_variants_bit_equal(prec):
+    """At the benchmark shape every GEMM variant -- one tile per workgroup,
+    flipped raster, persistent -- gives the same 2^30 outputs bit for bit
+    (same products, same order), so the autotuner's choice never changes a
+    result."""
+    m = cq()
+    cm = syn.chain_cutmap(BONDS_30Q, NS_30Q)
+    ents = _entries_30q()
+    ref = None
+    try:
+        for v in (0, 1, 6, 7):
+            m.cq_autotune_enable(variant=v)
+            print(f"30q {prec} variant {v}", flush=True)
+            out = m.cq_reconstruct_fd(cm, ents, prec=prec)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out
+            else:
+                assert torch.equal(out, ref), (prec, v)
+                del out
+    finally:
+        m.cq_autotune_enable(True)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
 def test_30_qubit_chain_full_size_h16(prec):
     m = cq()
