@@ -127,3 +127,47 @@ def run(subs, entries, states0, max_active, R):
         states = zoom(ch, max_active)
         r += 1
     return records
+
+
+def run_bfs(subs, entries, states0, max_active, levels, width):
+    """Breadth-first dynamic definition (the BFS-like query for dense
+    outputs, Section 4.3): a landscape refined level by level.
+
+    Readings where the paper gives only the strategy's name:
+
+    * A node is one recursion: its 2^{#active} bins are reconstructed and its
+      candidates are its ``width`` largest bins that still contain merged
+      qubits, ordered by value descending, then bin index ascending.
+    * Level 0 is the single node with the initial labels.  Level l + 1 has
+      one node per each of the ``width`` best candidates over all level-l
+      nodes, ordered by value descending, then parent node (in level order)
+      ascending, then bin index ascending; the node zooms into its bin with
+      the same rules as Algorithm 1 (the bin's active bits become fixed, the
+      first ``max_active[c]`` merged qubits become active).
+    * The query ends after ``levels`` levels or at a level with no
+      candidates.
+
+    Returns the nodes in level order: dict(level, parent (node index, -1
+    for the root), parent_bin, states, bins, total, candidates [(value, bin)]).
+    """
+    nodes = []
+    frontier = [(-1, 0, [st.copy() for st in states0])]
+    for level in range(levels):
+        if not frontier:
+            break
+        cands = []
+        for parent, pbin, states in frontier:
+            bins = bins_of(subs, entries, states)
+            mine = []
+            if any(st.merged for st in states):
+                order = sorted(range(len(bins)), key=lambda i: (-bins[i], i))[:width]
+                mine = [(float(bins[i]), i) for i in order]
+            k = len(nodes)
+            nodes.append(dict(level=level, parent=parent, parent_bin=pbin,
+                              states=[st.copy() for st in states], bins=bins,
+                              total=float(np.sum(bins)), candidates=mine))
+            cands += [(v, k, i) for (v, i) in mine]
+        cands.sort(key=lambda e: (-e[0], e[1], e[2]))
+        frontier = [(k, i, zoom(child_states(nodes[k]["states"], i), max_active))
+                    for (v, k, i) in cands[:width]]
+    return nodes

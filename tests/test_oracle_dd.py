@@ -137,3 +137,60 @@ def test_hidden_string_found_in_linear_recursions():
     for i, q in enumerate(perm):
         state[q] = bits[i]
     assert state == secret + [1]
+
+
+# --- breadth-first query (dense outputs) --------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bfs_nodes_are_brute_force_bins_and_refine_their_parent(seed):
+    """Every node's bins are brute-force sums of the full distribution over
+    its labels; a child's bins partition the parent bin it zooms into; each
+    level zooms into the best candidates of the level above (value desc,
+    then parent, then bin) and every node's candidates are its best bins."""
+    rng = np.random.default_rng(40 + seed)
+    bonds = [int(rng.integers(1, 3)), int(rng.integers(1, 3))]
+    ns = [4, 3, 4]
+    cm = syn.chain_cutmap(bonds, ns)
+    E = [syn.integer_entries(rng, k, n, lo=0, hi=3) for k, n in zip(syn.chain_ks(bonds, 3), ns)]
+    p = rc.fd_definition(cm, E)
+    M = [1, 1, 2]
+    W = 3
+    nodes = dd.run_bfs(cm, E, dd.initial_states(cm, M), M, levels=3, width=W)
+    assert nodes[0]["level"] == 0 and nodes[0]["parent"] == -1
+    by_level = {}
+    for k, nd in enumerate(nodes):
+        by_level.setdefault(nd["level"], []).append(k)
+        assert np.array_equal(nd["bins"], brute_force_bins(cm, p, nd["states"]))
+        if nd["parent"] >= 0:
+            par = nodes[nd["parent"]]
+            assert par["level"] == nd["level"] - 1
+            assert nd["total"] == par["bins"][nd["parent_bin"]]   # integer sums: exact
+        # candidates: the W best bins (value desc, index asc) of a node that still merges
+        if any(st.merged for st in nd["states"]):
+            want = sorted(range(len(nd["bins"])), key=lambda i: (-nd["bins"][i], i))[:W]
+            assert [i for (_, i) in nd["candidates"]] == want
+    for lv in range(1, max(by_level) + 1):
+        pool = [(v, k, i) for k in by_level[lv - 1] for (v, i) in nodes[k]["candidates"]]
+        pool.sort(key=lambda e: (-e[0], e[1], e[2]))
+        got = [(nodes[k]["parent"], nodes[k]["parent_bin"]) for k in by_level[lv]]
+        assert got == [(k, i) for (_, k, i) in pool[:W]]
+    assert len(by_level) == 3 and len(by_level[1]) == W
+
+
+def test_bfs_reaches_full_definition_of_the_heaviest_region():
+    """With nothing left merged after enough levels, the deepest nodes'
+    bins are single probabilities of the full distribution."""
+    cm, E = syn.chain_instance(9, [1, 1], [3, 3, 3])
+    p = rc.fd_definition(cm, E)
+    M = [1, 1, 1]
+    nodes = dd.run_bfs(cm, E, dd.initial_states(cm, M), M, levels=3, width=2)
+    deep = [nd for nd in nodes if nd["level"] == 2]
+    assert deep
+    for nd in deep:
+        assert not any(st.merged for st in nd["states"])
+        assert not nd["candidates"]
+        ref = brute_force_bins(cm, p, nd["states"])
+        assert np.max(np.abs(nd["bins"] - ref)) < 1e-15
+    # a level with no candidates ends the query
+    more = dd.run_bfs(cm, E, dd.initial_states(cm, M), M, levels=6, width=2)
+    assert max(nd["level"] for nd in more) == 2
