@@ -235,6 +235,10 @@ DD_WORKLOAD = ("batched DD: 16 chain instances x 4 subcircuits x 20 outputs (80 
                "R = 4 recursions, one hipGraph per batch")
 
 
+DD_BFS_LEVELS = 4
+DD_BFS_WIDTH = 4
+
+
 def dd_leg(torch, cq, forms, runs):
     """Times the whole batch (16 instances x R recursions, one call, graph
     launch) per precision; flops are the planner's per recursion shape."""
@@ -288,6 +292,22 @@ def dd_leg(torch, cq, forms, runs):
                            "algorithmic_flops": flops,
                            "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                            "same_zoom_path_as_first_form": lists == ref_lists}
+    # breadth-first query on the first instance: levels of nodes with 2^32
+    # bins each, every level one batched call
+    f = forms[0]
+    ws = torch.empty(cq.cq_dd_bfs_workspace_size(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH),
+                     dtype=torch.uint8, device="cuda:0")
+    cq.cq_reconstruct_dd_bfs(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nodes = cq.cq_reconstruct_dd_bfs(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    del ws
+    bins = sum(2 ** nd["n_active"] for nd in nodes)
+    out["bfs"] = {"precision": f, "levels": DD_BFS_LEVELS, "width": DD_BFS_WIDTH,
+                  "nodes": len(nodes), "bins": bins, "ms": round(ms, 3),
+                  "bins_per_s": bins / (ms * 1e-3)}
     return out
 
 

@@ -238,6 +238,50 @@ cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst, const cq
                             cq_dd_record* records, void* const* bins, int32_t* recursions_done,
                             void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* -------------------------------------------------------------------------
+ * Breadth-first dynamic definition (Section 4.3: the BFS-like query that
+ * builds a "blurred" landscape of a dense distribution).
+ *
+ * A node is one recursion of the root instance's circuit: its bins are
+ * reconstructed as in cq_reconstruct_dd and its candidates are its `width`
+ * largest bins (FP64-refined values) that still contain merged outputs,
+ * value descending, then bin index ascending (node.rec.list_*, n_list of
+ * them; list_rec is 0).  Level 0 is the root.  Level l + 1 has one node for
+ * each of the `width` best candidates over all level-l nodes -- value
+ * descending, then parent node ascending, then bin ascending -- zoomed as in
+ * cq_reconstruct_dd: the bin's active outputs become fixed at its values and
+ * the first max_active[c] merged outputs become active.  The query stops
+ * after `levels` levels or at a level without candidates.  Each level runs
+ * as one batched call (all its nodes captured together).
+ * ------------------------------------------------------------------------- */
+typedef struct cq_dd_bfs_params {
+  cq_precision prec;  /* arithmetic of the bin contractions */
+  int32_t levels;     /* >= 1 */
+  int32_t width;      /* nodes per level and candidates per node, 1..CQ_MAX_DD_R */
+  int32_t launch;     /* cq_dd_launch, per level */
+} cq_dd_bfs_params;
+
+typedef struct cq_dd_bfs_node {
+  cq_dd_record rec;     /* the node's recursion: masks, n_active, total, candidates */
+  int32_t level;
+  int32_t parent;       /* index of the parent node in the output, -1 for the root */
+  uint64_t parent_bin;  /* the parent's bin this node zooms into (0 for the root) */
+} cq_dd_bfs_node;
+
+/* Workspace for one level: `width` nodes planned like the root. */
+cq_status cq_dd_bfs_workspace_size(const cq_dd_instance* root, const cq_dd_bfs_params* params,
+                                   size_t* bytes);
+
+/* root: as for cq_reconstruct_dd (entries stay on the device for the whole
+ * query).  nodes: host, max_nodes >= 1 + (levels - 1) * width, filled in
+ * level order; *n_nodes receives the count.  Validation of the root happens
+ * before the first launch; each level is validated before its launches, so
+ * an error at level l leaves the nodes of levels < l written.  Synchronises
+ * `stream` once per level. */
+cq_status cq_reconstruct_dd_bfs(const cq_dd_instance* root, const cq_dd_bfs_params* params,
+                                cq_dd_bfs_node* nodes, int32_t max_nodes, int32_t* n_nodes,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

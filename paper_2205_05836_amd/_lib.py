@@ -20,7 +20,8 @@ EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune
             "cq_autotune_json",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
-            "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd"]
+            "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd",
+            "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs"]
 
 
 class cq_subcircuit(C.Structure):
@@ -50,6 +51,15 @@ class cq_dd_record(C.Structure):
                 ("n_active", C.c_int32), ("total", C.c_double), ("n_list", C.c_int32),
                 ("list_val", C.c_double * MAX_DD_R), ("list_rec", C.c_int32 * MAX_DD_R),
                 ("list_bin", C.c_uint64 * MAX_DD_R), ("popped", C.c_int32)]
+
+
+class cq_dd_bfs_params(C.Structure):
+    _fields_ = [("prec", C.c_int), ("levels", C.c_int32), ("width", C.c_int32), ("launch", C.c_int32)]
+
+
+class cq_dd_bfs_node(C.Structure):
+    _fields_ = [("rec", cq_dd_record), ("level", C.c_int32), ("parent", C.c_int32),
+                ("parent_bin", C.c_uint64)]
 
 
 _lib = None
@@ -86,6 +96,13 @@ def lib():
     L.cq_dd_workspace_size.restype = st
     L.cq_dd_workspace_size.argtypes = [C.c_int32, C.POINTER(cq_dd_instance),
                                        C.POINTER(cq_dd_params), C.c_int32, C.POINTER(C.c_size_t)]
+    L.cq_dd_bfs_workspace_size.restype = st
+    L.cq_dd_bfs_workspace_size.argtypes = [C.POINTER(cq_dd_instance), C.POINTER(cq_dd_bfs_params),
+                                           C.POINTER(C.c_size_t)]
+    L.cq_reconstruct_dd_bfs.restype = st
+    L.cq_reconstruct_dd_bfs.argtypes = [C.POINTER(cq_dd_instance), C.POINTER(cq_dd_bfs_params),
+                                        C.POINTER(cq_dd_bfs_node), C.c_int32, C.POINTER(C.c_int32),
+                                        C.c_void_p, C.c_size_t, C.c_void_p]
     L.cq_reconstruct_dd.restype = st
     L.cq_reconstruct_dd.argtypes = [C.c_int32, C.POINTER(cq_dd_instance), C.POINTER(cq_dd_params),
                                     C.POINTER(cq_dd_record), C.POINTER(C.c_void_p),

@@ -223,6 +223,43 @@ def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, st
     return out, list(done)
 
 
+def _record_dict(rc, ns):
+    return dict(active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
+                fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
+                n_active=rc.n_active, total=rc.total,
+                list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],
+                popped=bool(rc.popped))
+
+
+def cq_dd_bfs_workspace_size(instance, prec="fp64", levels=2, width=4):
+    ins = _Instances([instance])
+    par = _lib.cq_dd_bfs_params(_lib.PRECISION[prec], int(levels), int(width), 0)
+    b = C.c_size_t()
+    check(lib().cq_dd_bfs_workspace_size(ins.arr, C.byref(par), C.byref(b)))
+    return b.value
+
+
+def cq_reconstruct_dd_bfs(instance, prec="fp64", levels=2, width=4, workspace=None, stream=None,
+                          launch="graph"):
+    """Breadth-first dynamic definition from one root instance (a dict as
+    for cq_reconstruct_dd).  Returns the nodes in level order, each a dict:
+    level, parent (node index, -1 for the root), parent_bin, and the
+    node's record (masks, n_active, total, candidates in ``list``)."""
+    ins = _Instances([instance])
+    par = _lib.cq_dd_bfs_params(_lib.PRECISION[prec], int(levels), int(width),
+                                _lib.DD_LAUNCH[launch])
+    nbytes = cq_dd_bfs_workspace_size(instance, prec, levels, width)
+    ws = _workspace(nbytes, instance["entries"][0].device, workspace)
+    cap = max(1, 1 + (int(levels) - 1) * int(width))
+    nodes = (_lib.cq_dd_bfs_node * cap)()
+    n = C.c_int32()
+    check(lib().cq_reconstruct_dd_bfs(ins.arr, C.byref(par), nodes, cap, C.byref(n), _dev_ptr(ws),
+                                      C.c_size_t(nbytes), _stream(stream)))
+    ns = len(instance["subs"])
+    return [dict(level=nodes[k].level, parent=nodes[k].parent, parent_bin=nodes[k].parent_bin,
+                 **_record_dict(nodes[k].rec, ns)) for k in range(n.value)]
+
+
 def cq_plan_json(subs, prec="fp64", out_bits=None, out_perm=None):
     """The contraction plan as a dict (host only, launches nothing)."""
     import json

@@ -741,7 +741,7 @@ struct DDLaneSet {
   }
 };
 
-cq_status dd_enqueue_instance(int i, const cq_dd_params& p, const DDInstancePlan& D,
+cq_status dd_enqueue_instance(int i, const cq_dd_params& p, int recursions, const DDInstancePlan& D,
                               void* const* bins_user, char* region, char* ctrl, hipStream_t stream) {
   const DDCtrl L = dd_ctrl(p.R);
   DDInit init;
@@ -755,7 +755,7 @@ cq_status dd_enqueue_instance(int i, const cq_dd_params& p, const DDInstancePlan
   hipError_t e = launch_dd_init(reinterpret_cast<DDState*>(ctrl + L.state),
                                 reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, init, stream);
   if (e != hipSuccess) return hip_fail(e, "init launch");
-  for (int r = 0; r < p.R; ++r) {
+  for (int r = 0; r < recursions; ++r) {
     void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
     if (!bins && D.topc_step < 0) bins = region + D.bins_off;
     cq_status st = dd_enqueue_level(D, p, region, ctrl, r, bins, stream);
@@ -766,14 +766,15 @@ cq_status dd_enqueue_instance(int i, const cq_dd_params& p, const DDInstancePlan
 
 // Enqueues the batch behind `stream`: lane l runs instances l, l + lanes, ...
 // on a stream of its own forked from and joined back into `stream`.
-cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p,
+cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
                          const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
                          int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
   const DDCtrl L = dd_ctrl(p.R);
   char* ctrl0 = ws + (int64_t)lanes * align256(big);
   if (lanes <= 1) {
     for (int i = 0; i < n_inst; ++i) {
-      cq_status st = dd_enqueue_instance(i, p, plans[i], bins_user, ws, ctrl0 + (int64_t)i * L.bytes, stream);
+      cq_status st = dd_enqueue_instance(i, p, recursions, plans[i], bins_user, ws, ctrl0 + (int64_t)i * L.bytes,
+                                         stream);
       if (st != CQ_OK) return st;
     }
     return CQ_OK;
@@ -793,7 +794,8 @@ cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p,
     if (e != hipSuccess) return hip_fail(e, "lane wait");
     char* region = ws + (int64_t)l * align256(big);
     for (int i = l; i < n_inst; i += lanes) {
-      cq_status st = dd_enqueue_instance(i, p, plans[i], bins_user, region, ctrl0 + (int64_t)i * L.bytes, s);
+      cq_status st = dd_enqueue_instance(i, p, recursions, plans[i], bins_user, region,
+                                         ctrl0 + (int64_t)i * L.bytes, s);
       if (st != CQ_OK) return st;
     }
     hipEvent_t join = nullptr;
@@ -821,7 +823,7 @@ struct DDGraph {
 };
 
 // Captures the batch on a private stream and launches it once on `stream`.
-cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p,
+cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions,
                        const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
                        int64_t big, int lanes, hipStream_t stream, DDGraph& G, DDLaneSet& ls) {
   hipStream_t cs = nullptr;
@@ -832,7 +834,7 @@ cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p,
     (void)hipStreamDestroy(cs);
     return hip_fail(e, "begin capture");
   }
-  cq_status st = dd_enqueue_all(n_inst, p, plans, bins_user, ws, big, lanes, cs, ls);
+  cq_status st = dd_enqueue_all(n_inst, p, recursions, plans, bins_user, ws, big, lanes, cs, ls);
   e = hipStreamEndCapture(cs, &G.graph);
   (void)hipStreamDestroy(cs);
   if (st != CQ_OK) return st;
@@ -861,10 +863,15 @@ extern "C" cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* 
   return CQ_OK;
 }
 
-extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst,
-                                       const cq_dd_params* params, cq_dd_record* records,
-                                       void* const* bins, int32_t* recursions_done, void* workspace,
-                                       size_t workspace_bytes, hipStream_t stream) {
+namespace {
+
+// Validates, plans and runs a batch: every instance for `recursions` (<= R)
+// recursions, R being the list capacity.  Records are instance-major, R per
+// instance.
+cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params* params,
+                       int recursions, cq_dd_record* records, void* const* bins,
+                       int32_t* recursions_done, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream) {
   if (n_inst < 1 || !inst || !params || !records || !recursions_done)
     return fail(CQ_ERR_ARG, "null or empty argument");
   if (!prec_supported(params->prec)) return fail(CQ_ERR_UNSUPPORTED, "precision not built");
@@ -876,6 +883,7 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   int lanes = 1;
   cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, plans, big, lanes, total);
   if (st != CQ_OK) return st;
+  if (recursions < 1 || recursions > params->R) return fail(CQ_ERR_ARG, "recursion count out of range");
   if (!workspace || (int64_t)workspace_bytes < total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
   if (bins)
     for (int i = 0; i < n_inst; ++i)
@@ -897,9 +905,9 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   DDLaneSet lane_set;  // destroyed after the graph (declared first)
   DDGraph graph;
   if (params->launch == CQ_DD_GRAPH)
-    st = dd_run_graph(n_inst, *params, plans, bins, ws, big, lanes, stream, graph, lane_set);
+    st = dd_run_graph(n_inst, *params, recursions, plans, bins, ws, big, lanes, stream, graph, lane_set);
   else
-    st = dd_enqueue_all(n_inst, *params, plans, bins, ws, big, lanes, stream, lane_set);
+    st = dd_enqueue_all(n_inst, *params, recursions, plans, bins, ws, big, lanes, stream, lane_set);
   if (st != CQ_OK) return st;
   std::vector<int32_t> done(n_inst, 0);
   for (int i = 0; i < n_inst; ++i) {
@@ -914,6 +922,146 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "synchronise");
   for (int i = 0; i < n_inst; ++i) recursions_done[i] = done[i];
+  return CQ_OK;
+}
+
+// Masks of the node that zooms into bin `bin` of record `rec`: the bin's
+// active bits become fixed at the bin's values, then the first max_active[c]
+// merged outputs (output order) of each subcircuit become active -- the rule
+// of the device's list update.
+void bfs_child(const cq_dd_record& rec, int ns, uint64_t bin, const int32_t* max_active, uint64_t* act,
+               uint64_t* mer, uint64_t* fix, uint64_t* fv) {
+  int shift = rec.n_active;
+  for (int c = 0; c < ns; ++c) {
+    const uint64_t a_mask = rec.active[c];
+    const int a = popc(a_mask);
+    shift -= a;
+    const uint64_t bits = a ? (bin >> shift) & (a >= 64 ? ~0ull : ((1ull << a) - 1)) : 0;
+    uint64_t v = rec.fixed_vals[c];
+    int t = 0;
+    for (int p = 0; p < 64; ++p)
+      if ((a_mask >> p) & 1) {
+        if ((bits >> (a - 1 - t)) & 1) v |= 1ull << p;
+        ++t;
+      }
+    uint64_t m = rec.merged[c], na = 0;
+    int taken = 0;
+    for (int p = 0; p < 64 && taken < max_active[c]; ++p)
+      if ((m >> p) & 1) {
+        na |= 1ull << p;
+        ++taken;
+      }
+    act[c] = na;
+    mer[c] = m & ~na;
+    fix[c] = rec.fixed[c] | a_mask;
+    fv[c] = v;
+  }
+}
+
+cq_dd_params bfs_batch_params(const cq_dd_bfs_params& p) {
+  cq_dd_params q;
+  q.prec = p.prec;
+  q.R = p.width;
+  q.launch = p.launch;
+  return q;
+}
+
+}  // namespace
+
+extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst,
+                                       const cq_dd_params* params, cq_dd_record* records,
+                                       void* const* bins, int32_t* recursions_done, void* workspace,
+                                       size_t workspace_bytes, hipStream_t stream) {
+  if (!params) return fail(CQ_ERR_ARG, "null or empty argument");
+  return dd_run_batch(n_inst, inst, params, params->R, records, bins, recursions_done, workspace,
+                      workspace_bytes, stream);
+}
+
+extern "C" cq_status cq_dd_bfs_workspace_size(const cq_dd_instance* root, const cq_dd_bfs_params* params,
+                                              size_t* bytes) {
+  if (!root || !params || !bytes) return fail(CQ_ERR_ARG, "null argument");
+  if (params->width < 1 || params->width > CQ_MAX_DD_R) return fail(CQ_ERR_ARG, "width out of range");
+  // a level runs at most `width` nodes, each planned like the root
+  const cq_dd_params q = bfs_batch_params(*params);
+  std::vector<cq_dd_instance> many((size_t)params->width, *root);
+  return cq_dd_workspace_size(params->width, many.data(), &q, 0, bytes);
+}
+
+extern "C" cq_status cq_reconstruct_dd_bfs(const cq_dd_instance* root, const cq_dd_bfs_params* params,
+                                           cq_dd_bfs_node* nodes, int32_t max_nodes, int32_t* n_nodes,
+                                           void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!root || !params || !nodes || !n_nodes) return fail(CQ_ERR_ARG, "null argument");
+  if (params->levels < 1) return fail(CQ_ERR_ARG, "levels must be positive");
+  if (params->width < 1 || params->width > CQ_MAX_DD_R) return fail(CQ_ERR_ARG, "width out of range");
+  if ((int64_t)max_nodes < 1 + (int64_t)(params->levels - 1) * params->width)
+    return fail(CQ_ERR_ARG, "node buffer smaller than 1 + (levels - 1) * width");
+  if (root->n_sub < 1 || root->n_sub > CQ_MAX_SUBCIRCUITS || !root->max_active)
+    return fail(CQ_ERR_ARG, "bad root instance");
+  const cq_dd_params q = bfs_batch_params(*params);
+  const int W = params->width, ns = root->n_sub;
+  *n_nodes = 0;
+  // frontier: node masks (owned here), parent node and parent bin
+  struct Front {
+    uint64_t act[CQ_MAX_SUBCIRCUITS], mer[CQ_MAX_SUBCIRCUITS], fix[CQ_MAX_SUBCIRCUITS], fv[CQ_MAX_SUBCIRCUITS];
+    int32_t parent;
+    uint64_t parent_bin;
+  };
+  std::vector<Front> front(1);
+  for (int c = 0; c < ns; ++c) {
+    front[0].act[c] = root->active[c];
+    front[0].mer[c] = root->merged[c];
+    front[0].fix[c] = root->fixed[c];
+    front[0].fv[c] = root->fixed_vals[c];
+  }
+  front[0].parent = -1;
+  front[0].parent_bin = 0;
+  int count = 0;
+  for (int level = 0; level < params->levels && !front.empty(); ++level) {
+    const int n = (int)front.size();
+    std::vector<cq_dd_instance> inst((size_t)n, *root);
+    for (int i = 0; i < n; ++i) {
+      inst[i].active = front[i].act;
+      inst[i].merged = front[i].mer;
+      inst[i].fixed = front[i].fix;
+      inst[i].fixed_vals = front[i].fv;
+    }
+    std::vector<cq_dd_record> recs((size_t)n * W);
+    std::vector<int32_t> done((size_t)n, 0);
+    cq_status st = dd_run_batch(n, inst.data(), &q, 1, recs.data(), nullptr, done.data(), workspace,
+                                workspace_bytes, stream);
+    if (st != CQ_OK) return st;
+    // candidates of the level: (value, node, bin), best first
+    struct Cand {
+      double v;
+      int node;
+      uint64_t bin;
+    };
+    std::vector<Cand> cands;
+    for (int i = 0; i < n; ++i) {
+      cq_dd_bfs_node& nd = nodes[count + i];
+      nd.rec = recs[(size_t)i * W];
+      nd.level = level;
+      nd.parent = front[i].parent;
+      nd.parent_bin = front[i].parent_bin;
+      for (int j = 0; j < nd.rec.n_list; ++j) cands.push_back({nd.rec.list_val[j], count + i, nd.rec.list_bin[j]});
+    }
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) {
+      if (a.v != b.v) return a.v > b.v;
+      if (a.node != b.node) return a.node < b.node;
+      return a.bin < b.bin;
+    });
+    if ((int)cands.size() > W) cands.resize(W);
+    std::vector<Front> next(cands.size());
+    for (size_t j = 0; j < cands.size(); ++j) {
+      bfs_child(nodes[cands[j].node].rec, ns, cands[j].bin, root->max_active, next[j].act, next[j].mer,
+                next[j].fix, next[j].fv);
+      next[j].parent = cands[j].node;
+      next[j].parent_bin = cands[j].bin;
+    }
+    count += n;
+    *n_nodes = count;
+    front.swap(next);
+  }
   return CQ_OK;
 }
 

@@ -263,3 +263,56 @@ def test_parallel_lanes_graph_and_direct_agree_with_single_instances():
         recs, done = m.cq_reconstruct_dd(insts, "fp32", R, launch=launch)
         assert done == [d[1][0] for d in alone]
         assert recs == [d[0][0] for d in alone]
+
+
+# --- breadth-first query -------------------------------------------------------
+
+def _bfs_compare(cm, E, M, levels, width, prec, tol, exact):
+    """GPU nodes against the oracle's: level, parent, parent bin, labels,
+    FP64 total and candidates (bins exact; values exact or within tol)."""
+    st0 = dd.initial_states(cm, M)
+    ref = dd.run_bfs(cm, E, st0, M, levels, width)
+    print(f"bfs {prec} levels {levels} width {width}: {len(ref)} nodes", flush=True)
+    got = cq().cq_reconstruct_dd_bfs(instance(cm, E, st0, M), prec, levels, width)
+    torch.cuda.synchronize()
+    assert len(got) == len(ref)
+    for g, r in zip(got, ref):
+        assert (g["level"], g["parent"], g["parent_bin"]) == (r["level"], r["parent"], r["parent_bin"])
+        assert g["active"] == [mask(s.active) for s in r["states"]]
+        assert g["merged"] == [mask(s.merged) for s in r["states"]]
+        assert g["fixed"] == [mask(s.fixed.keys()) for s in r["states"]]
+        assert g["fixed_vals"] == [mask(p for p, v in s.fixed.items() if v) for s in r["states"]]
+        assert [b for (_, _, b) in g["list"]] == [i for (_, i) in r["candidates"]]
+        vals = [v for (v, _, _) in g["list"]]
+        want = [v for (v, _) in r["candidates"]]
+        if exact:
+            assert g["total"] == r["total"] and vals == want
+        else:
+            assert abs(g["total"] - r["total"]) <= tol
+            assert np.max(np.abs(np.array(vals) - np.array(want)), initial=0.0) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", range(3))
+def test_bfs_integer_entries_exact(case, prec):
+    rng = np.random.default_rng(70 + case)
+    bonds = [int(rng.integers(1, 3)), int(rng.integers(1, 3))]
+    ns = [5, 4, 5]
+    cm = syn.chain_cutmap(bonds, ns)
+    E = [syn.integer_entries(rng, k, n, lo=0, hi=3) for k, n in zip(syn.chain_ks(bonds, 3), ns)]
+    _bfs_compare(cm, E, [1, 2, 1], levels=3, width=4, prec=prec, tol=0.0, exact=True)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7)])
+def test_bfs_dirichlet_chain(prec, tol):
+    cm, E = syn.chain_instance(17, [2, 2], [5, 5, 5])
+    _bfs_compare(cm, E, [2, 1, 2], levels=4, width=5, prec=prec, tol=tol, exact=False)
+
+
+def test_bfs_arguments_rejected_before_launch():
+    m = cq()
+    cm, E = syn.chain_instance(3, [1], [3, 3])
+    inst = instance(cm, E, dd.initial_states(cm, [1, 1]), [1, 1])
+    for kw in (dict(levels=0, width=2), dict(levels=2, width=0), dict(levels=2, width=17)):
+        with pytest.raises(m.CQError):
+            m.cq_reconstruct_dd_bfs(inst, "fp64", **kw)

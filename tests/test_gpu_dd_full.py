@@ -214,3 +214,38 @@ def test_largest_instance_stored_bins_grid(prec):
         # the recursion total against the sum of the bins (FP64 from the GPU's own bins)
         s = float(torch.sum(bins[r][: 2 ** sum(na)], dtype=torch.float64).item())
         assert abs(s - rr[r]["total"]) <= (1e-9 if prec == "fp64" else 1e-5)
+
+
+def test_bfs_full_size_candidates_and_children():
+    """Breadth-first query at full size on instance 0 of the batch (four
+    20-output subcircuits, 8 active outputs each: 2^32 bins per node), three
+    levels of width 3.  Every node's candidate values against the oracle
+    (local problem of the sampled bins), every child's FP64 total against
+    the candidate value of the parent bin it refines, and the level
+    structure (level 1 zooms into the root's candidates in order)."""
+    m = cq()
+    bonds = batch()[0]
+    inst, cm, ks = make_instance(0, bonds)
+    W = 3
+    print(f"bfs full size, bonds {bonds}", flush=True)
+    nodes = m.cq_reconstruct_dd_bfs(inst, "fp32", levels=3, width=W)
+    torch.cuda.synchronize()
+    assert nodes[0]["level"] == 0 and nodes[0]["parent"] == -1
+    lv1 = [nd for nd in nodes if nd["level"] == 1]
+    assert [nd["parent_bin"] for nd in lv1] == [b for (_, _, b) in nodes[0]["list"][:W]]
+    for k, nd in enumerate(nodes):
+        if nd["parent"] >= 0:
+            par = nodes[nd["parent"]]
+            v = {b: val for (val, _, b) in par["list"]}[nd["parent_bin"]]
+            assert abs(nd["total"] - v) <= 1e-12 * max(abs(v), 1e-300) + 1e-300, (k, nd["total"], v)
+        if not nd["list"]:
+            continue
+        states = states_of(nd)
+        bins = [b for (_, _, b) in nd["list"]]
+        parts = [split_bin(b, states) for b in bins]
+        samples = [sorted(set(p[c] for p in parts)) for c in range(4)]
+        cm_loc, red = local_problem(SEED, bonds, ks, states, samples)
+        grid = grid_values(cm_loc, red).reshape(16, 16, 16, 16)
+        for (val, _, b), p in zip(nd["list"], parts):
+            ref = grid[tuple(samples[c].index(p[c]) for c in range(4))]
+            assert abs(val - ref) <= 1e-10, (k, b, val, ref)
