@@ -282,6 +282,53 @@ cq_status cq_reconstruct_dd_bfs(const cq_dd_instance* root, const cq_dd_bfs_para
                                 cq_dd_bfs_node* nodes, int32_t max_nodes, int32_t* n_nodes,
                                 void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* -------------------------------------------------------------------------
+ * Finite-shot emulation (Section 2: a QPU run reports the distribution of a
+ * finite number of measured bit strings) and the chi-square loss (Eq. 3).
+ *
+ * Each row of a rows x cols FP64 probability table (one subcircuit variant's
+ * 2^w outcomes, say) is sampled `shots` times, independently of the other
+ * rows, and replaced by its empirical frequencies count / shots.  Every
+ * decision is taken in integers, so the counts are a function of
+ * (table, shots, seed) alone:
+ *   q_i = floor(clamp(p_i, 0, 1) * 2^52), C_i = q_0 + ... + q_i (exact uint64);
+ *   shot s of row r: Philox4x32-10 with key (seed & 0xffffffff, seed >> 32)
+ *   and counter (s & 0xffffffff, s >> 32, r & 0xffffffff, r >> 32) gives words
+ *   w0..w3; x = w0 + 2^32 w1; t = floor(x * T / 2^64) with T = C_{cols-1};
+ *   the shot lands on the first i with C_i > t.
+ * Negative entries count as zero probability; a row whose q sum to 0 gets no
+ * counts (all frequencies 0).  Entries need not sum to 1: the row is sampled
+ * in proportion to its clamped entries, whose sum must stay below 2^12 so
+ * that C fits in 64 bits (a probability row sums to 1).  A row above that
+ * is not detected: its counts are unspecified, but every access stays in
+ * bounds.
+ * ------------------------------------------------------------------------- */
+
+/* Limits: 1 <= rows <= 65535, rows * cols <= 2^34, rows * shots <= 2^40. */
+cq_status cq_sample_shots_workspace_size(int64_t rows, int64_t cols, int64_t shots, size_t* bytes);
+
+/* probs: device, rows x cols row-major FP64, read only.  freqs: device,
+ * rows x cols FP64, written (may not alias probs).  workspace: device, at
+ * least cq_sample_shots_workspace_size bytes (prefix sums and counts),
+ * owned by the caller, contents on entry ignored.  Asynchronous on `stream`;
+ * arguments are checked before any launch (CQ_ERR_ARG, CQ_ERR_SHAPE,
+ * CQ_ERR_WORKSPACE leave freqs untouched). */
+cq_status cq_sample_shots(const double* probs, int64_t rows, int64_t cols, int64_t shots, uint64_t seed,
+                          double* freqs, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Eq. 3: chi2 = sum_i (a_i - b_i)^2 / (a_i + b_i) over n entries; a term
+ * with a_i + b_i = 0 contributes 0.  Applied as written to any real inputs,
+ * so quasi-probabilities with negative entries can give negative terms.  The
+ * sum runs in a fixed order (1024 x 256 strided partial sums, then a tree),
+ * so repeated calls give the same bits. */
+cq_status cq_chi2_workspace_size(size_t* bytes);
+
+/* a, b: device FP64, n >= 1 entries each.  result: device, one FP64,
+ * written on `stream` (no synchronisation).  workspace: device, at least
+ * cq_chi2_workspace_size bytes. */
+cq_status cq_chi2(const double* a, const double* b, int64_t n, double* result, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,9 @@ make every decision in integers, so they agree shot for shot:
   row's cumulative sums C_i = q_0 + ... + q_i are exact 64-bit integers.
 * With T = C_last, a shot's target is t = floor(x * T / 2^64) in [0, T), and
   it lands on the first index i with C_i > t.  A row with T = 0 gets no
-  counts.
+  counts.  The clamped entries of a row must sum below 2^12 so that C fits
+  in 64 bits (a probability row sums to 1); the oracle rejects a row that
+  does not.
 * Frequencies are count / shots in FP64.
 
 The chi-square loss of Eq. 3 sums (a_i - b_i)^2 / (a_i + b_i); terms with
@@ -80,6 +82,8 @@ def shot_uniforms(seed, row, shots):
 def sample_counts(p_row, shots, seed, row):
     """Counts of one row's ``shots`` samples."""
     q = quantise(p_row)
+    if float(np.sum(q.astype(np.float64))) >= 2.0 ** 64:
+        raise ValueError("clamped row sum must be below 2^12")
     cdf = np.cumsum(q, dtype=np.uint64)
     counts = np.zeros(len(q), dtype=np.int64)
     T = int(cdf[-1]) if len(cdf) else 0

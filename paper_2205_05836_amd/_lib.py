@@ -21,7 +21,8 @@ EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
             "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd",
-            "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs"]
+            "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs",
+            "cq_sample_shots_workspace_size", "cq_sample_shots", "cq_chi2_workspace_size", "cq_chi2"]
 
 
 class cq_subcircuit(C.Structure):
@@ -103,6 +104,14 @@ def lib():
     L.cq_reconstruct_dd_bfs.argtypes = [C.POINTER(cq_dd_instance), C.POINTER(cq_dd_bfs_params),
                                         C.POINTER(cq_dd_bfs_node), C.c_int32, C.POINTER(C.c_int32),
                                         C.c_void_p, C.c_size_t, C.c_void_p]
+    L.cq_sample_shots_workspace_size.restype = st
+    L.cq_sample_shots_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
+    L.cq_sample_shots.restype = st
+    L.cq_sample_shots.argtypes = [p, C.c_int64, C.c_int64, C.c_int64, C.c_uint64, p, p, C.c_size_t, p]
+    L.cq_chi2_workspace_size.restype = st
+    L.cq_chi2_workspace_size.argtypes = [C.POINTER(C.c_size_t)]
+    L.cq_chi2.restype = st
+    L.cq_chi2.argtypes = [p, p, C.c_int64, p, p, C.c_size_t, p]
     L.cq_reconstruct_dd.restype = st
     L.cq_reconstruct_dd.argtypes = [C.c_int32, C.POINTER(cq_dd_instance), C.POINTER(cq_dd_params),
                                     C.POINTER(cq_dd_record), C.POINTER(C.c_void_p),

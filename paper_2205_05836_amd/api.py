@@ -260,6 +260,54 @@ def cq_reconstruct_dd_bfs(instance, prec="fp64", levels=2, width=4, workspace=No
                  **_record_dict(nodes[k].rec, ns)) for k in range(n.value)]
 
 
+def cq_sample_shots_workspace_size(rows, cols, shots):
+    b = C.c_size_t()
+    check(lib().cq_sample_shots_workspace_size(int(rows), int(cols), int(shots), C.byref(b)))
+    return b.value
+
+
+def cq_sample_shots(probs, shots, seed, out=None, workspace=None, stream=None):
+    """Empirical frequencies of ``shots`` samples of every row of ``probs``
+    (a device FP64 tensor, last axis = outcomes), as a new FP64 tensor of the
+    same shape unless ``out`` is given."""
+    import torch
+    _dev_ptr(probs, torch.float64)
+    cols = int(probs.shape[-1]) if probs.dim() else 1
+    rows = probs.numel() // max(cols, 1)
+    if out is None:
+        out = torch.empty_like(probs)
+    elif out.shape != probs.shape:
+        raise ValueError("out must have the shape of probs")
+    nbytes = cq_sample_shots_workspace_size(rows, cols, shots)
+    ws = _workspace(nbytes, probs.device, workspace)
+    check(lib().cq_sample_shots(_dev_ptr(probs), rows, cols, int(shots), C.c_uint64(int(seed)),
+                                _dev_ptr(out, torch.float64), _dev_ptr(ws), C.c_size_t(nbytes),
+                                _stream(stream)))
+    return out
+
+
+def cq_chi2_workspace_size():
+    b = C.c_size_t()
+    check(lib().cq_chi2_workspace_size(C.byref(b)))
+    return b.value
+
+
+def cq_chi2(a, b, out=None, workspace=None, stream=None):
+    """Eq. 3 between two device FP64 tensors of equal size; returns a
+    one-element device tensor (``out`` if given), written asynchronously."""
+    import torch
+    if a.numel() != b.numel():
+        raise ValueError("a and b differ in size")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=a.device)
+    nbytes = cq_chi2_workspace_size()
+    ws = _workspace(nbytes, a.device, workspace)
+    check(lib().cq_chi2(_dev_ptr(a, torch.float64), _dev_ptr(b, torch.float64), a.numel(),
+                        _dev_ptr(out, torch.float64), _dev_ptr(ws), C.c_size_t(nbytes),
+                        _stream(stream)))
+    return out
+
+
 def cq_plan_json(subs, prec="fp64", out_bits=None, out_perm=None):
     """The contraction plan as a dict (host only, launches nothing)."""
     import json

@@ -62,6 +62,13 @@ def test_sampling_special_cases():
     assert np.array_equal(f1, f2)
     assert np.allclose(f1.sum(axis=1), 1.0)
     assert np.all(f1 * 1000 == np.round(f1 * 1000))
+    # unnormalised rows are sampled in proportion; sums that overflow 64 bits
+    # are rejected
+    u = shots.sample_counts(np.array([0.5, 1.0, 1.0, 1.0]) * 1000, 10, 3, 0)
+    assert u.sum() == 10
+    with pytest.raises(ValueError):
+        shots.sample_counts(np.ones(4096), 10, 3, 0)
+    assert shots.sample_counts(np.ones(4095), 10, 3, 0).sum() == 10
 
 
 def test_sampling_goodness_of_fit():
