@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--dd-runs", type=int, default=3)
     ap.add_argument("--skip-attribution", action="store_true",
                     help="skip the entry-attribution leg")
+    ap.add_argument("--skip-shots", action="store_true",
+                    help="skip the finite-shot sampling and chi-square leg")
     return ap.parse_args()
 
 
@@ -342,6 +344,55 @@ def attribution_leg(torch, cq, runs=3):
             "achieved_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+SHOTS_PER_VARIANT = 8192
+SHOTS_WORKLOAD = ("finite shots: variant table of one DD subcircuit (16 x 9 rows of 2^22 "
+                  "outcomes, Uniform[0, 2/2^22) FP64, seed 5), 8192 shots per row, seed 2022; "
+                  "chi-square (Eq. 3) of the frequencies against the table")
+
+
+def shots_leg(torch, cq, runs=3):
+    """Times cq_sample_shots on a variant table of the DD subcircuit shape
+    (a QPU run of every variant with a few thousand shots) and cq_chi2 of the
+    frequencies against the table.  Algorithmic bytes: the table read once
+    and the frequencies written once (16 B an entry); chi-square reads both
+    (16 B an entry)."""
+    rows, cols = 16 * 9, 2 ** 22
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(5)
+    P = torch.rand((rows, cols), dtype=torch.float64, device="cuda:0", generator=gen) * (2.0 / cols)
+    F = torch.empty_like(P)
+    ws = torch.empty(cq.cq_sample_shots_workspace_size(rows, cols, SHOTS_PER_VARIANT),
+                     dtype=torch.uint8, device="cuda:0")
+    cws = torch.empty(cq.cq_chi2_workspace_size(), dtype=torch.uint8, device="cuda:0")
+    res = torch.empty(1, dtype=torch.float64, device="cuda:0")
+
+    def timed(fn):
+        fn()
+        times = []
+        for _ in range(runs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return sorted(times)[len(times) // 2]
+
+    ms = timed(lambda: cq.cq_sample_shots(P, SHOTS_PER_VARIANT, 2022, out=F, workspace=ws))
+    cms = timed(lambda: cq.cq_chi2(F.reshape(-1), P.reshape(-1), out=res, workspace=cws))
+    alg = rows * cols * 16
+    out = {"workload": SHOTS_WORKLOAD, "ms": round(ms, 3), "algorithmic_bytes": alg,
+           "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+           "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "shots_per_s": rows * SHOTS_PER_VARIANT / (ms * 1e-3),
+           "chi2": {"ms": round(cms, 3), "value": float(res.item()),
+                    "achieved_GBps": round(alg / (cms * 1e-3) / 1e9, 1),
+                    "frac_hbm": round(alg / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    del P, F, ws
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -430,6 +481,9 @@ def main():
     result["autotune"] = cq.cq_autotune_json()
     if not args.skip_attribution:
         result["attribution"] = attribution_leg(torch, cq)
+        torch.cuda.empty_cache()
+    if not args.skip_shots:
+        result["shots"] = shots_leg(torch, cq)
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         cpu, err = cpu_baseline_leg(torch, ents, out, args.cpu_seconds)

@@ -304,7 +304,9 @@ cq_status cq_reconstruct_dd_bfs(const cq_dd_instance* root, const cq_dd_bfs_para
  * bounds.
  * ------------------------------------------------------------------------- */
 
-/* Limits: 1 <= rows <= 65535, rows * cols <= 2^34, rows * shots <= 2^40. */
+/* Limits: 1 <= rows <= 65535, rows * cols <= 2^34, shots < 2^32,
+ * rows * shots <= 2^34.  The workspace holds per-block sums and shot
+ * counters of each row (2048 entries a block) and one 8-byte slot per shot. */
 cq_status cq_sample_shots_workspace_size(int64_t rows, int64_t cols, int64_t shots, size_t* bytes);
 
 /* probs: device, rows x cols row-major FP64, read only.  freqs: device,

@@ -23,102 +23,80 @@ namespace cq {
 
 namespace {
 
-constexpr int kBlock = 4096;  // elements per prefix-sum block
+constexpr int kBlock = 2048;  // row entries per block
 constexpr int kThreads = 256;
+constexpr int kPer = kBlock / kThreads;
+constexpr int kPad = kPer + 1;          // LDS words per thread run (one pad word)
+constexpr int kScanThreads = 1024;      // row scans of block sums and counts
+constexpr int kShotsPerThread = 64;
+constexpr int kShotsPerGroup = kThreads * kShotsPerThread;
+constexpr int kLdsBins = 4096;          // rows with at most this many blocks search and count in LDS
 
 __device__ inline uint64_t quant52(double p) {
   const double c = p > 0.0 ? (p < 1.0 ? p : 1.0) : 0.0;
   return (uint64_t)(c * 0x1p52);
 }
 
-// q of every element, and each block's sum
-__global__ void __launch_bounds__(kThreads) shots_quant_kernel(const double* __restrict__ P, int64_t cols,
-                                                               int64_t nblk, uint64_t* __restrict__ cdf,
-                                                               uint64_t* __restrict__ bsum) {
+// Pass 1: the quantised sum of every block of a row (coalesced), and the
+// block's shot counters cleared.
+__global__ void __launch_bounds__(kThreads) shots_bsum_kernel(const double* __restrict__ P, int64_t cols,
+                                                              int64_t nblk, uint64_t* __restrict__ bend,
+                                                              uint32_t* __restrict__ bcnt,
+                                                              uint32_t* __restrict__ bfill) {
   const int64_t row = blockIdx.y, blk = blockIdx.x;
-  const int64_t c0 = blk * kBlock;
+  const double* p = P + row * cols + blk * kBlock;
+  const int64_t n = cols - blk * kBlock < kBlock ? cols - blk * kBlock : kBlock;
   __shared__ unsigned long long part[kThreads];
   unsigned long long s = 0;
-  for (int e = threadIdx.x; e < kBlock; e += kThreads) {
-    const int64_t c = c0 + e;
-    if (c < cols) {
-      const uint64_t q = quant52(P[row * cols + c]);
-      cdf[row * cols + c] = q;
-      s += q;
-    }
-  }
+#pragma unroll 4
+  for (int e = threadIdx.x; e < n; e += kThreads) s += quant52(__builtin_nontemporal_load(p + e));
   part[threadIdx.x] = s;
   __syncthreads();
   for (int h = kThreads / 2; h > 0; h >>= 1) {
     if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[row * nblk + blk] = part[0];
+  if (threadIdx.x == 0) {
+    const int64_t k = row * nblk + blk;
+    bend[k] = part[0];
+    bcnt[k] = 0;
+    bfill[k] = 0;
+  }
 }
 
-// exclusive prefix of one row's block sums: one workgroup per row, thread t
-// owns a contiguous run of blocks
-__global__ void __launch_bounds__(kThreads) shots_block_scan_kernel(uint64_t* __restrict__ bsum, int64_t nblk) {
-  uint64_t* B = bsum + (int64_t)blockIdx.x * nblk;
-  const int64_t per = (nblk + kThreads - 1) / kThreads;
+// Prefix over one row of `n` values (one workgroup per row, thread t owns a
+// contiguous run): inclusive in place when `out` is null, else exclusive
+// into `out`.
+template <typename T>
+__device__ inline void row_scan(T* __restrict__ v, T* __restrict__ out, int64_t n) {
+  const int64_t per = (n + kScanThreads - 1) / kScanThreads;
   const int64_t b0 = (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
-  __shared__ unsigned long long part[kThreads];
+  const int64_t b1 = b0 + per < n ? b0 + per : n;
+  __shared__ unsigned long long part[kScanThreads];
   unsigned long long s = 0;
-  for (int64_t b = b0; b < b1; ++b) s += B[b];
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) s += v[b];
   part[threadIdx.x] = s;
   __syncthreads();
-  for (int h = 1; h < kThreads; h <<= 1) {
+  for (int h = 1; h < kScanThreads; h <<= 1) {
     const unsigned long long add = threadIdx.x >= h ? part[threadIdx.x - h] : 0ull;
     __syncthreads();
     part[threadIdx.x] += add;
     __syncthreads();
   }
   unsigned long long run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+#pragma unroll 8
   for (int64_t b = b0; b < b1; ++b) {
-    const uint64_t v = B[b];
-    B[b] = run;
-    run += v;
+    const T x = v[b];
+    if (out) out[b] = (T)run;
+    run += x;
+    if (!out) v[b] = (T)run;
   }
 }
 
-// inclusive prefix inside each block plus the block's offset: thread t owns
-// kBlock / kThreads consecutive elements
-__global__ void __launch_bounds__(kThreads) shots_cdf_kernel(int64_t cols, int64_t nblk,
-                                                             uint64_t* __restrict__ cdf,
-                                                             const uint64_t* __restrict__ boff) {
-  constexpr int PER = kBlock / kThreads;
-  const int64_t row = blockIdx.y, blk = blockIdx.x;
-  const int64_t c0 = blk * kBlock + (int64_t)threadIdx.x * PER;
-  __shared__ unsigned long long part[kThreads];
-  unsigned long long loc[PER];
-  unsigned long long s = 0;
-#pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int64_t c = c0 + e;
-    s += c < cols ? cdf[row * cols + c] : 0ull;
-    loc[e] = s;
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  // inclusive scan of the threads' totals (Hillis-Steele)
-  for (int h = 1; h < kThreads; h <<= 1) {
-    const unsigned long long add = threadIdx.x >= h ? part[threadIdx.x - h] : 0ull;
-    __syncthreads();
-    part[threadIdx.x] += add;
-    __syncthreads();
-  }
-  const unsigned long long before = (threadIdx.x ? part[threadIdx.x - 1] : 0ull) + boff[row * nblk + blk];
-#pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int64_t c = c0 + e;
-    if (c < cols) cdf[row * cols + c] = before + loc[e];
-  }
-}
-
-__global__ void shots_zero_kernel(uint32_t* __restrict__ counts, int64_t n) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) counts[i] = 0;
+// Pass 2: block sums -> inclusive block ends (C at each block's last entry).
+__global__ void __launch_bounds__(kScanThreads) shots_bend_kernel(uint64_t* __restrict__ bend, int64_t nblk) {
+  row_scan<uint64_t>(bend + (int64_t)blockIdx.x * nblk, nullptr, nblk);
 }
 
 // Philox4x32-10: ten rounds of two 32 x 32 -> 64-bit products of counter
@@ -140,35 +118,232 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-// one thread per (row, shot)
-__global__ void __launch_bounds__(kThreads) shots_sample_kernel(const uint64_t* __restrict__ cdf, int64_t rows,
-                                                                int64_t cols, int64_t shots, uint64_t seed,
-                                                                uint32_t* __restrict__ counts) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows * shots) return;
-  const int64_t row = i / shots, s = i - row * shots;
-  const uint64_t* C = cdf + row * cols;
-  const uint64_t T = C[cols - 1];
-  if (T == 0) return;
+// Target t of shot s of row `row` (total mass T > 0) and its block: the
+// first whose inclusive end exceeds t.
+__device__ inline void shot_target(const uint64_t* __restrict__ E, int64_t nblk, uint64_t T, uint64_t seed,
+                                   int64_t row, int64_t s, uint64_t& t, uint32_t& blk) {
   uint32_t w[4] = {(uint32_t)s, (uint32_t)((uint64_t)s >> 32), (uint32_t)row, (uint32_t)((uint64_t)row >> 32)};
   philox4x32_10(w, (uint32_t)seed, (uint32_t)(seed >> 32));
   const uint64_t x = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
-  const uint64_t t = __umul64hi(x, T);
-  // first index with C > t
-  int64_t lo = 0, hi = cols - 1;
+  t = __umul64hi(x, T);
+  uint32_t lo = 0, hi = (uint32_t)nblk - 1;
   while (lo < hi) {
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (C[mid] > t) hi = mid;
+    const uint32_t mid = (lo + hi) >> 1;
+    if (E[mid] > t) hi = mid;
     else lo = mid + 1;
   }
-  atomicAdd(&counts[row * cols + lo], 1u);
+  blk = lo;
 }
 
-__global__ void shots_freq_kernel(const uint32_t* __restrict__ counts, int64_t n, double shots,
-                                  double* __restrict__ out) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
-    out[i] = (double)counts[i] / shots;
+// Pass 3: shots per block.  grid (shot groups, rows); a group takes
+// kShotsPerGroup consecutive shots of one row and, for rows of at most
+// kLdsBins blocks, searches the block ends and counts its shots in LDS
+// before one global add per block hit.  A row of one block needs no
+// counting at all.
+__global__ void __launch_bounds__(kThreads) shots_count_kernel(const uint64_t* __restrict__ bend, int64_t nblk,
+                                                               int64_t shots, uint64_t seed,
+                                                               uint32_t* __restrict__ bcnt) {
+  __shared__ uint32_t hist[kLdsBins];
+  __shared__ uint64_t Es[kLdsBins];
+  const int64_t row = blockIdx.y, s0 = (int64_t)blockIdx.x * kShotsPerGroup;
+  const uint64_t* E = bend + row * nblk;
+  uint32_t* cnt = bcnt + row * nblk;
+  const uint64_t T = E[nblk - 1];
+  if (T == 0) return;
+  if (nblk == 1) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0] = (uint32_t)shots;
+    return;
+  }
+  if (nblk > kLdsBins) {
+#pragma unroll 4
+    for (int j = 0; j < kShotsPerThread; ++j) {
+      const int64_t s = s0 + j * kThreads + threadIdx.x;
+      if (s < shots) {
+        uint64_t t;
+        uint32_t blk;
+        shot_target(E, nblk, T, seed, row, s, t, blk);
+        atomicAdd(&cnt[blk], 1u);
+      }
+    }
+    return;
+  }
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    hist[b] = 0;
+    Es[b] = E[b];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < kShotsPerThread; ++j) {
+    const int64_t s = s0 + j * kThreads + threadIdx.x;
+    if (s < shots) {
+      uint64_t t;
+      uint32_t blk;
+      shot_target(Es, nblk, T, seed, row, s, t, blk);
+      atomicAdd(&hist[blk], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nblk; b += kThreads)
+    if (hist[b]) atomicAdd(&cnt[b], hist[b]);
+}
+
+// Pass 4: exclusive prefix of each row's block counts (bucket offsets).
+__global__ void __launch_bounds__(kScanThreads) shots_bptr_kernel(uint32_t* __restrict__ bcnt,
+                                                                  uint32_t* __restrict__ bptr, int64_t nblk) {
+  const int64_t off = (int64_t)blockIdx.x * nblk;
+  row_scan<uint32_t>(bcnt + off, bptr + off, nblk);
+}
+
+// Pass 5: every shot's target, relative to its block's first entry, into
+// the block's bucket; row r's buckets fill slots [r shots, (r + 1) shots).
+// Same groups as pass 3.  For rows counted in LDS the group counts its shots
+// per block again, reserves one run of each bucket it hits with one global
+// add, and then recomputes every shot and takes the next position of its
+// run from LDS, so a group's shots of one bucket land next to each other
+// (plain stores, so that L2 merges each run before it goes to HBM).
+__global__ void __launch_bounds__(kThreads) shots_scatter_kernel(const uint64_t* __restrict__ bend, int64_t nblk,
+                                                                 int64_t shots, uint64_t seed,
+                                                                 const uint32_t* __restrict__ bptr,
+                                                                 uint32_t* __restrict__ bfill,
+                                                                 uint64_t* __restrict__ slots) {
+  __shared__ uint32_t hist[kLdsBins];  // group counts, then the next position in each bucket
+  __shared__ uint64_t Es[kLdsBins];
+  const int64_t row = blockIdx.y, s0 = (int64_t)blockIdx.x * kShotsPerGroup;
+  const uint64_t* E = bend + row * nblk;
+  const uint32_t* ptr = bptr + row * nblk;
+  uint32_t* fill = bfill + row * nblk;
+  uint64_t* S = slots + row * shots;
+  const uint64_t T = E[nblk - 1];
+  if (T == 0) return;
+  if (nblk == 1) {
+#pragma unroll 4
+    for (int j = 0; j < kShotsPerThread; ++j) {
+      const int64_t s = s0 + j * kThreads + threadIdx.x;
+      if (s < shots) {
+        uint64_t t;
+        uint32_t blk;
+        shot_target(E, 1, T, seed, row, s, t, blk);
+        S[s] = t;
+      }
+    }
+    return;
+  }
+  if (nblk > kLdsBins) {
+#pragma unroll 4
+    for (int j = 0; j < kShotsPerThread; ++j) {
+      const int64_t s = s0 + j * kThreads + threadIdx.x;
+      if (s < shots) {
+        uint64_t t;
+        uint32_t blk;
+        shot_target(E, nblk, T, seed, row, s, t, blk);
+        const uint32_t pos = ptr[blk] + atomicAdd(&fill[blk], 1u);
+        S[pos] = t - (blk ? E[blk - 1] : 0);
+      }
+    }
+    return;
+  }
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    hist[b] = 0;
+    Es[b] = E[b];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < kShotsPerThread; ++j) {
+    const int64_t s = s0 + j * kThreads + threadIdx.x;
+    if (s < shots) {
+      uint64_t t;
+      uint32_t blk;
+      shot_target(Es, nblk, T, seed, row, s, t, blk);
+      atomicAdd(&hist[blk], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nblk; b += kThreads)
+    if (hist[b]) hist[b] = ptr[b] + atomicAdd(&fill[b], hist[b]);
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < kShotsPerThread; ++j) {
+    const int64_t s = s0 + j * kThreads + threadIdx.x;
+    if (s < shots) {
+      uint64_t t;
+      uint32_t blk;
+      shot_target(Es, nblk, T, seed, row, s, t, blk);
+      const uint32_t pos = atomicAdd(&hist[blk], 1u);
+      S[pos] = t - (blk ? Es[blk - 1] : 0);
+    }
+  }
+}
+
+// Pass 6: per block, the inclusive prefix of its quantised entries in LDS,
+// its bucket's shots resolved there (the first entry whose prefix exceeds
+// the shot's target), and count / shots written out.  A block without shots
+// writes zeros without reading its entries.  LDS layout: thread t's run of
+// kPer entries at [t kPad, t kPad + kPer).
+__global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* __restrict__ P, int64_t cols,
+                                                                 int64_t nblk, int64_t shots,
+                                                                 const uint32_t* __restrict__ bcnt,
+                                                                 const uint32_t* __restrict__ bptr,
+                                                                 const uint64_t* __restrict__ slots,
+                                                                 double* __restrict__ F) {
+  __shared__ unsigned long long C[kThreads * kPad];
+  __shared__ uint32_t cnt[kBlock];
+  __shared__ unsigned long long wtot[kThreads / 64];
+  const int64_t row = blockIdx.y, blk = blockIdx.x;
+  const int64_t c0 = blk * kBlock;
+  const int n = (int)(cols - c0 < kBlock ? cols - c0 : kBlock);
+  const int64_t k = row * nblk + blk;
+  const uint32_t m = bcnt[k];
+  double* f = F + row * cols + c0;
+  if (m == 0) {
+    for (int e = threadIdx.x; e < n; e += kThreads) __builtin_nontemporal_store(0.0, f + e);
+    return;
+  }
+  const double* p = P + row * cols + c0;
+#pragma unroll
+  for (int e = threadIdx.x; e < kBlock; e += kThreads) {
+    C[(e / kPer) * kPad + e % kPer] = e < n ? quant52(__builtin_nontemporal_load(p + e)) : 0ull;
+    cnt[e] = 0;
+  }
+  __syncthreads();
+  unsigned long long* mine = C + threadIdx.x * kPad;
+  unsigned long long v[kPer];
+  unsigned long long s = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    s += mine[e];
+    v[e] = s;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned long long x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wtot[wid] = x;
+  __syncthreads();
+  unsigned long long before = x - s;
+  for (int w = 0; w < wid; ++w) before += wtot[w];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) mine[e] = v[e] + before;
+  __syncthreads();
+  const uint64_t* sl = slots + row * shots + bptr[k];
+  for (uint32_t j = threadIdx.x; j < m; j += kThreads) {
+    const uint64_t t = __builtin_nontemporal_load(sl + j);
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (C[(mid / kPer) * kPad + mid % kPer] > t) hi = mid;
+      else lo = mid + 1;
+    }
+    atomicAdd(&cnt[lo], 1u);
+  }
+  __syncthreads();
+  const double ds = (double)shots;
+  for (int e = threadIdx.x; e < n; e += kThreads) {
+    const uint32_t c = cnt[e];
+    __builtin_nontemporal_store(c ? (double)c / ds : 0.0, f + e);
+  }
 }
 
 // Eq. 3, terms with a + b = 0 taken as 0: per-block partial sums in a fixed
@@ -209,7 +384,7 @@ __global__ void __launch_bounds__(kThreads) chi2_final_kernel(const double* __re
 }
 
 struct ShotsWs {
-  int64_t cdf = 0, bsum = 0, counts = 0, bytes = 0;
+  int64_t bend = 0, bcnt = 0, bptr = 0, bfill = 0, slots = 0, bytes = 0;
 };
 
 cq_status hip_error(hipError_t e, const char* what) {
@@ -218,13 +393,15 @@ cq_status hip_error(hipError_t e, const char* what) {
 
 int64_t al256(int64_t x) { return (x + 255) / 256 * 256; }
 
-ShotsWs shots_ws(int64_t rows, int64_t cols) {
+ShotsWs shots_ws(int64_t rows, int64_t cols, int64_t shots) {
   ShotsWs w;
-  const int64_t nblk = (cols + kBlock - 1) / kBlock;
-  w.cdf = 0;
-  w.bsum = al256(rows * cols * 8);
-  w.counts = w.bsum + al256(rows * nblk * 8);
-  w.bytes = w.counts + al256(rows * cols * 4);
+  const int64_t nb = rows * ((cols + kBlock - 1) / kBlock);
+  w.bend = 0;
+  w.bcnt = al256(nb * 8);
+  w.bptr = w.bcnt + al256(nb * 4);
+  w.bfill = w.bptr + al256(nb * 4);
+  w.slots = w.bfill + al256(nb * 4);
+  w.bytes = w.slots + al256(rows * shots * 8);
   return w;
 }
 
@@ -232,7 +409,8 @@ cq_status shots_check(int64_t rows, int64_t cols, int64_t shots) {
   if (rows < 1 || cols < 1 || shots < 1) return fail(CQ_ERR_ARG, "rows, cols and shots must be positive");
   if (rows > 65535) return fail(CQ_ERR_SHAPE, "more than 65535 rows");
   if (cols > ((int64_t)1 << 34) / rows) return fail(CQ_ERR_SHAPE, "table larger than 2^34 entries");
-  if (shots > ((int64_t)1 << 40) / rows) return fail(CQ_ERR_SHAPE, "more than 2^40 shots in total");
+  if (shots > 0xffffffffLL) return fail(CQ_ERR_SHAPE, "2^32 or more shots per row");
+  if (shots > ((int64_t)1 << 34) / rows) return fail(CQ_ERR_SHAPE, "more than 2^34 shots in total");
   return CQ_OK;
 }
 
@@ -246,7 +424,7 @@ extern "C" cq_status cq_sample_shots_workspace_size(int64_t rows, int64_t cols, 
   if (!bytes) return fail(CQ_ERR_ARG, "null argument");
   cq_status st = shots_check(rows, cols, shots);
   if (st != CQ_OK) return st;
-  *bytes = (size_t)shots_ws(rows, cols).bytes;
+  *bytes = (size_t)shots_ws(rows, cols, shots).bytes;
   return CQ_OK;
 }
 
@@ -256,28 +434,26 @@ extern "C" cq_status cq_sample_shots(const double* probs, int64_t rows, int64_t 
   if (!probs || !freqs) return fail(CQ_ERR_ARG, "null argument");
   cq_status st = shots_check(rows, cols, shots);
   if (st != CQ_OK) return st;
-  const ShotsWs w = shots_ws(rows, cols);
+  const ShotsWs w = shots_ws(rows, cols, shots);
   if (!workspace || (int64_t)workspace_bytes < w.bytes) return fail(CQ_ERR_WORKSPACE, "workspace too small");
   char* ws = static_cast<char*>(workspace);
-  uint64_t* cdf = reinterpret_cast<uint64_t*>(ws + w.cdf);
-  uint64_t* bsum = reinterpret_cast<uint64_t*>(ws + w.bsum);
-  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + w.counts);
-  const int64_t nblk = (cols + kBlock - 1) / kBlock;
-  if (nblk > 0x7fffffffLL) return fail(CQ_ERR_SHAPE, "too many columns");
-  const dim3 gq((unsigned)nblk, (unsigned)rows);
-  hipLaunchKernelGGL(shots_quant_kernel, gq, dim3(kThreads), 0, stream, probs, cols, nblk, cdf, bsum);
-  hipLaunchKernelGGL(shots_block_scan_kernel, dim3((unsigned)rows), dim3(kThreads), 0, stream, bsum, nblk);
-  hipLaunchKernelGGL(shots_cdf_kernel, gq, dim3(kThreads), 0, stream, cols, nblk, cdf, (const uint64_t*)bsum);
-  const int64_t n = rows * cols;
-  const unsigned gz = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 65536);
-  hipLaunchKernelGGL(shots_zero_kernel, dim3(gz), dim3(kThreads), 0, stream, counts, n);
-  const int64_t total = rows * shots;
-  const int64_t gs = (total + kThreads - 1) / kThreads;
-  if (gs > 0x7fffffffLL) return fail(CQ_ERR_SHAPE, "too many shots");
-  hipLaunchKernelGGL(shots_sample_kernel, dim3((unsigned)gs), dim3(kThreads), 0, stream, (const uint64_t*)cdf,
-                     rows, cols, shots, seed, counts);
-  hipLaunchKernelGGL(shots_freq_kernel, dim3(gz), dim3(kThreads), 0, stream, (const uint32_t*)counts, n,
-                     (double)shots, freqs);
+  uint64_t* bend = reinterpret_cast<uint64_t*>(ws + w.bend);
+  uint32_t* bcnt = reinterpret_cast<uint32_t*>(ws + w.bcnt);
+  uint32_t* bptr = reinterpret_cast<uint32_t*>(ws + w.bptr);
+  uint32_t* bfill = reinterpret_cast<uint32_t*>(ws + w.bfill);
+  uint64_t* slots = reinterpret_cast<uint64_t*>(ws + w.slots);
+  const int64_t nblk = (cols + kBlock - 1) / kBlock;  // <= 2^23 by the limits
+  const dim3 gt((unsigned)nblk, (unsigned)rows);
+  const dim3 gs((unsigned)((shots + kShotsPerGroup - 1) / kShotsPerGroup), (unsigned)rows);
+  hipLaunchKernelGGL(shots_bsum_kernel, gt, dim3(kThreads), 0, stream, probs, cols, nblk, bend, bcnt, bfill);
+  hipLaunchKernelGGL(shots_bend_kernel, dim3((unsigned)rows), dim3(kScanThreads), 0, stream, bend, nblk);
+  hipLaunchKernelGGL(shots_count_kernel, gs, dim3(kThreads), 0, stream, (const uint64_t*)bend, nblk, shots, seed,
+                     bcnt);
+  hipLaunchKernelGGL(shots_bptr_kernel, dim3((unsigned)rows), dim3(kScanThreads), 0, stream, bcnt, bptr, nblk);
+  hipLaunchKernelGGL(shots_scatter_kernel, gs, dim3(kThreads), 0, stream, (const uint64_t*)bend, nblk, shots,
+                     seed, (const uint32_t*)bptr, bfill, slots);
+  hipLaunchKernelGGL(shots_resolve_kernel, gt, dim3(kThreads), 0, stream, probs, cols, nblk, shots,
+                     (const uint32_t*)bcnt, (const uint32_t*)bptr, (const uint64_t*)slots, freqs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "shot sampling launch");
   return CQ_OK;

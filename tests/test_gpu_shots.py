@@ -4,8 +4,10 @@ against the oracle, through the C ABI.
 Sampling takes every decision in integers (quantised probabilities, exact
 prefix sums, Philox4x32-10 words, a 64 x 64 high product), so the device
 frequencies must equal the oracle's bit for bit: on ragged widths that span
-several prefix-sum blocks, on negative, zero and unnormalised rows, on seeds
-above 2^32, and at the dynamic-definition subcircuit shape on sampled rows.
+several blocks of 2048 entries (rows of one block, rows counted in LDS, rows
+of more than 8192 blocks counted in global memory), on negative, zero,
+unnormalised and single-spike rows, on seeds above 2^32, and at the
+dynamic-definition subcircuit shape on sampled rows.
 The loss is a floating-point sum in another order than the oracle's: it must
 agree within 1e-12 of the sum of the terms' magnitudes, and repeat bit for
 bit."""
@@ -53,6 +55,11 @@ def _table(rng, rows, cols, kind):
             P[2] = -np.abs(P[2])
         P[-1, cols // 2] = 1.7
         return P
+    if kind == "spike":       # every shot of row 0 in one entry of a many-block row
+        P = rng.dirichlet(np.ones(cols), size=rows)
+        P[0] = 0.0
+        P[0, (7 * cols) // 9] = 1.0
+        return P
     raise ValueError(kind)
 
 
@@ -66,6 +73,9 @@ def _table(rng, rows, cols, kind):
     (6, 300, 7777, 4, "mixed"),
     (16 * 9, 64, 1000, 9, "dirichlet"),
     (1, 1 << 20, 100000, 12345678901, "uniform"),
+    (3, 10000, 100000, 6, "spike"),
+    (4096, 16, 5000, 8, "dirichlet"),
+    (1, (1 << 24) + 4099, 200000, 10, "dirichlet"),
 ])
 def test_frequencies_bit_exact(rows, cols, n, seed, kind):
     print(f"case rows={rows} cols={cols} shots={n} seed={seed} {kind}", flush=True)
