@@ -331,6 +331,94 @@ cq_status cq_chi2_workspace_size(size_t* bytes);
 cq_status cq_chi2(const double* a, const double* b, int64_t n, double* result, void* workspace,
                   size_t workspace_bytes, hipStream_t stream);
 
+/* -------------------------------------------------------------------------
+ * State-vector simulation on the device (the noiseless ground truth of
+ * Section 2) and the variants of a subcircuit (Section 3.1), FP64 complex.
+ *
+ * A circuit is a list of gates on n qubits, qubit 0 the most significant bit
+ * of a basis-state index: CQ_GATE_U applies the 2 x 2 unitary u (row-major,
+ * (re, im) of u00, u01, u10, u11) to qubit q0; CQ_GATE_CZ applies CZ to q0
+ * and q1.  The matrix is applied as given (unitarity is not checked).
+ * Consecutive gates are applied in groups to tiles of 2^10 amplitudes held
+ * in LDS, in circuit order, so the state crosses HBM once per group.
+ * ------------------------------------------------------------------------- */
+#define CQ_MAX_SV_QUBITS 34  /* 2^34 amplitudes = 256 GiB of workspace */
+
+typedef enum cq_gate_kind { CQ_GATE_U = 0, CQ_GATE_CZ = 1 } cq_gate_kind;
+
+typedef struct cq_gate {
+  int32_t kind;  /* cq_gate_kind */
+  int32_t q0;    /* target qubit */
+  int32_t q1;    /* second qubit of CQ_GATE_CZ, ignored otherwise */
+  double u[8];   /* CQ_GATE_U matrix, ignored otherwise */
+} cq_gate;
+
+/* 16 * 2^n bytes (the state); n in 1..CQ_MAX_SV_QUBITS. */
+cq_status cq_simulate_workspace_size(int32_t n, size_t* bytes);
+
+/* |psi|^2 of gates applied to |0...0>.  gates: host, read during the call.
+ * probs: device, 2^n FP64, written.  workspace: device, at least
+ * cq_simulate_workspace_size bytes; it holds the state before the last
+ * group of gates on return.  Asynchronous on `stream`.  Errors (before any
+ * launch): CQ_ERR_SHAPE for n out of range, CQ_ERR_ARG for a gate with an
+ * unknown kind, a qubit out of range, equal CZ qubits or a non-finite
+ * matrix entry, CQ_ERR_WORKSPACE. */
+cq_status cq_simulate_probabilities(int32_t n, const cq_gate* gates, int32_t n_gates, double* probs,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* 16 * 2^width bytes (one state). */
+cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t* bytes);
+
+/* Every variant of subcircuit `sub` running `gates` (qubits = its register
+ * slots): for each init string (init slots in slot order, first most
+ * significant, prepared in |0>, |1>, |+>, |+i> = digits 0..3; other slots
+ * start in |0>) and each basis string (measured slots, Z, X, Y = digits
+ * 0..2, rotated by nothing, H, or H S^dagger before the computational-basis
+ * measurement), the probabilities of the 2^width register outcomes.
+ * variants: device, FP64, layout (4^r, 3^o, 2^width) as cq_attribute reads
+ * it, written whole.  workspace: device, cq_variants_workspace_size bytes.
+ * Asynchronous on `stream`; errors as for cq_simulate_probabilities plus
+ * the cut-map checks of the subcircuit. */
+cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq_gate* gates, int32_t n_gates,
+                                   double* variants, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Exact cut search for small circuits (Section 4.1; host only, no GPU).
+ *
+ * The circuit's two-qubit gates, in circuit order, are the vertices of its
+ * DAG; each qubit wire joins consecutive two-qubit gates on that qubit
+ * (one-qubit gates play no part).  A clustering of the gates into
+ * subcircuits cuts every wire edge between two clusters.  Subcircuit c then
+ * holds width_c qubits: the qubits whose first two-qubit gate it holds plus
+ * one per cut it initialises; n_c = width_c minus the cuts it measures are
+ * its outputs.  With the subcircuits ordered by n_c ascending, the cost is
+ *     L = 4^K * sum_{c=2}^{n_C} prod_{i=1}^{c} 2^{n_i}
+ * (the multiplications of Eq. 1's Kronecker products; 0 without cuts).
+ * The search is exhaustive over clusterings into at most max_subcircuits
+ * clusters with every width_c <= max_width, and returns the minimum; among
+ * equal costs, the clustering whose label string (labels numbered in order
+ * of first use) is lexicographically smallest.
+ * ------------------------------------------------------------------------- */
+#define CQ_MAX_FIND_GATES 16
+
+typedef struct cq_cut_problem {
+  int32_t n_qubits;            /* every qubit must take part in a two-qubit gate */
+  int32_t n_gates;             /* two-qubit gates, 1..CQ_MAX_FIND_GATES */
+  const int32_t* gate_qubits;  /* host, 2 * n_gates: the qubit pair of each gate */
+  int32_t max_width;           /* qubits per subcircuit (the device size) */
+  int32_t max_subcircuits;     /* 1..CQ_MAX_SUBCIRCUITS (the paper uses 5) */
+} cq_cut_problem;
+
+/* cluster: host, n_gates, receives each gate's subcircuit (0-based, numbered
+ * in order of first use).  n_subcircuits, n_cuts, cost: host, receive n_C,
+ * K and L.  Errors: CQ_ERR_ARG for null pointers, an empty circuit, gate
+ * qubits out of range or equal, an idle qubit or limits out of range;
+ * CQ_ERR_SHAPE for more than CQ_MAX_FIND_GATES gates or when no clustering
+ * fits the limits.  Nothing is written on error. */
+cq_status cq_find_cuts(const cq_cut_problem* problem, int32_t* cluster, int32_t* n_subcircuits,
+                       int32_t* n_cuts, double* cost);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,8 @@ from .api import (attribute, cq_attribute, cq_autotune_enable, cq_autotune_json,
                   cq_fd_workspace_size, cq_reconstruct_dd, cq_reconstruct_fd, cq_validate_cutmap,
                   cq_dd_bfs_workspace_size, cq_reconstruct_dd_bfs, cq_sample_shots,
                   cq_sample_shots_workspace_size, cq_chi2, cq_chi2_workspace_size,
+                  cq_simulate_probabilities, cq_simulate_workspace_size, cq_variant_probabilities,
+                  cq_variants_workspace_size, cq_find_cuts,
                   mask, reconstruct_dd, reconstruct_fd, validate_cutmap)
 from ._lib import CQError, PRECISION
 
@@ -13,5 +15,7 @@ __all__ = ["attribute", "reconstruct_fd", "reconstruct_dd", "validate_cutmap", "
            "cq_attribute_workspace_size", "cq_fd_workspace_size", "cq_dd_workspace_size",
            "cq_plan_json", "cq_profile_enable", "cq_profile_read", "cq_autotune_enable",
            "cq_autotune_json", "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs", "cq_sample_shots",
-           "cq_sample_shots_workspace_size", "cq_chi2", "cq_chi2_workspace_size", "CQError",
+           "cq_sample_shots_workspace_size", "cq_chi2", "cq_chi2_workspace_size",
+           "cq_simulate_probabilities", "cq_simulate_workspace_size", "cq_variant_probabilities",
+           "cq_variants_workspace_size", "cq_find_cuts", "CQError",
            "PRECISION"]

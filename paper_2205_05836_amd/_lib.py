@@ -22,7 +22,11 @@ EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
             "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd",
             "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs",
-            "cq_sample_shots_workspace_size", "cq_sample_shots", "cq_chi2_workspace_size", "cq_chi2"]
+            "cq_sample_shots_workspace_size", "cq_sample_shots", "cq_chi2_workspace_size", "cq_chi2",
+            "cq_simulate_workspace_size", "cq_simulate_probabilities", "cq_variants_workspace_size",
+            "cq_variant_probabilities", "cq_find_cuts"]
+
+GATE_U, GATE_CZ = 0, 1
 
 
 class cq_subcircuit(C.Structure):
@@ -56,6 +60,16 @@ class cq_dd_record(C.Structure):
 
 class cq_dd_bfs_params(C.Structure):
     _fields_ = [("prec", C.c_int), ("levels", C.c_int32), ("width", C.c_int32), ("launch", C.c_int32)]
+
+
+class cq_cut_problem(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32),
+                ("gate_qubits", C.POINTER(C.c_int32)), ("max_width", C.c_int32),
+                ("max_subcircuits", C.c_int32)]
+
+
+class cq_gate(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("q0", C.c_int32), ("q1", C.c_int32), ("u", C.c_double * 8)]
 
 
 class cq_dd_bfs_node(C.Structure):
@@ -112,6 +126,18 @@ def lib():
     L.cq_chi2_workspace_size.argtypes = [C.POINTER(C.c_size_t)]
     L.cq_chi2.restype = st
     L.cq_chi2.argtypes = [p, p, C.c_int64, p, p, C.c_size_t, p]
+    L.cq_simulate_workspace_size.restype = st
+    L.cq_simulate_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    L.cq_simulate_probabilities.restype = st
+    L.cq_simulate_probabilities.argtypes = [C.c_int32, C.POINTER(cq_gate), C.c_int32, p, p, C.c_size_t, p]
+    L.cq_variants_workspace_size.restype = st
+    L.cq_variants_workspace_size.argtypes = [C.POINTER(cq_subcircuit), C.POINTER(C.c_size_t)]
+    L.cq_variant_probabilities.restype = st
+    L.cq_variant_probabilities.argtypes = [C.POINTER(cq_subcircuit), C.POINTER(cq_gate), C.c_int32, p, p,
+                                           C.c_size_t, p]
+    L.cq_find_cuts.restype = st
+    L.cq_find_cuts.argtypes = [C.POINTER(cq_cut_problem), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     L.cq_reconstruct_dd.restype = st
     L.cq_reconstruct_dd.argtypes = [C.c_int32, C.POINTER(cq_dd_instance), C.POINTER(cq_dd_params),
                                     C.POINTER(cq_dd_record), C.POINTER(C.c_void_p),

@@ -308,6 +308,103 @@ def cq_chi2(a, b, out=None, workspace=None, stream=None):
     return out
 
 
+def _gates(ops):
+    """Gate list -> ctypes array.  An op is an object with ``name`` ('u' or
+    'cz'), ``qubits`` and ``matrix`` (2 x 2 complex for 'u'), or a tuple
+    ('u', q, matrix) / ('cz', q0, q1)."""
+    ops = list(ops)
+    arr = (_lib.cq_gate * max(len(ops), 1))()
+    for i, op in enumerate(ops):
+        if isinstance(op, tuple):
+            name, rest = op[0], op[1:]
+            qubits = (rest[0],) if name == "u" else (rest[0], rest[1])
+            matrix = rest[1] if name == "u" else None
+        else:
+            name, qubits, matrix = op.name, op.qubits, op.matrix
+        if name == "u":
+            arr[i].kind, arr[i].q0 = _lib.GATE_U, int(qubits[0])
+            m = [complex(matrix[r][c]) for r in range(2) for c in range(2)]
+            for j, z in enumerate(m):
+                arr[i].u[2 * j], arr[i].u[2 * j + 1] = z.real, z.imag
+        elif name == "cz":
+            arr[i].kind, arr[i].q0, arr[i].q1 = _lib.GATE_CZ, int(qubits[0]), int(qubits[1])
+        else:
+            raise ValueError(f"unknown gate {name!r}")
+    return arr, len(ops)
+
+
+def cq_simulate_workspace_size(n):
+    b = C.c_size_t()
+    check(lib().cq_simulate_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def cq_simulate_probabilities(n, ops, out=None, workspace=None, device="cuda:0", stream=None):
+    """|psi|^2 (2^n FP64 on the device) of ``ops`` applied to |0...0>."""
+    import torch
+    if out is None:
+        out = torch.empty(2 ** int(n), dtype=torch.float64, device=device)
+    elif out.numel() != 2 ** int(n):
+        raise ValueError("out must hold 2^n values")
+    arr, cnt = _gates(ops)
+    nbytes = cq_simulate_workspace_size(n)
+    ws = _workspace(nbytes, out.device, workspace)
+    check(lib().cq_simulate_probabilities(int(n), arr, cnt, _dev_ptr(out, torch.float64), _dev_ptr(ws),
+                                          C.c_size_t(nbytes), _stream(stream)))
+    return out
+
+
+def cq_variants_workspace_size(sub):
+    s = _Subs([sub])
+    b = C.c_size_t()
+    check(lib().cq_variants_workspace_size(s.ptr(), C.byref(b)))
+    return b.value
+
+
+def cq_variant_probabilities(sub, ops=None, out=None, workspace=None, device="cuda:0", stream=None):
+    """Every variant of subcircuit ``sub`` (its ``ops`` unless given) as a
+    (4^r, 3^o, 2^width) FP64 device tensor, the layout cq_attribute reads."""
+    import torch
+    w, ic, mc = _sub_fields(sub)
+    if ops is None:
+        ops = sub.ops
+    r = sum(1 for x in ic if x != -1)
+    o = sum(1 for x in mc if x != -1)
+    shape = (4 ** r, 3 ** o, 2 ** w)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=device)
+    elif tuple(out.shape) != shape:
+        raise ValueError(f"out must have shape {shape}")
+    s = _Subs([sub])
+    arr, cnt = _gates(ops)
+    nbytes = cq_variants_workspace_size(sub)
+    ws = _workspace(nbytes, out.device, workspace)
+    check(lib().cq_variant_probabilities(s.ptr(), arr, cnt, _dev_ptr(out, torch.float64), _dev_ptr(ws),
+                                         C.c_size_t(nbytes), _stream(stream)))
+    return out
+
+
+def cq_find_cuts(n_qubits, gates, max_width, max_subcircuits=5):
+    """Exact minimum-cost clustering of a small circuit's two-qubit gates
+    (host only).  ``gates``: qubit pairs in circuit order, or ops whose
+    two-qubit ones ('cz') are taken.  Returns a dict with each gate's
+    ``cluster``, ``n_subcircuits``, ``n_cuts`` and ``cost``."""
+    pairs = []
+    for g in gates:
+        if isinstance(g, (tuple, list)):
+            pairs.append((int(g[0]), int(g[1])))
+        elif len(g.qubits) == 2:
+            pairs.append((int(g.qubits[0]), int(g.qubits[1])))
+    flat = (C.c_int32 * max(2 * len(pairs), 1))(*[q for p in pairs for q in p])
+    prob = _lib.cq_cut_problem(int(n_qubits), len(pairs), C.cast(flat, C.POINTER(C.c_int32)),
+                               int(max_width), int(max_subcircuits))
+    cluster = (C.c_int32 * max(len(pairs), 1))()
+    ns, nc, cost = C.c_int32(), C.c_int32(), C.c_double()
+    check(lib().cq_find_cuts(C.byref(prob), cluster, C.byref(ns), C.byref(nc), C.byref(cost)))
+    return dict(cluster=list(cluster[:len(pairs)]), n_subcircuits=ns.value, n_cuts=nc.value,
+                cost=cost.value)
+
+
 def cq_plan_json(subs, prec="fp64", out_bits=None, out_perm=None):
     """The contraction plan as a dict (host only, launches nothing)."""
     import json

@@ -1,0 +1,375 @@
+// State-vector simulation on the device: the noiseless output distribution
+// of a circuit of one-qubit unitaries and CZ gates (the ground truth of
+// Section 2), and every variant of a subcircuit (Section 3.1: each cut-end
+// initialisation |0>, |1>, |+>, |+i> and each measurement basis Z, X, Y).
+//
+// Amplitudes are FP64 complex, qubit 0 the most significant index bit.
+// Gates run in groups: gates whose qubits fit one tile of kTileBits index
+// bits are applied together to tiles of 2^kTileBits amplitudes staged in
+// LDS (one workgroup a tile, the tile's other index bits fixed), in circuit
+// order, so the state makes one HBM round trip per group instead of one per
+// gate.  A tile always holds the kLowBits lowest index bits, which keeps
+// the gathers coalesced, and a group may take a later gate that commutes
+// with every gate it overtakes (no shared qubit).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace cq {
+
+namespace {
+
+constexpr int kTileBits = 11;
+constexpr int kLowBits = 4;
+constexpr int kTile = 1 << kTileBits;
+constexpr int kSvThreads = 256;
+constexpr int kPerThread = kTile / kSvThreads;
+constexpr int kMaxGroupGates = 40;
+
+struct TileGate {
+  int32_t kind;  // CQ_GATE_U or CQ_GATE_CZ
+  int32_t a, b;  // tile-local bit positions (b for CZ only)
+  int32_t pad;
+  double u[8];   // (re, im) of u00, u01, u10, u11
+};
+
+// One launch: the tile's index bits (ascending), the complement bits that
+// number the tiles, and the gates.  mode 0 writes amplitudes back, mode 1
+// writes |amplitude|^2 to `probs` in the same index order.
+struct TileGroup {
+  int32_t k;          // tile bits (<= kTileBits)
+  int32_t ngates;
+  int32_t mode;
+  int32_t nouter;     // index bits outside the tile
+  uint8_t bits[kTileBits];
+  uint8_t outer[CQ_MAX_SV_QUBITS];
+  TileGate g[kMaxGroupGates];
+};
+
+static_assert(sizeof(TileGroup) + 3 * sizeof(void*) <= 4096, "kernel arguments exceed 4 KiB");
+
+struct Complex {
+  double re, im;
+};
+
+__device__ inline Complex cmul(double ur, double ui, Complex x) {
+  return {ur * x.re - ui * x.im, ur * x.im + ui * x.re};
+}
+
+// `in` and `out` may be the same array (each workgroup reads and writes only
+// its own tile).
+__global__ void __launch_bounds__(kSvThreads) sv_tile_kernel(const double2* in, double2* out, double* probs,
+                                                             TileGroup G) {
+  __shared__ double2 S[kTile];
+  // the tile's base address: the workgroup index deposited into the outer bits
+  uint64_t base = 0;
+  const uint64_t w = blockIdx.x;
+  for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
+  const int n = 1 << G.k;
+  uint64_t addr[kPerThread];
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    const int t = threadIdx.x + e * kSvThreads;
+    uint64_t a = base;
+    for (int i = 0; i < G.k; ++i) a |= (uint64_t)((t >> i) & 1) << G.bits[i];
+    addr[e] = a;
+    if (t < n) S[t] = in[a];
+  }
+  __syncthreads();
+  for (int gi = 0; gi < G.ngates; ++gi) {
+    const TileGate& g = G.g[gi];
+    if (g.kind == CQ_GATE_U) {
+      const int half = n >> 1, m = 1 << g.a;
+      for (int p = threadIdx.x; p < half; p += kSvThreads) {
+        const int i0 = ((p >> g.a) << (g.a + 1)) | (p & (m - 1)), i1 = i0 | m;
+        const Complex x0{S[i0].x, S[i0].y}, x1{S[i1].x, S[i1].y};
+        const Complex a0 = cmul(g.u[0], g.u[1], x0), b0 = cmul(g.u[2], g.u[3], x1);
+        const Complex a1 = cmul(g.u[4], g.u[5], x0), b1 = cmul(g.u[6], g.u[7], x1);
+        S[i0] = make_double2(a0.re + b0.re, a0.im + b0.im);
+        S[i1] = make_double2(a1.re + b1.re, a1.im + b1.im);
+      }
+    } else {
+      const int both = (1 << g.a) | (1 << g.b);
+      for (int t = threadIdx.x; t < n; t += kSvThreads)
+        if ((t & both) == both) S[t] = make_double2(-S[t].x, -S[t].y);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    const int t = threadIdx.x + e * kSvThreads;
+    if (t < n) {
+      const double2 v = S[t];
+      if (G.mode == 0) out[addr[e]] = v;
+      else probs[addr[e]] = v.x * v.x + v.y * v.y;
+    }
+  }
+}
+
+// Product state: amplitude(x) = prod over qubits q of ket_q[bit q of x].
+struct Kets {
+  int32_t n;
+  double k[CQ_MAX_WIDTH][4];  // (re, im) of <0|ket>, <1|ket> per qubit
+};
+
+__global__ void __launch_bounds__(kSvThreads) sv_product_kernel(double2* __restrict__ psi, int64_t size, Kets K) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < size; x += step) {
+    double re = 1.0, im = 0.0;
+    for (int q = 0; q < K.n; ++q) {
+      const int bit = (int)((x >> (K.n - 1 - q)) & 1);
+      const double kr = K.k[q][2 * bit], ki = K.k[q][2 * bit + 1];
+      const double nr = re * kr - im * ki;
+      im = re * ki + im * kr;
+      re = nr;
+    }
+    psi[x] = make_double2(re, im);
+  }
+}
+
+__global__ void __launch_bounds__(kSvThreads) sv_zero_state_kernel(double2* __restrict__ psi, int64_t size) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < size; x += step)
+    psi[x] = make_double2(x == 0 ? 1.0 : 0.0, 0.0);
+}
+
+unsigned fill_grid(int64_t size) {
+  return (unsigned)std::min<int64_t>((size + kSvThreads - 1) / kSvThreads, 1 << 16);
+}
+
+cq_status sv_hip_error(hipError_t e, const char* what) {
+  return fail(CQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+cq_status check_gates(int32_t n, const cq_gate* gates, int32_t n_gates) {
+  if (n_gates < 0) return fail(CQ_ERR_ARG, "negative gate count");
+  if (n_gates > 0 && !gates) return fail(CQ_ERR_ARG, "null gate array");
+  for (int i = 0; i < n_gates; ++i) {
+    const cq_gate& g = gates[i];
+    if (g.kind != CQ_GATE_U && g.kind != CQ_GATE_CZ) return fail(CQ_ERR_ARG, "unknown gate kind");
+    if (g.q0 < 0 || g.q0 >= n) return fail(CQ_ERR_ARG, "gate qubit out of range");
+    if (g.kind == CQ_GATE_CZ && (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0))
+      return fail(CQ_ERR_ARG, "CZ qubits out of range or equal");
+    if (g.kind == CQ_GATE_U)
+      for (double v : g.u)
+        if (!std::isfinite(v)) return fail(CQ_ERR_ARG, "non-finite gate matrix");
+  }
+  return CQ_OK;
+}
+
+// Gates -> groups whose index bits fit one tile together with the kLowBits
+// lowest bits (which keep every gather in runs of 2^kLowBits amplitudes).
+// A gate joins the open group when it fits and shares no qubit with an
+// earlier gate left for a later group, so it commutes with every gate it
+// overtakes; the gates of a group keep their circuit order.
+struct Group {
+  std::vector<int> gates;
+  uint64_t mask = 0;
+};
+
+std::vector<Group> make_groups(int n, const cq_gate* gates, int n_gates, const std::vector<cq_gate>& tail) {
+  const int k = std::min(n, kTileBits);
+  const uint64_t low = (1ull << std::min(n, kLowBits)) - 1;
+  auto bit = [n](int q) { return 1ull << (n - 1 - q); };
+  const int total = n_gates + (int)tail.size();
+  std::vector<uint64_t> masks(total);
+  for (int i = 0; i < total; ++i) {
+    const cq_gate& g = i < n_gates ? gates[i] : tail[i - n_gates];
+    masks[i] = bit(g.q0) | (g.kind == CQ_GATE_CZ ? bit(g.q1) : 0ull);
+  }
+  std::vector<int> rest(total);
+  for (int i = 0; i < total; ++i) rest[i] = i;
+  std::vector<Group> out;
+  while (!rest.empty()) {
+    Group cur;
+    uint64_t blocked = 0;
+    std::vector<int> left;
+    for (int i : rest) {
+      const uint64_t m = masks[i];
+      if ((m & blocked) == 0 && (int)cur.gates.size() < kMaxGroupGates &&
+          __builtin_popcountll(cur.mask | m | low) <= k) {
+        cur.gates.push_back(i);
+        cur.mask |= m;
+      } else {
+        blocked |= m;
+        left.push_back(i);
+      }
+    }
+    out.push_back(cur);
+    rest.swap(left);
+  }
+  return out;
+}
+
+TileGroup tile_group(int n, const Group& grp, const cq_gate* gates, int n_gates, const std::vector<cq_gate>& tail,
+                     int mode) {
+  TileGroup G{};
+  const int k = std::min(n, kTileBits);
+  uint64_t mask = grp.mask | ((1ull << std::min(n, kLowBits)) - 1);
+  for (int b = 0; b < n && __builtin_popcountll(mask) < k; ++b) mask |= 1ull << b;
+  G.k = k;
+  G.mode = mode;
+  int local[64];
+  int nb = 0, no = 0;
+  for (int b = 0; b < n; ++b) {
+    if (mask >> b & 1) {
+      local[b] = nb;
+      G.bits[nb++] = (uint8_t)b;
+    } else {
+      G.outer[no++] = (uint8_t)b;
+    }
+  }
+  G.nouter = no;
+  G.ngates = (int)grp.gates.size();
+  for (int j = 0; j < G.ngates; ++j) {
+    const int i = grp.gates[j];
+    const cq_gate& g = i < n_gates ? gates[i] : tail[i - n_gates];
+    TileGate& t = G.g[j];
+    t.kind = g.kind;
+    t.a = local[n - 1 - g.q0];
+    t.b = g.kind == CQ_GATE_CZ ? local[n - 1 - g.q1] : 0;
+    for (int c = 0; c < 8; ++c) t.u[c] = g.kind == CQ_GATE_U ? g.u[c] : 0.0;
+  }
+  return G;
+}
+
+// Applies `gates` then `tail` to psi in place; the last group writes
+// |amplitude|^2 to probs instead when probs is set (psi then keeps the state
+// before that group), and a probability pass runs alone when there are no
+// gates at all.
+hipError_t run_gates(int n, const cq_gate* gates, int n_gates, const std::vector<cq_gate>& tail, double2* psi,
+                     double* probs, hipStream_t stream) {
+  std::vector<Group> groups = make_groups(n, gates, n_gates, tail);
+  if (groups.empty() && probs) groups.push_back(Group());
+  const int k = std::min(n, kTileBits);
+  const unsigned tiles = (unsigned)(1ull << (n - k));
+  for (size_t i = 0; i < groups.size(); ++i) {
+    const bool last = i + 1 == groups.size();
+    const int mode = last && probs ? 1 : 0;
+    const TileGroup G = tile_group(n, groups[i], gates, n_gates, tail, mode);
+    hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, (const double2*)psi, psi, probs, G);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+cq_gate u_gate(int q, const double (&m)[8]) {
+  cq_gate g{};
+  g.kind = CQ_GATE_U;
+  g.q0 = q;
+  for (int c = 0; c < 8; ++c) g.u[c] = m[c];
+  return g;
+}
+
+}  // namespace
+
+}  // namespace cq
+
+using namespace cq;
+
+extern "C" cq_status cq_simulate_workspace_size(int32_t n, size_t* bytes) {
+  if (!bytes) return fail(CQ_ERR_ARG, "null argument");
+  if (n < 1 || n > CQ_MAX_SV_QUBITS) return fail(CQ_ERR_SHAPE, "qubit count out of range");
+  *bytes = (size_t)16 << n;
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_simulate_probabilities(int32_t n, const cq_gate* gates, int32_t n_gates, double* probs,
+                                               void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!probs) return fail(CQ_ERR_ARG, "null argument");
+  if (n < 1 || n > CQ_MAX_SV_QUBITS) return fail(CQ_ERR_SHAPE, "qubit count out of range");
+  cq_status st = check_gates(n, gates, n_gates);
+  if (st != CQ_OK) return st;
+  if (!workspace || workspace_bytes < ((size_t)16 << n)) return fail(CQ_ERR_WORKSPACE, "workspace too small");
+  double2* psi = static_cast<double2*>(workspace);
+  const int64_t size = (int64_t)1 << n;
+  hipLaunchKernelGGL(sv_zero_state_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi, size);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = run_gates(n, gates, n_gates, {}, psi, probs, stream);
+  if (e != hipSuccess) return sv_hip_error(e, "state-vector launch");
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t* bytes) {
+  if (!bytes) return fail(CQ_ERR_ARG, "null argument");
+  SubInfo si;
+  cq_status st = build_subinfo(sub, si);
+  if (st != CQ_OK) return st;
+  if (si.width < 1) return fail(CQ_ERR_SHAPE, "subcircuit has no slots");
+  *bytes = (size_t)16 << si.width;
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq_gate* gates, int32_t n_gates,
+                                              double* variants, void* workspace, size_t workspace_bytes,
+                                              hipStream_t stream) {
+  if (!variants) return fail(CQ_ERR_ARG, "null argument");
+  SubInfo si;
+  cq_status st = build_subinfo(sub, si);
+  if (st != CQ_OK) return st;
+  const int w = si.width;
+  if (w < 1) return fail(CQ_ERR_SHAPE, "subcircuit has no slots");
+  st = check_gates(w, gates, n_gates);
+  if (st != CQ_OK) return st;
+  if (!workspace || workspace_bytes < ((size_t)16 << w)) return fail(CQ_ERR_WORKSPACE, "workspace too small");
+  double2* psi = static_cast<double2*>(workspace);
+  const int64_t size = (int64_t)1 << w;
+  const int r = si.r(), o = si.o();
+  int64_t n_init = 1, n_basis = 1;
+  for (int i = 0; i < r; ++i) n_init *= 4;
+  for (int i = 0; i < o; ++i) n_basis *= 3;
+  // prepared states of a cut's downstream end: |0>, |1>, |+>, |+i>
+  const double h = 1.0 / std::sqrt(2.0);
+  const double init_ket[4][4] = {{1, 0, 0, 0}, {0, 0, 1, 0}, {h, 0, h, 0}, {h, 0, 0, h}};
+  // rotations before a computational-basis measurement: Z (none), X (H),
+  // Y (S^dagger then H, i.e. H S^dagger = [[1, -i], [1, i]] / sqrt 2)
+  const double rot_x[8] = {h, 0, h, 0, h, 0, -h, 0};
+  const double rot_y[8] = {h, 0, 0, -h, h, 0, 0, h};
+  for (int64_t j = 0; j < n_init; ++j) {
+    Kets K{};
+    K.n = w;
+    for (int q = 0; q < w; ++q) {
+      K.k[q][0] = 1.0;
+      K.k[q][1] = K.k[q][2] = K.k[q][3] = 0.0;
+    }
+    for (int t = 0; t < r; ++t) {
+      const int digit = (int)((j >> (2 * (r - 1 - t))) & 3);
+      for (int c = 0; c < 4; ++c) K.k[si.init_slots[t]][c] = init_ket[digit][c];
+    }
+    hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi, size, K);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = run_gates(w, gates, n_gates, {}, psi, nullptr, stream);
+    for (int64_t b = 0; b < n_basis && e == hipSuccess; ++b) {
+      std::vector<cq_gate> rot;
+      int64_t rest = b;
+      std::vector<int> digits(o);
+      for (int u = o - 1; u >= 0; --u) {
+        digits[u] = (int)(rest % 3);
+        rest /= 3;
+      }
+      for (int u = 0; u < o; ++u) {
+        if (digits[u] == 1) rot.push_back(u_gate(si.meas_slots[u], rot_x));
+        if (digits[u] == 2) rot.push_back(u_gate(si.meas_slots[u], rot_y));
+      }
+      // the rotations read psi and write probabilities only, so psi stays
+      // the post-circuit state for the next basis; at most CQ_MAX_LOCAL_CUTS
+      // measured slots, so they form one group
+      double* out = variants + (j * n_basis + b) * size;
+      std::vector<Group> groups = make_groups(w, nullptr, 0, rot);
+      if (groups.empty()) groups.push_back(Group());
+      const TileGroup G = tile_group(w, groups[0], nullptr, 0, rot, 1);
+      const unsigned tiles = (unsigned)(1ull << (w - std::min(w, kTileBits)));
+      hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, (const double2*)psi, psi, out, G);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return sv_hip_error(e, "variant launch");
+  }
+  return CQ_OK;
+}

@@ -197,6 +197,19 @@ def two_way_circuit_20q(seed: int = 1) -> CutCircuit:
     return masked_brickwork(20, 10, [(8, 4), (9, 4), (10, 4), (11, 4)], assign, seed)
 
 
+def two_way_circuit_30q(seed: int = 3, layers: int = 8) -> CutCircuit:
+    """30 qubits, ``layers`` brickwork layers, four cuts after layer 3: q12,
+    q13 move from subcircuit 0 to 1 and q14, q15 from subcircuit 1 to 0,
+    giving subcircuits of 16 slots (14 outputs) and 18 slots (16 outputs)."""
+    def assign(q, s):
+        if q in (12, 13):
+            return 0 if s == 0 else 1
+        if q in (14, 15):
+            return 1 if s == 0 else 0
+        return 0 if q < 12 else 1
+    return masked_brickwork(30, layers, [(12, 3), (13, 3), (14, 3), (15, 3)], assign, seed)
+
+
 def hidden_string_circuit(secret, groups) -> CutCircuit:
     """Bernstein-Vazirani hidden-string circuit (Section 5.3 lists it as a
     sparse-output benchmark) written from the algorithm's definition.
