@@ -59,6 +59,8 @@ def parse():
                     help="skip the entry-attribution leg")
     ap.add_argument("--skip-shots", action="store_true",
                     help="skip the finite-shot sampling and chi-square leg")
+    ap.add_argument("--skip-statevector", action="store_true",
+                    help="skip the device state-vector leg")
     return ap.parse_args()
 
 
@@ -393,6 +395,47 @@ def shots_leg(torch, cq, runs=3):
     return out
 
 
+SV_WORKLOAD = ("state vector: the 30-qubit two-way cut circuit (8 brickwork layers, 348 gates, "
+               "seed 3) from |0...0> to its 2^30 probabilities; the variants of a 22-slot "
+               "subcircuit (8 brickwork layers, 260 gates, seed 4; 2 init and 2 measured slots, "
+               "16 x 9 x 2^22 probabilities)")
+
+
+def statevector_leg(torch, cq, runs=3):
+    """Times cq_simulate_probabilities on the 30-qubit cut circuit's uncut
+    form and cq_variant_probabilities at the DD subcircuit shape.  Each tile
+    pass moves the state once in and once out (32 B an amplitude)."""
+    from workloads import circuits as wc
+
+    def timed(fn):
+        fn()
+        times = []
+        for _ in range(runs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return sorted(times)[len(times) // 2]
+
+    cc = wc.two_way_circuit_30q()
+    out = torch.empty(2 ** 30, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(cq.cq_simulate_workspace_size(30), dtype=torch.uint8, device="cuda:0")
+    ms30 = timed(lambda: cq.cq_simulate_probabilities(30, cc.ops, out=out, workspace=ws))
+    del out, ws
+    torch.cuda.empty_cache()
+    ops = wc.masked_brickwork(22, 8, [], lambda q, s: 0, seed=4).ops
+    sub = (22, [0, 1] + [-1] * 20, [-1] * 20 + [2, 3])
+    V = torch.empty((16, 9, 2 ** 22), dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(cq.cq_variants_workspace_size(sub), dtype=torch.uint8, device="cuda:0")
+    msv = timed(lambda: cq.cq_variant_probabilities(sub, ops, out=V, workspace=ws))
+    del V, ws
+    return {"workload": SV_WORKLOAD, "ms_30q": round(ms30, 2), "gates_30q": len(cc.ops),
+            "ms_variants_22": round(msv, 2), "gates_22": len(ops)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -484,6 +527,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.skip_shots:
         result["shots"] = shots_leg(torch, cq)
+        torch.cuda.empty_cache()
+    if not args.skip_statevector:
+        result["statevector"] = statevector_leg(torch, cq)
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         cpu, err = cpu_baseline_leg(torch, ents, out, args.cpu_seconds)
