@@ -112,6 +112,100 @@ __global__ void __launch_bounds__(kSvThreads) sv_tile_kernel(const double2* in, 
   }
 }
 
+// Full tiles (kTileBits bits) keep the amplitudes in registers: thread t
+// holds local indices t + 256 e, e = 0..7, so local bits 0-5 are lane bits,
+// 6-7 wave bits and 8-10 register bits.  CZ is a sign flip on elements the
+// thread owns; a one-qubit gate on a register bit pairs two of the thread's
+// own elements; on a lane bit the partner comes from another lane by a
+// cross-lane read; on a wave bit it goes through LDS.  The host places the
+// group's busiest qubits on register bits.
+__device__ inline double2 u_row(double r0, double i0, double r1, double i1, double2 x, double2 y) {
+  // (r0 + i i0) x + (r1 + i i1) y
+  return make_double2(r0 * x.x - i0 * x.y + r1 * y.x - i1 * y.y, r0 * x.y + i0 * x.x + r1 * y.y + i1 * y.x);
+}
+
+template <int R>
+__device__ inline void u_reg(double2 (&v)[kPerThread], const double* u) {
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    if (e & (1 << R)) continue;
+    const double2 x0 = v[e], x1 = v[e | (1 << R)];
+    v[e] = u_row(u[0], u[1], u[2], u[3], x0, x1);
+    v[e | (1 << R)] = u_row(u[4], u[5], u[6], u[7], x0, x1);
+  }
+}
+
+// new value of an element whose partner (the other value of its pair) is y:
+// bit 0 takes row 0 of u with (mine, partner), bit 1 row 1 with (partner, mine)
+__device__ inline double2 u_exchange(const double* u, int bit, double2 mine, double2 y) {
+  return bit ? u_row(u[4], u[5], u[6], u[7], y, mine) : u_row(u[0], u[1], u[2], u[3], mine, y);
+}
+
+template <int M>
+__device__ inline void u_lane(double2 (&v)[kPerThread], const double* u, int lane) {
+  const int bit = (lane & M) ? 1 : 0;
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    const double2 y = make_double2(__shfl_xor(v[e].x, M), __shfl_xor(v[e].y, M));
+    v[e] = u_exchange(u, bit, v[e], y);
+  }
+}
+
+__global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, double2* out, double* probs,
+                                                            TileGroup G) {
+  static_assert(kPerThread == 8 && kSvThreads == 256, "bit layout assumes 8 elements a thread, 256 threads");
+  __shared__ double2 S[kTile];
+  uint64_t base = 0;
+  const uint64_t w = blockIdx.x;
+  for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
+  const int tid = threadIdx.x, lane = tid & 63;
+  uint64_t addr[kPerThread];
+  double2 v[kPerThread];
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    const int t = tid + e * kSvThreads;
+    uint64_t a = base;
+    for (int i = 0; i < kTileBits; ++i) a |= (uint64_t)((t >> i) & 1) << G.bits[i];
+    addr[e] = a;
+    v[e] = in[a];
+  }
+  for (int gi = 0; gi < G.ngates; ++gi) {
+    const TileGate& g = G.g[gi];
+    if (g.kind == CQ_GATE_CZ) {
+      const int both = (1 << g.a) | (1 << g.b);
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e)
+        if (((tid + e * kSvThreads) & both) == both) v[e] = make_double2(-v[e].x, -v[e].y);
+    } else if (g.a >= 8) {
+      if (g.a == 8) u_reg<0>(v, g.u);
+      else if (g.a == 9) u_reg<1>(v, g.u);
+      else u_reg<2>(v, g.u);
+    } else if (g.a < 6) {
+      switch (g.a) {
+        case 0: u_lane<1>(v, g.u, lane); break;
+        case 1: u_lane<2>(v, g.u, lane); break;
+        case 2: u_lane<4>(v, g.u, lane); break;
+        case 3: u_lane<8>(v, g.u, lane); break;
+        case 4: u_lane<16>(v, g.u, lane); break;
+        default: u_lane<32>(v, g.u, lane); break;
+      }
+    } else {
+      const int bit = (tid >> g.a) & 1, m = 1 << g.a;
+      __syncthreads();  // the previous exchange has read S
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) S[tid + e * kSvThreads] = v[e];
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) v[e] = u_exchange(g.u, bit, v[e], S[(tid + e * kSvThreads) ^ m]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kPerThread; ++e) {
+    if (G.mode == 0) out[addr[e]] = v[e];
+    else probs[addr[e]] = v[e].x * v[e].x + v[e].y * v[e].y;
+  }
+}
+
 // Product state: amplitude(x) = prod over qubits q of ket_q[bit q of x].
 struct Kets {
   int32_t n;
@@ -215,21 +309,38 @@ TileGroup tile_group(int n, const Group& grp, const cq_gate* gates, int n_gates,
   for (int b = 0; b < n && __builtin_popcountll(mask) < k; ++b) mask |= 1ull << b;
   G.k = k;
   G.mode = mode;
-  int local[64];
-  int nb = 0, no = 0;
-  for (int b = 0; b < n; ++b) {
-    if (mask >> b & 1) {
-      local[b] = nb;
-      G.bits[nb++] = (uint8_t)b;
-    } else {
-      G.outer[no++] = (uint8_t)b;
-    }
+  auto gate = [&](int i) -> const cq_gate& { return i < n_gates ? gates[i] : tail[i - n_gates]; };
+  // local positions: ascending global bits for partial tiles; for full
+  // tiles the kLowBits lowest bits first (coalesced lanes), then the other
+  // bits by one-qubit gate count, busiest first, on the register positions
+  // 8-10, then lane positions 4-5, then wave positions 6-7
+  std::vector<int> order;
+  for (int b = 0; b < n; ++b)
+    if (mask >> b & 1) order.push_back(b);
+  if (k == kTileBits) {
+    int uses[64] = {};
+    for (int i : grp.gates)
+      if (gate(i).kind == CQ_GATE_U) ++uses[n - 1 - gate(i).q0];
+    std::vector<int> rest(order.begin() + kLowBits, order.end());
+    std::stable_sort(rest.begin(), rest.end(), [&](int x, int y) { return uses[x] > uses[y]; });
+    const int slot[kTileBits - kLowBits] = {8, 9, 10, 4, 5, 6, 7};
+    std::vector<int> placed(kTileBits, -1);
+    for (int i = 0; i < kLowBits; ++i) placed[i] = order[i];
+    for (int i = 0; i < (int)rest.size(); ++i) placed[slot[i]] = rest[i];
+    order = placed;
   }
+  int local[64];
+  int no = 0;
+  for (int i = 0; i < k; ++i) {
+    local[order[i]] = i;
+    G.bits[i] = (uint8_t)order[i];
+  }
+  for (int b = 0; b < n; ++b)
+    if (!(mask >> b & 1)) G.outer[no++] = (uint8_t)b;
   G.nouter = no;
   G.ngates = (int)grp.gates.size();
   for (int j = 0; j < G.ngates; ++j) {
-    const int i = grp.gates[j];
-    const cq_gate& g = i < n_gates ? gates[i] : tail[i - n_gates];
+    const cq_gate& g = gate(grp.gates[j]);
     TileGate& t = G.g[j];
     t.kind = g.kind;
     t.a = local[n - 1 - g.q0];
@@ -237,6 +348,18 @@ TileGroup tile_group(int n, const Group& grp, const cq_gate* gates, int n_gates,
     for (int c = 0; c < 8; ++c) t.u[c] = g.kind == CQ_GATE_U ? g.u[c] : 0.0;
   }
   return G;
+}
+
+// One tile pass: the register kernel for full tiles, the LDS kernel for
+// registers narrower than a tile.
+hipError_t launch_tiles(int n, const TileGroup& G, const double2* in, double2* out, double* probs,
+                        hipStream_t stream) {
+  const unsigned tiles = (unsigned)(1ull << (n - G.k));
+  if (G.k == kTileBits)
+    hipLaunchKernelGGL(sv_reg_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, in, out, probs, G);
+  else
+    hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, in, out, probs, G);
+  return hipGetLastError();
 }
 
 // Applies `gates` then `tail` to psi in place; the last group writes
@@ -247,14 +370,11 @@ hipError_t run_gates(int n, const cq_gate* gates, int n_gates, const std::vector
                      double* probs, hipStream_t stream) {
   std::vector<Group> groups = make_groups(n, gates, n_gates, tail);
   if (groups.empty() && probs) groups.push_back(Group());
-  const int k = std::min(n, kTileBits);
-  const unsigned tiles = (unsigned)(1ull << (n - k));
   for (size_t i = 0; i < groups.size(); ++i) {
     const bool last = i + 1 == groups.size();
     const int mode = last && probs ? 1 : 0;
     const TileGroup G = tile_group(n, groups[i], gates, n_gates, tail, mode);
-    hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, (const double2*)psi, psi, probs, G);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = launch_tiles(n, G, psi, psi, probs, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -365,9 +485,7 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
       std::vector<Group> groups = make_groups(w, nullptr, 0, rot);
       if (groups.empty()) groups.push_back(Group());
       const TileGroup G = tile_group(w, groups[0], nullptr, 0, rot, 1);
-      const unsigned tiles = (unsigned)(1ull << (w - std::min(w, kTileBits)));
-      hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, (const double2*)psi, psi, out, G);
-      e = hipGetLastError();
+      e = launch_tiles(w, G, psi, psi, out, stream);
     }
     if (e != hipSuccess) return sv_hip_error(e, "variant launch");
   }
