@@ -52,12 +52,16 @@ cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap, i
 /* GEMM autotuner for the full-definition label GEMMs.  The first launch of
  * each GEMM shape (outside stream capture, at least 64 output tiles) times
  * every kernel variant twice on the caller's stream and keeps the fastest for
- * that shape; that call synchronises the stream.  Variant v: bit 0 flips the
- * tile raster order (M- or N-fastest); v >> 1 picks, for the 16-bit forms,
- * the asynchronous LDS-staged kernel with its default ring depth (0), with
- * the other depth (1), or the register-path kernel (2).  FP32 and FP64 have
- * variants 0 and 1; 16-bit forms 0..5 (2..5 only where the asynchronous
- * kernel's alignment holds).  Every variant computes the same sums.
+ * that shape; that call synchronises the stream.  Under stream capture a
+ * shape tuned before keeps its variant and an untuned shape takes variant 0
+ * (nothing is timed).  Variant v: bit 0 flips the tile raster order (M- or
+ * N-fastest); v >> 1 picks, for the 16-bit forms, the asynchronous
+ * LDS-staged kernel with its default ring depth (0), with the other depth
+ * (1), the register-path kernel (2) or the persistent kernel (3); for FP32
+ * the tiled kernel (0) or the persistent kernel (3).  FP64 has variants 0
+ * and 1; FP32 0, 1, 6 and 7 (6 and 7 where rows are 16-byte aligned);
+ * 16-bit forms 0..7 (2..7 only where the asynchronous kernel's alignment
+ * holds).  Every variant computes the same sums.
  *
  * mode: 0 = variant 0 always (cached choices ignored); 1 = tune (the
  * default, also set by the environment variable CQ_AUTOTUNE unless it starts

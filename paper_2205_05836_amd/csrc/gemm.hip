@@ -1495,17 +1495,15 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     default:
       return hipErrorInvalidValue;
   }
-  // tune only shapes worth it (a few microseconds of work or more), never
-  // inside a capture
+  // tune only shapes worth it (a few microseconds of work or more); inside a
+  // capture nothing is timed: a shape tuned before keeps its variant, an
+  // untuned one takes variant 0
   const int mode = tune_mode();
   if (mode >= 2) {
     const int v = mode - 2;
     return launch_variant(prec, a, g.tc, nt, variant_applies(prec, a, g.tc, v) ? v : 0, stream);
   }
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (mode == 0 || a.tiles < 64 || hipStreamIsCapturing(stream, &cap) != hipSuccess ||
-      cap != hipStreamCaptureStatusNone)
-    return launch_variant(prec, a, g.tc, nt, 0, stream);
+  if (mode == 0 || a.tiles < 64) return launch_variant(prec, a, g.tc, nt, 0, stream);
   const TuneKey key{(int)prec, (int)g.tc, nt ? 1 : 0, g.sAz ? 1 : 0, g.sBz ? 1 : 0,
                     h16_async_ok(a, g.tc) ? 1 : 0, g.M, g.N, g.K, g.Z};
   {
@@ -1513,6 +1511,9 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return launch_variant(prec, a, g.tc, nt, it->second.variant, stream);
   }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return launch_variant(prec, a, g.tc, nt, 0, stream);
   TuneEntry te{0, {0, 0, 0, 0, 0, 0, 0, 0}, 0};
   hipEvent_t ev[3];
   for (int i = 0; i < 3; ++i)
