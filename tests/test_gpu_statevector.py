@@ -130,6 +130,25 @@ def test_30_qubit_product_circuit_against_oracle_halves():
     assert abs(torch.sum(p).item() - 1.0) < 1e-10
 
 
+def test_32_qubit_product_circuit_sampled_against_oracle_halves():
+    """32 qubits (2^32 amplitudes, indices past 2^31 and 2^21 tiles): two
+    non-interacting 16-qubit halves, 10^6 sampled probabilities against the
+    products of the oracle's half distributions."""
+    cc = wc.masked_brickwork(32, 4, [], lambda q, s: 0 if q < 16 else 1, seed=13)
+    print("32q product circuit", flush=True)
+    p = cq().cq_simulate_probabilities(32, cc.ops)
+    pa = sv.probabilities(16, _restrict(cc.ops, range(16)))
+    pb = sv.probabilities(16, _restrict(cc.ops, range(16, 32)))
+    idx = np.random.default_rng(14).integers(0, 1 << 32, size=1000000, dtype=np.int64)
+    idx[:4] = [0, (1 << 32) - 1, (1 << 31), (1 << 31) - 1]
+    got = p[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    total = torch.sum(p).item()
+    del p
+    want = pa[idx >> 16] * pb[idx & 0xFFFF]
+    assert np.max(np.abs(got - want)) <= 1e-13 * max(pa.max() * pb.max(), 1e-300)
+    assert abs(total - 1.0) < 1e-10
+
+
 def test_30_qubit_cut_circuit_reconstruction_matches_state_vector():
     """The 30-qubit two-way cut circuit (subcircuits of 16 and 18 slots, four
     cuts): device variants, attribution and FP64 full definition against the
