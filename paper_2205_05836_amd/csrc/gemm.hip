@@ -708,7 +708,7 @@ __global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmA
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline int swz(int row, int chunk) { return chunk ^ ((row & 3) << 1); }
+__device__ inline int swz(int row, int chunk) { return chunk ^ ((row & 3) << 2); }
 
 // s_waitcnt vmcnt(N) lgkmcnt(0)
 template <int N>
