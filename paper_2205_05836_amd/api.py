@@ -367,6 +367,8 @@ def cq_variant_probabilities(sub, ops=None, out=None, workspace=None, device="cu
     import torch
     w, ic, mc = _sub_fields(sub)
     if ops is None:
+        if not hasattr(sub, "ops"):
+            raise ValueError("pass ops for a subcircuit given as a tuple")
         ops = sub.ops
     r = sum(1 for x in ic if x != -1)
     o = sum(1 for x in mc if x != -1)
