@@ -321,8 +321,8 @@ cq_status cq_sample_shots(const double* probs, int64_t rows, int64_t cols, int64
 /* Eq. 3: chi2 = sum_i (a_i - b_i)^2 / (a_i + b_i) over n entries; a term
  * with a_i + b_i = 0 contributes 0.  Applied as written to any real inputs,
  * so quasi-probabilities with negative entries can give negative terms.  The
- * sum runs in a fixed order (1024 x 256 strided partial sums, then a tree),
- * so repeated calls give the same bits. */
+ * sum runs in a fixed order (2048 x 256 threads summing four strided
+ * streams each, then trees), so repeated calls give the same bits. */
 cq_status cq_chi2_workspace_size(size_t* bytes);
 
 /* a, b: device FP64, n >= 1 entries each.  result: device, one FP64,
