@@ -10,12 +10,18 @@ Quantum and Classical Platforms", Tang & Martonosi):
 * ``attribution``  -- variant probabilities -> entry vectors p_{i,k}.
 * ``reconstruct``  -- Eq. 1, the Kronecker sum over all 4^K cut labelings,
   as a literal loop, per output bin, and as one einsum contraction.
-* ``dd``           -- dynamic definition, Algorithm 1.
+* ``dd``           -- dynamic definition, Algorithm 1, and the breadth-first
+  query.
+* ``shots``        -- finite-shot emulation and the chi-square loss of Eq. 3.
+* ``cutfind``      -- exhaustive cut search with the objective of Section 4.1.
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the HIP library and must never
 serve as a fallback for it.  numpy float64 throughout.
 
 Every function that has no independent pin says "parity unpinned" in its
-docstring; all functions here are pinned by tests/test_oracle_*.py.
+docstring; all functions here are pinned by tests/test_oracle_*.py and
+tests/test_cutfind.py, with one caveat: ``shots.philox4x32_10`` is pinned by
+its statistics only, so its identity with the published generator (its round
+constants) is parity unpinned.
 """

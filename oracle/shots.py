@@ -39,7 +39,12 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     with key words k0, k1.  Each round: the two products of counter words 0
     and 2 with the round multipliers split into high and low halves, the
     high halves xor-ed with the other counter words and the key; the key
-    advances by the Weyl constants between rounds."""
+    advances by the Weyl constants between rounds.
+
+    Parity unpinned as to identity with the published generator: the tests
+    pin its output statistics and distinct streams, not known-answer
+    vectors, so a wrong round constant would go unnoticed (the sampling
+    built on it stays valid and bit-exact between oracle and device)."""
     c0, c1, c2, c3 = (np.asarray(x, dtype=np.uint64) & M32 for x in (c0, c1, c2, c3))
     k0 = np.uint64(int(k0) & 0xFFFFFFFF)
     k1 = np.uint64(int(k1) & 0xFFFFFFFF)
