@@ -135,19 +135,29 @@ __device__ inline void u_reg(double2 (&v)[kPerThread], const double* u) {
   }
 }
 
-// new value of an element whose partner (the other value of its pair) is y:
-// bit 0 takes row 0 of u with (mine, partner), bit 1 row 1 with (partner, mine)
-__device__ inline double2 u_exchange(const double* u, int bit, double2 mine, double2 y) {
-  return bit ? u_row(u[4], u[5], u[6], u[7], y, mine) : u_row(u[0], u[1], u[2], u[3], mine, y);
+// An element whose partner (the other value of its pair) sits elsewhere:
+// bit 0 takes u00 * mine + u01 * partner, bit 1 u11 * mine + u10 * partner.
+// The two coefficients are picked once per gate, so each element costs one
+// complex row, not two and a select.
+struct ExchangeCoef {
+  double ar, ai, br, bi;  // coefficient of mine, of the partner
+};
+
+__device__ inline ExchangeCoef exchange_coef(const double* u, int bit) {
+  return bit ? ExchangeCoef{u[6], u[7], u[4], u[5]} : ExchangeCoef{u[0], u[1], u[2], u[3]};
+}
+
+__device__ inline double2 u_exchange(const ExchangeCoef& c, double2 mine, double2 y) {
+  return u_row(c.ar, c.ai, c.br, c.bi, mine, y);
 }
 
 template <int M>
 __device__ inline void u_lane(double2 (&v)[kPerThread], const double* u, int lane) {
-  const int bit = (lane & M) ? 1 : 0;
+  const ExchangeCoef c = exchange_coef(u, (lane & M) ? 1 : 0);
 #pragma unroll
   for (int e = 0; e < kPerThread; ++e) {
     const double2 y = make_double2(__shfl_xor(v[e].x, M), __shfl_xor(v[e].y, M));
-    v[e] = u_exchange(u, bit, v[e], y);
+    v[e] = u_exchange(c, v[e], y);
   }
 }
 
@@ -190,13 +200,14 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
         default: u_lane<32>(v, g.u, lane); break;
       }
     } else {
-      const int bit = (tid >> g.a) & 1, m = 1 << g.a;
+      const ExchangeCoef c = exchange_coef(g.u, (tid >> g.a) & 1);
+      const int m = 1 << g.a;
       __syncthreads();  // the previous exchange has read S
 #pragma unroll
       for (int e = 0; e < kPerThread; ++e) S[tid + e * kSvThreads] = v[e];
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < kPerThread; ++e) v[e] = u_exchange(g.u, bit, v[e], S[(tid + e * kSvThreads) ^ m]);
+      for (int e = 0; e < kPerThread; ++e) v[e] = u_exchange(c, v[e], S[(tid + e * kSvThreads) ^ m]);
     }
   }
 #pragma unroll
