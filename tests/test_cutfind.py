@@ -5,7 +5,10 @@ C ABI against the oracle's exhaustive search.  Host only."""
 import numpy as np
 import pytest
 
+from oracle import attribution as at
 from oracle import cutfind as cf
+from oracle import reconstruct as rc
+from oracle import statevector as sv
 from workloads import circuits as wc
 
 
@@ -113,3 +116,31 @@ def test_sixteen_gate_brickwork_finishes():
     cuts, width, outputs = cf.structure(9, pairs, tuple(got["cluster"]))
     assert max(width) <= 5 and cuts == got["n_cuts"]
     assert got["cost"] == cf.cost(cuts, outputs)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_found_cuts_reconstruct_the_circuit(seed):
+    """The library's cut search on a random 6-qubit circuit for 4-qubit
+    devices; the circuit cut where it says, simulated per variant and
+    reconstructed by the oracle (Eq. 1), equals the uncut state vector, and
+    the cut circuit's subcircuits fit the device."""
+    rng = np.random.default_rng(100 + seed)
+    n = 6
+    ops = []
+    chain = rng.permutation(n)
+    pairs = [(int(chain[i]), int(chain[i + 1])) for i in range(n - 1)]
+    pairs += [tuple(int(x) for x in rng.choice(n, size=2, replace=False)) for _ in range(3)]
+    for a, b in pairs:
+        ops.append(wc.Op("u", (a,), wc.haar_u2(rng)))
+        ops.append(wc.Op("u", (b,), wc.haar_u2(rng)))
+        ops.append(wc.Op("cz", (a, b)))
+    ops += [wc.Op("u", (q,), wc.haar_u2(rng)) for q in range(n)]
+    found = cq().cq_find_cuts(n, ops, max_width=4, max_subcircuits=3)
+    cc = wc.cut_circuit_from_clusters(n, ops, found["cluster"])
+    subs = cc.subcircuits()
+    assert found["n_cuts"] >= 1                   # six qubits cannot fit one device of four
+    assert len(cc.cuts) == found["n_cuts"] and len(subs) == found["n_subcircuits"]
+    assert max(s.width for s in subs) <= 4
+    E = [at.attribute(s, sv.variant_probabilities(s)) for s in subs]
+    p = rc.apply_out_perm(rc.fd_definition(subs, E), cc.out_perm())
+    assert np.max(np.abs(p - sv.probabilities(n, ops))) < 1e-12

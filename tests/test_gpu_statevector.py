@@ -191,3 +191,24 @@ def test_state_vector_arguments_rejected_before_launch():
     assert torch.all(out == -2.0)
     with pytest.raises(cq().CQError):
         cq().cq_variant_probabilities((3, [0, -1, -1], [-1, -1, 0]), [])
+
+
+def test_found_cuts_reconstruct_on_device():
+    """An 8-qubit circuit cut by the library's exact search for 5-qubit
+    devices, then run end to end on the device (variants, attribution, FP64
+    full definition) against the oracle's state vector of the uncut
+    circuit."""
+    m = cq()
+    rng = np.random.default_rng(31)
+    n, ops = 8, []
+    for t in range(3):
+        ops += [wc.Op("u", (q,), wc.haar_u2(rng)) for q in range(n)]
+        ops += [wc.Op("cz", (i, i + 1)) for i in range(t % 2, n - 1, 2)]
+    ops += [wc.Op("u", (q,), wc.haar_u2(rng)) for q in range(n)]
+    found = m.cq_find_cuts(n, ops, max_width=5, max_subcircuits=3)
+    cc = wc.cut_circuit_from_clusters(n, ops, found["cluster"])
+    subs = cc.subcircuits()
+    assert found["n_cuts"] >= 1 and max(s.width for s in subs) <= 5
+    E = [m.cq_attribute(s, m.cq_variant_probabilities(s)) for s in subs]
+    p = m.cq_reconstruct_fd(subs, E, prec="fp64", out_perm=cc.out_perm()).cpu().numpy()
+    assert np.max(np.abs(p - sv.probabilities(n, ops))) < 1e-12

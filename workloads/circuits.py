@@ -210,6 +210,32 @@ def two_way_circuit_30q(seed: int = 3, layers: int = 8) -> CutCircuit:
     return masked_brickwork(30, layers, [(12, 3), (13, 3), (14, 3), (15, 3)], assign, seed)
 
 
+def cut_circuit_from_clusters(n: int, ops, cluster) -> CutCircuit:
+    """The cut circuit that a clustering of the two-qubit gates defines:
+    ``cluster[g]`` is the subcircuit of the g-th two-qubit gate of ``ops``.
+    A wire is cut right after a two-qubit gate whose next two-qubit gate on
+    that wire lies in another cluster; every wire segment belongs to the
+    cluster of the two-qubit gates it holds (a segment before a wire's first
+    two-qubit gate to that gate's cluster)."""
+    two = [i for i, op in enumerate(ops) if len(op.qubits) == 2]
+    if len(two) != len(cluster):
+        raise ValueError("one cluster label per two-qubit gate")
+    label = dict(zip(two, cluster))
+    cuts, assignment = [], {}
+    for q in range(n):
+        on_q = [i for i in two if q in ops[i].qubits]
+        if not on_q:
+            raise ValueError(f"qubit {q} takes part in no two-qubit gate")
+        seg = 0
+        assignment[(q, 0)] = label[on_q[0]]
+        for a, b in zip(on_q, on_q[1:]):
+            if label[a] != label[b]:
+                cuts.append((q, a))
+                seg += 1
+                assignment[(q, seg)] = label[b]
+    return CutCircuit(n, list(ops), cuts, assignment)
+
+
 def hidden_string_circuit(secret, groups) -> CutCircuit:
     """Bernstein-Vazirani hidden-string circuit (Section 5.3 lists it as a
     sparse-output benchmark) written from the algorithm's definition.
