@@ -239,8 +239,8 @@ cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* inst, const cq
                             void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------------------
- * Breadth-first dynamic definition (Section 4.3: the BFS-like query that
- * builds a "blurred" landscape of a dense distribution).
+ * Breadth-first dynamic definition (Section 4.3: a breadth-first query that
+ * refines a coarse picture of a dense distribution level by level).
  *
  * A node is one recursion of the root instance's circuit: its bins are
  * reconstructed as in cq_reconstruct_dd and its candidates are its `width`
