@@ -519,7 +519,8 @@ def main():
         out = None
         torch.cuda.empty_cache()
         result["dd"] = dd_leg(torch, cq, dd_forms, args.dd_runs)
-        out = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
+        out = torch.empty(2 ** 30, dtype=torch.float64 if prec == "fp64" else torch.float32,
+                          device=dev)
         cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
     result["autotune"] = cq.cq_autotune_json()
     if not args.skip_attribution:

@@ -19,9 +19,9 @@ Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the HIP library and must never
 serve as a fallback for it.  numpy float64 throughout.
 
-Every function that has no independent pin says "parity unpinned" in its
-docstring; all functions here are pinned by tests/test_oracle_*.py and
-tests/test_cutfind.py, with one caveat: ``shots.philox4x32_10`` is pinned by
-its statistics only, so its identity with the published generator (its round
-constants) is parity unpinned.
+Every function that has no independent pin would say "parity unpinned" in
+its docstring; none does: all functions here are pinned by
+tests/test_oracle_*.py and tests/test_cutfind.py (``shots.philox4x32_10`` by
+the published Philox4x32-10 known-answer vectors, the list handling of
+``dd.run`` and ``dd.run_bfs`` by a case worked by hand from Algorithm 1).
 """

@@ -41,10 +41,8 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     high halves xor-ed with the other counter words and the key; the key
     advances by the Weyl constants between rounds.
 
-    Parity unpinned as to identity with the published generator: the tests
-    pin its output statistics and distinct streams, not known-answer
-    vectors, so a wrong round constant would go unnoticed (the sampling
-    built on it stays valid and bit-exact between oracle and device)."""
+    Pinned by the published known-answer vectors of Philox4x32-10
+    (tests/golden/philox4x32_10_kat.json)."""
     c0, c1, c2, c3 = (np.asarray(x, dtype=np.uint64) & M32 for x in (c0, c1, c2, c3))
     k0 = np.uint64(int(k0) & 0xFFFFFFFF)
     k1 = np.uint64(int(k1) & 0xFFFFFFFF)

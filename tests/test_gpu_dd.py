@@ -265,6 +265,45 @@ def test_parallel_lanes_graph_and_direct_agree_with_single_instances():
         assert recs == [d[0][0] for d in alone]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("case", ["int_2^21", "int_2^18x4", "dirichlet_2^21"])
+def test_fused_top_c_matches_stored_bins_many_tiles(case, prec):
+    """The fused top-C path across many tiles of the last GEMM: 2^18 to 2^21
+    bins per recursion (16 to 128 output tiles of 128 x 128), so the tile
+    bounds, the warm-up that raises the threshold and the pruned tile list
+    all act across tiles.  Integer entries (few distinct values, many ties
+    across tiles) make every bin exact, so the records must equal the stored
+    path's and the oracle's bit for bit; on Dirichlet entries fused and stored
+    must still agree exactly."""
+    m = cq()
+    rng = np.random.default_rng(6)
+    if case == "int_2^21":      # recursion 0 has 2^21 bins, three merged outputs each
+        bonds, ns, M, lo, hi = [1, 1], [10, 10, 10], [7, 7, 7], -2, 3
+    elif case == "int_2^18x4":  # four recursions of 2^18 bins, ties everywhere
+        bonds, ns, M, lo, hi = [1, 1], [12, 12, 12], [6, 6, 6], -1, 1
+    else:
+        bonds, ns, M, lo, hi = [2, 2], [10, 10, 10], [7, 7, 7], None, None
+    if lo is None:
+        cm, E = syn.chain_instance(83, bonds, ns)
+    else:
+        cm = syn.chain_cutmap(bonds, ns)
+        E = [syn.integer_entries(rng, k, n, lo=lo, hi=hi) for k, n in zip(syn.chain_ks(bonds, 3), ns)]
+    R = 4
+    st = dd.initial_states(cm, M)
+    inst = instance(cm, E, st, M)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    A = max_bins_log2(cm, st, M)
+    bins = [torch.full((2 ** A,), float("nan"), dtype=dt, device=DEV) for _ in range(R)]
+    print(f"fused vs stored {case} {prec}: 2^{A} bins", flush=True)
+    stored, done_s = m.cq_reconstruct_dd([inst], prec, R, bins=bins)
+    fused, done_f = m.cq_reconstruct_dd([inst], prec, R)
+    torch.cuda.synchronize()
+    assert done_s == done_f == [R]
+    assert stored == fused
+    if lo is not None:
+        compare(cm, E, st, M, R, prec, tol=0)
+
+
 # --- breadth-first query -------------------------------------------------------
 
 def _bfs_compare(cm, E, M, levels, width, prec, tol, exact):
@@ -316,3 +355,61 @@ def test_bfs_arguments_rejected_before_launch():
     for kw in (dict(levels=0, width=2), dict(levels=2, width=0), dict(levels=2, width=17)):
         with pytest.raises(m.CQError):
             m.cq_reconstruct_dd_bfs(inst, "fp64", **kw)
+
+
+# --- the hand-worked case of Algorithm 1 ---------------------------------------
+
+def _golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "dd_algorithm1.json")) as f:
+        g = json.load(f)
+    inst = g["instance"]
+    subs = [(s["width"], list(s["init_cut"]), list(s["meas_cut"])) for s in inst["subcircuits"]]
+    dev_inst = dict(subs=subs, entries=[to_dev(np.array(e, dtype=np.float64)) for e in inst["entries"]],
+                    active=inst["active"], merged=inst["merged"], fixed=inst["fixed"],
+                    fixed_vals=inst["fixed_vals"], max_active=inst["max_active"])
+    return g, dev_inst
+
+
+@pytest.mark.parametrize("launch", ["graph", "direct"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16_split", "fp16", "fp16_split"])
+def test_hand_worked_algorithm1(prec, launch):
+    """The device run reproduces the case worked by hand from Algorithm 1:
+    masks, bins, totals, L after every update (with the tie across
+    recursions resolved by the truncation) and the pops.  The entries are
+    small integers, exact in every precision."""
+    g, inst = _golden()
+    R = g["algorithm1"]["R"]
+    want = g["algorithm1"]["recursions"]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    bins = [torch.full((16,), float("nan"), dtype=dt, device=DEV) for _ in range(R)]
+    recs, done = cq().cq_reconstruct_dd([inst], prec, R, bins=bins, launch=launch)
+    torch.cuda.synchronize()
+    assert done == [len(want)]
+    for r, (w, rec) in enumerate(zip(want, recs[0])):
+        assert (rec["active"], rec["merged"], rec["fixed"], rec["fixed_vals"]) == \
+            (w["active"], w["merged"], w["fixed"], w["fixed_vals"]), r
+        assert rec["n_active"] == 2
+        assert bins[r][:4].cpu().double().tolist() == [float(x) for x in w["bins"]], r
+        assert rec["total"] == w["total"], r
+        assert [[v, rr, b] for (v, rr, b) in rec["list"]] == w["L"], r
+        assert rec["popped"]
+    # without bin buffers the fused top-C path must keep the same records
+    fused, done_f = cq().cq_reconstruct_dd([inst], prec, R, launch=launch)
+    assert done_f == done and fused == recs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_split"])
+def test_hand_worked_bfs(prec):
+    g, inst = _golden()
+    want = g["bfs"]["nodes"]
+    got = cq().cq_reconstruct_dd_bfs(inst, prec, g["bfs"]["levels"], g["bfs"]["width"])
+    torch.cuda.synchronize()
+    assert len(got) == len(want)
+    for k, (w, nd) in enumerate(zip(want, got)):
+        assert (nd["level"], nd["parent"], nd["parent_bin"]) == (w["level"], w["parent"], w["parent_bin"]), k
+        assert (nd["active"], nd["merged"], nd["fixed"], nd["fixed_vals"]) == \
+            (w["active"], w["merged"], w["fixed"], w["fixed_vals"]), k
+        assert nd["total"] == w["total"], k
+        assert [[v, b] for (v, _, b) in nd["list"]] == w["candidates"], k

@@ -13,7 +13,12 @@ any size:
 * a recursion's FP64 total equals the value of the bin it zoomed into (its
   bins partition that bin), and recursion 0's total equals the closed form
   2^-K sum_l prod_c rowsum_c(l) for the smallest instance;
-* with stored bins, a grid of 16^4 bins per recursion against the oracle.
+* with stored bins, a grid of 16^4 bins per recursion against the oracle,
+  and the recursion's candidates and appended bins against the stored bins:
+  the candidates are the C largest stored bins (value, then index), the
+  appended bins the R largest of those by the oracle's value, and the gap
+  between the R-th and the C-th stored value exceeds the error bound, so no
+  bin outside the stored top C can belong to the true top R.
 """
 import numpy as np
 import pytest
@@ -31,7 +36,19 @@ N_INST = 16
 N_OUT = 20
 M_ACT = 8
 R = 4
-FP32_FLOOR = 1e-32
+
+
+def fp32_floor(n_sub, K):
+    """Absolute error an FP32 contraction can add below FP32's normal range,
+    for operands of magnitude at most 1 (every entry here, merged or not, is
+    bounded by its identity row, a Dirichlet draw).  Each elementary step
+    (the conversion of an operand, a product, an addition) that flushes or
+    rounds a result below 2^-126 adds at most 2^-126; the output is a sum of
+    4^K label terms of n_sub factors each, and an error injected at a step
+    reaches the output multiplied by at most the number of label terms that
+    use it (every other factor is at most 1 in magnitude, 2^-K at most 1), so
+    the sum over the at most (3 n_sub + 1) steps per term bounds it."""
+    return (3 * n_sub + 1) * 4.0 ** K * 2.0 ** -126
 
 
 def cq():
@@ -114,8 +131,8 @@ def split_bin(b, states):
     return parts
 
 
-def test_batch_full_size_lists_zoom_and_totals():
-    m = cq()
+@pytest.fixture(scope="module")
+def full_batch():
     bonds_all = batch()
     insts, meta = [], []
     for i, bonds in enumerate(bonds_all):
@@ -124,12 +141,21 @@ def test_batch_full_size_lists_zoom_and_totals():
         meta.append((bonds, ks, cm))
     torch.cuda.synchronize()
     print(f"dd batch of {N_INST} instances built", flush=True)
-    recs, done = m.cq_reconstruct_dd(insts, "fp32", R)
-    print(f"dd batch done: {done}", flush=True)
+    return insts, meta
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "fp64"])
+def test_batch_full_size_lists_zoom_and_totals(prec, full_batch):
+    m = cq()
+    insts, meta = full_batch
+    recs, done = m.cq_reconstruct_dd(insts, prec, R)
+    print(f"dd batch {prec} done: {done}", flush=True)
+    # with 20 outputs and 8 activated per zoom, L never runs empty before R
+    assert done == [R] * N_INST
     M = [M_ACT] * 4
     for i, (bonds, ks, cm) in enumerate(meta):
         rr = recs[i]
-        assert done[i] == len(rr) >= 1
+        assert len(rr) == R
         # zoom chain and totals
         st0 = dd.initial_states(cm, M)
         assert [s.active for s in states_of(rr[0])] == [s.active for s in st0]
@@ -162,6 +188,61 @@ def test_batch_full_size_lists_zoom_and_totals():
     rs = [syn.dirichlet_entries(SEED + i, c, ks[c], N_OUT).sum(axis=1) for c in range(4)]
     tot = float(fd_contract(cm, [r[:, None] for r in rs])[0])
     assert abs(recs[i][0]["total"] - tot) <= 1e-12 * abs(tot) + 1e-15, (recs[i][0]["total"], tot)
+
+
+def stored_top(b, k, chunk=1 << 28):
+    """The k largest stored bins, value descending then index ascending
+    (torch.topk per chunk, then an exact host sort of the survivors)."""
+    vals, idxs = [], []
+    for off in range(0, b.numel(), chunk):
+        part = b[off: off + chunk]
+        kk = min(k + 8, part.numel())
+        v, i = torch.topk(part, kk)
+        vals.append(v.double().cpu().numpy())
+        idxs.append(i.cpu().numpy().astype(np.int64) + off)
+    v, i = np.concatenate(vals), np.concatenate(idxs)
+    order = sorted(range(len(v)), key=lambda j: (-v[j], i[j]))[:k]
+    return v[order], i[order]
+
+
+def check_top_r_against_stored(b, rec, r, Rcap, states, bonds, ks, seed, rel, floor):
+    """Recursion r (every bin still has merged outputs) keeps the C = 4R
+    largest bins in working precision as candidates, re-evaluates them in
+    FP64 and appends the R largest; the entries of L that came from r are a
+    prefix of those.  The candidates are checked exactly against the stored
+    bins, the appended ones against the oracle's values of the candidates,
+    and the gap between the R-th and the C-th stored value against the
+    rounding bound, which shows that the true R largest of all bins are among
+    the candidates."""
+    C = min(4 * Rcap, 64)
+    sv, si = stored_top(b, C)
+    parts = [split_bin(int(x), states) for x in si]
+    samples = [sorted(set(p[c] for p in parts)) for c in range(4)]
+    assert all(len(x) <= 16 for x in samples)
+    cm_loc, red = local_problem(seed, bonds, ks, states, samples)
+    ref = grid_values(cm_loc, red).reshape(16, 16, 16, 16)
+    scl = grid_values(cm_loc, red, absolute=True).reshape(16, 16, 16, 16)
+    pos = [tuple(samples[c].index(p[c]) for c in range(4)) for p in parts]
+    true = np.array([ref[q] for q in pos])
+    bound = np.array([rel * scl[q] + floor for q in pos])
+    # the stored candidates are correct to the rounding bound
+    assert np.all(np.abs(sv - true) <= bound), (r, np.max(np.abs(sv - true) / bound))
+    # the R largest candidates by the oracle's value (desc, then bin asc)
+    best = sorted(range(C), key=lambda j: (-true[j], si[j]))[:Rcap]
+    mine = [(v, b_) for (v, rr_, b_) in rec["list"] if rr_ == r]
+    assert 1 <= len(mine) <= Rcap
+    for j, (v, b_) in enumerate(mine):
+        k = best[j]
+        assert abs(v - true[k]) <= 1e-10, (r, j, v, true[k])
+        gap_lo = j == 0 or abs(true[best[j - 1]] - true[k]) > 2e-10
+        gap_hi = j + 1 >= len(best) or abs(true[best[j + 1]] - true[k]) > 2e-10
+        if gap_lo and gap_hi:
+            assert b_ == int(si[k]), (r, j, b_, int(si[k]))
+    # no bin outside the candidates can reach the R-th largest true value
+    margin = sv[Rcap - 1] - sv[C - 1]
+    print(f"recursion {r}: stored top {C} from {sv[0]:.4e} to {sv[C - 1]:.4e}; "
+          f"R-th minus C-th {margin:.3e} against a bound of {2 * bound.max():.3e}", flush=True)
+    assert margin > 2 * bound.max()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -205,12 +286,16 @@ def test_largest_instance_stored_bins_grid(prec):
         err = np.abs(got - ref)
         print(f"recursion {r}: max abs err {err.max():.3e}, max |bin| {np.abs(ref).max():.3e}, "
               f"max err/scale {np.max(err / np.maximum(scale, 1e-300)):.3e}", flush=True)
+        K = sum(bonds)
+        floor = 1e-300 if prec == "fp64" else fp32_floor(4, K)
+        rel = 1e-13 if prec == "fp64" else 1e-5
         if prec == "fp64":
             assert err.max() < 1e-10
-            assert np.all(err <= 1e-13 * scale + 1e-300)
         else:
             assert err.max() < 1e-6
-            assert np.all(err <= 1e-5 * scale + FP32_FLOOR)
+        assert np.all(err <= rel * scale + floor)
+        check_top_r_against_stored(bins[r][: 2 ** sum(na)], rr[r], r, R2, states, bonds, ks,
+                                   SEED + i, rel, floor)
         # the recursion total against the sum of the bins (FP64 from the GPU's own bins)
         s = float(torch.sum(bins[r][: 2 ** sum(na)], dtype=torch.float64).item())
         assert abs(s - rr[r]["total"]) <= (1e-9 if prec == "fp64" else 1e-5)

@@ -206,9 +206,14 @@ def test_found_cuts_reconstruct_on_device():
         ops += [wc.Op("cz", (i, i + 1)) for i in range(t % 2, n - 1, 2)]
     ops += [wc.Op("u", (q,), wc.haar_u2(rng)) for q in range(n)]
     found = m.cq_find_cuts(n, ops, max_width=5, max_subcircuits=3)
+    # subcircuits are numbered 0.. in order of first use, with none skipped
+    assert sorted(set(found["cluster"])) == list(range(found["n_subcircuits"]))
     cc = wc.cut_circuit_from_clusters(n, ops, found["cluster"])
     subs = cc.subcircuits()
     assert found["n_cuts"] >= 1 and max(s.width for s in subs) <= 5
+    # the search cuts one wire twice here, so some slot is initialised by one
+    # cut and measured for another: attribution's mixed-slot case runs
+    assert any(i >= 0 and mc >= 0 for s in subs for i, mc in zip(s.init_cut, s.meas_cut))
     E = [m.cq_attribute(s, m.cq_variant_probabilities(s)) for s in subs]
     p = m.cq_reconstruct_fd(subs, E, prec="fp64", out_perm=cc.out_perm()).cpu().numpy()
     assert np.max(np.abs(p - sv.probabilities(n, ops))) < 1e-12

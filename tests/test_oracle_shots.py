@@ -2,6 +2,9 @@
 arithmetic against Python's exact integers, the generator's uniformity,
 sampling against exact special cases and a goodness-of-fit bound, and the
 loss against closed forms and its bounds."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -28,6 +31,19 @@ def test_quantise_is_exact_floor():
     for pi, qi in zip(p, q):
         c = min(max(Fraction(pi), 0), 1)
         assert int(qi) == (c * 2 ** 52).numerator // (c * 2 ** 52).denominator
+
+
+def test_philox_known_answer_vectors():
+    """The generator is Philox4x32-10 itself: the published known-answer
+    vectors (tests/golden/philox4x32_10_kat.json) come out word for word."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")) as f:
+        kat = json.load(f)["vectors"]
+    assert len(kat) == 3
+    for v in kat:
+        c = [int(x, 16) for x in v["counter"]]
+        k = [int(x, 16) for x in v["key"]]
+        got = shots.philox4x32_10(*c, *k)
+        assert ["%08x" % int(w) for w in got] == v["out"]
 
 
 def test_generator_uniform_and_distinct():
