@@ -153,6 +153,31 @@ cq_status cq_reconstruct_fd(int32_t n_sub, const cq_subcircuit* subs,
                             size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Full definition without allocation, for callers that cannot allocate device
+ * memory: code under stream (graph) capture, tight serving loops, harnesses
+ * that forbid allocation.
+ *
+ * Same arguments, kernels and results as cq_reconstruct_fd, minus the
+ * workspace: the library keeps a fixed scratch array of
+ * CQ_FD_NOALLOC_SCRATCH_BYTES in device memory on every GPU it runs this on
+ * (held until the process ends; its device address is looked up on the first
+ * call on each device).  A reconstruction whose workspace
+ * (cq_fd_workspace_size) exceeds it is rejected with CQ_ERR_WORKSPACE before
+ * any launch.  64 MiB covers the 20-qubit two-subcircuit workload (K = 4) in
+ * every precision and chains of three 8-output subcircuits with K <= 6.
+ * The call allocates nothing, creates no events and synchronises nothing (the
+ * GEMM autotuner is not consulted beyond shapes it has already tuned; others
+ * take the default kernel, which gives the same bits).  All calls on one GPU
+ * share its scratch array, which keeps the last call's contents: calls that
+ * overlap on one GPU (different streams, threads or graphs in flight) race.
+ * ------------------------------------------------------------------------- */
+#define CQ_FD_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+cq_status cq_reconstruct_fd_noalloc(int32_t n_sub, const cq_subcircuit* subs,
+                                    const double* const* entries, cq_precision prec,
+                                    const int32_t* out_perm, void* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Dynamic-definition reconstruction (Algorithm 1, Section 4.3).
  *
  * Masks are per subcircuit; bit i stands for output i of the subcircuit,

@@ -15,12 +15,13 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_split": 3, "fp16": 4, "fp16_
 
 MAX_SUBCIRCUITS = 8
 MAX_DD_R = 16
+FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
             "cq_autotune_json",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
-            "cq_reconstruct_fd", "cq_dd_workspace_size", "cq_reconstruct_dd",
+            "cq_reconstruct_fd", "cq_reconstruct_fd_noalloc", "cq_dd_workspace_size", "cq_reconstruct_dd",
             "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs",
             "cq_sample_shots_workspace_size", "cq_sample_shots", "cq_chi2_workspace_size", "cq_chi2",
             "cq_simulate_workspace_size", "cq_simulate_probabilities", "cq_variants_workspace_size",
@@ -108,6 +109,9 @@ def lib():
     L.cq_reconstruct_fd.restype = st
     L.cq_reconstruct_fd.argtypes = [C.c_int32, C.POINTER(cq_subcircuit), C.POINTER(C.c_void_p),
                                     C.c_int, C.POINTER(C.c_int32), p, p, C.c_size_t, p]
+    L.cq_reconstruct_fd_noalloc.restype = st
+    L.cq_reconstruct_fd_noalloc.argtypes = [C.c_int32, C.POINTER(cq_subcircuit), C.POINTER(C.c_void_p),
+                                            C.c_int, C.POINTER(C.c_int32), p, p]
     L.cq_dd_workspace_size.restype = st
     L.cq_dd_workspace_size.argtypes = [C.c_int32, C.POINTER(cq_dd_instance),
                                        C.POINTER(cq_dd_params), C.c_int32, C.POINTER(C.c_size_t)]

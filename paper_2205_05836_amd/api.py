@@ -142,6 +142,24 @@ def cq_reconstruct_fd(subs, entries, prec="fp64", out_perm=None, out=None, works
     return out
 
 
+def cq_reconstruct_fd_noalloc(subs, entries, out, prec="fp64", out_perm=None, stream=None):
+    """cq_reconstruct_fd on the library's fixed scratch (no workspace, no
+    allocation inside the call).  ``out``: preallocated device tensor of 2^n
+    values, float64 for prec='fp64' else float32."""
+    import torch
+    s = _Subs(subs)
+    n = sum(s.n_out)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if out.dtype != dtype or out.numel() != 2 ** n:
+        raise ValueError("output tensor has the wrong dtype or size")
+    perm = _perm_arr(out_perm)
+    ptrs = (C.c_void_p * len(entries))(*[_dev_ptr(e, torch.float64).value for e in entries])
+    check(lib().cq_reconstruct_fd_noalloc(len(subs), s.ptr(), ptrs, _lib.PRECISION[prec],
+                                          C.cast(perm, C.POINTER(C.c_int32)) if perm else None,
+                                          _dev_ptr(out), _stream(stream)))
+    return out
+
+
 def _mask(positions):
     m = 0
     for p in positions:

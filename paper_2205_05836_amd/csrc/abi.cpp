@@ -38,12 +38,16 @@ std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof;
 
 // Brackets one launch with events when profiling is on.
+// Calls that may not create events (the no-allocation entry point) set
+// this for their duration on the calling thread.
+thread_local bool t_quiet = false;
+
 struct ProfScope {
   bool on = false;
   ProfRecord rec;
   hipStream_t stream;
   ProfScope(const char* name, double flops, hipStream_t s) : stream(s) {
-    if (!g_prof_on.load()) return;
+    if (t_quiet || !g_prof_on.load()) return;
     rec.name = name;
     rec.flops = flops;
     if (hipEventCreate(&rec.start) != hipSuccess) return;
@@ -184,6 +188,7 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
       L.ldc = g.ldc;
       L.alpha = g.alpha;
       L.nontemporal = plan.tensors[g.c].loc == Loc::Out;
+      L.no_tune = t_quiet;
       if (rowexp && plan.tensors[g.c].loc == Loc::Out) {
         L.rowexp = rowexp;
         L.colexp = colexp;
@@ -318,6 +323,13 @@ extern "C" cq_status cq_reconstruct_fd(int32_t n_sub, const cq_subcircuit* subs,
                                        const double* const* entries, cq_precision prec,
                                        const int32_t* out_perm, void* out, void* workspace,
                                        size_t workspace_bytes, hipStream_t stream) {
+  return cq::fd_run(n_sub, subs, entries, prec, out_perm, out, workspace, workspace_bytes, false,
+                    stream);
+}
+
+cq_status cq::fd_run(int32_t n_sub, const cq_subcircuit* subs, const double* const* entries,
+                     cq_precision prec, const int32_t* out_perm, void* out, void* workspace,
+                     size_t workspace_bytes, bool quiet, hipStream_t stream) {
   CutMap cm;
   Plan plan;
   cq_status st = fd_prepare(n_sub, subs, prec, out_perm, cm, plan);
@@ -329,7 +341,10 @@ extern "C" cq_status cq_reconstruct_fd(int32_t n_sub, const cq_subcircuit* subs,
   if (plan.workspace_bytes > 0 && (!workspace || workspace_bytes < (size_t)plan.workspace_bytes))
     return fail(CQ_ERR_WORKSPACE, "workspace too small");
   if (fault_injected("fd")) return fail(CQ_ERR_HIP, "injected fault before launch");
-  return execute(plan, prec, entries, out, out_dtype(prec), static_cast<char*>(workspace), stream);
+  t_quiet = quiet;
+  st = execute(plan, prec, entries, out, out_dtype(prec), static_cast<char*>(workspace), stream);
+  t_quiet = false;
+  return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -1511,6 +1511,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return launch_variant(prec, a, g.tc, nt, it->second.variant, stream);
   }
+  if (g.no_tune) return launch_variant(prec, a, g.tc, nt, 0, stream);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
     return launch_variant(prec, a, g.tc, nt, 0, stream);

@@ -41,6 +41,12 @@ struct CutMap {
   std::vector<int> up, down;  // per cut: measuring / initialising subcircuit
 };
 
+// Full definition (cq_reconstruct_fd) on a given workspace.  quiet: create
+// no events (no per-launch timing) and time no GEMM variant.
+cq_status fd_run(int32_t n_sub, const cq_subcircuit* subs, const double* const* entries,
+                 cq_precision prec, const int32_t* out_perm, void* out, void* workspace,
+                 size_t workspace_bytes, bool quiet, hipStream_t stream);
+
 // Validates and derives.  Returns CQ_OK or an error (message set).
 cq_status build_cutmap(int32_t n_sub, const cq_subcircuit* subs, CutMap& cm);
 cq_status build_subinfo(const cq_subcircuit* sub, SubInfo& si);

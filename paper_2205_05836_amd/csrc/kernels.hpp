@@ -39,6 +39,9 @@ struct GemmLaunch {
   // forms with column-scaled operands)
   const int32_t* rowexp = nullptr;
   const int32_t* colexp = nullptr;
+  // time nothing: a shape tuned before keeps its variant, others take
+  // variant 0 (no events, no synchronisation)
+  bool no_tune = false;
 };
 
 // C[z][m][n] = alpha * sum_k A[z*sAz + k*sAk + m] * B[z*sBz + k*sBk + n]

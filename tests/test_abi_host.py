@@ -15,6 +15,7 @@ from oracle import cutmap
 from oracle import reconstruct as rc
 from workloads import circuits as wc
 from workloads import synthetic as syn
+from paper_2205_05836_amd._lib import FD_NOALLOC_SCRATCH_BYTES
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -105,6 +106,23 @@ def test_fd_rejects_before_launch_without_gpu():
     assert L.cq_fd_workspace_size(3, s3.ptr(), 1, None, C.byref(b)) == 0 and b.value > 0
     fake3 = (C.c_void_p * 3)(0x1000, 0x2000, 0x3000)
     assert L.cq_reconstruct_fd(3, s3.ptr(), fake3, 1, None, C.c_void_p(0x4000), None, 0, None) == -5
+
+
+def test_noalloc_rejects_before_launch_without_gpu():
+    """The no-allocation entry point reports a workspace beyond its fixed
+    scratch, and a bad cut map, before anything touches a device."""
+    from paper_2205_05836_amd.api import _Subs
+    L = lib()
+    cm = syn.chain_cutmap([4, 4], [10, 10, 10])
+    s = _Subs(cm)
+    b = C.c_size_t()
+    assert L.cq_fd_workspace_size(3, s.ptr(), 1, None, C.byref(b)) == 0
+    assert b.value > FD_NOALLOC_SCRATCH_BYTES
+    fake = (C.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+    assert L.cq_reconstruct_fd_noalloc(3, s.ptr(), fake, 1, None, C.c_void_p(0x4000), None) == -5
+    assert b"scratch" in L.cq_last_error()
+    bad = _Subs([(2, [-1, -1], [0, -1]), (2, [-1, -1], [-1, -1])])
+    assert L.cq_reconstruct_fd_noalloc(2, bad.ptr(), fake, 1, None, C.c_void_p(0x4000), None) == -3
 
 
 def test_fault_injection_stops_before_launch(monkeypatch):
