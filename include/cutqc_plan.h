@@ -57,11 +57,13 @@ cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap, i
  * (nothing is timed).  Variant v: bit 0 flips the tile raster order (M- or
  * N-fastest); v >> 1 picks, for the 16-bit forms, the asynchronous
  * LDS-staged kernel with its default ring depth (0), with the other depth
- * (1), the register-path kernel (2) or the persistent kernel (3); for FP32
- * the tiled kernel (0) or the persistent kernel (3).  FP64 has variants 0
- * and 1; FP32 0, 1, 6 and 7 (6 and 7 where rows are 16-byte aligned);
- * 16-bit forms 0..7 (2..7 only where the asynchronous kernel's alignment
- * holds).  Every variant computes the same sums.
+ * (1), the register-path kernel (2), the persistent kernel (3) or the
+ * occupancy kernel with four (4) or three (5) resident workgroups per compute
+ * unit; for FP32 the tiled kernel (0) or the persistent kernel (3).  FP64 has
+ * variants 0 and 1; FP32 0, 1, 6 and 7 (6 and 7 where rows are 16-byte
+ * aligned); 16-bit forms 0..11 (2..11 only where the asynchronous kernel's
+ * alignment holds, 6..11 only without output exponents).  Every variant
+ * computes the same sums.
  *
  * mode: 0 = variant 0 always (cached choices ignored); 1 = tune (the
  * default, also set by the environment variable CQ_AUTOTUNE unless it starts

@@ -924,6 +924,202 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit path, occupancy form: one 128 x 128 tile per workgroup like
+// gemm_h16a_kernel, but sized for three or four resident workgroups per CU
+// (WPE waves per SIMD).  Stages hold 16 labels (16 KB for split operands) in
+// an NS-deep ring; the epilogue goes through the ring in 8-row slabs per wave,
+// so the kernel needs NS x 16 KB of LDS in all.  Each k-step loads a wave's
+// B fragments once and its A fragments one 32-row block at a time, which
+// keeps the live registers within the occupancy budget.  The operand DMA,
+// transposed fragment reads and product order are those of gemm_h16a_kernel,
+// so the sums are the same bit for bit.  Operand stages are the latency the
+// kernel hides: with more workgroups resident, one workgroup's wait for its
+// next stage overlaps another's products and stores.
+// ---------------------------------------------------------------------------
+template <int SPLIT, bool F16, int OUT, int NS, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+gemm_h16t_kernel(GemmArgs g) {
+  using H = Half<F16>;
+  using V8 = typename H::V8;
+  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int NP = SPLIT == 3 ? 2 : 1;
+  constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
+  constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
+  constexpr int LPW = 2 * NP;           // DMA instructions per wave per stage
+  constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
+  constexpr int EPI = 4 * 8 * EROW;
+  constexpr int SMEM = NS * STAGE > EPI ? NS * STAGE : EPI;
+  static_assert(NS >= 2 && NS <= 4, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+  // wave w's instruction for (operand, plane) fills rows 4w .. 4w + 3
+  const uint16_t* gbase[2][NP];
+  int64_t ccap[2];
+  {
+    const int64_t za = tc.z * g.sAz, zb = tc.z * g.sBz;
+    gbase[0][0] = static_cast<const uint16_t*>(g.A) + za + m0;
+    gbase[1][0] = static_cast<const uint16_t*>(g.B) + zb + n0;
+    if constexpr (NP == 2) {
+      gbase[0][NP - 1] = static_cast<const uint16_t*>(g.A_lo) + za + m0;
+      gbase[1][NP - 1] = static_cast<const uint16_t*>(g.B_lo) + zb + n0;
+    }
+    ccap[0] = ((g.M - 8) & ~(int64_t)7) - m0;
+    ccap[1] = ((g.N - 8) & ~(int64_t)7) - n0;
+  }
+  const int pc = wave * 64 + lane;  // 16-byte chunk of the stage plane this lane fills
+  const int lrow = pc >> 4;
+  int64_t lcol[2];
+#pragma unroll
+  for (int op = 0; op < 2; ++op) {
+    lcol[op] = (int64_t)swz(lrow, pc & 15) * 8;
+    if (lcol[op] > ccap[op]) lcol[op] = ccap[op];
+  }
+  auto issue = [&](int s) {
+    int64_t k = (int64_t)s * BK + lrow;
+    if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const uint16_t* src = gbase[op][p] + k * (op ? g.sBk : g.sAk) + lcol[op];
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(lsm + (s % NS) * STAGE + (op * NP + p) * TILE + wave * 1024));
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                     : "memory", "m0");
+      }
+  };
+  f16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  const int grp = lane >> 4, r16 = lane & 15;
+  const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
+  const int krow = 8 * (grp >> 1) + (r16 >> 2);
+  auto frag = [&](int tile, int c0, int64_t kvalid) -> V8 {
+    const int col = c0 + col_in_blk;
+    const int r0 = krow, r1 = r0 + 4;
+    const int o0 = tile + r0 * 256 + (swz(r0, col >> 3) << 4) + (col & 7) * 2;
+    const int o1 = tile + r1 * 256 + (swz(r1, col >> 3) << 4) + (col & 7) * 2;
+    s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
+    s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
+    if (kvalid < BK) {
+      // slot e of the two reads holds label 8*(grp>>1) + e (+4)
+      const int kb = 8 * (grp >> 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kvalid) lo[e] = 0;
+        if (kb + 4 + e >= kvalid) hi[e] = 0;
+      }
+    }
+    typedef short s8_t __attribute__((ext_vector_type(8)));
+    const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(V8, v);
+  };
+
+  for (int s = 0; s < NS - 1 && s < nstages; ++s) issue(s);
+  for (int s = 0; s < nstages; ++s) {
+    // this wave's loads of stage s have landed once at most `ahead` later
+    // stages are outstanding; the barrier then covers every wave's loads
+    const int ahead = (nstages - 1 - s) < (NS - 2) ? (nstages - 1 - s) : (NS - 2);
+    if (ahead >= 2) wait_vm<2 * LPW>();
+    else if (ahead == 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (s + NS - 1 < nstages) issue(s + NS - 1);
+    const int sb = (s % NS) * STAGE;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+    V8 b[NP][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[p][j] = frag(sb + (1 * NP + p) * TILE, wn + 32 * j, kvalid);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      V8 a[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) a[p] = frag(sb + (0 * NP + p) * TILE, wm + 32 * i, kvalid);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = H::mfma(a[0], b[0][j], acc[i][j]);
+        if constexpr (SPLIT == 3) {
+          acc[i][j] = H::mfma(a[0], b[NP - 1][j], acc[i][j]);
+          acc[i][j] = H::mfma(a[NP - 1], b[0][j], acc[i][j]);
+        }
+      }
+      // keep the second block's fragment reads after the first block's products
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // epilogue: slab u of a wave holds rows 32*(u>>2) + 8*(u&3) .. +7 of its
+  // 64 x 64 block; it is staged in the ring so that every store instruction
+  // writes whole row segments
+  const float alpha = float(g.alpha);
+  __syncthreads();  // every wave is done with the ring
+  char* const wbuf = smem + wave * 8 * EROW;
+  const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u >> 2, vg = u & 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 4 * (lane >> 5) + e;
+        const int c = 32 * j + (lane & 31);
+        *reinterpret_cast<float*>(wbuf + r * EROW + c * 4) = alpha * acc[i][j][4 * vg + e];
+      }
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rl = 4 * h + (lane >> 4);
+      const int c = 4 * (lane & 15);
+      const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + c * 4);
+      const int64_t m = m0 + wm + 32 * i + 8 * vg + rl, n = n0 + wn + c;
+      const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+      if constexpr (OUT == 2) {
+        typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+        u16x4 hh, ll;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hh[e] = to_h16<F16>(x[e]);
+          ll[e] = to_h16<F16>(x[e] - from_h16<F16>(hh[e]));
+        }
+        uint16_t* const ch = static_cast<uint16_t*>(g.C);
+        uint16_t* const cl = static_cast<uint16_t*>(g.C_lo);
+        if (full || (m < g.M && n + 3 < g.N)) {
+          *reinterpret_cast<u16x4*>(ch + idx) = hh;
+          if (cl) *reinterpret_cast<u16x4*>(cl + idx) = ll;
+        } else if (m < g.M) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (n + e < g.N) {
+              ch[idx + e] = hh[e];
+              if (cl) cl[idx + e] = ll[e];
+            }
+        }
+      } else if (full || (m < g.M && n + 3 < g.N)) {
+        store_out<f4_t, OUT == 1>(reinterpret_cast<f4_t*>(static_cast<float*>(g.C) + idx), x);
+      } else if (m < g.M) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < g.N) store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx + e, x[e]);
+      }
+    }
+    // the slab's LDS reads are done before the next slab overwrites it
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent form (no output exponents), for 16-bit and FP32 operands, with
 // FP32 output or -- 16-bit operands -- 16-bit hi (and lo) output planes.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
 // workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
@@ -1288,7 +1484,8 @@ bool h16_async_ok(const GemmArgs& a, DType tc) {
 
 // Variant `impl` of the 16-bit launch: 0 = asynchronous kernel with its
 // default ring depth, 1 = the other depth, 2 = register-path kernel,
-// 3 = persistent kernel.
+// 3 = persistent kernel, 4 and 5 = occupancy kernel (four workgroups per CU
+// with a two-deep ring, three with a three-deep one).
 // Persistent grid: two workgroups per compute unit, a multiple of 8 so that
 // workgroup b stays on XCD b % 8 for every tile it takes.
 int64_t persistent_grid(int64_t tiles) {
@@ -1319,11 +1516,24 @@ bool f32p_ok(const GemmArgs& a) {
          a.sCz % 4 == 0 && al(a.A) && al(a.B) && al(a.C);
 }
 
+template <int SPLIT, bool F16, int NS, int WPE>
+hipError_t launch_h16t(const GemmArgs& a, DType tc, bool nt, hipStream_t s) {
+  const dim3 grid((unsigned)a.tiles), block(256);
+  if (tc != DType::F32) hipLaunchKernelGGL((gemm_h16t_kernel<SPLIT, F16, 2, NS, WPE>), grid, block, 0, s, a);
+  else if (nt) hipLaunchKernelGGL((gemm_h16t_kernel<SPLIT, F16, 1, NS, WPE>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_h16t_kernel<SPLIT, F16, 0, NS, WPE>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
 template <int SPLIT, bool F16>
 hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int impl = 0) {
   constexpr int NS = SPLIT == 3 ? 2 : 3;
   constexpr int NS2 = SPLIT == 3 ? 3 : 2;
   constexpr int NSP = SPLIT == 3 ? 2 : 4;
+  // occupancy form: four workgroups per CU with a two-deep ring, or three
+  // with a three-deep one
+  if (impl == 4 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 2, 4>(a, tc, nt, s);
+  if (impl == 5 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 3, 3>(a, tc, nt, s);
   if (impl == 3 && h16p_ok(a, tc)) {
     const int64_t grid = persistent_grid(a.tiles);
     using P = PersistH16<SPLIT, F16>;
@@ -1399,9 +1609,11 @@ struct TuneKey {
   }
 };
 
+constexpr int kMaxVariants = 12;
+
 struct TuneEntry {
   int variant;
-  float ms[8];
+  float ms[kMaxVariants];
   int tried;
 };
 
@@ -1421,7 +1633,7 @@ int tune_mode() {
 }
 
 int variant_count(cq_precision prec) {
-  return prec == CQ_FP64 ? 2 : 8;
+  return prec == CQ_FP64 ? 2 : prec == CQ_FP32 ? 8 : kMaxVariants;
 }
 
 // whether variant v has a kernel of its own for this launch (else it would
@@ -1431,7 +1643,7 @@ bool variant_applies(cq_precision prec, const GemmArgs& a, DType tc, int v) {
   if (impl == 0) return true;
   if (v >= variant_count(prec)) return false;
   if (prec == CQ_FP32) return impl == 3 && f32p_ok(a);
-  return impl == 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
+  return impl >= 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
 }
 
 }  // namespace
@@ -1515,7 +1727,7 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
     return launch_variant(prec, a, g.tc, nt, 0, stream);
-  TuneEntry te{0, {0, 0, 0, 0, 0, 0, 0, 0}, 0};
+  TuneEntry te{0, {}, 0};
   hipEvent_t ev[3];
   for (int i = 0; i < 3; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return launch_variant(prec, a, g.tc, nt, 0, stream);
@@ -1568,7 +1780,7 @@ std::string autotune_json() {
                           (long long)k.K, (long long)k.Z, e.variant);
     s.append(buf, n);
     bool f2 = true;
-    for (int v = 0; v < 8; ++v)
+    for (int v = 0; v < kMaxVariants; ++v)
       if ((e.tried >> v) & 1) {
         n = std::snprintf(buf, sizeof(buf), "%s[%d, %.4f]", f2 ? "" : ", ", v, e.ms[v]);
         s.append(buf, n);

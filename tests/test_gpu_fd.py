@@ -169,8 +169,8 @@ def test_deterministic_repeat():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 8), ("bf16_split", 8),
-                                            ("fp16", 8)])
+@pytest.mark.parametrize("prec,variants", [("fp64", 2), ("fp32", 8), ("bf16_split", 12),
+                                            ("fp16", 12), ("bf16", 12)])
 def test_every_gemm_variant_matches_oracle(prec, variants):
     """Each autotuner variant forced in turn; 2^24 outputs give every GEMM
     hundreds of tiles, so all variants apply.  Raster order changes no sum,
@@ -210,15 +210,16 @@ RAGGED = [(22, [4, 4], [10, 4, 10]), (23, [3, 3], [10, 3, 10]), (24, [5, 2], [10
 @pytest.mark.parametrize("seed,bonds,ns", RAGGED)
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_split"])
 def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
-    """Variants 6 and 7 (persistent kernel, both rasters) against variant 0
-    bit for bit -- same products, same order -- and against the oracle."""
+    """Variants 6 and 7 (persistent kernel, both rasters) and 8 and 10 (the
+    occupancy kernel, two- and three-deep rings) against variant 0 bit for
+    bit -- same products, same order -- and against the oracle."""
     m = cq()
     cm, E = syn.chain_instance(seed, bonds, ns)
     ref = rc.fd_contract(cm, E)
     scale = rc.fd_contract(cm, [np.abs(e) for e in E])
     outs = {}
     try:
-        for v in (0, 6, 7):
+        for v in (0, 6, 7, 8, 10):
             m.cq_autotune_enable(variant=v)
             print(f"{prec} {bonds} {ns} variant {v}", flush=True)
             outs[v] = gpu_fd(cm, E, prec)
@@ -226,8 +227,8 @@ def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
         m.cq_autotune_enable(True)
     err = np.abs(outs[0] - ref)
     assert np.all(err <= {"fp32": 1e-5, **H16_REL}[prec] * scale + fp32_floor(cm)), float(err.max())
-    assert np.array_equal(outs[6], outs[0])
-    assert np.array_equal(outs[7], outs[0])
+    for v in (6, 7, 8, 10):
+        assert np.array_equal(outs[v], outs[0]), v
 
 
 def test_workspace_too_small_writes_nothing():
@@ -375,7 +376,7 @@ def test_30_qubit_chain_variants_bit_equal(prec):
     ents = _entries_30q()
     ref = None
     try:
-        for v in (0, 1, 6, 7):
+        for v in (0, 1, 6, 7, 8, 9, 10, 11):
             m.cq_autotune_enable(variant=v)
             print(f"30q {prec} variant {v}", flush=True)
             out = m.cq_reconstruct_fd(cm, ents, prec=prec)
