@@ -46,10 +46,15 @@
  *  - All arguments are validated before any launch; on error nothing is
  *    written and a status < 0 is returned (cq_last_error() has the detail).
  *    Nothing throws across the ABI and nothing aborts.
- *  - cq_attribute and cq_reconstruct_fd are asynchronous on `stream`.
- *    cq_reconstruct_dd synchronises `stream` between recursions and returns
- *    after the last one.  Calls are thread-safe; calls that share a workspace
- *    must not overlap.
+ *  - cq_attribute and cq_reconstruct_fd are asynchronous on `stream`, with
+ *    one exception: the first cq_reconstruct_fd of a GEMM shape the autotuner
+ *    has not seen (outside stream capture) times the kernel variants on
+ *    `stream` and waits for them (see cq_autotune_enable; CQ_AUTOTUNE=0 or a
+ *    warm-up call moves that cost out of a timed or captured region).
+ *    cq_reconstruct_dd enqueues every recursion of the batch (by default as
+ *    one captured graph), synchronises `stream` once at the end and returns
+ *    after reading the records back.  Calls are thread-safe; calls that share
+ *    a workspace must not overlap.
  */
 #ifndef CUTQC_H
 #define CUTQC_H
@@ -364,8 +369,9 @@ cq_status cq_chi2(const double* a, const double* b, int64_t n, double* result, v
  * of a basis-state index: CQ_GATE_U applies the 2 x 2 unitary u (row-major,
  * (re, im) of u00, u01, u10, u11) to qubit q0; CQ_GATE_CZ applies CZ to q0
  * and q1.  The matrix is applied as given (unitarity is not checked).
- * Consecutive gates are applied in groups to tiles of 2^10 amplitudes held
- * in LDS, in circuit order, so the state crosses HBM once per group.
+ * Consecutive gates are applied in groups to tiles of 2^11 amplitudes held
+ * in registers (8 per thread; registers narrower than a tile go through LDS),
+ * in circuit order, so the state crosses HBM once per group.
  * ------------------------------------------------------------------------- */
 #define CQ_MAX_SV_QUBITS 34  /* 2^34 amplitudes = 256 GiB of workspace */
 

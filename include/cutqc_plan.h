@@ -72,6 +72,20 @@ cq_status cq_profile_read(char* names, double* ms, double* flops, int32_t cap, i
  * Always returns CQ_OK. */
 cq_status cq_autotune_enable(int32_t mode);
 
+/* Per-label balance of the 16-bit operands of cq_reconstruct_fd (Eq. 1's
+ * labelling terms pair each cut's measured end with its initialised end, so
+ * a power of two s_j(d) on every entry row whose digit at cut j is d on the
+ * measuring subcircuit, and 1/s_j(d) on the initialising one, changes no
+ * term): s_j(d) brings the largest magnitudes of the two sides within a
+ * factor of two of each other before the 16-bit conversion.  FP16's narrow
+ * exponent range is what it protects; for the BF16 forms (FP32's exponent
+ * range) a power of two changes no rounding while every value stays in the
+ * normal range, so their results are the same bit for bit with or without it
+ * (only values near 2^-126 can round differently).  mode: 0 = off, 1 = FP16
+ * and FP16-split (the default), 2 = every 16-bit form.  Process-wide.
+ * Always CQ_OK. */
+cq_status cq_label_balance_enable(int32_t mode);
+
 /* The cached choices as JSON:
  *   [{"prec": ..., "M", "N", "K", "Z", "variant": v, "ms": [[v, ms], ...]}, ...]
  * *needed receives the length including the terminating NUL; with buf null

@@ -18,6 +18,7 @@ MAX_DD_R = 16
 FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
+            "cq_label_balance_enable",
             "cq_autotune_json",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
@@ -154,6 +155,8 @@ def lib():
     L.cq_profile_enable.argtypes = [C.c_int32]
     L.cq_autotune_enable.restype = st
     L.cq_autotune_enable.argtypes = [C.c_int32]
+    L.cq_label_balance_enable.restype = st
+    L.cq_label_balance_enable.argtypes = [C.c_int32]
     L.cq_autotune_json.restype = st
     L.cq_autotune_json.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.cq_profile_read.restype = st

@@ -445,6 +445,12 @@ def cq_autotune_enable(on=True, variant=None):
     check(lib().cq_autotune_enable(mode))
 
 
+def cq_label_balance_enable(mode=1):
+    """Per-label balance of the 16-bit operands: 0 off, 1 FP16 forms
+    (default), 2 every 16-bit form."""
+    check(lib().cq_label_balance_enable(int(mode)))
+
+
 def cq_autotune_json():
     """The autotuner's cached choices (list of dicts)."""
     import json

@@ -85,6 +85,17 @@ int work_elem_bytes(cq_precision p) { return dtype_bytes(work_dtype(p)); }
 
 bool is_f16(cq_precision p) { return p == CQ_FP16 || p == CQ_FP16_SPLIT; }
 
+bool is_h16(cq_precision p) { return p >= CQ_BF16 && p <= CQ_FP16_SPLIT; }
+
+// Per-label balance of the operands: 0 off, 1 the FP16 forms (default),
+// 2 every 16-bit form.
+std::atomic<int> g_lbal_mode{1};
+
+bool balance_applies(cq_precision p) {
+  const int m = g_lbal_mode.load();
+  return is_h16(p) && (m == 2 || (m == 1 && is_f16(p)));
+}
+
 DType out_dtype(cq_precision p) { return p == CQ_FP64 ? DType::F64 : DType::F32; }
 
 cq_status check_perm(const int32_t* out_perm, int n, std::vector<int>& perm) {
@@ -101,8 +112,10 @@ cq_status check_perm(const int32_t* out_perm, int n, std::vector<int>& perm) {
 }
 
 // Runs a plan.  inputs[c]: FP64 device pointer of subcircuit c's tensor.
+// bal (optional): per-label balance of the 16-bit operands, its row maxima and
+// exponents in the workspace.
 cq_status execute(const Plan& plan, cq_precision prec, const double* const* inputs, void* out,
-                  DType out_t, char* ws, hipStream_t stream) {
+                  DType out_t, char* ws, hipStream_t stream, const BalanceLaunch* bal = nullptr) {
   const DType wt = work_dtype(prec);
   const bool f16 = is_f16(prec);
   auto planes = [&](char* base, int64_t elems) -> Operand {
@@ -122,22 +135,42 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
     return planes(ws + plan.work_offset[t.index], t.elems);
   };
   auto colmax = [&](int c) { return reinterpret_cast<uint64_t*>(ws + plan.colmax_offset[c]); };
+  auto out_bits = [](const TensorRef& t) {
+    return t.axes.empty() || t.axes.back().kind != 1 ? 0 : t.axes.back().log2;
+  };
+  // per-label balance: row maxima of every converted input, then the
+  // exponents of every row
+  if (bal) {
+    ProfScope ps("balance", 0.0, stream);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < plan.tensors.size() && e == hipSuccess; ++i) {
+      const TensorRef& t = plan.tensors[i];
+      if (t.loc != Loc::Input || plan.input_offset[t.index] < 0) continue;
+      const int nb = out_bits(t);
+      e = launch_rowmax(inputs[t.index], t.elems >> nb, nb,
+                        const_cast<uint64_t*>(bal->rowmax[t.index]), stream);
+    }
+    if (e == hipSuccess) e = launch_balance(*bal, stream);
+    if (e != hipSuccess) return hip_fail(e, "label balance launch");
+  }
   // operand preparation: FP64 entries -> the precision's storage format
   for (size_t i = 0; i < plan.tensors.size(); ++i) {
     const TensorRef& t = plan.tensors[i];
     if (t.loc != Loc::Input || plan.input_offset[t.index] < 0) continue;
+    const int32_t* rexp = bal ? bal->rexp[t.index] : nullptr;
+    const int nb = out_bits(t);
     hipError_t e;
     {
       ProfScope ps("prep", 0.0, stream);
       if (plan.scaled) {
-        const int nb = t.axes.empty() || t.axes.back().kind != 1 ? 0 : t.axes.back().log2;
         const int64_t rows = t.elems >> nb;
-        e = launch_colmax(inputs[t.index], rows, nb, colmax(t.index), stream);
+        e = launch_colmax(inputs[t.index], rows, nb, colmax(t.index), stream, rexp);
         if (e == hipSuccess)
           e = launch_prep_scaled(inputs[t.index], ws + plan.input_offset[t.index], t.elems, nb,
-                                 colmax(t.index), wt, f16, stream);
+                                 colmax(t.index), wt, f16, stream, rexp);
       } else {
-        e = launch_prep(inputs[t.index], ws + plan.input_offset[t.index], t.elems, wt, f16, stream);
+        e = launch_prep(inputs[t.index], ws + plan.input_offset[t.index], t.elems, wt, f16, stream,
+                        rexp, nb);
       }
     }
     if (e != hipSuccess) return hip_fail(e, "operand prep launch");
@@ -245,7 +278,43 @@ cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec
   if (st != CQ_OK) return st;
   std::vector<int> ol;
   for (auto& s : cm.subs) ol.push_back(s.n());
-  return make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
+  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
+  if (st != CQ_OK || !is_h16(prec)) return st;
+  // per-label balance: row maxima and exponents of each input (reserved for
+  // every 16-bit form, used when balance_applies)
+  auto reserve = [&](int64_t bytes) {
+    const int64_t off = plan.workspace_bytes;
+    plan.workspace_bytes = off + (bytes + 255) / 256 * 256;
+    return off;
+  };
+  for (int c = 0; c < cm.n_sub; ++c) {
+    const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
+    plan.lbal_rowmax_offset.push_back(reserve(rows * 8));
+    plan.lbal_rexp_offset.push_back(reserve(rows * 4));
+  }
+  return CQ_OK;
+}
+
+// The balance arguments of a plan on workspace ws.
+BalanceLaunch balance_args(const CutMap& cm, const Plan& plan, char* ws) {
+  BalanceLaunch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n_sub = cm.n_sub;
+  b.K = cm.K;
+  for (int c = 0; c < cm.n_sub; ++c) {
+    const SubInfo& si = cm.subs[c];
+    b.rowmax[c] = reinterpret_cast<const uint64_t*>(ws + plan.lbal_rowmax_offset[c]);
+    b.rexp[c] = reinterpret_cast<int32_t*>(ws + plan.lbal_rexp_offset[c]);
+    b.k[c] = si.k();
+    for (int p = 0; p < si.k(); ++p) b.cut_of[c][p] = si.cuts[p];
+  }
+  for (int j = 0; j < cm.K; ++j) {
+    b.up[j] = cm.up[j];
+    b.down[j] = cm.down[j];
+    b.pos_up[j] = cm.subs[cm.up[j]].digit_pos(j);
+    b.pos_down[j] = cm.subs[cm.down[j]].digit_pos(j);
+  }
+  return b;
 }
 
 }  // namespace
@@ -341,8 +410,12 @@ cq_status cq::fd_run(int32_t n_sub, const cq_subcircuit* subs, const double* con
   if (plan.workspace_bytes > 0 && (!workspace || workspace_bytes < (size_t)plan.workspace_bytes))
     return fail(CQ_ERR_WORKSPACE, "workspace too small");
   if (fault_injected("fd")) return fail(CQ_ERR_HIP, "injected fault before launch");
+  BalanceLaunch bal;
+  const bool balanced = balance_applies(prec) && !plan.lbal_rexp_offset.empty();
+  if (balanced) bal = balance_args(cm, plan, static_cast<char*>(workspace));
   t_quiet = quiet;
-  st = execute(plan, prec, entries, out, out_dtype(prec), static_cast<char*>(workspace), stream);
+  st = execute(plan, prec, entries, out, out_dtype(prec), static_cast<char*>(workspace), stream,
+               balanced ? &bal : nullptr);
   t_quiet = false;
   return st;
 }
@@ -1185,6 +1258,11 @@ extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int
     (void)hipEventDestroy(recs[i].stop);
   }
   return st;
+}
+
+extern "C" cq_status cq_label_balance_enable(int32_t mode) {
+  g_lbal_mode.store(mode < 0 ? 0 : (mode > 2 ? 2 : mode));
+  return CQ_OK;
 }
 
 extern "C" cq_status cq_autotune_enable(int32_t mode) {

@@ -1,6 +1,8 @@
 // Layout permutes and entry attribution.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "kernels.hpp"
 
 namespace cq {
@@ -79,12 +81,14 @@ __global__ void __launch_bounds__(256) permute_ind_kernel(const PermArgs* __rest
   permute_body<SK, DK>(*p);
 }
 
-// FP64 -> FP32 or 16-bit planes (hi = rn16(x), lo = rn16(x - hi)).
+// FP64 -> FP32 or 16-bit planes (hi = rn16(x), lo = rn16(x - hi)); with
+// rexp, row i >> cols_log2 is first scaled by its power of two.
 template <int DK>
-__device__ inline void prep_body(const double* __restrict__ src, void* dst, void* dst_lo, int64_t n) {
+__device__ inline void prep_body(const double* __restrict__ src, void* dst, void* dst_lo, int64_t n,
+                                 const int32_t* __restrict__ rexp = nullptr, int cols_log2 = 0) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-    const float x = float(src[i]);
+    const float x = rexp ? float(ldexp(src[i], rexp[i >> cols_log2])) : float(src[i]);
     if constexpr (DK == kF32) {
       static_cast<float*>(dst)[i] = x;
     } else {
@@ -97,8 +101,9 @@ __device__ inline void prep_body(const double* __restrict__ src, void* dst, void
 
 template <int DK>
 __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ src, void* dst,
-                                                   void* dst_lo, int64_t n) {
-  prep_body<DK>(src, dst, dst_lo, n);
+                                                   void* dst_lo, int64_t n,
+                                                   const int32_t* __restrict__ rexp, int cols_log2) {
+  prep_body<DK>(src, dst, dst_lo, n, rexp, cols_log2);
 }
 
 // blockIdx.y selects the argument block
@@ -112,7 +117,7 @@ __global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restric
 // rows of one column, then one atomic max per thread.
 __global__ void __launch_bounds__(256) colmax_kernel(const double* __restrict__ E, int64_t rows,
                                                      int cols_log2, int rows_per_thread,
-                                                     uint64_t* colmax) {
+                                                     uint64_t* colmax, const int32_t* __restrict__ rexp) {
   const int64_t cols = (int64_t)1 << cols_log2;
   const int64_t chunks = (rows + rows_per_thread - 1) / rows_per_thread;
   const int64_t total = chunks * cols;
@@ -122,9 +127,117 @@ __global__ void __launch_bounds__(256) colmax_kernel(const double* __restrict__ 
     int64_t r1 = r0 + rows_per_thread;
     if (r1 > rows) r1 = rows;
     double m = 0.0;
-    for (int64_t r = r0; r < r1; ++r) m = fmax(m, fabs(E[(r << cols_log2) + col]));
+    for (int64_t r = r0; r < r1; ++r) {
+      const double x = E[(r << cols_log2) + col];
+      m = fmax(m, fabs(rexp ? ldexp(x, rexp[r]) : x));
+    }
     atomicMax(reinterpret_cast<unsigned long long*>(colmax + col),
               (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// max_b |E[l][b]| per row: one wave per row (rows strided over the grid's
+// waves), the wave's lanes striding the columns.
+__global__ void __launch_bounds__(256) rowmax_kernel(const double* __restrict__ E, int64_t rows,
+                                                     int cols_log2, uint64_t* rowmax) {
+  const int64_t cols = (int64_t)1 << cols_log2;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wave; r < rows; r += waves) {
+    const double* row = E + (r << cols_log2);
+    double m = 0.0;
+    for (int64_t c = lane; c < cols; c += 64) m = fmax(m, fabs(row[c]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) rowmax[r] = (uint64_t)__double_as_longlong(m);
+  }
+}
+
+// Binary exponent of a positive finite x (x = f * 2^e, f in [1, 2)).
+__device__ inline int bexp(double x) { return ilogb(x); }
+
+// One workgroup: per (subcircuit, digit position, digit) the largest row
+// maximum (LDS), then e_j(d) per cut and digit, then every row's exponent.
+// The largest row of a subcircuit sits at each digit's maximum over the other
+// positions, so the exponents carry an offset per subcircuit (the same for
+// all its rows); a final constant per subcircuit, summing to zero over the
+// subcircuits (every term of Eq. 1 takes one row of each), brings every
+// subcircuit's largest scaled row to their common mean binary exponent.
+__global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
+  __shared__ unsigned long long pmax[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS][4];
+  __shared__ int ej[CQ_MAX_CUTS][4];
+  __shared__ int smax[CQ_MAX_SUBCIRCUITS];
+  __shared__ int goff[CQ_MAX_SUBCIRCUITS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < CQ_MAX_SUBCIRCUITS * CQ_MAX_LOCAL_CUTS * 4; i += blockDim.x)
+    (&pmax[0][0][0])[i] = 0ull;
+  if (tid < CQ_MAX_SUBCIRCUITS) smax[tid] = INT_MIN;
+  __syncthreads();
+  for (int c = 0; c < b.n_sub; ++c) {
+    const int k = b.k[c];
+    const int64_t rows = (int64_t)1 << (2 * k);
+    for (int64_t l = tid; l < rows; l += blockDim.x) {
+      const unsigned long long v = b.rowmax[c][l];
+      if (v == 0ull) continue;
+      for (int p = 0; p < k; ++p) {
+        const int d = (int)((l >> (2 * (k - 1 - p))) & 3);
+        atomicMax(&pmax[c][p][d], v);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < b.K * 4; i += blockDim.x) {
+    const int j = i >> 2, d = i & 3;
+    const double mu = __longlong_as_double((long long)pmax[b.up[j]][b.pos_up[j]][d]);
+    const double md = __longlong_as_double((long long)pmax[b.down[j]][b.pos_down[j]][d]);
+    int e = 0;
+    if (mu > 0.0 && md > 0.0 && isfinite(mu) && isfinite(md)) {
+      const int diff = bexp(md) - bexp(mu);
+      e = diff >= 0 ? diff / 2 : -((-diff) / 2);  // round toward zero: exact halves
+      e = e > 200 ? 200 : (e < -200 ? -200 : e);
+    }
+    ej[j][d] = e;
+  }
+  __syncthreads();
+  for (int c = 0; c < b.n_sub; ++c) {
+    const int k = b.k[c];
+    const int64_t rows = (int64_t)1 << (2 * k);
+    for (int64_t l = tid; l < rows; l += blockDim.x) {
+      int e = 0;
+      for (int p = 0; p < k; ++p) {
+        const int j = b.cut_of[c][p];
+        const int d = (int)((l >> (2 * (k - 1 - p))) & 3);
+        e += b.up[j] == c ? ej[j][d] : -ej[j][d];
+      }
+      b.rexp[c][l] = e;
+      const double v = __longlong_as_double((long long)b.rowmax[c][l]);
+      if (v > 0.0 && isfinite(v)) atomicMax(&smax[c], bexp(v) + e);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int n = 0, last = -1;
+    long long sum = 0;
+    for (int c = 0; c < b.n_sub; ++c)
+      if (smax[c] != INT_MIN) {
+        sum += smax[c];
+        ++n;
+        last = c;
+      }
+    // floor of the mean
+    const long long mean = n ? (sum >= 0 ? sum / n : -((-sum + n - 1) / n)) : 0;
+    long long tot = 0;
+    for (int c = 0; c < b.n_sub; ++c) {
+      goff[c] = smax[c] == INT_MIN ? 0 : (int)(mean - smax[c]);
+      tot += goff[c];
+    }
+    if (last >= 0) goff[last] -= (int)tot;  // the offsets sum to zero
+  }
+  __syncthreads();
+  for (int c = 0; c < b.n_sub; ++c) {
+    const int64_t rows = (int64_t)1 << (2 * b.k[c]);
+    for (int64_t l = tid; l < rows; l += blockDim.x) b.rexp[c][l] += goff[c];
   }
 }
 
@@ -136,11 +249,13 @@ __global__ void __launch_bounds__(256) fill_u64_kernel(uint64_t* p, int64_t n, u
 template <int DK>
 __global__ void __launch_bounds__(256) prep_scaled_kernel(const double* __restrict__ src, void* dst,
                                                           void* dst_lo, int64_t n, int cols_log2,
-                                                          const uint64_t* __restrict__ colmax) {
+                                                          const uint64_t* __restrict__ colmax,
+                                                          const int32_t* __restrict__ rexp) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   const int64_t mask = ((int64_t)1 << cols_log2) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-    const float x = float(ldexp(src[i], -colmax_exp(colmax[i & mask])));
+    const int e = -colmax_exp(colmax[i & mask]) + (rexp ? rexp[i >> cols_log2] : 0);
+    const float x = float(ldexp(src[i], e));
     if constexpr (DK == kF32) {
       static_cast<float*>(dst)[i] = x;
     } else {
@@ -543,21 +658,35 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
 }
 
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
-                       hipStream_t stream) {
+                       hipStream_t stream, const int32_t* rexp, int cols_log2) {
   if (n <= 0) return hipSuccess;
   const dim3 grid(grid_for(n));
   void* lo = t == DType::H16X2 ? static_cast<char*>(dst) + n * 2 : nullptr;
   if (t == DType::F32)
-    hipLaunchKernelGGL((prep_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n);
+    hipLaunchKernelGGL((prep_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n, rexp,
+                       cols_log2);
   else if (f16)
-    hipLaunchKernelGGL((prep_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
+    hipLaunchKernelGGL((prep_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
   else
-    hipLaunchKernelGGL((prep_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n);
+    hipLaunchKernelGGL((prep_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowmax(const double* E, int64_t rows, int cols_log2, uint64_t* rowmax,
+                         hipStream_t stream) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rowmax_kernel, dim3(grid_for(rows * 64)), dim3(256), 0, stream, E, rows, cols_log2,
+                     rowmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_balance(const BalanceLaunch& b, hipStream_t stream) {
+  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 
 hipError_t launch_colmax(const double* E, int64_t rows, int cols_log2, uint64_t* colmax,
-                         hipStream_t stream) {
+                         hipStream_t stream, const int32_t* rexp) {
   const int64_t cols = (int64_t)1 << cols_log2;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cols)), dim3(256), 0, stream, colmax, cols,
                      (uint64_t)0);
@@ -566,24 +695,25 @@ hipError_t launch_colmax(const double* E, int64_t rows, int cols_log2, uint64_t*
   const int rpt = 64;
   const int64_t total = (rows + rpt - 1) / rpt * cols;
   hipLaunchKernelGGL(colmax_kernel, dim3(grid_for(total)), dim3(256), 0, stream, E, rows, cols_log2,
-                     rpt, colmax);
+                     rpt, colmax, rexp);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_scaled(const double* src, void* dst, int64_t n, int cols_log2,
-                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream) {
+                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream,
+                              const int32_t* rexp) {
   if (n <= 0) return hipSuccess;
   const dim3 grid(grid_for(n));
   void* lo = t == DType::H16X2 ? static_cast<char*>(dst) + n * 2 : nullptr;
   if (t == DType::F32)
     hipLaunchKernelGGL((prep_scaled_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n,
-                       cols_log2, colmax);
+                       cols_log2, colmax, rexp);
   else if (f16)
     hipLaunchKernelGGL((prep_scaled_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n,
-                       cols_log2, colmax);
+                       cols_log2, colmax, rexp);
   else
     hipLaunchKernelGGL((prep_scaled_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n,
-                       cols_log2, colmax);
+                       cols_log2, colmax, rexp);
   return hipGetLastError();
 }
 

@@ -694,8 +694,9 @@ __global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmA
 // the operands' own [label][column] layout; ds_read_b64_tr_b16 then returns
 // each lane's k-contiguous MFMA operand (within a group of 16 lanes, slot j of
 // lane i is word i%4 of the address given by lane 4j + i/4).  LDS rows are
-// 128 columns (256 B) whose 16-byte chunks are XOR-swizzled by 2*(row & 3),
-// so the 16 lanes of one transposed read touch 8 distinct chunks.  Results are
+// 128 columns (256 B) whose 16-byte chunks are XOR-swizzled by 4*(row & 3)
+// (swz), so the 32 lanes of a half-wave's transposed reads -- four rows, two
+// 32-column groups -- cover all 64 banks once.  Results are
 // staged through LDS per wave so each global store instruction writes whole
 // 256-byte row segments.  The DMA is issued from asm: the compiler would
 // otherwise wait for every in-flight LDS DMA before each LDS read; completion

@@ -130,6 +130,9 @@ struct Plan {
   int64_t rowexp_count = 0, colexp_count = 0;
   FacGroup row_fac, col_fac;            // final GEMM: over z*M + m, and over n
   FacGroup perm_fac;                    // final permute: over the source offset
+  // Per-label balance (16-bit operands): per input, 4^k_c row maxima (FP64
+  // bit patterns) and 4^k_c int32 row exponents; -1 when not reserved.
+  std::vector<int64_t> lbal_rowmax_offset, lbal_rexp_offset;
 };
 
 // `out_log2` per subcircuit = number of outputs taking part (n_c for FD, the

@@ -104,18 +104,45 @@ hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t 
                                 DType tc, bool nontemporal, bool topc, hipStream_t stream);
 
 // Converts n FP64 values to `t` (FP32, or BF16/FP16 planes when f16 is false/true).
+// rexp (optional): element i is first multiplied by 2^rexp[i >> cols_log2]
+// (the per-label balance of its row, exact).
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
-                       hipStream_t stream);
+                       hipStream_t stream, const int32_t* rexp = nullptr, int cols_log2 = 0);
+
+// Per-label balance of the 16-bit operands (powers of two, exact).  Every
+// labelling term of Eq. 1 carries, for each cut j, the factor of the
+// subcircuit that measures j's upstream end (row digit d at j) times that of
+// the subcircuit that initialises j's downstream end (same digit); scaling the
+// first by 2^e and the second by 2^-e leaves every term unchanged.  e_j(d) is
+// half the difference of the binary exponents of the two sides' largest
+// |entry| among rows with digit d at j, so both sides end up within a factor
+// of two of each other.  rowmax: per subcircuit, max_b |E_c[l][b]| per row l.
+struct BalanceLaunch {
+  int n_sub, K;
+  const uint64_t* rowmax[CQ_MAX_SUBCIRCUITS];  // FP64 bit patterns, 4^k_c each
+  int32_t* rexp[CQ_MAX_SUBCIRCUITS];           // out: row exponents, 4^k_c each
+  int k[CQ_MAX_SUBCIRCUITS];
+  int cut_of[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];  // cut at digit position p
+  int up[CQ_MAX_CUTS], pos_up[CQ_MAX_CUTS];            // measuring subcircuit, digit position
+  int down[CQ_MAX_CUTS], pos_down[CQ_MAX_CUTS];        // initialising subcircuit, digit position
+};
+// rowmax of E (rows x 2^cols_log2, FP64)
+hipError_t launch_rowmax(const double* E, int64_t rows, int cols_log2, uint64_t* rowmax,
+                         hipStream_t stream);
+hipError_t launch_balance(const BalanceLaunch& b, hipStream_t stream);
 
 // Column scaling by powers of two (16-bit operands).  colmax[b] receives the
 // bit pattern of max_l |E[l][b]| (FP64, so the unsigned order is the value
 // order); column b is then scaled by 2^-e, e the binary exponent with
 // max = f * 2^e, f in [0.5, 1).  Scaling is exact, and the result's
 // per-subcircuit exponents are added back at the end.
+// rexp (optional) as for launch_prep, applied before the maxima and the
+// conversion.
 hipError_t launch_colmax(const double* E, int64_t rows, int cols_log2, uint64_t* colmax,
-                         hipStream_t stream);
+                         hipStream_t stream, const int32_t* rexp = nullptr);
 hipError_t launch_prep_scaled(const double* src, void* dst, int64_t n, int cols_log2,
-                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream);
+                              const uint64_t* colmax, DType t, bool f16, hipStream_t stream,
+                              const int32_t* rexp = nullptr);
 // out[r] = sum_c e_c(colmax[c][(r >> shift[c]) & (2^bits[c] - 1)]) for r < count.
 struct ExpSumLaunch {
   int32_t* out;

@@ -411,6 +411,85 @@ def test_30_qubit_chain_full_size_h16(prec):
     assert np.all(err <= H16_REL[prec] * scale + fp32_floor(cm))
 
 
+# --- per-label balance of the 16-bit operands --------------------------------
+
+LABEL_SHIFT = {0: 0, 1: 20, 2: -20, 3: 10}   # digit I, X, Y, Z -> log2 factor
+
+
+def imbalance_labels(cm, E, shift=LABEL_SHIFT):
+    """Entries whose rows are scaled per cut label: a row with digit d at cut
+    j gets 2^shift[d] on the subcircuit measuring j and 2^-shift[d] on the one
+    initialising it.  Every labelling term of Eq. 1 keeps its value exactly,
+    so the reconstruction is unchanged, but within one subcircuit the label
+    rows now differ by up to 2^40."""
+    out = []
+    for sub, e in zip(cm, E):
+        _, init, meas = sub
+        cuts = cutmap.incident_cuts(sub)
+        k = len(cuts)
+        ex = np.zeros(4 ** k, dtype=np.int64)
+        for l in range(4 ** k):
+            for p, cut in enumerate(cuts):
+                d = (l >> (2 * (k - 1 - p))) & 3
+                ex[l] += shift[d] if cut in meas else -shift[d]
+        out.append(np.ldexp(e, ex[:, None]))
+    return out
+
+
+def test_label_balance_keeps_bf16_bits():
+    """For the BF16 forms a power of two changes no rounding while values stay
+    in BF16's normal range (FP32's exponents): balanced and unbalanced runs
+    agree bit for bit.  Entries here are in +-[1e-3, 1], so even the 2^+-100
+    row factors keep every operand and product normal (Dirichlet entries reach
+    below 1e-38, where scaling does change what underflows)."""
+    m = cq()
+    rng = np.random.default_rng(12)
+    cm = syn.chain_cutmap([3, 2], [8, 6, 7])
+    E = [np.copysign(rng.uniform(1e-3, 1.0, size=(4 ** k, 2 ** n)), rng.uniform(-1, 1, size=(4 ** k, 2 ** n)))
+         for k, n in zip(syn.chain_ks([3, 2], 3), [8, 6, 7])]
+    Ei = imbalance_labels(cm, E)
+    try:
+        for prec in ("bf16", "bf16_split"):
+            m.cq_label_balance_enable(0)
+            off = gpu_fd(cm, Ei, prec)
+            m.cq_label_balance_enable(2)
+            on = gpu_fd(cm, Ei, prec)
+            assert np.array_equal(on, off), prec
+    finally:
+        m.cq_label_balance_enable(1)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp16_split"])
+def test_label_balance_rescues_fp16_on_imbalanced_labels(prec):
+    """Label rows 2^+-20 apart within a subcircuit: without the balance the
+    FP16 conversion loses the small rows (column scaling cannot help, the
+    rows share columns); with it both sides of every cut meet in FP16's
+    range and the result matches the oracle as on balanced data."""
+    m = cq()
+    cm, E = syn.chain_instance(12, [3, 2], [8, 6, 7])
+    Ei = imbalance_labels(cm, E)
+    ref = rc.fd_contract(cm, E)
+    assert np.array_equal(rc.fd_contract(cm, Ei), ref)  # the input change is exact
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    try:
+        m.cq_label_balance_enable(0)
+        err_off = np.abs(gpu_fd(cm, Ei, prec) - ref)
+        m.cq_label_balance_enable(1)
+        err_on = np.abs(gpu_fd(cm, Ei, prec) - ref)
+        err_plain = np.abs(gpu_fd(cm, E, prec) - ref)
+    finally:
+        m.cq_label_balance_enable(1)
+    print(f"{prec}: max abs balanced input {err_plain.max():.3e}; imbalanced without balance "
+          f"{err_off.max():.3e}, with balance {err_on.max():.3e}", flush=True)
+    tol = {"fp16": 4e-3, "fp16_split": 1e-5}[prec]
+    assert np.all(err_on <= tol * scale + fp32_floor(cm))
+    assert err_on.max() <= 4 * err_plain.max() + 1e-30
+    if prec == "fp16_split":
+        assert err_on.max() < 1e-6
+    # the arm matters: without the balance the error is far larger
+    assert err_off.max() > 100 * err_on.max()
+
+
 # --- 32-qubit chain of four: the mixed-precision accuracy matrix -------------
 
 SEED_32Q = 3
@@ -531,3 +610,42 @@ def test_attribution_all_pass_shapes(r, o):
     got = gpu_attribute(sub, V)
     assert got.shape == ref.shape
     assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("balance", [1, 0])
+@pytest.mark.parametrize("prec", ["fp16_split", "fp16", "bf16_split"])
+def test_32_qubit_chain_of_four_imbalanced_labels(prec, balance):
+    """The accuracy matrix's per-label arm: the 32-qubit chain with label
+    rows 2^+-20 apart inside each subcircuit (imbalance_labels: the exact
+    result is unchanged), with and without the per-label balance, against the
+    oracle on the same 10^5 sampled bins.  FP16-split with the balance must
+    meet 1e-6; the BF16 forms do not depend on it (bit-identical either way)."""
+    m = cq()
+    cm, E = syn.chain_instance(SEED_32Q, BONDS_32Q, NS_32Q)
+    Ei = imbalance_labels(cm, E)
+    ents = [to_dev(e) for e in Ei]
+    print(f"32q imbalanced labels {prec} balance {balance}", flush=True)
+    try:
+        m.cq_label_balance_enable(balance)
+        out = m.cq_reconstruct_fd(cm, ents, prec=prec)
+        torch.cuda.synchronize()
+    finally:
+        m.cq_label_balance_enable(1)
+    rng = np.random.default_rng(31)
+    bins = rng.integers(0, 2 ** 32, size=100_000).astype(np.int64)
+    got = out[torch.from_numpy(bins).to(DEV)].cpu().numpy().astype(np.float64)
+    del out
+    ref = rc.fd_per_bin(cm, E, bins)
+    scale = rc.fd_per_bin(cm, [np.abs(e) for e in E], bins)
+    err = np.abs(got - ref)
+    rel = err / np.maximum(scale, 1e-300)
+    print(f"{prec} balance {balance}: sampled max abs {err.max():.3e}, TV estimate "
+          f"{2.0 ** 31 * err.mean():.3e}, median err/scale {np.median(rel):.3e}", flush=True)
+    if balance and prec == "fp16_split":
+        assert err.max() < 1e-6
+        assert np.all(err <= 1e-5 * scale + fp32_floor(cm))
+    if prec == "bf16_split":
+        assert err.max() < 1e-6
+    if not balance and prec.startswith("fp16"):
+        # without the balance the small label rows are lost in FP16
+        assert np.median(rel) > 1e-3
