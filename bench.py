@@ -61,6 +61,10 @@ def parse():
                     help="skip the finite-shot sampling and chi-square leg")
     ap.add_argument("--skip-statevector", action="store_true",
                     help="skip the device state-vector leg")
+    ap.add_argument("--fd32-forms", default="fp32,bf16_split",
+                    help="forms of the 32-qubit chain-of-four leg (empty: skip)")
+    ap.add_argument("--fd20-forms", default="fp64,fp32,bf16_split",
+                    help="forms of the 20-qubit circuit leg (empty: skip)")
     return ap.parse_args()
 
 
@@ -185,6 +189,18 @@ def roofline(plan, prec, name, kfl, kms, kcnt):
     return r
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(torch, ents, out_fp, budget_s):
     """Times the FP64 oracle on leading-bit slices of the workload and
     evaluates it on sampled bins for the error report."""
@@ -213,7 +229,24 @@ def cpu_baseline_leg(torch, ents, out_fp, budget_s):
            "kind": "oracle",
            "sample": f"oracle einsum contraction (numpy FP64, BLAS) of subcircuit-0 outputs "
                      f"0..{rows - 1} of 1024 ({rows * 2 ** 20} of 2^30 probabilities), {t:.1f} s",
-           "outputs_per_s": rows * 2 ** 20 / t}
+           "outputs_per_s": rows * 2 ** 20 / t, "cpu_model": cpu_model()}
+    # the same contraction on one thread, on a slice sized for about a quarter
+    # of the budget
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            rc.fd_contract(cm, E, lead=(0, 8))
+            t8 = time.perf_counter() - t0
+            rows1 = int(min(1024, max(8, 8 * 0.25 * budget_s / max(t8, 1e-3))))
+            t0 = time.perf_counter()
+            rc.fd_contract(cm, E, lead=(0, rows1))
+            t1 = time.perf_counter() - t0
+        cpu["one_thread"] = {"value": total_flops * rows1 / 1024.0 / t1 / 1e12, "unit": "TFLOP/s",
+                             "sample": f"subcircuit-0 outputs 0..{rows1 - 1} of 1024, {t1:.1f} s",
+                             "outputs_per_s": rows1 * 2 ** 20 / t1}
+    except Exception as ex:  # threadpoolctl absent: report why
+        cpu["one_thread"] = {"skipped": str(ex).splitlines()[0] if str(ex) else type(ex).__name__}
     # error of the GPU output on those slice values and on sampled bins
     got = out_fp[:rows * 2 ** 20].double().cpu().numpy()
     slice_err = float(np.max(np.abs(got - part)))
@@ -230,6 +263,99 @@ def cpu_baseline_leg(torch, ents, out_fp, budget_s):
     got = out_fp[torch.from_numpy(bins).to(out_fp.device)].double().cpu().numpy()
     samp_err = float(np.max(np.abs(got - ref)))
     return cpu, {"max_abs_vs_oracle_slice": slice_err, "max_abs_vs_oracle_sampled_1000": samp_err}
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def _time_calls(torch, fn, runs, warmup=1):
+    """Median of `runs` timed calls (HIP events on the current stream) after
+    `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(runs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return _median(ts)
+
+
+FD32_SEED, FD32_BONDS, FD32_NS = 3, [3, 2, 3], [8, 8, 8, 8]
+
+
+def fd32_leg(torch, cq, forms, runs=5):
+    """32-qubit full definition: a chain of four 8-output subcircuits with
+    bonds of 3, 2 and 3 cuts (K = 8), 2^32 FP32 outputs.  The contraction is
+    small (0.138 TFLOP); writing 17.2 GB of output binds it (2.15 ms at
+    8 TB/s).  Reports per form the call time, the algorithmic bytes (FP64
+    entries read once, intermediates written and read once, output written
+    once) per second and the fraction of the HBM peak, and the output write
+    alone against the peak."""
+    from workloads import synthetic as syn
+    cm = syn.chain_cutmap(FD32_BONDS, FD32_NS)
+    ks = syn.chain_ks(FD32_BONDS, 4)
+    ents = [syn.entries_torch(FD32_SEED, c, ks[c], FD32_NS[c], "cuda:0") for c in range(4)]
+    out_bytes = 2 ** 32 * 4
+    res = {"workload": "32-qubit FD: chain of 4 subcircuits x 8 outputs, bonds 3+2+3 (K=8), entries "
+                       "(64|1024|1024|64, 256) FP64 as in the 30-qubit workload (seed 3), 2^32 FP32 "
+                       "outputs",
+           "output_write_floor_ms": round(out_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4), "forms": {}}
+    out = torch.empty(2 ** 32, dtype=torch.float32, device="cuda:0")
+    for f in forms:
+        plan = cq.cq_plan_json(cm, f)
+        ws = torch.empty(max(plan["workspace_bytes"], 1), dtype=torch.uint8, device="cuda:0")
+        ms = _time_calls(torch, lambda: cq.cq_reconstruct_fd(cm, ents, prec=f, out=out, workspace=ws),
+                         runs)
+        sr = step_roofline(plan, f, ms)
+        res["forms"][f] = {"ms": round(ms, 4), "tflops": round(plan["flops"] / (ms * 1e-3) / 1e12, 3),
+                           "algorithmic_bytes": sr["algorithmic_bytes"],
+                           "achieved_GBps": round(sr["algorithmic_bytes"] / (ms * 1e-3) / 1e9, 1),
+                           "frac_hbm": round(sr["algorithmic_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "output_write_frac": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "outputs_per_s": 2 ** 32 / (ms * 1e-3)}
+        del ws
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def fd20_leg(torch, cq, forms, runs=50):
+    """The 20-qubit circuit: 10 brickwork layers on a line, four wire cuts
+    giving two subcircuits of 12 register slots and 10 outputs each.  The
+    device simulates every variant (16 init x 9 basis strings of each
+    subcircuit), attributes them to entries (256 x 1024 each) and
+    reconstructs the 2^20 probabilities in uncut-qubit order (a non-block
+    output permutation).  A 1024 x 1024 x 256 label GEMM: latency bound, so
+    the leg reports microseconds per call."""
+    from workloads import circuits as wc
+    cc = wc.two_way_circuit_20q(1)
+    subs = cc.subcircuits()
+    perm = cc.out_perm()
+    Vs = [cq.cq_variant_probabilities(s) for s in subs]
+    torch.cuda.synchronize()
+    t_attr = _time_calls(torch, lambda: [cq.cq_attribute(s, V) for s, V in zip(subs, Vs)], runs)
+    ents = [cq.cq_attribute(s, V) for s, V in zip(subs, Vs)]
+    res = {"workload": "20-qubit circuit (10 brickwork layers, seed 1), 4 wire cuts into 2 subcircuits "
+                       "of 12 slots / 10 outputs; variants simulated on the device, entries (256, 1024) "
+                       "each, 2^20 outputs in uncut-qubit order",
+           "attribution_us_both_subcircuits": round(t_attr * 1e3, 1), "forms": {}}
+    for f in forms:
+        dt = torch.float64 if f == "fp64" else torch.float32
+        out = torch.empty(2 ** 20, dtype=dt, device="cuda:0")
+        ws = torch.empty(max(cq.cq_fd_workspace_size(subs, f, perm), 1), dtype=torch.uint8,
+                         device="cuda:0")
+        ms = _time_calls(torch, lambda: cq.cq_reconstruct_fd(subs, ents, prec=f, out_perm=perm, out=out,
+                                                             workspace=ws), runs, warmup=3)
+        res["forms"][f] = {"us_per_call": round(ms * 1e3, 1),
+                           "outputs_per_s": 2 ** 20 / (ms * 1e-3)}
+    return res
 
 
 DD_SEED, DD_INST, DD_NOUT, DD_ACT, DD_R = 400, 16, 20, 8, 4
@@ -522,6 +648,12 @@ def main():
         out = torch.empty(2 ** 30, dtype=torch.float64 if prec == "fp64" else torch.float32,
                           device=dev)
         cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out)
+    fd32_forms = [f for f in args.fd32_forms.split(",") if f]
+    fd20_forms = [f for f in args.fd20_forms.split(",") if f]
+    if fd32_forms:
+        result["fd32"] = fd32_leg(torch, cq, fd32_forms)
+    if fd20_forms:
+        result["fd20"] = fd20_leg(torch, cq, fd20_forms)
     result["autotune"] = cq.cq_autotune_json()
     if not args.skip_attribution:
         result["attribution"] = attribution_leg(torch, cq)

@@ -267,6 +267,22 @@ cq_status execute(const Plan& plan, cq_precision prec, const double* const* inpu
   return CQ_OK;
 }
 
+// Per-label balance: row maxima and exponents of each input, reserved at the
+// end of a full-definition plan's workspace for every 16-bit form (used when
+// balance_applies).
+void reserve_balance(const CutMap& cm, Plan& plan) {
+  auto reserve = [&](int64_t bytes) {
+    const int64_t off = plan.workspace_bytes;
+    plan.workspace_bytes = off + (bytes + 255) / 256 * 256;
+    return off;
+  };
+  for (int c = 0; c < cm.n_sub; ++c) {
+    const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
+    plan.lbal_rowmax_offset.push_back(reserve(rows * 8));
+    plan.lbal_rexp_offset.push_back(reserve(rows * 4));
+  }
+}
+
 cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec,
                      const int32_t* out_perm, CutMap& cm, Plan& plan) {
   cq_status st = build_cutmap(n_sub, subs, cm);
@@ -279,20 +295,8 @@ cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec
   std::vector<int> ol;
   for (auto& s : cm.subs) ol.push_back(s.n());
   st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
-  if (st != CQ_OK || !is_h16(prec)) return st;
-  // per-label balance: row maxima and exponents of each input (reserved for
-  // every 16-bit form, used when balance_applies)
-  auto reserve = [&](int64_t bytes) {
-    const int64_t off = plan.workspace_bytes;
-    plan.workspace_bytes = off + (bytes + 255) / 256 * 256;
-    return off;
-  };
-  for (int c = 0; c < cm.n_sub; ++c) {
-    const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
-    plan.lbal_rowmax_offset.push_back(reserve(rows * 8));
-    plan.lbal_rexp_offset.push_back(reserve(rows * 4));
-  }
-  return CQ_OK;
+  if (st == CQ_OK && is_h16(prec)) reserve_balance(cm, plan);
+  return st;
 }
 
 // The balance arguments of a plan on workspace ws.
@@ -1181,6 +1185,8 @@ extern "C" cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_p
   Plan plan;
   st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
   if (st != CQ_OK) return st;
+  // a full-definition plan reports the workspace cq_fd_workspace_size asks for
+  if (!out_bits && is_h16(prec)) reserve_balance(cm, plan);
   std::string js = "{\"workspace_bytes\": " + std::to_string(plan.workspace_bytes) +
                    ", \"work_elem_bytes\": " + std::to_string(plan.work_elem_bytes) +
                    ", \"flops\": " + std::to_string(plan.flops) + ", \"tensors\": [";

@@ -316,3 +316,13 @@ def test_autotune_json_and_modes_without_gpu():
     for mode in (0, 1, 2, 7, -3):
         assert L.cq_autotune_enable(mode) == 0
     cq.cq_autotune_enable(True)
+
+
+def test_plan_json_workspace_matches_fd_query():
+    """The plan JSON reports the workspace cq_fd_workspace_size asks for, in
+    every precision (the 16-bit forms include the per-label balance rows)."""
+    import paper_2205_05836_amd as cq
+    for bonds, ns in [([4, 4], [10, 10, 10]), ([3, 2, 3], [8, 8, 8, 8]), ([1], [3, 4])]:
+        cm = syn.chain_cutmap(bonds, ns)
+        for p in ("fp64", "fp32", "bf16", "bf16_split", "fp16", "fp16_split"):
+            assert cq.cq_plan_json(cm, p)["workspace_bytes"] == cq.cq_fd_workspace_size(cm, p), (bonds, p)
