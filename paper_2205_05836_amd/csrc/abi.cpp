@@ -508,6 +508,33 @@ DDCtrl dd_ctrl(int R) {
   return c;
 }
 
+// Beyond the control blocks: the programs of all instances back to back (one
+// upload per call; a copy kernel at the head of the batch moves each into its
+// control block) and the readback block (records and recursion count of every
+// instance back to back, gathered by a copy kernel at the tail of the batch).
+struct DDAreas {
+  char* ctrl0;
+  char* upload;
+  char* gather;
+  int64_t prog_stride, rec_bytes, gather_stride, bytes;
+};
+
+DDAreas dd_areas(char* ws, int n_inst, int R, int lanes, int64_t big) {
+  DDAreas A;
+  const DDCtrl L = dd_ctrl(R);
+  A.prog_stride = ((int64_t)sizeof(DDProgram) + 15) / 16 * 16;
+  A.rec_bytes = (int64_t)R * (int64_t)sizeof(cq_dd_record);
+  A.gather_stride = (A.rec_bytes + 8 + 15) / 16 * 16;  // records, then the int32 count
+  const int64_t ctrl = (int64_t)lanes * align256(big);
+  const int64_t up = ctrl + (int64_t)n_inst * L.bytes;
+  const int64_t ga = up + align256((int64_t)n_inst * A.prog_stride);
+  A.bytes = ga + align256((int64_t)n_inst * A.gather_stride);
+  A.ctrl0 = ws ? ws + ctrl : nullptr;
+  A.upload = ws ? ws + up : nullptr;
+  A.gather = ws ? ws + ga : nullptr;
+  return A;
+}
+
 cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool bins_stored,
                            DDInstancePlan& D) {
   cq_status st = dd_validate(in, p, D.cm, D.s0);
@@ -608,7 +635,7 @@ cq_status dd_plan_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_pa
     all_fused = all_fused && plans[i].topc_step >= 0;
   }
   lanes = all_fused ? std::min<int>(n_inst, kDDLanes) : 1;
-  total = (int64_t)lanes * align256(big) + (int64_t)n_inst * dd_ctrl(p.R).bytes;
+  total = dd_areas(nullptr, n_inst, p.R, lanes, big).bytes;
   return CQ_OK;
 }
 
@@ -858,9 +885,34 @@ cq_status dd_enqueue_instance(int i, const cq_dd_params& p, int recursions, cons
 
 // Enqueues the batch behind `stream`: lane l runs instances l, l + lanes, ...
 // on a stream of its own forked from and joined back into `stream`.
+cq_status dd_enqueue_lanes(int32_t n_inst, const cq_dd_params& p, int recursions,
+                           const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
+                           int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls);
+
+// Enqueues the batch behind `stream`: programs into place, every instance's
+// recursions (parallel lanes when there are several), then the records
+// gathered into the readback block.
 cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
                          const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
                          int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
+  const DDCtrl L = dd_ctrl(p.R);
+  const DDAreas A = dd_areas(ws, n_inst, p.R, lanes, big);
+  hipError_t e = launch_dd_copy(A.upload, A.prog_stride, A.ctrl0 + L.prog, L.bytes, (int64_t)sizeof(DDProgram),
+                                n_inst, stream);
+  if (e != hipSuccess) return hip_fail(e, "program scatter");
+  cq_status st = dd_enqueue_lanes(n_inst, p, recursions, plans, bins_user, ws, big, lanes, stream, ls);
+  if (st != CQ_OK) return st;
+  e = launch_dd_copy(A.ctrl0 + L.recs, L.bytes, A.gather, A.gather_stride, A.rec_bytes, n_inst, stream);
+  if (e == hipSuccess)
+    e = launch_dd_copy(A.ctrl0 + L.state + offsetof(DDState, done), L.bytes, A.gather + A.rec_bytes,
+                       A.gather_stride, 4, n_inst, stream);
+  if (e != hipSuccess) return hip_fail(e, "record gather");
+  return CQ_OK;
+}
+
+cq_status dd_enqueue_lanes(int32_t n_inst, const cq_dd_params& p, int recursions,
+                           const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
+                           int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
   const DDCtrl L = dd_ctrl(p.R);
   char* ctrl0 = ws + (int64_t)lanes * align256(big);
   if (lanes <= 1) {
@@ -901,40 +953,135 @@ cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
   return CQ_OK;
 }
 
-// Owns the captured graph; it is released only after `stream` has drained.
-struct DDGraph {
-  hipStream_t stream = nullptr;
+// Instantiated batch graphs, reused by later calls that repeat every launch
+// parameter (the key: device, precision, R, recursion count, workspace, bin
+// buffers and each instance's cut map, entry pointers and masks).  An entry in
+// use is taken out of the cache and put back once its call has synchronised,
+// so two calls never share one executable graph.  The cache is never
+// destroyed: graphs left in it at exit are reclaimed with the process.
+struct DDExec {
+  std::string key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool launched = false;
+  // the lane streams and fork/join events of the capture: a graph captured
+  // across streams must not outlive them, so they live as long as it does
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+constexpr size_t kDDGraphCache = 8;
+std::mutex g_ddg_mu;
+std::vector<DDExec>* g_ddg = new std::vector<DDExec>();  // least recently used first
+
+void dd_exec_destroy(DDExec& x) {
+  if (x.exec) (void)hipGraphExecDestroy(x.exec);
+  if (x.graph) (void)hipGraphDestroy(x.graph);
+  for (hipStream_t s : x.streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : x.events) (void)hipEventDestroy(e);
+  x = DDExec();
+}
+
+bool dd_graph_take(const std::string& key, DDExec& out) {
+  std::lock_guard<std::mutex> lk(g_ddg_mu);
+  for (size_t i = 0; i < g_ddg->size(); ++i)
+    if ((*g_ddg)[i].key == key) {
+      out = (*g_ddg)[i];
+      g_ddg->erase(g_ddg->begin() + (ptrdiff_t)i);
+      return true;
+    }
+  return false;
+}
+
+void dd_graph_put(DDExec& x) {
+  std::lock_guard<std::mutex> lk(g_ddg_mu);
+  g_ddg->push_back(x);
+  x = DDExec();
+  while (g_ddg->size() > kDDGraphCache) {
+    dd_exec_destroy(g_ddg->front());
+    g_ddg->erase(g_ddg->begin());
+  }
+}
+
+std::string dd_graph_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p, int recursions,
+                         void* const* bins, const void* ws, int64_t total, int lanes, int64_t big) {
+  std::string k;
+  auto put = [&](const void* d, size_t n) { k.append(static_cast<const char*>(d), n); };
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  put(&dev, sizeof dev);
+  put(&n_inst, sizeof n_inst);
+  put(&p.prec, sizeof p.prec);
+  put(&p.R, sizeof p.R);
+  put(&recursions, sizeof recursions);
+  put(&ws, sizeof ws);
+  put(&total, sizeof total);
+  put(&lanes, sizeof lanes);
+  put(&big, sizeof big);
+  for (int i = 0; i < n_inst; ++i) {
+    const cq_dd_instance& in = inst[i];
+    put(&in.n_sub, sizeof in.n_sub);
+    for (int c = 0; c < in.n_sub; ++c) {
+      const cq_subcircuit& sc = in.subs[c];
+      put(&sc.width, sizeof sc.width);
+      put(sc.init_cut, sizeof(int32_t) * (size_t)sc.width);
+      put(sc.meas_cut, sizeof(int32_t) * (size_t)sc.width);
+      put(&in.entries[c], sizeof(const double*));
+      put(&in.active[c], 8);
+      put(&in.merged[c], 8);
+      put(&in.fixed[c], 8);
+      put(&in.fixed_vals[c], 8);
+      put(&in.max_active[c], 4);
+    }
+  }
+  const int has_bins = bins ? 1 : 0;
+  put(&has_bins, sizeof has_bins);
+  if (bins) put(bins, sizeof(void*) * (size_t)n_inst * (size_t)p.R);
+  return k;
+}
+
+// The graph a call launches; once `stream` has drained it goes back to the
+// cache (kept) or is destroyed (on failure).
+struct DDGraph {
+  hipStream_t stream = nullptr;
+  DDExec ex;
+  bool launched = false, keep = false;
   ~DDGraph() {
     if (launched) (void)hipStreamSynchronize(stream);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    if (ex.exec && keep) dd_graph_put(ex);
+    else dd_exec_destroy(ex);
   }
 };
 
-// Captures the batch on a private stream and launches it once on `stream`.
+// Launches the batch as one graph on `stream`: the cached one for this key,
+// or one captured on a private stream and instantiated now.
 cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions,
                        const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                       int64_t big, int lanes, hipStream_t stream, DDGraph& G, DDLaneSet& ls) {
-  hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) return hip_fail(e, "capture stream");
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    return hip_fail(e, "begin capture");
+                       int64_t big, int lanes, const std::string& key, hipStream_t stream, DDGraph& G,
+                       DDLaneSet& ls) {
+  hipError_t e;
+  if (!dd_graph_take(key, G.ex)) {
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hip_fail(e, "begin capture");
+    }
+    cq_status st = dd_enqueue_all(n_inst, p, recursions, plans, bins_user, ws, big, lanes, cs, ls);
+    e = hipStreamEndCapture(cs, &G.ex.graph);
+    // the graph owns the capture stream and the lane streams and events from
+    // here on (released with it)
+    G.ex.streams.swap(ls.streams);
+    G.ex.events.swap(ls.events);
+    G.ex.streams.push_back(cs);
+    if (st != CQ_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&G.ex.exec, G.ex.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    G.ex.key = key;
   }
-  cq_status st = dd_enqueue_all(n_inst, p, recursions, plans, bins_user, ws, big, lanes, cs, ls);
-  e = hipStreamEndCapture(cs, &G.graph);
-  (void)hipStreamDestroy(cs);
-  if (st != CQ_OK) return st;
-  if (e != hipSuccess) return hip_fail(e, "end capture");
-  e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
   G.stream = stream;
-  e = hipGraphLaunch(G.exec, stream);
+  e = hipGraphLaunch(G.ex.exec, stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
   G.launched = true;
   return CQ_OK;
@@ -984,36 +1131,39 @@ cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_p
           return fail(CQ_ERR_ARG, "null bin buffer");
   if (fault_injected("dd")) return fail(CQ_ERR_HIP, "injected fault before launch");
   char* ws = static_cast<char*>(workspace);
-  const DDCtrl L = dd_ctrl(params->R);
-  // device programs (host images stay alive until the final synchronisation)
-  char* ctrl0 = ws + (int64_t)lanes * align256(big);
-  std::vector<DDProgram> progs(n_inst);
+  const DDAreas A = dd_areas(ws, n_inst, params->R, lanes, big);
+  // every instance's device program, uploaded with one copy
+  std::vector<char> upload((size_t)(n_inst * A.prog_stride), 0);
   for (int i = 0; i < n_inst; ++i) {
-    dd_program(plans[i], inst[i], *params, ws + (int64_t)(i % lanes) * align256(big), progs[i]);
-    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
-    hipError_t e = hipMemcpyAsync(ctrl + L.prog, &progs[i], sizeof(DDProgram), hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "program upload");
+    DDProgram prog;
+    dd_program(plans[i], inst[i], *params, ws + (int64_t)(i % lanes) * align256(big), prog);
+    std::memcpy(upload.data() + (size_t)i * A.prog_stride, &prog, sizeof(DDProgram));
   }
+  hipError_t e = hipMemcpyAsync(A.upload, upload.data(), upload.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "program upload");
   DDLaneSet lane_set;  // destroyed after the graph (declared first)
   DDGraph graph;
   if (params->launch == CQ_DD_GRAPH)
-    st = dd_run_graph(n_inst, *params, recursions, plans, bins, ws, big, lanes, stream, graph, lane_set);
+    st = dd_run_graph(n_inst, *params, recursions, plans, bins, ws, big, lanes,
+                      dd_graph_key(n_inst, inst, *params, recursions, bins, ws, total, lanes, big), stream,
+                      graph, lane_set);
   else
     st = dd_enqueue_all(n_inst, *params, recursions, plans, bins, ws, big, lanes, stream, lane_set);
   if (st != CQ_OK) return st;
-  std::vector<int32_t> done(n_inst, 0);
-  for (int i = 0; i < n_inst; ++i) {
-    char* ctrl = ctrl0 + (int64_t)i * L.bytes;
-    hipError_t e = hipMemcpyAsync(records + (size_t)i * params->R, ctrl + L.recs,
-                                  sizeof(cq_dd_record) * params->R, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&done[i], ctrl + L.state + offsetof(DDState, done), sizeof(int32_t),
-                         hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(e, "record readback");
-  }
-  hipError_t e = hipStreamSynchronize(stream);
+  // the gathered records and counts of all instances, read back with one copy
+  std::vector<char> back((size_t)(n_inst * A.gather_stride));
+  e = hipMemcpyAsync(back.data(), A.gather, back.size(), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "record readback");
+  e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "synchronise");
-  for (int i = 0; i < n_inst; ++i) recursions_done[i] = done[i];
+  graph.keep = true;
+  for (int i = 0; i < n_inst; ++i) {
+    const char* b = back.data() + (size_t)i * A.gather_stride;
+    std::memcpy(records + (size_t)i * params->R, b, (size_t)A.rec_bytes);
+    int32_t done = 0;
+    std::memcpy(&done, b + A.rec_bytes, sizeof done);
+    recursions_done[i] = done;
+  }
   return CQ_OK;
 }
 

@@ -890,6 +890,29 @@ __global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* gst, 
 
 }  // namespace
 
+// Block b copies `words` 32-bit words from src + b * src_stride to
+// dst + b * dst_stride (strides in bytes): programs from the upload area into
+// the control blocks, and records out of them into one readback block.
+__global__ void __launch_bounds__(256) dd_copy_kernel(const char* __restrict__ src, int64_t src_stride,
+                                                      char* __restrict__ dst, int64_t dst_stride,
+                                                      int64_t words) {
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(src + (int64_t)blockIdx.x * src_stride);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst + (int64_t)blockIdx.x * dst_stride);
+  for (int64_t w = threadIdx.x; w < words; w += blockDim.x) d[w] = s[w];
+}
+
+hipError_t launch_dd_copy(const void* src, int64_t src_stride, void* dst, int64_t dst_stride,
+                          int64_t bytes, int blocks, hipStream_t stream) {
+  if (blocks <= 0 || bytes <= 0) return hipSuccess;
+  if ((bytes & 3) || (src_stride & 3) || (dst_stride & 3) || (reinterpret_cast<uintptr_t>(src) & 3) ||
+      (reinterpret_cast<uintptr_t>(dst) & 3))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dd_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     static_cast<const char*>(src), src_stride, static_cast<char*>(dst), dst_stride,
+                     bytes / 4);
+  return hipGetLastError();
+}
+
 hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
                           hipStream_t stream) {
   hipLaunchKernelGGL(dd_init_kernel, dim3(1), dim3(256), 0, stream, st, recs, R, init);

@@ -405,6 +405,10 @@ struct DDInit {
 };
 
 // State <- recursion-0 masks, list empty, records zeroed.
+// `blocks` copies of `bytes` (a multiple of 4, 4-byte aligned) between
+// strided regions of device memory.
+hipError_t launch_dd_copy(const void* src, int64_t src_stride, void* dst, int64_t dst_stride,
+                          int64_t bytes, int blocks, hipStream_t stream);
 hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
                           hipStream_t stream);
 // Descriptors of recursion r from the state; `bins` receives its bins.

@@ -413,3 +413,33 @@ def test_hand_worked_bfs(prec):
             (w["active"], w["merged"], w["fixed"], w["fixed_vals"]), k
         assert nd["total"] == w["total"], k
         assert [[v, b] for (v, _, b) in nd["list"]] == w["candidates"], k
+
+
+def test_graph_cache_reuse_and_eviction():
+    """A batch repeated with the same launch parameters reuses its
+    instantiated graph (same records); batches with other parameters fill the
+    cache past its capacity, evicting graphs captured across parallel lanes;
+    the first batch then runs again (captured anew) with the same records."""
+    m = cq()
+    ws_keep = []
+
+    def batch(seed):
+        insts = []
+        for i, (bonds, ns) in enumerate([([2, 1], [5, 6, 4]), ([1, 1, 1], [4, 3, 4, 3]), ([0, 2], [4, 5, 5])]):
+            cm, E = syn.chain_instance(seed + i, bonds, ns)
+            M = [2] * len(ns)
+            insts.append(instance(cm, E, dd.initial_states(cm, M), M))
+        return insts
+
+    first = batch(300)
+    ws = torch.empty(m.cq_dd_workspace_size(first, "fp32", 4), dtype=torch.uint8, device=DEV)
+    ref = m.cq_reconstruct_dd(first, "fp32", 4, workspace=ws)
+    again = m.cq_reconstruct_dd(first, "fp32", 4, workspace=ws)
+    assert again == ref
+    for k in range(12):  # more distinct multi-lane batches than the cache keeps
+        other = batch(310 + 3 * k)
+        w = torch.empty(m.cq_dd_workspace_size(other, "fp32", 3), dtype=torch.uint8, device=DEV)
+        ws_keep.append(w)
+        m.cq_reconstruct_dd(other, "fp32", 3, workspace=w)
+    torch.cuda.synchronize()
+    assert m.cq_reconstruct_dd(first, "fp32", 4, workspace=ws) == ref
