@@ -404,7 +404,7 @@ def dd_leg(torch, cq, forms, runs):
             times.append(a.elapsed_time(b))
         del ws
         ms = sorted(times)[len(times) // 2]
-        flops, bins = 0.0, 0
+        flops, bins, tiles, tiles_run = 0.0, 0, 0, 0
         plans = {}
         for inst, rr in zip(insts, recs):
             for rec in rr:
@@ -414,13 +414,20 @@ def dd_leg(torch, cq, forms, runs):
                     plans[key] = cq.cq_plan_json(inst["subs"], f, out_bits=na)["flops"]
                 flops += plans[key]
                 bins += 2 ** rec["n_active"]
+                tiles += rec["tiles"]
+                tiles_run += rec["tiles_run"]
         lists = [[(e[1], e[2]) for e in rr[-1]["list"]] for rr in recs]
         if ref_lists is None:
             ref_lists = lists
+        # bins and flops count every bin of every recursion (the full plan);
+        # tile pruning evaluates only tiles_run of the selecting step's tiles,
+        # so the rates below are effective rates, not work done
         out["forms"][f] = {"ms_per_batch": round(ms, 3), "recursions": int(sum(done)),
-                           "bins": bins, "bins_per_s": bins / (ms * 1e-3),
-                           "algorithmic_flops": flops,
-                           "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                           "bins": bins, "effective_bins_per_s": bins / (ms * 1e-3),
+                           "full_plan_flops": flops,
+                           "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                           "selecting_step_tiles": tiles, "selecting_step_tiles_run": tiles_run,
+                           "fraction_of_tiles_run": round(tiles_run / tiles, 5) if tiles else None,
                            "same_zoom_path_as_first_form": lists == ref_lists}
     # breadth-first query on the first instance: levels of nodes with 2^32
     # bins each, every level one batched call
@@ -437,7 +444,7 @@ def dd_leg(torch, cq, forms, runs):
     bins = sum(2 ** nd["n_active"] for nd in nodes)
     out["bfs"] = {"precision": f, "levels": DD_BFS_LEVELS, "width": DD_BFS_WIDTH,
                   "nodes": len(nodes), "bins": bins, "ms": round(ms, 3),
-                  "bins_per_s": bins / (ms * 1e-3)}
+                  "effective_bins_per_s": bins / (ms * 1e-3)}
     return out
 
 

@@ -238,6 +238,11 @@ typedef struct cq_dd_record {  /* one recursion, written by the library */
   int32_t list_rec[CQ_MAX_DD_R];
   uint64_t list_bin[CQ_MAX_DD_R];
   int32_t popped;               /* 1 when a bin was popped */
+  int64_t tiles;                /* 128 x 128 output tiles of the contraction step that selects
+                                   the candidate bins in its epilogue (0 when bins are stored) */
+  int64_t tiles_run;            /* tile evaluations of that step: the warm-up tiles plus every
+                                   tile whose bound reached the threshold (tile pruning skips
+                                   the others) */
 } cq_dd_record;
 
 /* Workspace: the buffers of the largest instance plus a small control block

@@ -86,6 +86,14 @@ cq_status cq_autotune_enable(int32_t mode);
  * Always CQ_OK. */
 cq_status cq_label_balance_enable(int32_t mode);
 
+/* Parallel lanes of cq_reconstruct_dd (instances whose bins stay inside
+ * the contraction run on up to this many streams forked from the caller's,
+ * each with its own copy of the per-instance buffers).  lanes <= 0 restores
+ * the default (4); larger values are capped at 8.  Process-wide; it changes
+ * what cq_dd_workspace_size reports, so query the size after setting it.
+ * Always CQ_OK. */
+cq_status cq_dd_lanes(int32_t lanes);
+
 /* The cached choices as JSON:
  *   [{"prec": ..., "M", "N", "K", "Z", "variant": v, "ms": [[v, ms], ...]}, ...]
  * *needed receives the length including the terminating NUL; with buf null

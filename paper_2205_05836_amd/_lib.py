@@ -18,7 +18,7 @@ MAX_DD_R = 16
 FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
-            "cq_label_balance_enable",
+            "cq_label_balance_enable", "cq_dd_lanes",
             "cq_autotune_json",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
@@ -57,7 +57,8 @@ class cq_dd_record(C.Structure):
                 ("fixed_vals", C.c_uint64 * MAX_SUBCIRCUITS),
                 ("n_active", C.c_int32), ("total", C.c_double), ("n_list", C.c_int32),
                 ("list_val", C.c_double * MAX_DD_R), ("list_rec", C.c_int32 * MAX_DD_R),
-                ("list_bin", C.c_uint64 * MAX_DD_R), ("popped", C.c_int32)]
+                ("list_bin", C.c_uint64 * MAX_DD_R), ("popped", C.c_int32),
+                ("tiles", C.c_int64), ("tiles_run", C.c_int64)]
 
 
 class cq_dd_bfs_params(C.Structure):
@@ -157,6 +158,8 @@ def lib():
     L.cq_autotune_enable.argtypes = [C.c_int32]
     L.cq_label_balance_enable.restype = st
     L.cq_label_balance_enable.argtypes = [C.c_int32]
+    L.cq_dd_lanes.restype = st
+    L.cq_dd_lanes.argtypes = [C.c_int32]
     L.cq_autotune_json.restype = st
     L.cq_autotune_json.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.cq_profile_read.restype = st

@@ -236,7 +236,7 @@ def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, st
                 fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
                 n_active=rc.n_active, total=rc.total,
                 list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],
-                popped=bool(rc.popped)))
+                popped=bool(rc.popped), tiles=rc.tiles, tiles_run=rc.tiles_run))
         out.append(rows)
     return out, list(done)
 
@@ -246,7 +246,7 @@ def _record_dict(rc, ns):
                 fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
                 n_active=rc.n_active, total=rc.total,
                 list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],
-                popped=bool(rc.popped))
+                popped=bool(rc.popped), tiles=rc.tiles, tiles_run=rc.tiles_run)
 
 
 def cq_dd_bfs_workspace_size(instance, prec="fp64", levels=2, width=4):
@@ -449,6 +449,12 @@ def cq_label_balance_enable(mode=1):
     """Per-label balance of the 16-bit operands: 0 off, 1 FP16 forms
     (default), 2 every 16-bit form."""
     check(lib().cq_label_balance_enable(int(mode)))
+
+
+def cq_dd_lanes(lanes=0):
+    """Parallel lanes of cq_reconstruct_dd (0: the default, 4; at most 8).
+    Query the workspace size after changing it."""
+    check(lib().cq_dd_lanes(int(lanes)))
 
 
 def cq_autotune_json():

@@ -473,26 +473,74 @@ cq_status dd_validate(const cq_dd_instance& in, const cq_dd_params& p, CutMap& c
   return CQ_OK;
 }
 
-// Per-instance plan and the layout of its buffers.  The big buffers (reduced
-// entries, contraction workspace, bin scratch, top-C candidates) are shared
-// by the instances, which run one after another; each instance has its own
-// control block (program, state, descriptors, records).
+// Per-instance plan and the layout of its region: the buffers of its
+// recursions -- top-C selection scratch, reduced entries and their row sums,
+// the contraction workspace and (when bins are stored in scratch) the bins.
+struct DDSel {  // sizes of the top-C selection scratch
+  int64_t cand_cap = 0, seg_a = 0, seg_b = 0, tiles = 0;
+};
+
 struct DDInstancePlan {
   CutMap cm;
   std::vector<DDSub> s0;
   std::vector<int> amax;
   Plan plan;
   SymPlan sp;
-  std::vector<int64_t> ep_off, rs_off;
-  int64_t plan_off = 0, bins_off = 0, bins_bytes = 0, cand_off = 0, cand_cap = 0;
   int topc_step = -1;  // the GEMM that selects top-C instead of storing bins, or -1
-  int64_t stage_off = 0;
+  int64_t max_count = 0, bins_bytes = 0;
+  std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
+  DDSel sel;                      // this instance's own selection sizes
+  // region layout (dd_layout): offsets, and the selection sizes laid out
+  int64_t cand_off = 0, cand_cap = 0, stage_off = 0;
   int64_t seg_a = 0, seg_b = 0, bound_a_off = 0, bound_b_off = 0, bound_u_off = 0, list_off = 0;
   int64_t warm_out_off = 0;
-  int64_t big = 0;  // bytes of the shared region this instance needs
-  int64_t max_count = 0;
-  std::vector<int64_t> step_max;  // grid bound per step: tiles or elements
+  std::vector<int64_t> ep_off, rs_off;
+  int64_t plan_off = 0, bins_off = 0;
+  int64_t big = 0;  // bytes of the region
 };
+
+// Offsets of the region's buffers for selection sizes `s` (the instance's own,
+// or the largest of the instances advanced together with it, so that every
+// instance of such a group has the selection buffers at the same offsets).
+void dd_layout(DDInstancePlan& D, const DDSel& s) {
+  const CutMap& cm = D.cm;
+  int64_t off = 0;
+  D.cand_cap = s.cand_cap;
+  D.cand_off = off;
+  off = align256(off + s.cand_cap * 16);  // values, then indices
+  D.stage_off = off;  // fused top-C: keys staged between the two selection passes
+  off = align256(off + (int64_t)kTopcStage * kDDMaxC * 16);
+  D.seg_a = s.seg_a;
+  D.seg_b = s.seg_b;
+  if (D.topc_step >= 0) {
+    // tile pruning buffers of the top-C GEMM, sized for the largest shape
+    D.bound_a_off = off;
+    off = align256(off + s.seg_a * 4);
+    D.bound_b_off = off;
+    off = align256(off + s.seg_b * 4);
+    D.bound_u_off = off;
+    off = align256(off + s.tiles * 4);
+    D.list_off = off;
+    off = align256(off + s.tiles * 8);
+    D.warm_out_off = off;
+    off = align256(off + kDDMaxC * 16);
+  }
+  D.ep_off.clear();
+  D.rs_off.clear();
+  for (int c = 0; c < cm.n_sub; ++c) {
+    D.ep_off.push_back(off);
+    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * ((int64_t)1 << D.amax[c]) * 8);
+  }
+  for (int c = 0; c < cm.n_sub; ++c) {
+    D.rs_off.push_back(off);
+    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * 8);
+  }
+  D.plan_off = off;
+  off = align256(off + D.plan.workspace_bytes);
+  D.bins_off = off;
+  off += D.bins_bytes;
+  D.big = align256(off);
+}
 
 struct DDCtrl {
   int64_t prog = 0, state = 0, level = 0, recs = 0, bytes = 0;
@@ -506,33 +554,6 @@ DDCtrl dd_ctrl(int R) {
   c.recs = align256(c.level + (int64_t)sizeof(DDLevel));
   c.bytes = align256(c.recs + (int64_t)R * (int64_t)sizeof(cq_dd_record));
   return c;
-}
-
-// Beyond the control blocks: the programs of all instances back to back (one
-// upload per call; a copy kernel at the head of the batch moves each into its
-// control block) and the readback block (records and recursion count of every
-// instance back to back, gathered by a copy kernel at the tail of the batch).
-struct DDAreas {
-  char* ctrl0;
-  char* upload;
-  char* gather;
-  int64_t prog_stride, rec_bytes, gather_stride, bytes;
-};
-
-DDAreas dd_areas(char* ws, int n_inst, int R, int lanes, int64_t big) {
-  DDAreas A;
-  const DDCtrl L = dd_ctrl(R);
-  A.prog_stride = ((int64_t)sizeof(DDProgram) + 15) / 16 * 16;
-  A.rec_bytes = (int64_t)R * (int64_t)sizeof(cq_dd_record);
-  A.gather_stride = (A.rec_bytes + 8 + 15) / 16 * 16;  // records, then the int32 count
-  const int64_t ctrl = (int64_t)lanes * align256(big);
-  const int64_t up = ctrl + (int64_t)n_inst * L.bytes;
-  const int64_t ga = up + align256((int64_t)n_inst * A.prog_stride);
-  A.bytes = ga + align256((int64_t)n_inst * A.gather_stride);
-  A.ctrl0 = ws ? ws + ctrl : nullptr;
-  A.upload = ws ? ws + up : nullptr;
-  A.gather = ws ? ws + ga : nullptr;
-  return A;
 }
 
 cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool bins_stored,
@@ -554,19 +575,6 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   for (const Step& s : D.plan.steps)
     if (!s.is_gemm && (int)s.p.log2.size() > kDDMaxPermAxes)
       return fail(CQ_ERR_UNSUPPORTED, "bin contraction permute has too many axes");
-  int64_t off = 0;
-  D.ep_off.clear();
-  D.rs_off.clear();
-  for (int c = 0; c < cm.n_sub; ++c) {
-    D.ep_off.push_back(off);
-    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * ((int64_t)1 << D.amax[c]) * 8);
-  }
-  for (int c = 0; c < cm.n_sub; ++c) {
-    D.rs_off.push_back(off);
-    off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * 8);
-  }
-  D.plan_off = off;
-  off = align256(off + D.plan.workspace_bytes);
   D.max_count = (int64_t)1 << sum_a;
   D.step_max.clear();
   for (const Step& s : D.plan.steps) {
@@ -587,55 +595,169 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   D.topc_step = -1;
   if (!bins_stored && last.is_gemm && D.plan.tensors[last.g.c].loc == Loc::Out)
     D.topc_step = (int)D.plan.steps.size() - 1;
-  D.bins_off = off;
   D.bins_bytes = (bins_stored || D.topc_step >= 0) ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
-  off += D.bins_bytes;
-  D.cand_off = off;
-  D.cand_cap = D.topc_step >= 0 ? D.step_max[D.topc_step] * C_max
-                                : topk_indirect_capacity(D.max_count, C_max);
-  off = align256(off + D.cand_cap * 16);
-  D.stage_off = off;  // fused top-C: keys staged between the two selection passes
-  off = align256(off + (int64_t)kTopcStage * kDDMaxC * 16);  // values, then indices
+  D.sel = DDSel();
   if (D.topc_step >= 0) {
-    // tile pruning buffers of the top-C GEMM, sized for the largest shape
     const GemmStep& g = D.plan.steps[D.topc_step].g;
-    D.seg_a = (g.sAz ? g.Z : 1) * g.K * ((g.M + 127) / 128);
-    D.seg_b = (g.sBz ? g.Z : 1) * g.K * ((g.N + 127) / 128);
-    const int64_t tiles = D.step_max[D.topc_step];
-    D.bound_a_off = off;
-    off = align256(off + D.seg_a * 4);
-    D.bound_b_off = off;
-    off = align256(off + D.seg_b * 4);
-    D.bound_u_off = off;
-    off = align256(off + tiles * 4);
-    D.list_off = off;
-    off = align256(off + tiles * 8);
-    D.warm_out_off = off;
-    off = align256(off + kDDMaxC * 16);
+    D.sel.tiles = D.step_max[D.topc_step];
+    D.sel.cand_cap = D.sel.tiles * C_max;
+    D.sel.seg_a = (g.sAz ? g.Z : 1) * g.K * ((g.M + 127) / 128);
+    D.sel.seg_b = (g.sBz ? g.Z : 1) * g.K * ((g.N + 127) / 128);
+  } else {
+    D.sel.cand_cap = topk_indirect_capacity(D.max_count, C_max);
   }
-  D.big = off;
+  dd_layout(D, D.sel);
   return CQ_OK;
 }
 
-// Instances run on `lanes` parallel streams (graph branches) when none of
-// them stores bins: each lane then has its own copy of the shared region,
-// which is small without bin scratch.  Otherwise they run one after another.
+DType tensor_dtype(const Plan& plan, int t, cq_precision prec) {
+  const TensorRef& T = plan.tensors[t];
+  if (T.loc == Loc::Out) return out_dtype(prec);
+  if (T.loc == Loc::Input && plan.input_offset[T.index] < 0) return DType::F64;
+  return work_dtype(prec);
+}
+
+// Instances whose launches can be shared: the same subcircuit count and the
+// same step sequence with the same operand formats (their sizes may differ;
+// the launches are sized for the largest).
+std::string dd_signature(const DDInstancePlan& D, cq_precision prec) {
+  std::string k;
+  auto put = [&](int v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
+  put(D.cm.n_sub);
+  put((int)D.plan.steps.size());
+  put(D.topc_step);
+  for (const Step& s : D.plan.steps) {
+    put(s.is_gemm ? 1 : 0);
+    if (s.is_gemm) {
+      put((int)tensor_dtype(D.plan, s.g.a, prec));
+      put((int)tensor_dtype(D.plan, s.g.b, prec));
+      put((int)tensor_dtype(D.plan, s.g.c, prec));
+    } else {
+      put((int)tensor_dtype(D.plan, s.p.src, prec));
+      put((int)tensor_dtype(D.plan, s.p.dst, prec));
+    }
+  }
+  return k;
+}
+
+// How a batch runs.  When every instance keeps its bins inside the
+// contraction (no bin buffers), instances with one signature form a group
+// that advances in lockstep: recursion r of all of them is one launch per
+// kernel, grid z running over the group.  Each instance then owns a slot --
+// its control block, then its region -- of one size, and a group's slots are
+// consecutive, so instance z's arguments and buffers are instance 0's moved by
+// z slots.  Groups spread over up to `lanes` streams.  Otherwise the instances
+// run one after another on one region, each with its own control block.
+struct DDBatch {
+  bool lockstep = false;
+  std::vector<std::vector<int>> groups;  // lockstep: instances of each group, in slot order
+  std::vector<int> slot_of;              // instance -> slot (control block index otherwise)
+  int lanes = 1;
+  int64_t slot = 0;   // lockstep: bytes per slot
+  int64_t big = 0;    // otherwise: bytes of the shared region
+  int64_t total = 0;  // workspace bytes
+};
+
+// Beyond the slots (or the shared region and the control blocks): the
+// programs of all instances back to back in slot order (one upload per call;
+// a copy kernel at the head of the batch moves each into its control block)
+// and the readback block (records and recursion count of every slot back to
+// back, gathered by a copy kernel at the tail of the batch).
+struct DDAreas {
+  char* ctrl0;
+  int64_t ctrl_stride;
+  char* region0;
+  int64_t region_stride;
+  char* upload;
+  char* gather;
+  int64_t prog_stride, rec_bytes, gather_stride, bytes;
+  char* ctrl(int k) const { return ctrl0 + (int64_t)k * ctrl_stride; }
+  char* region(int k) const { return region0 + (int64_t)k * region_stride; }
+};
+
+DDAreas dd_areas(char* ws, int n_inst, int R, const DDBatch& B) {
+  DDAreas A;
+  const DDCtrl L = dd_ctrl(R);
+  A.prog_stride = ((int64_t)sizeof(DDProgram) + 15) / 16 * 16;
+  A.rec_bytes = (int64_t)R * (int64_t)sizeof(cq_dd_record);
+  A.gather_stride = (A.rec_bytes + 8 + 15) / 16 * 16;  // records, then the int32 count
+  int64_t ctrl, region, up;
+  if (B.lockstep) {
+    ctrl = 0;
+    region = L.bytes;
+    A.ctrl_stride = A.region_stride = B.slot;
+    up = (int64_t)n_inst * B.slot;
+  } else {
+    region = 0;
+    ctrl = align256(B.big);
+    A.ctrl_stride = L.bytes;
+    A.region_stride = 0;
+    up = ctrl + (int64_t)n_inst * L.bytes;
+  }
+  const int64_t ga = up + align256((int64_t)n_inst * A.prog_stride);
+  A.bytes = ga + align256((int64_t)n_inst * A.gather_stride);
+  A.ctrl0 = ws ? ws + ctrl : nullptr;
+  A.region0 = ws ? ws + region : nullptr;
+  A.upload = ws ? ws + up : nullptr;
+  A.gather = ws ? ws + ga : nullptr;
+  return A;
+}
+
 constexpr int kDDLanes = 4;
+constexpr int kDDMaxLanes = 8;
+std::atomic<int> g_dd_lanes{0};  // 0: kDDLanes
 
 cq_status dd_plan_all(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p,
-                      bool bins_stored, std::vector<DDInstancePlan>& plans, int64_t& big,
-                      int& lanes, int64_t& total) {
+                      bool bins_stored, std::vector<DDInstancePlan>& plans, DDBatch& B) {
   plans.assign(n_inst, DDInstancePlan());
-  big = 0;
+  B = DDBatch();
   bool all_fused = true;
   for (int i = 0; i < n_inst; ++i) {
     cq_status st = dd_plan_instance(inst[i], p, bins_stored, plans[i]);
     if (st != CQ_OK) return st;
-    big = std::max(big, plans[i].big);
     all_fused = all_fused && plans[i].topc_step >= 0;
   }
-  lanes = all_fused ? std::min<int>(n_inst, kDDLanes) : 1;
-  total = dd_areas(nullptr, n_inst, p.R, lanes, big).bytes;
+  B.slot_of.assign(n_inst, 0);
+  if (!all_fused) {
+    for (int i = 0; i < n_inst; ++i) {
+      B.big = std::max(B.big, plans[i].big);
+      B.slot_of[i] = i;
+    }
+  } else {
+    B.lockstep = true;
+    std::vector<std::string> sigs;
+    for (int i = 0; i < n_inst; ++i) {
+      const std::string sg = dd_signature(plans[i], p.prec);
+      size_t g = 0;
+      while (g < sigs.size() && sigs[g] != sg) ++g;
+      if (g == sigs.size()) {
+        sigs.push_back(sg);
+        B.groups.emplace_back();
+      }
+      B.groups[g].push_back(i);
+    }
+    int k = 0;
+    int64_t region = 0;
+    for (const std::vector<int>& G : B.groups) {
+      DDSel s;
+      for (int i : G) {
+        const DDSel& o = plans[i].sel;
+        s.cand_cap = std::max(s.cand_cap, o.cand_cap);
+        s.seg_a = std::max(s.seg_a, o.seg_a);
+        s.seg_b = std::max(s.seg_b, o.seg_b);
+        s.tiles = std::max(s.tiles, o.tiles);
+      }
+      for (int i : G) {
+        dd_layout(plans[i], s);
+        region = std::max(region, plans[i].big);
+        B.slot_of[i] = k++;
+      }
+    }
+    B.slot = dd_ctrl(p.R).bytes + align256(region);
+    const int want = g_dd_lanes.load();
+    B.lanes = std::max(1, std::min<int>((int)B.groups.size(), want > 0 ? want : kDDLanes));
+  }
+  B.total = dd_areas(nullptr, n_inst, p.R, B).bytes;
   return CQ_OK;
 }
 
@@ -648,13 +770,16 @@ SymPow to_dev(const SymQ& q) {
   return s;
 }
 
-// Host image of an instance's device program; pointers refer to `ws`.
+// Host image of an instance's device program; pointers refer to its region
+// `ws` and its control block `ctrl`.
 void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_params& p, char* ws,
-                DDProgram& P) {
+                char* ctrl, DDProgram& P) {
   std::memset(&P, 0, sizeof(P));
   const CutMap& cm = D.cm;
   const Plan& plan = D.plan;
   const DType wt = work_dtype(p.prec);
+  const DDCtrl L = dd_ctrl(p.R);
+  DDState* st = reinterpret_cast<DDState*>(ctrl + L.state);
   P.n_sub = cm.n_sub;
   P.K = cm.K;
   P.R = p.R;
@@ -670,7 +795,26 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
     P.Ep[c] = reinterpret_cast<double*>(ws + D.ep_off[c]);
     P.Rs[c] = reinterpret_cast<double*>(ws + D.rs_off[c]);
     P.prep_dst[c] = -1;
+    P.init.active[c] = D.s0[c].active;
+    P.init.merged[c] = D.s0[c].merged;
+    P.init.fixed[c] = D.s0[c].fixed;
+    P.init.fixed_vals[c] = D.s0[c].fixed_vals;
   }
+  // the recursion total: Eq. 1 over the row sums of the reduced entries, one bin
+  RefineArgs& T = P.total;
+  T.n_sub = cm.n_sub;
+  T.K = cm.K;
+  for (int c = 0; c < cm.n_sub; ++c) {
+    T.Ep[c] = P.Rs[c];
+    T.ld[c] = 1;
+    T.na[c] = 0;
+    T.kc[c] = P.kc[c];
+    for (int j = 0; j < T.kc[c]; ++j) T.cut[c][j] = P.cut[c][j];
+  }
+  T.bins = &st->zero_idx;
+  T.nbins = 1;
+  T.scale = std::ldexp(1.0, -cm.K);
+  T.out = &st->total;
   P.topc_step = D.topc_step;
   P.cand_v = reinterpret_cast<double*>(ws + D.cand_off);
   P.cand_i = reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8);
@@ -742,115 +886,105 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
   }
 }
 
-DType tensor_dtype(const Plan& plan, int t, cq_precision prec) {
-  const TensorRef& T = plan.tensors[t];
-  if (T.loc == Loc::Out) return out_dtype(prec);
-  if (T.loc == Loc::Input && plan.input_offset[T.index] < 0) return DType::F64;
-  return work_dtype(prec);
-}
-
-// Enqueues recursion r of one instance.
-cq_status dd_enqueue_level(const DDInstancePlan& D, const cq_dd_params& p, char* ws, char* ctrl,
-                           int r, void* bins, hipStream_t stream) {
+// Enqueues recursion r of the instances `G` (one, or a lockstep group whose
+// first slot has region `ws` and control block `ctrl`; `span` covers the
+// group).  Grids are sized for the largest member.
+cq_status dd_enqueue_level(const std::vector<const DDInstancePlan*>& G, const cq_dd_params& p,
+                           InstSpan span, char* ws, char* ctrl, int r, void* bins, hipStream_t stream) {
   const DDCtrl L = dd_ctrl(p.R);
+  const DDInstancePlan& D = *G[0];
   const DDProgram* prog = reinterpret_cast<const DDProgram*>(ctrl + L.prog);
   DDState* st = reinterpret_cast<DDState*>(ctrl + L.state);
   DDLevel* lv = reinterpret_cast<DDLevel*>(ctrl + L.level);
   cq_dd_record* recs = reinterpret_cast<cq_dd_record*>(ctrl + L.recs);
-  const CutMap& cm = D.cm;
-  const int ns = cm.n_sub;
+  const int ns = D.cm.n_sub;
   const cq_precision prec = p.prec;
-  hipError_t e = launch_dd_setup(prog, st, lv, recs, r, bins, stream);
+  hipError_t e = launch_dd_setup(prog, st, lv, recs, r, bins, stream, span);
   if (e != hipSuccess) return hip_fail(e, "setup launch");
   int64_t merge_threads = 0, rs_threads = 0, prep_n = 0;
-  for (int c = 0; c < ns; ++c) {
-    const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
-    merge_threads = std::max(merge_threads, (rows << D.amax[c]) << 6);
-    rs_threads = std::max(rs_threads, rows << 6);
-    prep_n = std::max(prep_n, rows << D.amax[c]);
+  std::vector<int64_t> step_max(D.step_max.size(), 0);
+  for (const DDInstancePlan* M : G) {
+    for (int c = 0; c < ns; ++c) {
+      const int64_t rows = (int64_t)1 << (2 * M->cm.subs[c].k());
+      merge_threads = std::max(merge_threads, (rows << M->amax[c]) << 6);
+      rs_threads = std::max(rs_threads, rows << 6);
+      prep_n = std::max(prep_n, rows << M->amax[c]);
+    }
+    for (size_t si = 0; si < step_max.size(); ++si) step_max[si] = std::max(step_max[si], M->step_max[si]);
   }
-  e = launch_merge_indirect(&lv->merge[0], ns, merge_threads, stream);
+  e = launch_merge_indirect(&lv->merge[0], ns, merge_threads, stream, span);
   if (e != hipSuccess) return hip_fail(e, "merge launch");
-  e = launch_merge_indirect(&lv->rowsum[0], ns, rs_threads, stream);
+  e = launch_merge_indirect(&lv->rowsum[0], ns, rs_threads, stream, span);
   if (e != hipSuccess) return hip_fail(e, "row-sum launch");
-  RefineLaunch T;
-  std::memset(&T, 0, sizeof(T));
-  T.n_sub = ns;
-  T.K = cm.K;
-  for (int c = 0; c < ns; ++c) {
-    T.Ep[c] = reinterpret_cast<const double*>(ws + D.rs_off[c]);
-    T.ld[c] = 1;
-    T.kc[c] = cm.subs[c].k();
-    for (int j = 0; j < T.kc[c]; ++j) T.cut[c][j] = cm.subs[c].cuts[j];
-  }
-  T.bins = &st->zero_idx;
-  T.nbins = 1;
-  T.scale = std::ldexp(1.0, -cm.K);
-  T.out = &st->total;
-  e = launch_refine(T, stream);
+  e = launch_refine_indirect(&prog->total, 1, stream, span);
   if (e != hipSuccess) return hip_fail(e, "total launch");
   if (work_dtype(prec) != DType::F64) {
-    e = launch_prep_indirect(&lv->prep[0], ns, work_dtype(prec), is_f16(prec), prep_n, stream);
+    e = launch_prep_indirect(&lv->prep[0], ns, work_dtype(prec), is_f16(prec), prep_n, stream, span);
     if (e != hipSuccess) return hip_fail(e, "operand prep launch");
   }
   for (size_t si = 0; si < D.plan.steps.size(); ++si) {
     const Step& s = D.plan.steps[si];
     if (s.is_gemm && (int)si == D.topc_step) {
       // fused top-C with tile pruning (see launch_tile_bounds)
-      const int64_t tiles = D.step_max[si];
+      const int64_t tiles = step_max[si];
       e = launch_tile_bounds(&lv->gemm[si], tensor_dtype(D.plan, s.g.a, prec), is_f16(prec),
                              reinterpret_cast<float*>((ws + D.bound_a_off)),
                              reinterpret_cast<float*>((ws + D.bound_b_off)),
                              reinterpret_cast<float*>(ws + D.bound_u_off), D.seg_a, D.seg_b,
-                             tiles, stream);
+                             tiles, stream, span);
       if (e == hipSuccess)
         e = launch_tile_warm(reinterpret_cast<const float*>(ws + D.bound_u_off), &st->n_tiles,
                              &st->warm_count, reinterpret_cast<uint64_t*>(ws + D.warm_out_off + kDDMaxC * 8),
-                             (int)std::min<int64_t>(tiles, kDDMaxC), stream);
+                             (int)std::min<int64_t>(tiles, kDDMaxC), stream, span);
       if (e == hipSuccess)
         e = launch_gemm_indirect(prec, &lv->topc_warm, std::min<int64_t>(tiles, kDDMaxC),
-                                 tensor_dtype(D.plan, s.g.c, prec), false, true, stream);
+                                 tensor_dtype(D.plan, s.g.c, prec), false, true, stream, span);
+      if (e == hipSuccess)
+        e = launch_warm_tau(reinterpret_cast<const double*>(ws + D.cand_off), &st->topc_count, &st->C,
+                            &st->topc_thr, stream, span);
       if (e == hipSuccess)
         e = launch_tile_compact(reinterpret_cast<const float*>(ws + D.bound_u_off), &st->n_tiles,
                                 &st->topc_thr, reinterpret_cast<uint64_t*>(ws + D.list_off),
-                                &st->list_count, tiles, stream);
+                                &st->list_count, tiles, stream, span);
       if (e == hipSuccess)
         e = launch_gemm_indirect(prec, &lv->gemm[si], tiles, tensor_dtype(D.plan, s.g.c, prec), false,
-                                 true, stream);
+                                 true, stream, span);
       if (e != hipSuccess) return hip_fail(e, "top-C GEMM launch");
     } else if (s.is_gemm) {
-      e = launch_gemm_indirect(prec, &lv->gemm[si], D.step_max[si], tensor_dtype(D.plan, s.g.c, prec),
-                               false, false, stream);
+      e = launch_gemm_indirect(prec, &lv->gemm[si], step_max[si], tensor_dtype(D.plan, s.g.c, prec), false,
+                               false, stream, span);
       if (e != hipSuccess) return hip_fail(e, "label GEMM launch");
     } else {
       e = launch_permute_indirect(&lv->perm[si], tensor_dtype(D.plan, s.p.src, prec),
-                                  tensor_dtype(D.plan, s.p.dst, prec), is_f16(prec), D.step_max[si],
-                                  stream);
+                                  tensor_dtype(D.plan, s.p.dst, prec), is_f16(prec), step_max[si],
+                                  stream, span);
       if (e != hipSuccess) return hip_fail(e, "permute launch");
     }
   }
-  if (D.topc_step >= 0)
+  if (D.topc_step >= 0) {
     e = launch_topk_candidates(reinterpret_cast<const double*>(ws + D.cand_off),
                                reinterpret_cast<const uint64_t*>(ws + D.cand_off + D.cand_cap * 8),
                                reinterpret_cast<const int64_t*>(&st->topc_count), &st->C,
                                std::min(4 * p.R, kDDMaxC), reinterpret_cast<double*>(ws + D.stage_off),
                                reinterpret_cast<uint64_t*>(ws + D.stage_off + (int64_t)kTopcStage * kDDMaxC * 8),
-                               st->top_val, st->top_idx, stream);
-  else
+                               st->top_val, st->top_idx, stream, span);
+  } else {
+    if (span.n != 1) return fail(CQ_ERR_UNSUPPORTED, "stored bins run one instance at a time");
     e = launch_topk_indirect(bins, out_dtype(prec), &st->count, &st->C, std::min(4 * p.R, kDDMaxC),
                              D.max_count, reinterpret_cast<double*>(ws + D.cand_off),
                              reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8),
                              D.cand_cap, st->top_val, st->top_idx, stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "top-C launch");
-  e = launch_refine_indirect(&lv->refine, std::min(4 * p.R, kDDMaxC), stream);
+  e = launch_refine_indirect(&lv->refine, std::min(4 * p.R, kDDMaxC), stream, span);
   if (e != hipSuccess) return hip_fail(e, "refine launch");
-  e = launch_dd_update(prog, st, recs, r, stream);
+  e = launch_dd_update(prog, st, recs, r, stream, span);
   if (e != hipSuccess) return hip_fail(e, "update launch");
   return CQ_OK;
 }
 
-// Streams and events of the parallel lanes; released after the call's final
-// synchronisation.
+// Streams and events of the parallel lanes; released with the graph that
+// captured them, or after the call's final synchronisation.
 struct DDLaneSet {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
@@ -860,107 +994,111 @@ struct DDLaneSet {
   }
 };
 
-cq_status dd_enqueue_instance(int i, const cq_dd_params& p, int recursions, const DDInstancePlan& D,
-                              void* const* bins_user, char* region, char* ctrl, hipStream_t stream) {
+// All recursions of the instances `G` (one instance, or a lockstep group
+// starting at slot k) on `stream`.
+cq_status dd_enqueue_group(const std::vector<int>& G, int k, const cq_dd_params& p, int recursions,
+                           const std::vector<DDInstancePlan>& plans, void* const* bins_user,
+                           const DDAreas& A, InstSpan span, hipStream_t stream) {
   const DDCtrl L = dd_ctrl(p.R);
-  DDInit init;
-  std::memset(&init, 0, sizeof(init));
-  for (int c = 0; c < D.cm.n_sub; ++c) {
-    init.active[c] = D.s0[c].active;
-    init.merged[c] = D.s0[c].merged;
-    init.fixed[c] = D.s0[c].fixed;
-    init.fixed_vals[c] = D.s0[c].fixed_vals;
-  }
-  hipError_t e = launch_dd_init(reinterpret_cast<DDState*>(ctrl + L.state),
-                                reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, init, stream);
+  char* ctrl = A.ctrl(k);
+  char* region = A.region(k);
+  std::vector<const DDInstancePlan*> members;
+  for (int i : G) members.push_back(&plans[i]);
+  hipError_t e = launch_dd_init(reinterpret_cast<const DDProgram*>(ctrl + L.prog),
+                                reinterpret_cast<DDState*>(ctrl + L.state),
+                                reinterpret_cast<cq_dd_record*>(ctrl + L.recs), p.R, stream, span);
   if (e != hipSuccess) return hip_fail(e, "init launch");
   for (int r = 0; r < recursions; ++r) {
-    void* bins = bins_user ? bins_user[(size_t)i * p.R + r] : nullptr;
-    if (!bins && D.topc_step < 0) bins = region + D.bins_off;
-    cq_status st = dd_enqueue_level(D, p, region, ctrl, r, bins, stream);
+    void* bins = nullptr;
+    if (G.size() == 1) {
+      const DDInstancePlan& D = plans[G[0]];
+      bins = bins_user ? bins_user[(size_t)G[0] * p.R + r] : nullptr;
+      if (!bins && D.topc_step < 0) bins = region + D.bins_off;
+    }
+    cq_status st = dd_enqueue_level(members, p, span, region, ctrl, r, bins, stream);
     if (st != CQ_OK) return st;
   }
   return CQ_OK;
 }
 
-// Enqueues the batch behind `stream`: lane l runs instances l, l + lanes, ...
-// on a stream of its own forked from and joined back into `stream`.
-cq_status dd_enqueue_lanes(int32_t n_inst, const cq_dd_params& p, int recursions,
-                           const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                           int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls);
-
 // Enqueues the batch behind `stream`: programs into place, every instance's
-// recursions (parallel lanes when there are several), then the records
+// recursions (lockstep groups spread over lanes -- streams forked from and
+// joined back into `stream` -- when there are several), then the records
 // gathered into the readback block.
 cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
                          const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                         int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
+                         const DDBatch& B, hipStream_t stream, DDLaneSet& ls) {
   const DDCtrl L = dd_ctrl(p.R);
-  const DDAreas A = dd_areas(ws, n_inst, p.R, lanes, big);
-  hipError_t e = launch_dd_copy(A.upload, A.prog_stride, A.ctrl0 + L.prog, L.bytes, (int64_t)sizeof(DDProgram),
-                                n_inst, stream);
+  const DDAreas A = dd_areas(ws, n_inst, p.R, B);
+  hipError_t e = launch_dd_copy(A.upload, A.prog_stride, A.ctrl0 + L.prog, A.ctrl_stride,
+                                (int64_t)sizeof(DDProgram), n_inst, stream);
   if (e != hipSuccess) return hip_fail(e, "program scatter");
-  cq_status st = dd_enqueue_lanes(n_inst, p, recursions, plans, bins_user, ws, big, lanes, stream, ls);
-  if (st != CQ_OK) return st;
-  e = launch_dd_copy(A.ctrl0 + L.recs, L.bytes, A.gather, A.gather_stride, A.rec_bytes, n_inst, stream);
+  if (!B.lockstep) {
+    for (int i = 0; i < n_inst; ++i) {
+      cq_status st = dd_enqueue_group({i}, B.slot_of[i], p, recursions, plans, bins_user, A, InstSpan(), stream);
+      if (st != CQ_OK) return st;
+    }
+  } else if (B.lanes <= 1) {
+    int k = 0;
+    for (const std::vector<int>& G : B.groups) {
+      cq_status st = dd_enqueue_group(G, k, p, recursions, plans, nullptr, A, InstSpan{(int)G.size(), B.slot},
+                                      stream);
+      if (st != CQ_OK) return st;
+      k += (int)G.size();
+    }
+  } else {
+    hipEvent_t fork = nullptr;
+    e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "lane event");
+    ls.events.push_back(fork);
+    e = hipEventRecord(fork, stream);
+    if (e != hipSuccess) return hip_fail(e, "lane fork");
+    for (int l = 0; l < B.lanes; ++l) {
+      hipStream_t s = nullptr;
+      e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "lane stream");
+      ls.streams.push_back(s);
+      e = hipStreamWaitEvent(s, fork, 0);
+      if (e != hipSuccess) return hip_fail(e, "lane wait");
+    }
+    int k = 0;
+    for (size_t g = 0; g < B.groups.size(); ++g) {
+      const std::vector<int>& G = B.groups[g];
+      cq_status st = dd_enqueue_group(G, k, p, recursions, plans, nullptr, A, InstSpan{(int)G.size(), B.slot},
+                                      ls.streams[g % (size_t)B.lanes]);
+      if (st != CQ_OK) return st;
+      k += (int)G.size();
+    }
+    for (int l = 0; l < B.lanes; ++l) {
+      hipEvent_t join = nullptr;
+      e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "lane event");
+      ls.events.push_back(join);
+      e = hipEventRecord(join, ls.streams[l]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
+      if (e != hipSuccess) return hip_fail(e, "lane join");
+    }
+  }
+  e = launch_dd_copy(A.ctrl0 + L.recs, A.ctrl_stride, A.gather, A.gather_stride, A.rec_bytes, n_inst, stream);
   if (e == hipSuccess)
-    e = launch_dd_copy(A.ctrl0 + L.state + offsetof(DDState, done), L.bytes, A.gather + A.rec_bytes,
+    e = launch_dd_copy(A.ctrl0 + L.state + offsetof(DDState, done), A.ctrl_stride, A.gather + A.rec_bytes,
                        A.gather_stride, 4, n_inst, stream);
   if (e != hipSuccess) return hip_fail(e, "record gather");
   return CQ_OK;
 }
 
-cq_status dd_enqueue_lanes(int32_t n_inst, const cq_dd_params& p, int recursions,
-                           const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                           int64_t big, int lanes, hipStream_t stream, DDLaneSet& ls) {
-  const DDCtrl L = dd_ctrl(p.R);
-  char* ctrl0 = ws + (int64_t)lanes * align256(big);
-  if (lanes <= 1) {
-    for (int i = 0; i < n_inst; ++i) {
-      cq_status st = dd_enqueue_instance(i, p, recursions, plans[i], bins_user, ws, ctrl0 + (int64_t)i * L.bytes,
-                                         stream);
-      if (st != CQ_OK) return st;
-    }
-    return CQ_OK;
-  }
-  hipEvent_t fork = nullptr;
-  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-  if (e != hipSuccess) return hip_fail(e, "lane event");
-  ls.events.push_back(fork);
-  e = hipEventRecord(fork, stream);
-  if (e != hipSuccess) return hip_fail(e, "lane fork");
-  for (int l = 0; l < lanes; ++l) {
-    hipStream_t s = nullptr;
-    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail(e, "lane stream");
-    ls.streams.push_back(s);
-    e = hipStreamWaitEvent(s, fork, 0);
-    if (e != hipSuccess) return hip_fail(e, "lane wait");
-    char* region = ws + (int64_t)l * align256(big);
-    for (int i = l; i < n_inst; i += lanes) {
-      cq_status st = dd_enqueue_instance(i, p, recursions, plans[i], bins_user, region,
-                                         ctrl0 + (int64_t)i * L.bytes, s);
-      if (st != CQ_OK) return st;
-    }
-    hipEvent_t join = nullptr;
-    e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "lane event");
-    ls.events.push_back(join);
-    e = hipEventRecord(join, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
-    if (e != hipSuccess) return hip_fail(e, "lane join");
-  }
-  return CQ_OK;
-}
-
-// Instantiated batch graphs, reused by later calls that repeat every launch
-// parameter (the key: device, precision, R, recursion count, workspace, bin
-// buffers and each instance's cut map, entry pointers and masks).  An entry in
-// use is taken out of the cache and put back once its call has synchronised,
-// so two calls never share one executable graph.  The cache is never
-// destroyed: graphs left in it at exit are reclaimed with the process.
-struct DDExec {
+// Calls of cq_reconstruct_dd that repeat every argument (the key: device,
+// precision, R, recursion count, launch mode, lane setting, workspace and bin
+// pointers, each instance's cut map, entry pointers and masks) reuse the
+// first one's plans, device programs and, in graph mode, its instantiated
+// graph.  An entry in use is taken out of the cache and put back once its
+// call has synchronised, so two calls never share one.  The cache is never
+// destroyed: entries left in it at exit are reclaimed with the process.
+struct DDCall {
   std::string key;
+  std::vector<DDInstancePlan> plans;
+  DDBatch B;
+  std::vector<char> upload;  // the programs, slot order
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // the lane streams and fork/join events of the capture: a graph captured
@@ -968,59 +1106,66 @@ struct DDExec {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
 };
-constexpr size_t kDDGraphCache = 8;
-std::mutex g_ddg_mu;
-std::vector<DDExec>* g_ddg = new std::vector<DDExec>();  // least recently used first
+constexpr size_t kDDCallCache = 8;
+std::mutex g_ddc_mu;
+std::vector<DDCall>* g_ddc = new std::vector<DDCall>();  // least recently used first
 
-void dd_exec_destroy(DDExec& x) {
+void dd_call_destroy(DDCall& x) {
   if (x.exec) (void)hipGraphExecDestroy(x.exec);
   if (x.graph) (void)hipGraphDestroy(x.graph);
   for (hipStream_t s : x.streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : x.events) (void)hipEventDestroy(e);
-  x = DDExec();
+  x = DDCall();
 }
 
-bool dd_graph_take(const std::string& key, DDExec& out) {
-  std::lock_guard<std::mutex> lk(g_ddg_mu);
-  for (size_t i = 0; i < g_ddg->size(); ++i)
-    if ((*g_ddg)[i].key == key) {
-      out = (*g_ddg)[i];
-      g_ddg->erase(g_ddg->begin() + (ptrdiff_t)i);
+bool dd_call_take(const std::string& key, DDCall& out) {
+  std::lock_guard<std::mutex> lk(g_ddc_mu);
+  for (size_t i = 0; i < g_ddc->size(); ++i)
+    if ((*g_ddc)[i].key == key) {
+      out = std::move((*g_ddc)[i]);
+      g_ddc->erase(g_ddc->begin() + (ptrdiff_t)i);
       return true;
     }
   return false;
 }
 
-void dd_graph_put(DDExec& x) {
-  std::lock_guard<std::mutex> lk(g_ddg_mu);
-  g_ddg->push_back(x);
-  x = DDExec();
-  while (g_ddg->size() > kDDGraphCache) {
-    dd_exec_destroy(g_ddg->front());
-    g_ddg->erase(g_ddg->begin());
+void dd_call_put(DDCall& x) {
+  std::lock_guard<std::mutex> lk(g_ddc_mu);
+  g_ddc->push_back(std::move(x));
+  x = DDCall();
+  while (g_ddc->size() > kDDCallCache) {
+    dd_call_destroy(g_ddc->front());
+    g_ddc->erase(g_ddc->begin());
   }
 }
 
-std::string dd_graph_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p, int recursions,
-                         void* const* bins, const void* ws, int64_t total, int lanes, int64_t big) {
+// The cache key, read straight from the arguments; empty (no caching) when
+// they are not well-formed enough to read -- the planner then reports why.
+std::string dd_call_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p, int recursions,
+                        void* const* bins, const void* ws) {
   std::string k;
+  if (n_inst < 1 || !inst) return k;
   auto put = [&](const void* d, size_t n) { k.append(static_cast<const char*>(d), n); };
   int dev = -1;
   (void)hipGetDevice(&dev);
+  const int lanes = g_dd_lanes.load();
   put(&dev, sizeof dev);
   put(&n_inst, sizeof n_inst);
   put(&p.prec, sizeof p.prec);
   put(&p.R, sizeof p.R);
+  put(&p.launch, sizeof p.launch);
   put(&recursions, sizeof recursions);
   put(&ws, sizeof ws);
-  put(&total, sizeof total);
   put(&lanes, sizeof lanes);
-  put(&big, sizeof big);
   for (int i = 0; i < n_inst; ++i) {
     const cq_dd_instance& in = inst[i];
+    if (in.n_sub < 1 || in.n_sub > CQ_MAX_SUBCIRCUITS || !in.subs || !in.entries || !in.active ||
+        !in.merged || !in.fixed || !in.fixed_vals || !in.max_active)
+      return std::string();
     put(&in.n_sub, sizeof in.n_sub);
     for (int c = 0; c < in.n_sub; ++c) {
       const cq_subcircuit& sc = in.subs[c];
+      if (sc.width < 1 || sc.width > 64 || !sc.init_cut || !sc.meas_cut) return std::string();
       put(&sc.width, sizeof sc.width);
       put(sc.init_cut, sizeof(int32_t) * (size_t)sc.width);
       put(sc.meas_cut, sizeof(int32_t) * (size_t)sc.width);
@@ -1038,27 +1183,26 @@ std::string dd_graph_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd
   return k;
 }
 
-// The graph a call launches; once `stream` has drained it goes back to the
-// cache (kept) or is destroyed (on failure).
-struct DDGraph {
+// The cache entry a call works with; once `stream` has drained it goes back
+// to the cache (kept) or is destroyed (on failure).
+struct DDCallHold {
   hipStream_t stream = nullptr;
-  DDExec ex;
+  DDCall x;
   bool launched = false, keep = false;
-  ~DDGraph() {
+  ~DDCallHold() {
     if (launched) (void)hipStreamSynchronize(stream);
-    if (ex.exec && keep) dd_graph_put(ex);
-    else dd_exec_destroy(ex);
+    if (keep && !x.key.empty()) dd_call_put(x);
+    else dd_call_destroy(x);
   }
 };
 
-// Launches the batch as one graph on `stream`: the cached one for this key,
-// or one captured on a private stream and instantiated now.
-cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions,
-                       const std::vector<DDInstancePlan>& plans, void* const* bins_user, char* ws,
-                       int64_t big, int lanes, const std::string& key, hipStream_t stream, DDGraph& G,
-                       DDLaneSet& ls) {
+// Launches the batch as one graph on `stream`: the entry's graph, or one
+// captured on a private stream and instantiated now.
+cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions, void* const* bins_user, char* ws,
+                       hipStream_t stream, DDCallHold& H, DDLaneSet& ls) {
   hipError_t e;
-  if (!dd_graph_take(key, G.ex)) {
+  DDCall& X = H.x;
+  if (!X.exec) {
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "capture stream");
@@ -1067,23 +1211,22 @@ cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions,
       (void)hipStreamDestroy(cs);
       return hip_fail(e, "begin capture");
     }
-    cq_status st = dd_enqueue_all(n_inst, p, recursions, plans, bins_user, ws, big, lanes, cs, ls);
-    e = hipStreamEndCapture(cs, &G.ex.graph);
+    cq_status st = dd_enqueue_all(n_inst, p, recursions, X.plans, bins_user, ws, X.B, cs, ls);
+    e = hipStreamEndCapture(cs, &X.graph);
     // the graph owns the capture stream and the lane streams and events from
     // here on (released with it)
-    G.ex.streams.swap(ls.streams);
-    G.ex.events.swap(ls.events);
-    G.ex.streams.push_back(cs);
+    X.streams.swap(ls.streams);
+    X.events.swap(ls.events);
+    X.streams.push_back(cs);
     if (st != CQ_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "end capture");
-    e = hipGraphInstantiate(&G.ex.exec, G.ex.graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&X.exec, X.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-    G.ex.key = key;
   }
-  G.stream = stream;
-  e = hipGraphLaunch(G.ex.exec, stream);
+  H.stream = stream;
+  e = hipGraphLaunch(X.exec, stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
-  G.launched = true;
+  H.launched = true;
   return CQ_OK;
 }
 
@@ -1094,11 +1237,10 @@ extern "C" cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* 
                                           size_t* bytes) {
   if (n_inst < 1 || !inst || !params || !bytes) return fail(CQ_ERR_ARG, "null or empty argument");
   std::vector<DDInstancePlan> plans;
-  int64_t big = 0, total = 0;
-  int lanes = 1;
-  cq_status st = dd_plan_all(n_inst, inst, *params, bins_stored != 0, plans, big, lanes, total);
+  DDBatch B;
+  cq_status st = dd_plan_all(n_inst, inst, *params, bins_stored != 0, plans, B);
   if (st != CQ_OK) return st;
-  *bytes = (size_t)total;
+  *bytes = (size_t)B.total;
   return CQ_OK;
 }
 
@@ -1116,39 +1258,45 @@ cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_p
   if (!prec_supported(params->prec)) return fail(CQ_ERR_UNSUPPORTED, "precision not built");
   if (params->launch != CQ_DD_GRAPH && params->launch != CQ_DD_DIRECT)
     return fail(CQ_ERR_ARG, "unknown launch mode");
-  // validate and plan everything before the first launch
-  std::vector<DDInstancePlan> plans;
-  int64_t big = 0, total = 0;
-  int lanes = 1;
-  cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, plans, big, lanes, total);
-  if (st != CQ_OK) return st;
-  if (recursions < 1 || recursions > params->R) return fail(CQ_ERR_ARG, "recursion count out of range");
-  if (!workspace || (int64_t)workspace_bytes < total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
-  if (bins)
-    for (int i = 0; i < n_inst; ++i)
-      for (int r = 0; r < params->R; ++r)
-        if (!bins[(size_t)i * params->R + r] && plans[i].bins_bytes == 0)
-          return fail(CQ_ERR_ARG, "null bin buffer");
-  if (fault_injected("dd")) return fail(CQ_ERR_HIP, "injected fault before launch");
   char* ws = static_cast<char*>(workspace);
-  const DDAreas A = dd_areas(ws, n_inst, params->R, lanes, big);
-  // every instance's device program, uploaded with one copy
-  std::vector<char> upload((size_t)(n_inst * A.prog_stride), 0);
-  for (int i = 0; i < n_inst; ++i) {
-    DDProgram prog;
-    dd_program(plans[i], inst[i], *params, ws + (int64_t)(i % lanes) * align256(big), prog);
-    std::memcpy(upload.data() + (size_t)i * A.prog_stride, &prog, sizeof(DDProgram));
+  DDLaneSet lane_set;  // destroyed after the entry's graph (declared first)
+  DDCallHold H;
+  const std::string key = dd_call_key(n_inst, inst, *params, recursions, bins, ws);
+  if (key.empty() || !dd_call_take(key, H.x)) {
+    // validate and plan everything before the first launch
+    cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, H.x.plans, H.x.B);
+    if (st != CQ_OK) return st;
+    if (recursions < 1 || recursions > params->R) return fail(CQ_ERR_ARG, "recursion count out of range");
+    if (bins)
+      for (int i = 0; i < n_inst; ++i)
+        for (int r = 0; r < params->R; ++r)
+          if (!bins[(size_t)i * params->R + r] && H.x.plans[i].bins_bytes == 0)
+            return fail(CQ_ERR_ARG, "null bin buffer");
+    // every instance's device program (slot order), uploaded with one copy
+    const DDAreas A = dd_areas(ws, n_inst, params->R, H.x.B);
+    H.x.upload.assign((size_t)(n_inst * A.prog_stride), 0);
+    for (int i = 0; i < n_inst; ++i) {
+      const int k = H.x.B.slot_of[i];
+      DDProgram prog;
+      dd_program(H.x.plans[i], inst[i], *params, A.region(k), A.ctrl(k), prog);
+      std::memcpy(H.x.upload.data() + (size_t)k * A.prog_stride, &prog, sizeof(DDProgram));
+    }
+    H.x.key = key;
   }
-  hipError_t e = hipMemcpyAsync(A.upload, upload.data(), upload.size(), hipMemcpyHostToDevice, stream);
+  const DDBatch& B = H.x.B;
+  if (!workspace || (int64_t)workspace_bytes < B.total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
+  if (fault_injected("dd")) return fail(CQ_ERR_HIP, "injected fault before launch");
+  const DDAreas A = dd_areas(ws, n_inst, params->R, B);
+  hipError_t e = hipMemcpyAsync(A.upload, H.x.upload.data(), H.x.upload.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "program upload");
-  DDLaneSet lane_set;  // destroyed after the graph (declared first)
-  DDGraph graph;
-  if (params->launch == CQ_DD_GRAPH)
-    st = dd_run_graph(n_inst, *params, recursions, plans, bins, ws, big, lanes,
-                      dd_graph_key(n_inst, inst, *params, recursions, bins, ws, total, lanes, big), stream,
-                      graph, lane_set);
-  else
-    st = dd_enqueue_all(n_inst, *params, recursions, plans, bins, ws, big, lanes, stream, lane_set);
+  cq_status st;
+  if (params->launch == CQ_DD_GRAPH) {
+    st = dd_run_graph(n_inst, *params, recursions, bins, ws, stream, H, lane_set);
+  } else {
+    st = dd_enqueue_all(n_inst, *params, recursions, H.x.plans, bins, ws, B, stream, lane_set);
+    H.stream = stream;
+    H.launched = true;
+  }
   if (st != CQ_OK) return st;
   // the gathered records and counts of all instances, read back with one copy
   std::vector<char> back((size_t)(n_inst * A.gather_stride));
@@ -1156,9 +1304,9 @@ cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_p
   if (e != hipSuccess) return hip_fail(e, "record readback");
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "synchronise");
-  graph.keep = true;
+  H.keep = true;
   for (int i = 0; i < n_inst; ++i) {
-    const char* b = back.data() + (size_t)i * A.gather_stride;
+    const char* b = back.data() + (size_t)B.slot_of[i] * A.gather_stride;
     std::memcpy(records + (size_t)i * params->R, b, (size_t)A.rec_bytes);
     int32_t done = 0;
     std::memcpy(&done, b + A.rec_bytes, sizeof done);
@@ -1418,6 +1566,11 @@ extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int
 
 extern "C" cq_status cq_label_balance_enable(int32_t mode) {
   g_lbal_mode.store(mode < 0 ? 0 : (mode > 2 ? 2 : mode));
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_dd_lanes(int32_t lanes) {
+  g_dd_lanes.store(lanes <= 0 ? 0 : std::min(lanes, kDDMaxLanes));
   return CQ_OK;
 }
 

@@ -76,9 +76,10 @@ __global__ void __launch_bounds__(256) permute_kernel(PermArgs p) {
   permute_body<SK, DK>(p);
 }
 
+// blockIdx.z selects the instance
 template <int SK, int DK>
-__global__ void __launch_bounds__(256) permute_ind_kernel(const PermArgs* __restrict__ p) {
-  permute_body<SK, DK>(*p);
+__global__ void __launch_bounds__(256) permute_ind_kernel(const PermArgs* __restrict__ p, int64_t slot) {
+  permute_body<SK, DK>(*inst_ptr(p, slot));
 }
 
 // FP64 -> FP32 or 16-bit planes (hi = rn16(x), lo = rn16(x - hi)); with
@@ -106,10 +107,10 @@ __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ sr
   prep_body<DK>(src, dst, dst_lo, n, rexp, cols_log2);
 }
 
-// blockIdx.y selects the argument block
+// blockIdx.y selects the argument block, blockIdx.z the instance
 template <int DK>
-__global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a) {
-  const PrepArgs p = a[blockIdx.y];
+__global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a, int64_t slot) {
+  const PrepArgs p = inst_ptr(a, slot)[blockIdx.y];
   prep_body<DK>(p.src, p.dst, p.dst_lo, p.n);
 }
 
@@ -587,41 +588,41 @@ void permute_dispatch_dst(int dk, dim3 grid, const PermArgs& a, hipStream_t s) {
 }
 
 template <int SK>
-void permute_ind_dispatch_dst(int dk, dim3 grid, const PermArgs* a, hipStream_t s) {
+void permute_ind_dispatch_dst(int dk, dim3 grid, const PermArgs* a, int64_t slot, hipStream_t s) {
   switch (dk) {
-    case kF64: hipLaunchKernelGGL((permute_ind_kernel<SK, kF64>), grid, dim3(256), 0, s, a); break;
-    case kF32: hipLaunchKernelGGL((permute_ind_kernel<SK, kF32>), grid, dim3(256), 0, s, a); break;
-    case kBF16: hipLaunchKernelGGL((permute_ind_kernel<SK, kBF16>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((permute_ind_kernel<SK, kF16>), grid, dim3(256), 0, s, a); break;
+    case kF64: hipLaunchKernelGGL((permute_ind_kernel<SK, kF64>), grid, dim3(256), 0, s, a, slot); break;
+    case kF32: hipLaunchKernelGGL((permute_ind_kernel<SK, kF32>), grid, dim3(256), 0, s, a, slot); break;
+    case kBF16: hipLaunchKernelGGL((permute_ind_kernel<SK, kBF16>), grid, dim3(256), 0, s, a, slot); break;
+    default: hipLaunchKernelGGL((permute_ind_kernel<SK, kF16>), grid, dim3(256), 0, s, a, slot); break;
   }
 }
 
 }  // namespace
 
 hipError_t launch_permute_indirect(const PermArgs* dev, DType ts, DType td, bool f16,
-                                   int64_t max_total, hipStream_t stream) {
-  if (max_total <= 0) return hipSuccess;
-  const dim3 grid(grid_ind(max_total));
+                                   int64_t max_total, hipStream_t stream, InstSpan span) {
+  if (max_total <= 0 || span.n <= 0) return hipSuccess;
+  const dim3 grid(grid_ind(max_total), 1, (unsigned)span.n);
   const int sk = kind_of(ts, f16), dk = kind_of(td, f16);
   switch (sk) {
-    case kF64: permute_ind_dispatch_dst<kF64>(dk, grid, dev, stream); break;
-    case kF32: permute_ind_dispatch_dst<kF32>(dk, grid, dev, stream); break;
-    case kBF16: permute_ind_dispatch_dst<kBF16>(dk, grid, dev, stream); break;
-    default: permute_ind_dispatch_dst<kF16>(dk, grid, dev, stream); break;
+    case kF64: permute_ind_dispatch_dst<kF64>(dk, grid, dev, span.stride, stream); break;
+    case kF32: permute_ind_dispatch_dst<kF32>(dk, grid, dev, span.stride, stream); break;
+    case kBF16: permute_ind_dispatch_dst<kBF16>(dk, grid, dev, span.stride, stream); break;
+    default: permute_ind_dispatch_dst<kF16>(dk, grid, dev, span.stride, stream); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_prep_indirect(const PrepArgs* dev, int count, DType t, bool f16, int64_t max_n,
-                                hipStream_t stream) {
-  if (max_n <= 0 || count <= 0) return hipSuccess;
-  const dim3 grid(grid_ind(max_n), (unsigned)count);
+                                hipStream_t stream, InstSpan span) {
+  if (max_n <= 0 || count <= 0 || span.n <= 0) return hipSuccess;
+  const dim3 grid(grid_ind(max_n), (unsigned)count, (unsigned)span.n);
   if (t == DType::F32)
-    hipLaunchKernelGGL((prep_ind_kernel<kF32>), grid, dim3(256), 0, stream, dev);
+    hipLaunchKernelGGL((prep_ind_kernel<kF32>), grid, dim3(256), 0, stream, dev, span.stride);
   else if (f16)
-    hipLaunchKernelGGL((prep_ind_kernel<kF16>), grid, dim3(256), 0, stream, dev);
+    hipLaunchKernelGGL((prep_ind_kernel<kF16>), grid, dim3(256), 0, stream, dev, span.stride);
   else
-    hipLaunchKernelGGL((prep_ind_kernel<kBF16>), grid, dim3(256), 0, stream, dev);
+    hipLaunchKernelGGL((prep_ind_kernel<kBF16>), grid, dim3(256), 0, stream, dev, span.stride);
   return hipGetLastError();
 }
 

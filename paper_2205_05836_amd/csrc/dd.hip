@@ -9,6 +9,7 @@
 #include <cfloat>
 
 #include "kernels.hpp"
+#include "select.hpp"
 
 namespace cq {
 
@@ -40,20 +41,32 @@ __device__ inline void merge_body(const MergeArgs& a) {
     const uint64_t av = (uint64_t)(out & (((int64_t)1 << a.na) - 1));
     const double* Er = a.E + (row << a.n);
     const uint64_t base = a.fixed_vals_flat | deposit(av, a.active_flat) | deposit((uint64_t)sub, a.merged_lo);
+    // next merged index: increment within the bits of merged_hi
+    auto next = [&](uint64_t x) { return ((x | ~a.merged_hi) + 1) & a.merged_hi; };
     double acc = 0.0;
     uint64_t d = 0;
-    for (int64_t t = 0; t < a.iters; ++t) {
+    int64_t t = 0;
+    for (; t + 4 <= a.iters; t += 4) {  // four loads in flight, added in order
+      const uint64_t d1 = next(d), d2 = next(d1), d3 = next(d2);
+      const double v0 = Er[base | d], v1 = Er[base | d1], v2 = Er[base | d2], v3 = Er[base | d3];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+      d = next(d3);
+    }
+    for (; t < a.iters; ++t) {
       acc += Er[base | d];
-      d = ((d | ~a.merged_hi) + 1) & a.merged_hi;
+      d = next(d);
     }
     for (int s = (1 << a.tpo_log2) >> 1; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
     if (sub == 0) a.Ep[out] = acc;
   }
 }
 
-// blockIdx.y selects the argument block
-__global__ void __launch_bounds__(256) merge_ind_kernel(const MergeArgs* __restrict__ a) {
-  const MergeArgs m = a[blockIdx.y];
+// blockIdx.y selects the argument block, blockIdx.z the instance
+__global__ void __launch_bounds__(256) merge_ind_kernel(const MergeArgs* __restrict__ a, int64_t slot) {
+  const MergeArgs m = inst_ptr(a, slot)[blockIdx.y];
   merge_body(m);
 }
 
@@ -109,10 +122,16 @@ __global__ void __launch_bounds__(256) topk_kernel(const T* __restrict__ vals,
                                                    uint64_t* __restrict__ out_i,
                                                    const int64_t* __restrict__ count_dev,
                                                    const int32_t* __restrict__ C_dev,
-                                                   int out_stride) {
+                                                   int out_stride, int64_t slot) {
   __shared__ Key buf[kTopS];
   __shared__ int cnt;
   __shared__ Key thr;
+  vals = inst_ptr(vals, slot);
+  idxs = inst_ptr(idxs, slot);
+  out_v = inst_ptr(out_v, slot);
+  out_i = inst_ptr(out_i, slot);
+  count_dev = inst_ptr(count_dev, slot);
+  C_dev = inst_ptr(C_dev, slot);
   if (C_dev) C = *C_dev;
   if (C <= 0) return;
   if (count_dev) {
@@ -345,57 +364,37 @@ __device__ inline void refine_body(const RefineArgs& a, double* red) {
   if (threadIdx.x == 0) a.out[blockIdx.x] = a.scale * red[0];
 }
 
-__global__ void __launch_bounds__(256) refine_kernel(RefineArgs a) {
+__global__ void __launch_bounds__(256) refine_ind_kernel(const RefineArgs* __restrict__ a, int64_t slot) {
   __shared__ double red[256];
-  refine_body(a, red);
-}
-
-__global__ void __launch_bounds__(256) refine_ind_kernel(const RefineArgs* __restrict__ a) {
-  __shared__ double red[256];
-  refine_body(*a, red);
+  refine_body(*inst_ptr(a, slot), red);
 }
 
 }  // namespace
 
-hipError_t launch_refine(const RefineLaunch& r, hipStream_t stream) {
-  RefineArgs a;
-  a.n_sub = r.n_sub;
-  a.K = r.K;
-  for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
-    a.Ep[c] = r.Ep[c];
-    a.ld[c] = r.ld[c];
-    a.na[c] = r.na[c];
-    a.kc[c] = r.kc[c];
-    for (int j = 0; j < CQ_MAX_LOCAL_CUTS; ++j) a.cut[c][j] = r.cut[c][j];
-  }
-  a.bins = r.bins;
-  a.nbins = r.nbins;
-  a.scale = r.scale;
-  a.out = r.out;
-  if (r.nbins <= 0) return hipSuccess;
-  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)r.nbins), dim3(256), 0, stream, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_merge_indirect(const MergeArgs* dev, int count, int64_t max_threads,
-                                 hipStream_t stream) {
-  if (count <= 0 || max_threads <= 0) return hipSuccess;
+                                 hipStream_t stream, InstSpan span) {
+  if (count <= 0 || max_threads <= 0 || span.n <= 0) return hipSuccess;
   int64_t b = (max_threads + 255) / 256;
   if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(merge_ind_kernel, dim3((unsigned)b, (unsigned)count), dim3(256), 0, stream, dev);
+  hipLaunchKernelGGL(merge_ind_kernel, dim3((unsigned)b, (unsigned)count, (unsigned)span.n), dim3(256), 0,
+                     stream, dev, span.stride);
   return hipGetLastError();
 }
 
-hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream) {
-  if (max_bins <= 0) return hipSuccess;
-  hipLaunchKernelGGL(refine_ind_kernel, dim3((unsigned)max_bins), dim3(256), 0, stream, dev);
+hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream, InstSpan span) {
+  if (max_bins <= 0 || span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_ind_kernel, dim3((unsigned)max_bins, 1, (unsigned)span.n), dim3(256), 0, stream,
+                     dev, span.stride);
   return hipGetLastError();
 }
 
 // Second pass for small key sets (count <= kSelCap): one workgroup; each
-// thread holds up to 64 keys in registers, each wave takes its C best by C
-// rounds of a wave arg-max, wave 0 merges the four lists the same way.
+// thread holds up to 64 keys in registers.  The bound-filter-rank selection
+// (sel_bound_top) answers unless more than kSelFastCap keys pass its bound;
+// then each wave takes its C best of the narrowed keys by C rounds of a wave
+// arg-max and wave 0 merges the four lists the same way.
 constexpr int kSelCap = 256 * 64;
+constexpr int kSelFastCap = 512;
 
 __device__ inline Key wave_best_key(Key k) {
 #pragma unroll
@@ -411,9 +410,17 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
                                                            const uint64_t* __restrict__ idxs,
                                                            int64_t count, const int32_t* __restrict__ C_dev,
                                                            double* __restrict__ out_v,
-                                                           uint64_t* __restrict__ out_i) {
+                                                           uint64_t* __restrict__ out_i, int64_t slot) {
+  using SK = SelKey<double, uint64_t>;
+  __shared__ SelShared<double, uint64_t, 256, kSelFastCap> sel;
+  __shared__ SK outk[kDDMaxC];
   __shared__ Key wk[4][kDDMaxC];
   __shared__ int wn[4];
+  vals = inst_ptr(vals, slot);
+  idxs = inst_ptr(idxs, slot);
+  C_dev = inst_ptr(C_dev, slot);
+  out_v = inst_ptr(out_v, slot);
+  out_i = inst_ptr(out_i, slot);
   const int C = *C_dev;
   if (C <= 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -432,6 +439,18 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
     const int64_t x = (int64_t)j * 256 + threadIdx.x;
     if (x >= count) h[j] = worst_key();
     if (better(h[j], worst_key())) live |= 1ull << j;
+  }
+  const Key wkey = worst_key();
+  const int found = sel_bound_top<double, uint64_t, KPT, 256, kSelFastCap>(
+      sel, live, [&](int j) { return SK{h[j].v, h[j].i}; }, C < 256 ? C : 256, SK{wkey.v, wkey.i},
+      outk);
+  if (found >= 0) {
+    for (int n = threadIdx.x; n < C; n += 256) {
+      const SK k = n < found ? outk[n] : SK{wkey.v, wkey.i};
+      out_v[n] = k.v;
+      out_i[n] = k.i;
+    }
+    return;
   }
   int got = 0;
   for (int round = 0; round < C; ++round) {
@@ -483,13 +502,17 @@ __global__ void __launch_bounds__(256) select_small_kernel(const double* __restr
 // one workgroup selects the C best of `count` <= kSelCap keys; the keys per
 // thread follow the count (fewer registers, all loads in flight)
 void launch_select_small(const double* vals, const uint64_t* idxs, int64_t count, const int32_t* C_dev,
-                         double* out_v, uint64_t* out_i, hipStream_t stream) {
+                         double* out_v, uint64_t* out_i, hipStream_t stream, InstSpan span = InstSpan()) {
+  const dim3 grid(1, 1, (unsigned)span.n);
   if (count <= 256 * 4)
-    hipLaunchKernelGGL(select_small_kernel<4>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+    hipLaunchKernelGGL(select_small_kernel<4>, grid, dim3(256), 0, stream, vals, idxs, count, C_dev, out_v,
+                       out_i, span.stride);
   else if (count <= 256 * 16)
-    hipLaunchKernelGGL(select_small_kernel<16>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+    hipLaunchKernelGGL(select_small_kernel<16>, grid, dim3(256), 0, stream, vals, idxs, count, C_dev, out_v,
+                       out_i, span.stride);
   else
-    hipLaunchKernelGGL(select_small_kernel<64>, dim3(1), dim3(256), 0, stream, vals, idxs, count, C_dev, out_v, out_i);
+    hipLaunchKernelGGL(select_small_kernel<64>, grid, dim3(256), 0, stream, vals, idxs, count, C_dev, out_v,
+                       out_i, span.stride);
 }
 
 int64_t topk_indirect_capacity(int64_t max_count, int C_max) {
@@ -517,27 +540,67 @@ hipError_t launch_topk_indirect(const void* bins, DType t, const int64_t* count_
   else
     hipLaunchKernelGGL((topk_kernel<double, true>), dim3(1), dim3(256), 0, stream,
                        (const double*)cand_val, (const uint64_t*)cand_idx, nc, nc, 0, out_val,
-                       out_idx, nullptr, C_dev, C_max);
+                       out_idx, nullptr, C_dev, C_max, (int64_t)0);
   return hipGetLastError();
 }
 
 hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
                                   const int64_t* count_dev, const int32_t* C_dev, int C_max,
                                   double* stage_val, uint64_t* stage_idx, double* out_val,
-                                  uint64_t* out_idx, hipStream_t stream) {
+                                  uint64_t* out_idx, hipStream_t stream, InstSpan span) {
   if (C_max < 1 || C_max > kDDMaxC) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(kTopcStage), dim3(256), 0, stream, cand_val,
-                     cand_idx, (int64_t)0, (int64_t)0, 0, stage_val, stage_idx, count_dev, C_dev, C_max);
+  if (span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((topk_kernel<double, true>), dim3(kTopcStage, 1, (unsigned)span.n), dim3(256), 0, stream,
+                     cand_val, cand_idx, (int64_t)0, (int64_t)0, 0, stage_val, stage_idx, count_dev, C_dev,
+                     C_max, span.stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nc = (int64_t)kTopcStage * C_max;  // <= kSelCap
-  launch_select_small((const double*)stage_val, (const uint64_t*)stage_idx, nc, C_dev, out_val, out_idx, stream);
+  launch_select_small((const double*)stage_val, (const uint64_t*)stage_idx, nc, C_dev, out_val, out_idx, stream,
+                      span);
   return hipGetLastError();
 }
 
+// After the warm-up tiles: the C-th best of the keys they appended is a key
+// that C keys reach, so the threshold rises to its value; the candidate list
+// then restarts (the main pass evaluates those tiles again).  At most
+// kDDMaxC tiles append at most kDDMaxC keys each: 16 keys per thread.
+__global__ void __launch_bounds__(256) warm_tau_kernel(const double* __restrict__ cand_v,
+                                                       unsigned long long* count,
+                                                       const int32_t* __restrict__ C_dev,
+                                                       unsigned long long* thr, int64_t slot) {
+  using SK = SelKey<double, uint32_t>;
+  constexpr int KPT = kDDMaxC * kDDMaxC / 256;
+  __shared__ SelShared<double, uint32_t, 256, kSelFastCap> sel;
+  __shared__ SK outk[kDDMaxC];
+  cand_v = inst_ptr(cand_v, slot);
+  count = inst_ptr(count, slot);
+  C_dev = inst_ptr(C_dev, slot);
+  thr = inst_ptr(thr, slot);
+  const int C = *C_dev;
+  const int64_t n = (int64_t)*count;
+  if (C > 0 && n >= C && n <= 256 * KPT) {
+    double h[KPT];
+    uint64_t live = 0;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int64_t x = (int64_t)j * 256 + threadIdx.x;
+      h[j] = cand_v[x < n ? x : 0];
+      if (x < n) live |= 1ull << j;
+    }
+    const int found = sel_bound_top<double, uint32_t, KPT, 256, kSelFastCap>(
+        sel, live, [&](int j) { return SK{h[j], (uint32_t)(j * 256 + threadIdx.x)}; }, C,
+        SK{-INFINITY, 0xffffffffu}, outk);
+    if (threadIdx.x == 0 && found == C) atomicMax(thr, ord_key(outk[C - 1].v));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *count = 0;
+}
+
 // ---------------------------------------------------------------------------
-// Device-driven recursion control.  These kernels run on one thread: they
-// handle a few hundred words per recursion.
+// Device-driven recursion control.  These kernels run as one wave: they
+// handle a few hundred words per recursion, a lane per descriptor, candidate
+// or list entry.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -591,11 +654,16 @@ __device__ inline void set_merge(MergeArgs& m, const double* E, double* Ep, int6
   m.fixed_vals_flat = fixed_vals_flat;
 }
 
-__global__ void dd_init_kernel(DDState* st, cq_dd_record* recs, int R, DDInit init) {
+__global__ void dd_init_kernel(const DDProgram* __restrict__ P, DDState* st, cq_dd_record* recs, int R,
+                               int64_t slot) {
+  P = inst_ptr(P, slot);
+  st = inst_ptr(st, slot);
+  recs = inst_ptr(recs, slot);
   uint64_t* w = reinterpret_cast<uint64_t*>(recs);
   const int64_t words = (int64_t)R * (int64_t)(sizeof(cq_dd_record) / 8);
   for (int64_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
   if (threadIdx.x != 0) return;
+  const DDInit& init = P->init;
   for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
     st->active[c] = init.active[c];
     st->merged[c] = init.merged[c];
@@ -609,6 +677,11 @@ __global__ void dd_init_kernel(DDState* st, cq_dd_record* recs, int R, DDInit in
   st->n_list = 0;
   st->C = 0;
   st->count = 0;
+  st->topc_thr = 0;
+  st->topc_count = 0;
+  st->n_tiles = 0;
+  st->warm_count = 0;
+  st->list_count = 0;
   st->zero_idx = 0;
   st->total = 0.0;
 }
@@ -618,7 +691,12 @@ __global__ void dd_init_kernel(DDState* st, cq_dd_record* recs, int R, DDInit in
 // 32 + s step s's, and thread 0 the recursion-wide fields -- the descriptor
 // writes are independent, so they no longer run one after another.
 __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DDLevel* lv,
-                                cq_dd_record* recs, int r, void* bins) {
+                                cq_dd_record* recs, int r, void* bins, int64_t slot) {
+  P = inst_ptr(P, slot);
+  st = inst_ptr(st, slot);
+  lv = inst_ptr(lv, slot);
+  recs = inst_ptr(recs, slot);
+  bins = inst_ptr(bins, slot);
   const int tid = threadIdx.x;
   const int ns = P->n_sub, nsteps = P->n_steps;
   const int step = tid - 32;  // the step this thread describes, if in range
@@ -718,9 +796,10 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.m_fastest = b_elems > a_elems ? 1 : 0;
       lv->gemm[s] = g;
       if (tc_here) {
-        // tile pruning: the 64 tiles with the largest bounds raise the
-        // threshold first, then only tiles whose bound reaches it are
-        // multiplied
+        // tile pruning: the 64 tiles with the largest bounds append their
+        // best keys first and the C-th best of those raises the threshold
+        // (the candidate list then restarts); only tiles whose bound reaches
+        // it are multiplied
         st->n_tiles = g.tiles;
         st->warm_C = (int)(g.tiles < 64 ? g.tiles : 64);
         st->warm_count = st->warm_C;
@@ -728,7 +807,7 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
         GemmArgs w = g;
         w.tile_list = P->warm_i;
         w.tile_count = &st->warm_count;
-        w.topc_publish_only = 1;
+        w.topc_publish_only = 2;
         lv->topc_warm = w;
       }
     } else {
@@ -779,113 +858,158 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
   }
 }
 
-__device__ inline bool entry_before(double v1, int r1, uint64_t b1, double v2, int r2, uint64_t b2) {
-  if (v1 != v2) return v1 > v2;
+// Order of L: larger FP64 value first, then the earlier recursion, then the
+// smaller bin.  Values compare through an order-preserving integer key (with
+// -0 taken as +0), which agrees with the numeric order on every non-NaN value
+// and still orders NaNs, so ranks of distinct entries are always distinct.
+__device__ inline uint64_t list_ord(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v + 0.0);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+__device__ inline bool list_before(uint64_t o1, int r1, uint64_t b1, uint64_t o2, int r2, uint64_t b2) {
+  if (o1 != o2) return o1 > o2;
   if (r1 != r2) return r1 < r2;
   return b1 < b2;
 }
 
-// The list update reads and rewrites a few kilobytes of state in a long
-// dependent chain; one thread runs it on a copy of the state in LDS (the 64
-// threads copy it in and out), not through global memory.
-__device__ void dd_update_body(const DDProgram* __restrict__ P, DDState* st, cq_dd_record* recs, int r) {
-  cq_dd_record& rec = recs[r];
-  rec.total = st->total;
-  const int ns = P->n_sub, R = P->R, C = st->C;
-  // candidates by (FP64 value desc, bin asc)
-  int order[kDDMaxC];
-  for (int i = 0; i < C; ++i) {
-    int j = i;
-    const double v = st->ref_val[i];
-    const uint64_t b = st->top_idx[i];
-    while (j > 0 && entry_before(v, 0, b, st->ref_val[order[j - 1]], 0, st->top_idx[order[j - 1]])) {
-      order[j] = order[j - 1];
-      --j;
-    }
-    order[j] = i;
-  }
-  int nl = st->n_list;
+// The list update of recursion r, one wave: the C candidates (FP64 refined
+// values of the selected bins) are ranked among themselves, the best
+// min(C, R) of them and the entries of L are ranked against each other (both
+// sides are sorted, so an entry's place in the merged list is its own rank
+// plus the number of the other side's entries before it), and the best R of
+// the union form the new L.  Then the best entry is popped and its bin
+// zoomed into: the first max_active[c] merged outputs of each subcircuit
+// become active.  Every place of the new list receives exactly one entry.
+__global__ void __launch_bounds__(64) dd_update_kernel(const DDProgram* __restrict__ P, DDState* st,
+                                                       cq_dd_record* recs, int r, int64_t slot) {
+  constexpr int W = (int)(sizeof(DDEntry) / 8);
+  static_assert(sizeof(DDEntry) % 8 == 0, "entries copied in 8-byte words");
+  static_assert(kDDMaxC <= 64 && CQ_MAX_DD_R <= 64, "one lane per candidate and per entry");
+  __shared__ DDEntry old_l[CQ_MAX_DD_R];
+  __shared__ DDEntry new_l[CQ_MAX_DD_R];
+  __shared__ uint64_t c_ord[kDDMaxC], c_bin[kDDMaxC];
+  __shared__ double c_val[kDDMaxC];
+  __shared__ int c_rank[kDDMaxC];
+  P = inst_ptr(P, slot);
+  st = inst_ptr(st, slot);
+  recs = inst_ptr(recs, slot);
+  const int tid = threadIdx.x;
+  if (st->stop) return;
+  const int ns = P->n_sub, R = P->R, C = st->C, nl = st->n_list;
   const int take = C < R ? C : R;
-  for (int i = 0; i < take; ++i) {
-    const double v = st->ref_val[order[i]];
-    const uint64_t bin = st->top_idx[order[i]];
-    // sorted insertion into L, keeping at most R entries
-    int pos = nl;
-    while (pos > 0 && entry_before(v, r, bin, st->list[pos - 1].v, st->list[pos - 1].rec,
-                                   st->list[pos - 1].bin))
-      --pos;
-    if (pos >= R) continue;
-    const int last = nl < R ? nl : R - 1;
-    for (int q = last; q > pos; --q) st->list[q] = st->list[q - 1];
-    if (nl < R) ++nl;
-    DDEntry& e = st->list[pos];
-    e.v = v;
-    e.rec = r;
-    e.bin = bin;
-    int shift = st->n_active;
-    for (int c = 0; c < ns; ++c) {
-      const int a = st->na[c];
-      shift -= a;
-      const uint64_t bits = (bin >> shift) & low_bits(a);
-      const uint64_t act = st->active[c];
-      uint64_t fv = st->fixed_vals[c];
-      int t = 0;
-      for (int p = 0; p < 64; ++p)
-        if ((act >> p) & 1) {
-          if ((bits >> (a - 1 - t)) & 1) fv |= (uint64_t)1 << p;
-          ++t;
-        }
-      e.fixed[c] = st->fixed[c] | act;
-      e.fixed_vals[c] = fv;
-      e.merged[c] = st->merged[c];
+  cq_dd_record& rec = recs[r];
+  {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(st->list);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(old_l);
+    for (int w = tid; w < nl * W; w += 64) dst[w] = src[w];
+  }
+  if (tid < C) {
+    c_val[tid] = st->ref_val[tid];
+    c_ord[tid] = list_ord(c_val[tid]);
+    c_bin[tid] = st->top_idx[tid];
+  }
+  __syncthreads();
+  // candidates among themselves (equal keys keep their selection order)
+  if (tid < C) {
+    const uint64_t o = c_ord[tid], b = c_bin[tid];
+    int rk = 0;
+    for (int j = 0; j < C; ++j)
+      rk += (c_ord[j] != o ? c_ord[j] > o : (c_bin[j] != b ? c_bin[j] < b : j < tid)) ? 1 : 0;
+    c_rank[tid] = rk;
+  }
+  __syncthreads();
+  // an entry of L keeps its rank plus the taken candidates before it
+  if (tid < nl) {
+    const DDEntry& e = old_l[tid];
+    const uint64_t o = list_ord(e.v);
+    int pos = tid;
+    for (int j = 0; j < C; ++j)
+      pos += (c_rank[j] < take && list_before(c_ord[j], r, c_bin[j], o, e.rec, e.bin)) ? 1 : 0;
+    if (pos < R) {
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(&e);
+      uint64_t* dst = reinterpret_cast<uint64_t*>(&new_l[pos]);
+      for (int w = 0; w < W; ++w) dst[w] = src[w];
     }
   }
-  st->n_list = nl;
-  rec.n_list = nl;
-  for (int i = 0; i < nl; ++i) {
-    rec.list_val[i] = st->list[i].v;
-    rec.list_rec[i] = st->list[i].rec;
-    rec.list_bin[i] = st->list[i].bin;
+  // a taken candidate keeps its rank plus the entries of L before it
+  if (tid < C && c_rank[tid] < take) {
+    const uint64_t o = c_ord[tid], bin = c_bin[tid];
+    int pos = c_rank[tid];
+    for (int q = 0; q < nl; ++q)
+      pos += list_before(list_ord(old_l[q].v), old_l[q].rec, old_l[q].bin, o, r, bin) ? 1 : 0;
+    if (pos < R) {
+      DDEntry& e = new_l[pos];
+      e.v = c_val[tid];
+      e.rec = r;
+      e.pad = 0;
+      e.bin = bin;
+      // the bin's digits, subcircuit 0 most significant, fix the active
+      // outputs: the lowest active position takes the digit's top bit
+      int shift = st->n_active;
+      for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
+        e.fixed[c] = e.fixed_vals[c] = e.merged[c] = 0;
+        if (c >= ns) continue;
+        const int a = st->na[c];
+        shift -= a;
+        const uint64_t bits = (bin >> shift) & low_bits(a);
+        uint64_t act = st->active[c], fv = st->fixed_vals[c];
+        for (int t = a - 1; act; --t) {
+          const uint64_t low = act & (~act + 1);
+          if ((bits >> t) & 1) fv |= low;
+          act ^= low;
+        }
+        e.fixed[c] = st->fixed[c] | st->active[c];
+        e.fixed_vals[c] = fv;
+        e.merged[c] = st->merged[c];
+      }
+    }
   }
-  st->done = r + 1;
-  if (nl == 0) {
-    st->stop = 1;
+  __syncthreads();
+  const int nl2 = nl + take < R ? nl + take : R;
+  if (tid == 0) {
+    rec.total = st->total;
+    rec.n_list = nl2;
+    if (P->topc_step >= 0) {
+      rec.tiles = st->n_tiles;
+      rec.tiles_run = st->warm_count + st->list_count;
+    }
+    st->done = r + 1;
+  }
+  if (tid < nl2) {
+    rec.list_val[tid] = new_l[tid].v;
+    rec.list_rec[tid] = new_l[tid].rec;
+    rec.list_bin[tid] = new_l[tid].bin;
+  }
+  if (nl2 == 0) {
+    if (tid == 0) {
+      st->n_list = 0;
+      st->stop = 1;
+    }
     return;
   }
-  rec.popped = 1;
-  // zoom: the first max_active[c] merged outputs of the popped bin become active
-  for (int c = 0; c < ns; ++c) {
-    const uint64_t mer = st->list[0].merged[c];
-    uint64_t act = 0;
-    int taken = 0;
-    for (int p = 0; p < 64 && taken < P->max_active[c]; ++p)
-      if ((mer >> p) & 1) {
-        act |= (uint64_t)1 << p;
-        ++taken;
-      }
+  // pop the best entry and zoom into its bin
+  if (tid == 0) rec.popped = 1;
+  if (tid < ns) {
+    const int c = tid;
+    const uint64_t mer = new_l[0].merged[c];
+    uint64_t act = 0, rest = mer;
+    for (int taken = 0; rest && taken < P->max_active[c]; ++taken) {
+      const uint64_t low = rest & (~rest + 1);
+      act |= low;
+      rest ^= low;
+    }
     st->active[c] = act;
     st->merged[c] = mer & ~act;
-    st->fixed[c] = st->list[0].fixed[c];
-    st->fixed_vals[c] = st->list[0].fixed_vals[c];
+    st->fixed[c] = new_l[0].fixed[c];
+    st->fixed_vals[c] = new_l[0].fixed_vals[c];
   }
-  for (int q = 0; q + 1 < nl; ++q) st->list[q] = st->list[q + 1];
-  st->n_list = nl - 1;
-}
-
-__global__ void dd_update_kernel(const DDProgram* __restrict__ P, DDState* gst, cq_dd_record* recs,
-                                 int r) {
-  __shared__ DDState S;
-  static_assert(sizeof(DDState) % 8 == 0, "state copied in 8-byte words");
-  constexpr int W = (int)(sizeof(DDState) / 8);
-  const uint64_t* src = reinterpret_cast<const uint64_t*>(gst);
-  uint64_t* lds = reinterpret_cast<uint64_t*>(&S);
-  for (int i = threadIdx.x; i < W; i += blockDim.x) lds[i] = src[i];
-  __syncthreads();
-  if (S.stop) return;
-  if (threadIdx.x == 0) dd_update_body(P, &S, recs, r);
-  __syncthreads();
-  uint64_t* dst = reinterpret_cast<uint64_t*>(gst);
-  for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = lds[i];
+  {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&new_l[1]);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(st->list);
+    for (int w = tid; w < (nl2 - 1) * W; w += 64) dst[w] = src[w];
+  }
+  if (tid == 0) st->n_list = nl2 - 1;
 }
 
 }  // namespace
@@ -901,6 +1025,14 @@ __global__ void __launch_bounds__(256) dd_copy_kernel(const char* __restrict__ s
   for (int64_t w = threadIdx.x; w < words; w += blockDim.x) d[w] = s[w];
 }
 
+hipError_t launch_warm_tau(const double* cand_v, unsigned long long* count, const int32_t* C_dev,
+                           unsigned long long* thr, hipStream_t stream, InstSpan span) {
+  if (span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(warm_tau_kernel, dim3(1, 1, (unsigned)span.n), dim3(256), 0, stream, cand_v, count, C_dev,
+                     thr, span.stride);
+  return hipGetLastError();
+}
+
 hipError_t launch_dd_copy(const void* src, int64_t src_stride, void* dst, int64_t dst_stride,
                           int64_t bytes, int blocks, hipStream_t stream) {
   if (blocks <= 0 || bytes <= 0) return hipSuccess;
@@ -913,21 +1045,27 @@ hipError_t launch_dd_copy(const void* src, int64_t src_stride, void* dst, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
-                          hipStream_t stream) {
-  hipLaunchKernelGGL(dd_init_kernel, dim3(1), dim3(256), 0, stream, st, recs, R, init);
+hipError_t launch_dd_init(const DDProgram* prog, DDState* st, cq_dd_record* recs, int R,
+                          hipStream_t stream, InstSpan span) {
+  if (span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dd_init_kernel, dim3(1, 1, (unsigned)span.n), dim3(256), 0, stream, prog, st, recs, R,
+                     span.stride);
   return hipGetLastError();
 }
 
 hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_dd_record* recs,
-                           int r, void* bins, hipStream_t stream) {
-  hipLaunchKernelGGL(dd_setup_kernel, dim3(1), dim3(64), 0, stream, prog, st, lv, recs, r, bins);
+                           int r, void* bins, hipStream_t stream, InstSpan span) {
+  if (span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dd_setup_kernel, dim3(1, 1, (unsigned)span.n), dim3(64), 0, stream, prog, st, lv, recs, r,
+                     bins, span.stride);
   return hipGetLastError();
 }
 
 hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
-                            hipStream_t stream) {
-  hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(64), 0, stream, prog, st, recs, r);
+                            hipStream_t stream, InstSpan span) {
+  if (span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dd_update_kernel, dim3(1, 1, (unsigned)span.n), dim3(64), 0, stream, prog, st, recs, r,
+                     span.stride);
   return hipGetLastError();
 }
 

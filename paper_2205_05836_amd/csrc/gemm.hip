@@ -25,6 +25,7 @@
 #include <string>
 
 #include "kernels.hpp"
+#include "select.hpp"
 
 namespace cq {
 
@@ -43,9 +44,11 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total) {
 }
 
 // Kernels take their arguments by value, or -- for shapes decided on the
-// device -- from device memory through `gp`; workgroups beyond the tile count
-// of an indirect launch exit at once.
+// device -- from device memory through `gp` (instance blockIdx.z's block
+// gp_stride bytes further on); workgroups beyond the tile count of an
+// indirect launch exit at once.
 #define CQ_LOAD_GEMM_ARGS                                                        \
+  gp = inst_ptr(gp, gp_stride);                                                  \
   const GemmArgs g = gp ? *gp : gv;                                              \
   if (gp && (int64_t)blockIdx.x >= (g.tile_list ? *g.tile_count : g.tiles)) return; \
   if (gp && g.tile_list && g.tile_list[blockIdx.x] >= (uint64_t)g.tiles) return;
@@ -57,6 +60,25 @@ struct TileCoord {
 template <int BM, int BN>
 __device__ inline TileCoord tile_coord_of(const GemmArgs& g, int64_t t) {
   TileCoord c;
+  if (g.tiles < ((int64_t)1 << 31)) {  // 32-bit division (the 64-bit one is a long routine)
+    const uint32_t t32 = (uint32_t)t, tm = (uint32_t)g.tilesM, tn = (uint32_t)g.tilesN;
+    uint32_t a, r, b;
+    if (g.m_fastest) {
+      r = t32 / tm;
+      a = t32 - r * tm;
+      b = r / tn;
+      c.m0 = (int64_t)a * BM;
+      c.n0 = (int64_t)(r - b * tn) * BN;
+    } else {
+      r = t32 / tn;
+      a = t32 - r * tn;
+      b = r / tm;
+      c.n0 = (int64_t)a * BN;
+      c.m0 = (int64_t)(r - b * tm) * BM;
+    }
+    c.z = b;
+    return c;
+  }
   if (g.m_fastest) {
     const int64_t tm = t % g.tilesM, r = t / g.tilesM;
     c.n0 = (r % g.tilesN) * BN;
@@ -89,6 +111,7 @@ __device__ inline TileCoord tile_coord_v(const GemmArgs& g, int64_t vb) {
 // needs no grid sized for every tile; a direct launch (one workgroup per
 // tile) runs the body once.
 #define CQ_TILE_LOOP(BODY)                                                                      \
+  gp = inst_ptr(gp, gp_stride);                                                                 \
   int64_t nvb = (int64_t)gridDim.x;                                                             \
   if (gp) {                                                                                     \
     const GemmArgs* q = gp;                                                                     \
@@ -171,15 +194,6 @@ __device__ inline void store_out(TC* p, TC v) {
 // the global top C is at or above tau and among its tile's C best, so the
 // candidates contain the global top C exactly.
 // ---------------------------------------------------------------------------
-__device__ inline unsigned long long ord_key(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  return (b >> 63) ? ~b : (b | (1ull << 63));
-}
-
-__device__ inline double ord_val(unsigned long long k) {
-  const unsigned long long b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
-  return __longlong_as_double((long long)b);
-}
 
 template <typename T>
 struct TcKey {
@@ -208,98 +222,201 @@ __device__ inline TcKey<T> wave_best(TcKey<T> k) {
   return k;
 }
 
-// get(e) -> (value, r * 128 + c, or 0xffffffff outside M x N) for e < V.
-// Each wave takes its C best keys at or above tau by C rounds of a wave
-// arg-max over the values its lanes hold (the owner retires the winner);
-// wave 0 then merges the waves' lists the same way.  Every loop over e is
-// unrolled, so the accumulators behind get() are indexed statically.
-template <typename T, int V, int NTHR, typename Get, typename Raw>
+// Keys of a tile that pass the bound of the tile selection at most (beyond
+// it the tile falls back to C rounds of a wave arg-max).
+constexpr int kTopcCap = 512;
+
+// The smallest T at or above tau: for T values, v >= tau_as<T>(tau) exactly
+// when double(v) >= tau.
+// Hides how a lane mask was built, so that later tests of its bits read the
+// mask (two VGPRs) instead of keeping every bit's defining condition alive.
+__device__ inline uint64_t opaque_mask(uint64_t m) {
+  uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+  asm volatile("" : "+v"(lo), "+v"(hi));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ inline T tau_as(double tau) {
+  if constexpr (sizeof(T) == 8) {
+    return tau;
+  } else {
+    float f = (float)tau;
+    if ((double)f < tau) {  // step to the next float up
+      uint32_t b = __float_as_uint(f);
+      b = (f == 0.0f) ? 1u : ((b >> 31) ? b - 1 : b + 1);
+      f = __uint_as_float(b);
+    }
+    return f;
+  }
+}
+
+// Tile selection.  Lane key e has value val(e) and index base + koff(e)
+// (r * 128 + c inside the tile; koff(e) is a constant once the loops over e
+// are unrolled, so keys of one lane compare by their offsets); valid(e):
+// inside M x N, asked on partial tiles only.
+//
+// Keys at or above tau take part.  The C-th best of the lanes' own best keys
+// bounds the tile's C-th best key from below (at least C keys reach it), so
+// only keys reaching it are appended to LDS, where each key's rank among
+// them is its place in the answer.  Should more than kTopcCap keys reach the
+// bound (the best keys crowd into a few lanes), each wave instead takes its C
+// best of them by C rounds of a wave arg-max and wave 0 merges the waves'
+// lists the same way.  The per-key steps are selects, not branches, which
+// keeps the unrolled code short.
+template <typename T, int V, int NTHR, typename Val, typename Off, typename Valid>
 __device__ __forceinline__ void topc_tile(const GemmArgs& g, int64_t z, int64_t m0, int64_t n0, bool full,
-                                          Get get, Raw raw) {
+                                          Val val, Off koff, int base, Valid valid) {
+  using K = TcKey<T>;
   constexpr int NW = NTHR / 64;
+  constexpr int kNone = 0x7fffffff;
   static_assert(V <= 64, "one live bit per value");
-  __shared__ TcKey<T> wk[NW][kDDMaxC];
-  __shared__ TcKey<T> outk[kDDMaxC];
+  __shared__ K lane_best[NTHR];
+  __shared__ K cand[kTopcCap + NTHR];  // beyond kTopcCap: one parking slot per thread
+  __shared__ K wk[NW][kDDMaxC];
+  __shared__ K outk[kDDMaxC];
   __shared__ int wn[NW];
-  __shared__ int nout;
-  __shared__ unsigned long long base;
+  __shared__ int cnt, owner, nfound, nout;
+  __shared__ unsigned long long obase;
   const int C = *g.topc_C;
   if (C <= 0) return;
-  const double tau = ord_val(*g.topc_thr);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // fast test on full tiles: the largest value against tau
-  if (full) {
-    T mx = raw(0);
+  const T tau = tau_as<T>(ord_val(*g.topc_thr));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    // most tiles end here: nothing (not even outside M x N) reaches tau
+    T mx = val(0);
 #pragma unroll
-    for (int e = 1; e < V; ++e) mx = raw(e) > mx ? raw(e) : mx;
-    if (__syncthreads_count(double(mx) >= tau) == 0) return;
+    for (int e = 1; e < V; ++e) mx = val(e) > mx ? val(e) : mx;
+    if (__syncthreads_count(mx >= tau) == 0) return;
   }
+  // the keys at or above tau and the lane's best of them
   uint64_t live = 0;
+  T bv = T(0);
+  int bk = kNone;
 #pragma unroll
   for (int e = 0; e < V; ++e) {
-    const TcKey<T> k = get(e);
-    if (k.i != 0xffffffffu && double(k.v) >= tau) live |= 1ull << e;
+    const T v = val(e);
+    const int k = koff(e);
+    // bitwise, not short-circuit: selects instead of branches
+    const bool ok = (full | valid(e)) & (v >= tau);
+    live |= (uint64_t)ok << e;
+    const bool b = ok & ((bk == kNone) | (v > bv) | ((v == bv) & (k < bk)));
+    bv = b ? v : bv;
+    bk = b ? k : bk;
   }
+  live = opaque_mask(live);
   if (__syncthreads_count(live != 0) == 0) return;
-  int got = 0;
-  for (int round = 0; round < C; ++round) {
-    if (__ballot(live != 0) == 0) break;
-    TcKey<T> best = tc_worst<T>();
-    int be = -1;
-#pragma unroll
-    for (int e = 0; e < V; ++e)
-      if ((live >> e) & 1) {
-        const TcKey<T> k = get(e);
-        if (tc_better(k, best)) {
-          best = k;
-          be = e;
-        }
-      }
-    const TcKey<T> w = wave_best(best);
-    if (lane == 0) wk[wave][got] = w;
-    if (be >= 0 && best.i == w.i) live &= ~(1ull << be);
-    ++got;
+  if (tid == 0) {
+    cnt = 0;
+    owner = -1;
   }
-  if (lane == 0) wn[wave] = got;
+  const bool has = bk != kNone;
+  const K mine = has ? K{bv, (uint32_t)(base + bk)} : tc_worst<T>();
+  lane_best[tid] = mine;
   __syncthreads();
-  if (wave == 0) {
-    // lane l holds key l of every wave's list
-    uint32_t hl = 0;
-    TcKey<T> h[NW];
+  if (has && rank_of(lane_best, NTHR, mine) == C - 1) owner = tid;  // distinct keys, distinct ranks
+  __syncthreads();
+  const int own = owner;
+  if (own >= 0) {
+    const K t0 = lane_best[own];
+    const int d = (int)t0.i - base;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      h[w] = tc_worst<T>();
-      if (lane < wn[w]) {
-        h[w] = wk[w][lane];
-        hl |= 1u << w;
-      }
+    for (int e = 0; e < V; ++e) {
+      const T v = val(e);
+      const bool drop = (t0.v > v) | ((t0.v == v) & (d < koff(e)));
+      live &= ~((uint64_t)drop << e);
     }
-    int n = 0;
-    for (; n < C; ++n) {
-      if (__ballot(hl != 0) == 0) break;
-      TcKey<T> best = tc_worst<T>();
-      int bw = -1;
+    live = opaque_mask(live);
+  }
+  int off = __popcll(live);
+  off = off ? atomicAdd(&cnt, off) : 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w)
-        if (((hl >> w) & 1) && tc_better(h[w], best)) {
-          best = h[w];
-          bw = w;
-        }
-      const TcKey<T> win = wave_best(best);
-      if (lane == 0) outk[n] = win;
-      if (bw >= 0 && best.i == win.i) hl &= ~(1u << bw);
-    }
-    if (lane == 0) {
-      if (n == C) atomicMax(g.topc_thr, ord_key(double(outk[C - 1].v)));
-      nout = g.topc_publish_only ? 0 : n;
-      base = g.topc_publish_only ? 0 : atomicAdd(g.topc_count, (unsigned long long)n);
-    }
+  for (int e = 0; e < V; ++e) {
+    const bool l = (live >> e) & 1;
+    cand[(l & (off < kTopcCap)) ? off : kTopcCap + tid] = K{val(e), (uint32_t)(base + koff(e))};
+    off += l ? 1 : 0;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nout; t += NTHR) {
-    const TcKey<T> k = outk[t];
-    g.topc_v[base + t] = double(k.v);
-    g.topc_i[base + t] = (uint64_t)(z * g.sCz + (m0 + (k.i >> 7)) * g.ldc + n0 + (k.i & 127));
+  int n = cnt;
+  if (n > kTopcCap && g.topc_publish_only) {
+    // warm-up tiles need no exact answer: t0 is at most the tile's C-th best
+    // key, so it may stand in for it (and the tile appends nothing)
+    if (tid == 0 && own >= 0) atomicMax(g.topc_thr, ord_key(double(lane_best[own].v)));
+    return;
+  }
+  if (n <= kTopcCap) {
+    for (int t = tid; t < n; t += NTHR) {
+      const K k = cand[t];
+      const int r = rank_of(cand, n, k);
+      if (r < C) outk[r] = k;
+    }
+    n = n < C ? n : C;
+  } else {
+    int got = 0;
+    for (int round = 0; round < C; ++round) {
+      if (__ballot(live != 0) == 0) break;
+      T rv = T(0);
+      int rk = kNone, re = -1;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T v = val(e);
+        const int k = koff(e);
+        const bool b = (bool)((live >> e) & 1) & ((rk == kNone) | (v > rv) | ((v == rv) & (k < rk)));
+        rv = b ? v : rv;
+        rk = b ? k : rk;
+        re = b ? e : re;
+      }
+      const K best = re >= 0 ? K{rv, (uint32_t)(base + rk)} : tc_worst<T>();
+      const K w = wave_best(best);
+      if (lane == 0) wk[wave][got] = w;
+      if (re >= 0 && best.i == w.i) live &= ~(1ull << re);
+      ++got;
+    }
+    if (lane == 0) wn[wave] = got;
+    __syncthreads();
+    if (wave == 0) {
+      // lane l holds key l of every wave's list
+      uint32_t hl = 0;
+      K h[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        h[w] = tc_worst<T>();
+        if (lane < wn[w]) {
+          h[w] = wk[w][lane];
+          hl |= 1u << w;
+        }
+      }
+      int m = 0;
+      for (; m < C; ++m) {
+        if (__ballot(hl != 0) == 0) break;
+        K best = tc_worst<T>();
+        int bw = -1;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+          if (((hl >> w) & 1) && tc_better(h[w], best)) {
+            best = h[w];
+            bw = w;
+          }
+        const K win = wave_best(best);
+        if (lane == 0) outk[m] = win;
+        if (bw >= 0 && best.i == win.i) hl &= ~(1u << bw);
+      }
+      if (lane == 0) nfound = m;
+    }
+    __syncthreads();
+    n = nfound;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (n == C) atomicMax(g.topc_thr, ord_key(double(outk[C - 1].v)));
+    nout = g.topc_publish_only == 1 ? 0 : n;
+    obase = g.topc_publish_only == 1 ? 0 : atomicAdd(g.topc_count, (unsigned long long)n);
+  }
+  __syncthreads();
+  for (int t = tid; t < nout; t += NTHR) {
+    const K k = outk[t];
+    g.topc_v[obase + t] = double(k.v);
+    g.topc_i[obase + t] = (uint64_t)(z * g.sCz + (m0 + (k.i >> 7)) * g.ldc + n0 + (k.i & 127));
   }
 }
 
@@ -360,14 +477,22 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, int64_t vb) {
   }
   if constexpr (TC) {
     const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
-    auto get = [&](int e) -> TcKey<double> {
+    const int rem_m = (int)(g.M - m0 < BM ? g.M - m0 : BM), rem_n = (int)(g.N - n0 < BN ? g.N - n0 : BN);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] *= g.alpha;
+    // f64 16x16x4 accumulators: item v of lane l is row l/16 + 4v, column l%16
+    const int base = (wm + (lane >> 4)) * 128 + wn + (lane & 15);
+    auto val = [&](int e) -> double { return acc[e >> 4][(e >> 2) & 3][e & 3]; };
+    auto koff = [](int e) -> int { return ((e >> 4) * 16 + 4 * (e & 3)) * 128 + ((e >> 2) & 3) * 16; };
+    auto valid = [&](int e) -> bool {
       const int i = e >> 4, j = (e >> 2) & 3, v = e & 3;
-      const int r = wm + i * 16 + (lane >> 4) + 4 * v, c = wn + j * 16 + (lane & 15);
-      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
-      return TcKey<double>{g.alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+      return (wm + i * 16 + (lane >> 4) + 4 * v < rem_m) & (wn + j * 16 + (lane & 15) < rem_n);
     };
-    auto raw = [&](int e) -> double { return g.alpha * acc[e >> 4][(e >> 2) & 3][e & 3]; };
-    topc_tile<double, 32, 512>(g, tc.z, m0, n0, full, get, raw);
+    topc_tile<double, 32, 512>(g, tc.z, m0, n0, full, val, koff, base, valid);
     return;
   }
   double* C = static_cast<double*>(g.C) + tc.z * g.sCz;
@@ -385,7 +510,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, int64_t vb) {
 }
 
 template <bool NT, bool TC = false>
-__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+__global__ void __launch_bounds__(512) gemm_f64_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp,
+                                                       int64_t gp_stride) {
   CQ_TILE_LOOP((gemm_f64_tile<NT, TC>(g, vb)))
 }
 
@@ -449,15 +575,25 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int64_t vb) {
   }
   if constexpr (TC) {
     const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
-    auto get = [&](int e) -> TcKey<float> {
-      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
-      const int r = wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const int c = wn + j * 32 + (lane & 31);
-      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
-      return TcKey<float>{alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+    const int rem_m = (int)(g.M - m0 < BM ? g.M - m0 : BM), rem_n = (int)(g.N - n0 < BN ? g.N - n0 : BN);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] *= alpha;
+    // 32x32 accumulators: item v of lane l is row 8(v/4) + 4(l/32) + v%4, column l%32
+    const int base = (wm + 4 * (lane >> 5)) * 128 + wn + (lane & 31);
+    auto val = [&](int e) -> float { return acc[e >> 5][(e >> 4) & 1][e & 15]; };
+    auto koff = [](int e) -> int {
+      const int v = e & 15;
+      return ((e >> 5) * 32 + 8 * (v >> 2) + (v & 3)) * 128 + ((e >> 4) & 1) * 32;
     };
-    auto raw = [&](int e) -> float { return alpha * acc[e >> 5][(e >> 4) & 1][e & 15]; };
-    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, get, raw);
+    auto valid = [&](int e) -> bool {
+      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
+      return (wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3) < rem_m) & (wn + j * 32 + (lane & 31) < rem_n);
+    };
+    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, val, koff, base, valid);
     return;
   }
   float* C = static_cast<float*>(g.C) + tc.z * g.sCz;
@@ -474,7 +610,8 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int64_t vb) {
 }
 
 template <bool NT, bool TC = false>
-__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp,
+                                                       int64_t gp_stride) {
   CQ_TILE_LOOP((gemm_f32_tile<NT, TC>(g, vb)))
 }
 
@@ -640,15 +777,25 @@ __device__ __forceinline__ void gemm_h16_tile(const GemmArgs& g, int64_t vb) {
   const float alpha = float(g.alpha);
   if constexpr (OUT == 3) {
     const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
-    auto get = [&](int e) -> TcKey<float> {
-      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
-      const int r = wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const int c = wn + j * 32 + (lane & 31);
-      const bool ok = full || (m0 + r < g.M && n0 + c < g.N);
-      return TcKey<float>{alpha * acc[i][j][v], ok ? (uint32_t)(r * 128 + c) : 0xffffffffu};
+    const int rem_m = (int)(g.M - m0 < BM ? g.M - m0 : BM), rem_n = (int)(g.N - n0 < BN ? g.N - n0 : BN);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] *= alpha;
+    // 32x32 accumulators: item v of lane l is row 8(v/4) + 4(l/32) + v%4, column l%32
+    const int base = (wm + 4 * (lane >> 5)) * 128 + wn + (lane & 31);
+    auto val = [&](int e) -> float { return acc[e >> 5][(e >> 4) & 1][e & 15]; };
+    auto koff = [](int e) -> int {
+      const int v = e & 15;
+      return ((e >> 5) * 32 + 8 * (v >> 2) + (v & 3)) * 128 + ((e >> 4) & 1) * 32;
     };
-    auto raw = [&](int e) -> float { return alpha * acc[e >> 5][(e >> 4) & 1][e & 15]; };
-    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, get, raw);
+    auto valid = [&](int e) -> bool {
+      const int i = e >> 5, j = (e >> 4) & 1, v = e & 15;
+      return (wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3) < rem_m) & (wn + j * 32 + (lane & 31) < rem_n);
+    };
+    topc_tile<float, 64, 256>(g, tc.z, m0, n0, full, val, koff, base, valid);
     return;
   }
   const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
@@ -682,7 +829,8 @@ __device__ __forceinline__ void gemm_h16_tile(const GemmArgs& g, int64_t vb) {
 
 template <int SPLIT, bool F16, int OUT>
 __global__ void __launch_bounds__(256, SPLIT == 3 ? 1 : 2) gemm_h16_kernel(GemmArgs gv,
-                                                                           const GemmArgs* __restrict__ gp) {
+                                                                           const GemmArgs* __restrict__ gp,
+                                                                           int64_t gp_stride) {
   CQ_TILE_LOOP((gemm_h16_tile<SPLIT, F16, OUT>(g, vb)))
 }
 
@@ -734,7 +882,8 @@ __device__ inline void wait_vm_n(int n) {
 }
 
 template <int SPLIT, bool F16, int OUT, int NS>
-__global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp) {
+__global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmArgs* __restrict__ gp,
+                                                        int64_t gp_stride) {
   CQ_LOAD_GEMM_ARGS
   using H = Half<F16>;
   using V8 = typename H::V8;
@@ -1459,17 +1608,18 @@ __global__ void __launch_bounds__(256, 2) gemm_persist_kernel(GemmArgs g) {
 template <typename K>
 hipError_t launch(K kernel, const GemmArgs& a, hipStream_t s, int threads = 256) {
   hipLaunchKernelGGL(kernel, dim3((unsigned)a.tiles), dim3(threads), 0, s, a,
-                     static_cast<const GemmArgs*>(nullptr));
+                     static_cast<const GemmArgs*>(nullptr), (int64_t)0);
   return hipGetLastError();
 }
 
 template <typename K>
-hipError_t launch_ind(K kernel, const GemmArgs* dev, int64_t max_tiles, hipStream_t s,
+hipError_t launch_ind(K kernel, const GemmArgs* dev, int64_t max_tiles, hipStream_t s, InstSpan span,
                       int threads = 256) {
-  if (max_tiles <= 0) return hipSuccess;
+  if (max_tiles <= 0 || span.n <= 0) return hipSuccess;
   if (max_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
   GemmArgs dummy{};
-  hipLaunchKernelGGL(kernel, dim3((unsigned)max_tiles), dim3(threads), 0, s, dummy, dev);
+  hipLaunchKernelGGL(kernel, dim3((unsigned)max_tiles, 1, (unsigned)span.n), dim3(threads), 0, s, dummy, dev,
+                     span.stride);
   return hipGetLastError();
 }
 
@@ -1809,38 +1959,118 @@ __device__ inline double operand_at(const void* hi, const void* lo, int64_t i) {
   }
 }
 
-// One wave per 128-element row segment of A (then of B): its max |value|.
+// max |value| over elements i .. i+3, with one vector load per plane when
+// they are aligned for it
+template <int KIND>
+__device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i) {
+  double m = 0.0;
+  if constexpr (KIND == 1) {
+    const float* p = static_cast<const float*>(hi) + i;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      return double(fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+  } else if constexpr (KIND == 0) {
+    const double* p = static_cast<const double*>(hi) + i;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+      return fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(b.x), fabs(b.y)));
+    }
+  } else {
+    const uint16_t* h = static_cast<const uint16_t*>(hi) + i;
+    const uint16_t* l = lo ? static_cast<const uint16_t*>(lo) + i : nullptr;
+    if ((reinterpret_cast<uintptr_t>(h) & 7) == 0 && (!l || (reinterpret_cast<uintptr_t>(l) & 7) == 0)) {
+      const uint2 hv = *reinterpret_cast<const uint2*>(h);
+      const uint2 lv = l ? *reinterpret_cast<const uint2*>(l) : make_uint2(0u, 0u);
+      const uint16_t hs[4] = {(uint16_t)hv.x, (uint16_t)(hv.x >> 16), (uint16_t)hv.y, (uint16_t)(hv.y >> 16)};
+      const uint16_t ls[4] = {(uint16_t)lv.x, (uint16_t)(lv.x >> 16), (uint16_t)lv.y, (uint16_t)(lv.y >> 16)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = double(from_h16<KIND == 3>(hs[q]));
+        if (l) v += double(from_h16<KIND == 3>(ls[q]));
+        m = fmax(m, fabs(v));
+      }
+      return m;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) m = fmax(m, fabs(operand_at<KIND>(hi, lo, i + q)));
+  return m;
+}
+
+// Max |value| of every 128-element row segment of A (then of B).  Each half
+// wave takes a segment (four consecutive elements per lane), and a wave
+// loads four pairs of segments before reducing any, so sixteen loads per
+// lane are in flight; the waves of the grid take the segments in turn.
 template <int KIND>
 __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __restrict__ gp, float* amax,
-                                                          float* bmax) {
-  const GemmArgs g = *gp;
-  const int lane = threadIdx.x & 63;
-  const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+                                                          float* bmax, int64_t slot) {
+  constexpr int U = 4;  // segment pairs per wave and round
+  const GemmArgs g = *inst_ptr(gp, slot);
+  amax = inst_ptr(amax, slot);
+  bmax = inst_ptr(bmax, slot);
+  const int lane = threadIdx.x & 63, half = lane >> 5, sub = lane & 31;
   const int64_t Z = g.tilesM * g.tilesN > 0 ? g.tiles / (g.tilesM * g.tilesN) : 0;
   const int64_t za_n = g.sAz ? Z : 1, zb_n = g.sBz ? Z : 1;
   const int64_t na = za_n * g.K * g.tilesM, nb = zb_n * g.K * g.tilesN;
-  if (seg >= na + nb) return;  // whole waves exit together
-  const bool isA = seg < na;
-  const int64_t s = isA ? seg : seg - na;
-  const int64_t tl = isA ? g.tilesM : g.tilesN;
-  const int64_t t = s % tl, zk = s / tl, k = zk % g.K, z = zk / g.K;
-  const int64_t base = isA ? z * g.sAz + k * g.sAk : z * g.sBz + k * g.sBk;
-  const int64_t lim = isA ? g.M : g.N;
-  const void* hi = isA ? g.A : g.B;
-  const void* lo = isA ? g.A_lo : g.B_lo;
-  double m = 0.0;
-  for (int e = lane; e < 128; e += 64) {
-    const int64_t c = t * 128 + e;
-    if (c < lim) m = fmax(m, fabs(operand_at<KIND>(hi, lo, base + c)));
+  const int64_t total = na + nb;
+  const bool small = total < ((int64_t)1 << 31) && g.K < ((int64_t)1 << 31);
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * 2 * U < total; w += waves) {
+    double m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      m[u] = 0.0;
+      const int64_t seg = (w * U + u) * 2 + half;
+      if (seg < total) {
+        const bool isA = seg < na;
+        const int64_t s = isA ? seg : seg - na;
+        const int64_t tl = isA ? g.tilesM : g.tilesN;
+        int64_t t, k, z;
+        if (small) {  // 32-bit division: the 64-bit one costs a hundred instructions
+          const uint32_t s32 = (uint32_t)s, tl32 = (uint32_t)tl, K32 = (uint32_t)g.K, zk = s32 / tl32;
+          t = s32 - zk * tl32;
+          z = zk / K32;
+          k = zk - (uint32_t)z * K32;
+        } else {
+          const int64_t zk = s / tl;
+          t = s - zk * tl;
+          z = zk / g.K;
+          k = zk - z * g.K;
+        }
+        const int64_t base = isA ? z * g.sAz + k * g.sAk : z * g.sBz + k * g.sBk;
+        const int64_t lim = isA ? g.M : g.N;
+        const void* hi = isA ? g.A : g.B;
+        const void* lo = isA ? g.A_lo : g.B_lo;
+        const int64_t c0 = t * 128 + sub * 4;
+        if (c0 + 4 <= lim) {
+          m[u] = quad_absmax<KIND>(hi, lo, base + c0);
+        } else {
+          for (int q = 0; q < 4; ++q)
+            if (c0 + q < lim) m[u] = fmax(m[u], fabs(operand_at<KIND>(hi, lo, base + c0 + q)));
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      for (int o = 16; o >= 1; o >>= 1) m[u] = fmax(m[u], __shfl_xor(m[u], o));  // within the half wave
+      const int64_t seg = (w * U + u) * 2 + half;
+      if (sub == 0 && seg < total) {
+        const bool isA = seg < na;
+        (isA ? amax : bmax)[isA ? seg : seg - na] = __double2float_ru(m[u]);
+      }
+    }
   }
-  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  if (lane == 0) (isA ? amax : bmax)[s] = __double2float_ru(m);
 }
 
 __global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restrict__ gp,
                                                          const float* __restrict__ amax,
-                                                         const float* __restrict__ bmax, float* U) {
-  const GemmArgs g = *gp;
+                                                         const float* __restrict__ bmax, float* U,
+                                                         int64_t slot) {
+  const GemmArgs g = *inst_ptr(gp, slot);
+  amax = inst_ptr(amax, slot);
+  bmax = inst_ptr(bmax, slot);
+  U = inst_ptr(U, slot);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.tiles) return;
   const TileCoord c = tile_coord_of<128, 128>(g, t);
@@ -1859,9 +2089,13 @@ __global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restr
 __global__ void __launch_bounds__(256) tile_warm_kernel(const float* __restrict__ U,
                                                         const int64_t* __restrict__ n_tiles,
                                                         const int64_t* __restrict__ warm,
-                                                        uint64_t* list) {
+                                                        uint64_t* list, int64_t slot) {
   __shared__ float bv[4];
   __shared__ uint64_t bi[4];
+  U = inst_ptr(U, slot);
+  n_tiles = inst_ptr(n_tiles, slot);
+  warm = inst_ptr(warm, slot);
+  list = inst_ptr(list, slot);
   const int64_t n = *n_tiles, w = *warm;
   if ((int64_t)blockIdx.x >= w) return;
   const int64_t chunk = n / w;
@@ -1901,93 +2135,112 @@ __global__ void __launch_bounds__(256) tile_warm_kernel(const float* __restrict_
 __global__ void __launch_bounds__(256) tile_compact_kernel(const float* __restrict__ U,
                                                            const int64_t* __restrict__ n_tiles,
                                                            const unsigned long long* __restrict__ thr,
-                                                           uint64_t* list, int64_t* count) {
+                                                           uint64_t* list, int64_t* count, int64_t slot) {
+  U = inst_ptr(U, slot);
+  n_tiles = inst_ptr(n_tiles, slot);
+  thr = inst_ptr(thr, slot);
+  list = inst_ptr(list, slot);
+  count = inst_ptr(count, slot);
+  // one atomic per wave: lanes take consecutive places by their rank among
+  // the wave's passing lanes
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= *n_tiles) return;
-  if (double(U[t]) >= ord_val(*thr)) {
-    const unsigned long long p = atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
-    list[p] = (uint64_t)t;
-  }
+  const int64_t n = *n_tiles;
+  const bool pass = t < n && double(U[t]) >= ord_val(*thr);
+  const uint64_t bal = __ballot(pass);
+  if (bal == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int rank = __popcll(bal & ((1ull << lane) - 1));
+  unsigned long long base = 0;
+  if (rank == 0 && pass)
+    base = atomicAdd(reinterpret_cast<unsigned long long*>(count), (unsigned long long)__popcll(bal));
+  base = (unsigned long long)__shfl((long long)base, __ffsll((unsigned long long)bal) - 1);
+  if (pass) list[base + rank] = (uint64_t)t;
 }
 
 }  // namespace
 
 hipError_t launch_tile_bounds(const GemmArgs* dev, DType t, bool f16, float* amax, float* bmax,
                               float* U, int64_t max_seg_a, int64_t max_seg_b, int64_t max_tiles,
-                              hipStream_t stream) {
+                              hipStream_t stream, InstSpan span) {
   const int64_t segs = max_seg_a + max_seg_b;
-  if (segs <= 0 || max_tiles <= 0) return hipSuccess;
-  const dim3 g1((unsigned)((segs * 64 + 255) / 256));
+  if (segs <= 0 || max_tiles <= 0 || span.n <= 0) return hipSuccess;
+  const int64_t blocks = (segs * 64 + 255) / 256;
+  const dim3 g1((unsigned)(blocks < 1024 ? blocks : 1024), 1, (unsigned)span.n);
+  const int64_t sl = span.stride;
   switch (t) {
-    case DType::F64: hipLaunchKernelGGL(tile_rowmax_kernel<0>, g1, dim3(256), 0, stream, dev, amax, bmax); break;
-    case DType::F32: hipLaunchKernelGGL(tile_rowmax_kernel<1>, g1, dim3(256), 0, stream, dev, amax, bmax); break;
+    case DType::F64: hipLaunchKernelGGL(tile_rowmax_kernel<0>, g1, dim3(256), 0, stream, dev, amax, bmax, sl); break;
+    case DType::F32: hipLaunchKernelGGL(tile_rowmax_kernel<1>, g1, dim3(256), 0, stream, dev, amax, bmax, sl); break;
     default:
-      if (f16) hipLaunchKernelGGL(tile_rowmax_kernel<3>, g1, dim3(256), 0, stream, dev, amax, bmax);
-      else hipLaunchKernelGGL(tile_rowmax_kernel<2>, g1, dim3(256), 0, stream, dev, amax, bmax);
+      if (f16) hipLaunchKernelGGL(tile_rowmax_kernel<3>, g1, dim3(256), 0, stream, dev, amax, bmax, sl);
+      else hipLaunchKernelGGL(tile_rowmax_kernel<2>, g1, dim3(256), 0, stream, dev, amax, bmax, sl);
       break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(tile_bound_kernel, dim3((unsigned)((max_tiles + 255) / 256)), dim3(256), 0, stream,
-                     dev, (const float*)amax, (const float*)bmax, U);
+  hipLaunchKernelGGL(tile_bound_kernel, dim3((unsigned)((max_tiles + 255) / 256), 1, (unsigned)span.n),
+                     dim3(256), 0, stream, dev, (const float*)amax, (const float*)bmax, U, sl);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_warm(const float* U, const int64_t* n_tiles, const int64_t* warm,
-                            uint64_t* list, int max_warm, hipStream_t stream) {
-  if (max_warm <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_warm_kernel, dim3((unsigned)max_warm), dim3(256), 0, stream, U, n_tiles, warm,
-                     list);
+                            uint64_t* list, int max_warm, hipStream_t stream, InstSpan span) {
+  if (max_warm <= 0 || span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_warm_kernel, dim3((unsigned)max_warm, 1, (unsigned)span.n), dim3(256), 0, stream, U,
+                     n_tiles, warm, list, span.stride);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_compact(const float* U, const int64_t* n_tiles,
                                const unsigned long long* thr_key, uint64_t* list,
-                               int64_t* count, int64_t max_tiles, hipStream_t stream) {
-  if (max_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_compact_kernel, dim3((unsigned)((max_tiles + 255) / 256)), dim3(256), 0,
-                     stream, U, n_tiles, thr_key, list, count);
+                               int64_t* count, int64_t max_tiles, hipStream_t stream, InstSpan span) {
+  if (max_tiles <= 0 || span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_compact_kernel, dim3((unsigned)((max_tiles + 255) / 256), 1, (unsigned)span.n),
+                     dim3(256), 0, stream, U, n_tiles, thr_key, list, count, span.stride);
   return hipGetLastError();
 }
 
 constexpr int64_t kTopcGrid = 1024;
+constexpr int64_t kIndGrid = 4096;
 
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
-                                DType tc, bool nontemporal, bool topc, hipStream_t stream) {
+                                DType tc, bool nontemporal, bool topc, hipStream_t stream,
+                                InstSpan span) {
   if (topc) {
     // the tiles come from a pruned list whose length only the device knows:
     // a few workgroups per CU walk it instead of one per possible tile (a
     // grid of 2^18 workgroups that mostly exit costs 0.4-0.8 ms by itself)
     const int64_t grid = max_tiles < kTopcGrid ? max_tiles : kTopcGrid;
     switch (prec) {
-      case CQ_FP64: return launch_ind(gemm_f64_kernel<false, true>, dev, grid, stream, 512);
-      case CQ_FP32: return launch_ind(gemm_f32_kernel<false, true>, dev, grid, stream);
-      case CQ_BF16: return launch_ind(gemm_h16_kernel<1, false, 3>, dev, grid, stream);
-      case CQ_BF16_SPLIT: return launch_ind(gemm_h16_kernel<3, false, 3>, dev, grid, stream);
-      case CQ_FP16: return launch_ind(gemm_h16_kernel<1, true, 3>, dev, grid, stream);
-      case CQ_FP16_SPLIT: return launch_ind(gemm_h16_kernel<3, true, 3>, dev, grid, stream);
+      case CQ_FP64: return launch_ind(gemm_f64_kernel<false, true>, dev, grid, stream, span, 512);
+      case CQ_FP32: return launch_ind(gemm_f32_kernel<false, true>, dev, grid, stream, span);
+      case CQ_BF16: return launch_ind(gemm_h16_kernel<1, false, 3>, dev, grid, stream, span);
+      case CQ_BF16_SPLIT: return launch_ind(gemm_h16_kernel<3, false, 3>, dev, grid, stream, span);
+      case CQ_FP16: return launch_ind(gemm_h16_kernel<1, true, 3>, dev, grid, stream, span);
+      case CQ_FP16_SPLIT: return launch_ind(gemm_h16_kernel<3, true, 3>, dev, grid, stream, span);
     }
     return hipErrorInvalidValue;
   }
+  // beyond kIndGrid tiles the workgroups loop (a multiple of 8 keeps each on its XCD)
+  max_tiles = max_tiles < kIndGrid ? max_tiles : kIndGrid;
   switch (prec) {
     case CQ_FP64:
-      return nontemporal ? launch_ind(gemm_f64_kernel<true>, dev, max_tiles, stream, 512)
-                         : launch_ind(gemm_f64_kernel<false>, dev, max_tiles, stream, 512);
+      return nontemporal ? launch_ind(gemm_f64_kernel<true>, dev, max_tiles, stream, span, 512)
+                         : launch_ind(gemm_f64_kernel<false>, dev, max_tiles, stream, span, 512);
     case CQ_FP32:
-      return nontemporal ? launch_ind(gemm_f32_kernel<true>, dev, max_tiles, stream)
-                         : launch_ind(gemm_f32_kernel<false>, dev, max_tiles, stream);
+      return nontemporal ? launch_ind(gemm_f32_kernel<true>, dev, max_tiles, stream, span)
+                         : launch_ind(gemm_f32_kernel<false>, dev, max_tiles, stream, span);
     case CQ_BF16:
-      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, false, 0>, dev, max_tiles, stream);
-      return launch_ind(gemm_h16_kernel<1, false, 2>, dev, max_tiles, stream);
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, false, 0>, dev, max_tiles, stream, span);
+      return launch_ind(gemm_h16_kernel<1, false, 2>, dev, max_tiles, stream, span);
     case CQ_BF16_SPLIT:
-      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, false, 0>, dev, max_tiles, stream);
-      return launch_ind(gemm_h16_kernel<3, false, 2>, dev, max_tiles, stream);
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, false, 0>, dev, max_tiles, stream, span);
+      return launch_ind(gemm_h16_kernel<3, false, 2>, dev, max_tiles, stream, span);
     case CQ_FP16:
-      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, true, 0>, dev, max_tiles, stream);
-      return launch_ind(gemm_h16_kernel<1, true, 2>, dev, max_tiles, stream);
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<1, true, 0>, dev, max_tiles, stream, span);
+      return launch_ind(gemm_h16_kernel<1, true, 2>, dev, max_tiles, stream, span);
     case CQ_FP16_SPLIT:
-      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, true, 0>, dev, max_tiles, stream);
-      return launch_ind(gemm_h16_kernel<3, true, 2>, dev, max_tiles, stream);
+      if (tc == DType::F32) return launch_ind(gemm_h16_kernel<3, true, 0>, dev, max_tiles, stream, span);
+      return launch_ind(gemm_h16_kernel<3, true, 2>, dev, max_tiles, stream, span);
   }
   return hipErrorInvalidValue;
 }

@@ -11,6 +11,22 @@
 
 namespace cq {
 
+// Instances launched together (dynamic definition): a launch covers n
+// instances along grid z, and instance z's argument blocks and buffers are
+// those of instance 0 moved by z * stride bytes (each instance of such a batch
+// owns a slot of `stride` bytes, all slots with one layout).
+struct InstSpan {
+  int n = 1;
+  int64_t stride = 0;
+};
+
+// p moved to the slot of this workgroup's instance (null stays null).
+template <typename T>
+__device__ __forceinline__ T* inst_ptr(T* p, int64_t slot) {
+  if (!p) return p;
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((int64_t)blockIdx.z * slot));
+}
+
 // Storage formats of contraction operands.  H16: one plane of 16-bit values
 // (BF16 or FP16); H16X2: a hi plane followed by a lo plane of the same length
 // (x = hi + lo).
@@ -75,7 +91,10 @@ struct GemmArgs {
   const int32_t* topc_C;
   double* topc_v;
   uint64_t* topc_i;
-  int topc_publish_only;           // raise the threshold only, append nothing
+  // 0: exact; 1: warm-up, raise the threshold only, append nothing; 2:
+  // warm-up, append the exact C best where they are cheap to find, else
+  // raise the threshold by a bound only
+  int topc_publish_only;
   // Optional tile list: workgroup b takes tile tile_list[b] if b < *tile_count.
   const uint64_t* tile_list;
   const int64_t* tile_count;
@@ -87,21 +106,25 @@ struct GemmArgs {
 // every output of tile t (inflated for FP32 accumulation, rounded up).
 hipError_t launch_tile_bounds(const GemmArgs* dev, DType t, bool f16, float* amax, float* bmax,
                               float* U, int64_t max_seg_a, int64_t max_seg_b, int64_t max_tiles,
-                              hipStream_t stream);
+                              hipStream_t stream, InstSpan span = InstSpan());
 // list[b] <- the tile with the largest bound in slice b of *warm slices.
 hipError_t launch_tile_warm(const float* U, const int64_t* n_tiles, const int64_t* warm,
-                            uint64_t* list, int max_warm, hipStream_t stream);
+                            uint64_t* list, int max_warm, hipStream_t stream, InstSpan span = InstSpan());
 // list <- the tiles t < *n_tiles with U[t] >= the threshold, *count their number.
 hipError_t launch_tile_compact(const float* U, const int64_t* n_tiles,
                                const unsigned long long* thr_key, uint64_t* list,
-                               int64_t* count, int64_t max_tiles, hipStream_t stream);
+                               int64_t* count, int64_t max_tiles, hipStream_t stream,
+                               InstSpan span = InstSpan());
 
-// Launches `max_tiles` workgroups of the precision's GEMM kernel reading its
-// arguments from device memory (`dev`); surplus workgroups exit.  Operands and
-// output are in the precision's storage format (tc: F32/F64 output or the
-// precision's own planes); the register-path 16-bit kernel is used.
+// Runs the precision's GEMM kernel on arguments in device memory (`dev`) for
+// up to `max_tiles` tiles: at most 4096 workgroups (1024 with topc) per
+// instance of `span`, each looping over the tiles that the stored tile count
+// (or tile list) holds.  Operands and output are in the precision's storage
+// format (tc: F32/F64 output or the precision's own planes); the
+// register-path 16-bit kernel is used.
 hipError_t launch_gemm_indirect(cq_precision prec, const GemmArgs* dev, int64_t max_tiles,
-                                DType tc, bool nontemporal, bool topc, hipStream_t stream);
+                                DType tc, bool nontemporal, bool topc, hipStream_t stream,
+                                InstSpan span = InstSpan());
 
 // Converts n FP64 values to `t` (FP32, or BF16/FP16 planes when f16 is false/true).
 // rexp (optional): element i is first multiplied by 2^rexp[i >> cols_log2]
@@ -185,21 +208,6 @@ struct AttrLaunch {
 };
 hipError_t launch_attribute(const AttrLaunch& a, hipStream_t stream);
 
-// Dynamic definition helpers.
-struct RefineLaunch {
-  int n_sub, K;
-  const double* Ep[CQ_MAX_SUBCIRCUITS];
-  int64_t ld[CQ_MAX_SUBCIRCUITS];      // columns of Ep[c]
-  int na[CQ_MAX_SUBCIRCUITS];          // active bits of c
-  int kc[CQ_MAX_SUBCIRCUITS];
-  int cut[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];
-  const uint64_t* bins;                // device, nbins
-  int nbins;
-  double scale;                        // 2^-K
-  double* out;                         // device, nbins
-};
-// FP64 value of chosen bins: scale * sum over all 4^K labels of prod_c Ep[c][row][a_c].
-hipError_t launch_refine(const RefineLaunch& r, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Kernel argument blocks.  Host launchers fill them; the device-driven
@@ -240,28 +248,31 @@ struct MergeArgs {
   uint64_t active_flat, merged_lo, merged_hi, fixed_vals_flat;
 };
 
+// FP64 value of chosen bins: out[b] = scale * sum over all 4^K labels of
+// prod_c Ep[c][row_c(label)][a_c(bins[b])].
 struct RefineArgs {
   int n_sub, K;
   const double* Ep[CQ_MAX_SUBCIRCUITS];
-  int64_t ld[CQ_MAX_SUBCIRCUITS];
-  int na[CQ_MAX_SUBCIRCUITS];
+  int64_t ld[CQ_MAX_SUBCIRCUITS];      // columns of Ep[c]
+  int na[CQ_MAX_SUBCIRCUITS];          // active bits of c
   int kc[CQ_MAX_SUBCIRCUITS];
   int cut[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS];
-  const uint64_t* bins;
+  const uint64_t* bins;                // device, nbins
   int nbins;
-  double scale;
-  double* out;
+  double scale;                        // 2^-K
+  double* out;                         // device, nbins
 };
 
 // Indirect launches: `max_*` bounds the grid; the kernels read their
 // arguments from device memory and skip work beyond the stored sizes.
 hipError_t launch_permute_indirect(const PermArgs* dev, DType ts, DType td, bool f16,
-                                   int64_t max_total, hipStream_t stream);
+                                   int64_t max_total, hipStream_t stream, InstSpan span = InstSpan());
 hipError_t launch_prep_indirect(const PrepArgs* dev, int count, DType t, bool f16,
-                                int64_t max_n, hipStream_t stream);
+                                int64_t max_n, hipStream_t stream, InstSpan span = InstSpan());
 hipError_t launch_merge_indirect(const MergeArgs* dev, int count, int64_t max_threads,
-                                 hipStream_t stream);
-hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream);
+                                 hipStream_t stream, InstSpan span = InstSpan());
+hipError_t launch_refine_indirect(const RefineArgs* dev, int max_bins, hipStream_t stream,
+                                  InstSpan span = InstSpan());
 // Top-C of *count bins (value desc, index asc) with C = *C_dev <= C_max
 // (nothing when C <= 0): pass one keeps C_max keys per workgroup in the
 // candidate buffers, pass two selects from them.
@@ -276,7 +287,7 @@ constexpr int kTopcStage = 256;
 hipError_t launch_topk_candidates(const double* cand_val, const uint64_t* cand_idx,
                                   const int64_t* count_dev, const int32_t* C_dev, int C_max,
                                   double* stage_val, uint64_t* stage_idx, double* out_val,
-                                  uint64_t* out_idx, hipStream_t stream);
+                                  uint64_t* out_idx, hipStream_t stream, InstSpan span = InstSpan());
 
 // ---------------------------------------------------------------------------
 // Device-driven dynamic definition (Algorithm 1).  One recursion is a fixed
@@ -323,6 +334,13 @@ struct DDPermSym {
   double alpha;
 };
 
+struct DDInit {  // recursion-0 masks
+  uint64_t active[CQ_MAX_SUBCIRCUITS];
+  uint64_t merged[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
+  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
+};
+
 struct DDProgram {
   int32_t n_sub, K, R, n_steps;
   int32_t C_max;                             // min(4R, 64)
@@ -347,6 +365,8 @@ struct DDProgram {
   uint64_t* tile_list;
   double* warm_v;                            // the 64 tiles with the largest bounds
   uint64_t* warm_i;
+  DDInit init;
+  RefineArgs total;                          // the recursion total: the row sums' single bin
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -397,25 +417,22 @@ struct DDLevel {  // descriptors of the current recursion
   RefineArgs refine;
 };
 
-struct DDInit {
-  uint64_t active[CQ_MAX_SUBCIRCUITS];
-  uint64_t merged[CQ_MAX_SUBCIRCUITS];
-  uint64_t fixed[CQ_MAX_SUBCIRCUITS];
-  uint64_t fixed_vals[CQ_MAX_SUBCIRCUITS];
-};
-
-// State <- recursion-0 masks, list empty, records zeroed.
+// Threshold from the warm-up tiles' candidates (the C-th best of them, C =
+// *C_dev), then the candidate count back to zero.
+hipError_t launch_warm_tau(const double* cand_v, unsigned long long* count, const int32_t* C_dev,
+                           unsigned long long* thr, hipStream_t stream, InstSpan span = InstSpan());
 // `blocks` copies of `bytes` (a multiple of 4, 4-byte aligned) between
 // strided regions of device memory.
 hipError_t launch_dd_copy(const void* src, int64_t src_stride, void* dst, int64_t dst_stride,
                           int64_t bytes, int blocks, hipStream_t stream);
-hipError_t launch_dd_init(DDState* st, cq_dd_record* recs, int R, const DDInit& init,
-                          hipStream_t stream);
+// State <- the program's recursion-0 masks, list empty, records zeroed.
+hipError_t launch_dd_init(const DDProgram* prog, DDState* st, cq_dd_record* recs, int R,
+                          hipStream_t stream, InstSpan span = InstSpan());
 // Descriptors of recursion r from the state; `bins` receives its bins.
 hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_dd_record* recs,
-                           int r, void* bins, hipStream_t stream);
+                           int r, void* bins, hipStream_t stream, InstSpan span = InstSpan());
 // List update, record r and zoom into the popped bin.
 hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
-                            hipStream_t stream);
+                            hipStream_t stream, InstSpan span = InstSpan());
 
 }  // namespace cq
