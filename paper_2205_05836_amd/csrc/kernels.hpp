@@ -20,12 +20,14 @@ struct InstSpan {
   int64_t stride = 0;
 };
 
+#ifdef __HIPCC__
 // p moved to the slot of this workgroup's instance (null stays null).
 template <typename T>
 __device__ __forceinline__ T* inst_ptr(T* p, int64_t slot) {
   if (!p) return p;
   return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((int64_t)blockIdx.z * slot));
 }
+#endif
 
 // Storage formats of contraction operands.  H16: one plane of 16-bit values
 // (BF16 or FP16); H16X2: a hi plane followed by a lo plane of the same length
