@@ -892,6 +892,9 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
   constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
   constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
   constexpr int LPW = 2 * 2 * NP;       // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage; the
+  // build checks the assembly against this marker
+  asm volatile("; cq-vm-lpw %0" ::"n"(LPW));
   constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
   constexpr int EPI = 4 * 64 * EROW;
   constexpr int SMEM = NS * STAGE > EPI ? NS * STAGE : EPI;
@@ -1096,6 +1099,9 @@ gemm_h16t_kernel(GemmArgs g) {
   constexpr int TILE = BK * 256;        // bytes of one operand-plane stage
   constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
   constexpr int LPW = 2 * NP;           // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage; the
+  // build checks the assembly against this marker
+  asm volatile("; cq-vm-lpw %0" ::"n"(LPW));
   constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
   constexpr int EPI = 4 * 8 * EROW;
   constexpr int SMEM = NS * STAGE > EPI ? NS * STAGE : EPI;
@@ -1399,6 +1405,10 @@ __global__ void __launch_bounds__(256, 2) gemm_persist_kernel(GemmArgs g) {
   constexpr int TILE = 8192;            // bytes of one operand-plane stage
   constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
   constexpr int LPW = 2 * 2 * NP;       // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage and one
+  // store instruction per output row and plane; the build checks the assembly
+  // against this marker
+  asm volatile("; cq-vm-lpw %0 out %1" ::"n"(LPW), "n"(OUT));
   constexpr int RING = NS * STAGE;
   constexpr int EROW = 288;             // bytes per staged output row (64 floats + pad)
   static_assert(NS >= 2 && NS <= 5, "stage count");
