@@ -203,6 +203,13 @@ cq_status cq_reconstruct_fd_noalloc(int32_t n_sub, const cq_subcircuit* subs,
  * fixed at the bin's values and the first max_active[c] of its merged outputs
  * (output order) become active for the next recursion.  The run stops after R
  * recursions or when L is empty at a pop.
+ *
+ * Algorithm 1's state between two recursions -- the list L (each entry with
+ * the masks of its bin), the next recursion index r and the masks to
+ * reconstruct next -- can be saved after a call (params.checkpoint) and a
+ * later call can continue from it (params.resume), so a run may be split
+ * over several calls (params.recursions per call) and resumed after an
+ * interruption.
  * ------------------------------------------------------------------------- */
 typedef struct cq_dd_instance {
   int32_t n_sub;
@@ -224,9 +231,21 @@ typedef struct cq_dd_params {
   cq_precision prec;  /* arithmetic of the bin contraction */
   int32_t R;          /* recursions and list capacity, 1..CQ_MAX_DD_R */
   int32_t launch;     /* cq_dd_launch */
+  int32_t recursions; /* recursions this call runs per instance, counted from the state it
+                         starts at; 0 or more than remain: up to recursion R - 1 */
+  const void* resume; /* host, NULL or n_inst checkpoints (cq_dd_checkpoint_bytes each, as
+                         written by an earlier call with the same instances, prec and R):
+                         instance i continues from checkpoint i instead of its masks */
+  void* checkpoint;   /* host, NULL or room for n_inst checkpoints: receives each instance's
+                         state after the call */
 } cq_dd_params;
 
+/* Bytes of one instance's checkpoint (an opaque blob, valid for the library
+ * build that wrote it). */
+size_t cq_dd_checkpoint_bytes(void);
+
 typedef struct cq_dd_record {  /* one recursion, written by the library */
+  int32_t recursion;            /* its index r (0 for the first recursion of a fresh run) */
   uint64_t active[CQ_MAX_SUBCIRCUITS];
   uint64_t merged[CQ_MAX_SUBCIRCUITS];
   uint64_t fixed[CQ_MAX_SUBCIRCUITS];
@@ -245,25 +264,30 @@ typedef struct cq_dd_record {  /* one recursion, written by the library */
                                    the others) */
 } cq_dd_record;
 
-/* Workspace: the buffers of the largest instance plus a small control block
- * per instance (device program, recursion state, launch descriptors,
- * records).  Instances share those buffers and run one after another, except
- * when no bins are stored (bins_stored == 0) and every instance's contraction
- * ends in a GEMM, so its bins never leave that GEMM's epilogue: then they run
- * on min(n_inst, 4) parallel lanes -- streams forked from and joined back
- * into `stream` -- each with its own copy of the buffers, instance i on lane
- * i % lanes.  bins_stored != 0 when the caller
- * passes a bin buffer for every recursion (then no bin scratch is
- * counted). */
+/* Workspace: a control block per instance (device program, recursion
+ * state, launch descriptors, records) and the buffers of the recursions.
+ * When no bins are stored (bins_stored == 0) and every instance's
+ * contraction ends in a GEMM, so its bins never leave that GEMM's epilogue,
+ * each instance has buffers of its own and instances with the same step
+ * sequence advance in lockstep -- every kernel of a recursion is one launch
+ * for all of them -- with such groups spread over up to 4 streams forked from
+ * and joined back into `stream` (cq_dd_lanes).  Otherwise the instances share
+ * the buffers of the largest and run one after another.  bins_stored != 0
+ * when the caller passes a bin buffer for every recursion (then no bin
+ * scratch is counted). */
 cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
                                const cq_dd_params* params, int32_t bins_stored, size_t* bytes);
 
-/* records: host, n_inst * R records (instance-major).  bins: NULL, or a host
- * array of n_inst * R device pointers, each NULL (bins go to workspace
- * scratch) or a buffer of 2^A values (double for CQ_FP64 else float), A =
- * sum_c max(#active_c at recursion 0, min(max_active[c], n_c)), the most bins
- * a recursion can have; recursion r's 2^n_active bins are written at its
- * start.  recursions_done: host, n_inst.
+/* records: host, n_inst * R records (instance-major); the call's j-th
+ * recursion of instance i (recursion r0 + j, r0 its starting index) goes to
+ * records[i * R + j].  bins: NULL, or a host array of n_inst * R device
+ * pointers indexed the same way, each NULL (bins go to workspace scratch) or
+ * a buffer of 2^A values (double for CQ_FP64 else float), A = sum_c
+ * max(#active_c at recursion 0, min(max_active[c], n_c)), the most bins a
+ * recursion can have; the recursion's 2^n_active bins are written at its
+ * start.  recursions_done: host, n_inst: recursions this call ran.  A resume
+ * checkpoint that does not fit the instance (masks, list, index) is rejected
+ * with CQ_ERR_ARG before any launch.
  *
  * Every recursion of every instance is enqueued without a host round trip:
  * shapes that depend on the zoom are computed on the device.  The call

@@ -23,6 +23,7 @@ EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
             "cq_reconstruct_fd", "cq_reconstruct_fd_noalloc", "cq_dd_workspace_size", "cq_reconstruct_dd",
+            "cq_dd_checkpoint_bytes",
             "cq_dd_bfs_workspace_size", "cq_reconstruct_dd_bfs",
             "cq_sample_shots_workspace_size", "cq_sample_shots", "cq_chi2_workspace_size", "cq_chi2",
             "cq_simulate_workspace_size", "cq_simulate_probabilities", "cq_variants_workspace_size",
@@ -45,14 +46,15 @@ class cq_dd_instance(C.Structure):
 
 
 class cq_dd_params(C.Structure):
-    _fields_ = [("prec", C.c_int), ("R", C.c_int32), ("launch", C.c_int32)]
+    _fields_ = [("prec", C.c_int), ("R", C.c_int32), ("launch", C.c_int32), ("recursions", C.c_int32),
+                ("resume", C.c_void_p), ("checkpoint", C.c_void_p)]
 
 
 DD_LAUNCH = {"graph": 0, "direct": 1}
 
 
 class cq_dd_record(C.Structure):
-    _fields_ = [("active", C.c_uint64 * MAX_SUBCIRCUITS), ("merged", C.c_uint64 * MAX_SUBCIRCUITS),
+    _fields_ = [("recursion", C.c_int32), ("active", C.c_uint64 * MAX_SUBCIRCUITS), ("merged", C.c_uint64 * MAX_SUBCIRCUITS),
                 ("fixed", C.c_uint64 * MAX_SUBCIRCUITS),
                 ("fixed_vals", C.c_uint64 * MAX_SUBCIRCUITS),
                 ("n_active", C.c_int32), ("total", C.c_double), ("n_list", C.c_int32),
@@ -160,6 +162,8 @@ def lib():
     L.cq_label_balance_enable.argtypes = [C.c_int32]
     L.cq_dd_lanes.restype = st
     L.cq_dd_lanes.argtypes = [C.c_int32]
+    L.cq_dd_checkpoint_bytes.restype = C.c_size_t
+    L.cq_dd_checkpoint_bytes.argtypes = []
     L.cq_autotune_json.restype = st
     L.cq_autotune_json.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.cq_profile_read.restype = st

@@ -194,25 +194,44 @@ class _Instances:
 
 def cq_dd_workspace_size(instances, prec="fp64", R=4, bins_stored=False):
     ins = _Instances(instances)
-    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), 0)
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), 0, 0, None, None)
     b = C.c_size_t()
     check(lib().cq_dd_workspace_size(len(instances), ins.arr, C.byref(par), int(bins_stored),
                                      C.byref(b)))
     return b.value
 
 
+def cq_dd_checkpoint_bytes():
+    """Bytes of one instance's dynamic-definition checkpoint."""
+    return int(lib().cq_dd_checkpoint_bytes())
+
+
 def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, stream=None,
-                      launch="graph"):
+                      launch="graph", recursions=0, resume=None, checkpoint=False):
     """Dynamic definition over a batch of instances.  Each instance is a dict
     with keys subs, entries (FP64 device tensors), active, merged, fixed,
     fixed_vals (recursion-0 masks, bit i = output i, i = 0 most significant)
     and max_active.  ``bins``: optional list (instance-major, R per instance)
     of device tensors that receive each recursion's bins (each sized for the
     most bins a recursion can have).  ``launch``: "graph" (one hipGraph for
-    the batch) or "direct".
-    Returns (records, recursions_done): records[i][r] is a dict."""
+    the batch) or "direct".  ``recursions``: recursions this call runs per
+    instance (0: up to R in total).  ``resume``: checkpoints (bytes) of an
+    earlier call to continue from; ``checkpoint``: also return the states
+    after this call.
+    Returns (records, recursions_done), plus the checkpoints (bytes) when
+    ``checkpoint``: records[i][j] is a dict for recursion
+    records[i][j]["recursion"]."""
     ins = _Instances(instances)
-    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), _lib.DD_LAUNCH[launch])
+    ck = cq_dd_checkpoint_bytes()
+    res_buf = None
+    if resume is not None:
+        if len(resume) != ck * len(instances):
+            raise ValueError("resume holds %d bytes, expected %d" % (len(resume), ck * len(instances)))
+        res_buf = C.create_string_buffer(bytes(resume), len(resume))
+    out_buf = C.create_string_buffer(ck * len(instances)) if checkpoint else None
+    par = _lib.cq_dd_params(_lib.PRECISION[prec], int(R), _lib.DD_LAUNCH[launch], int(recursions),
+                            C.cast(res_buf, C.c_void_p) if res_buf is not None else None,
+                            C.cast(out_buf, C.c_void_p) if out_buf is not None else None)
     nbytes = cq_dd_workspace_size(instances, prec, R, bins is not None)
     dev = instances[0]["entries"][0].device
     ws = _workspace(nbytes, dev, workspace)
@@ -232,17 +251,19 @@ def cq_reconstruct_dd(instances, prec="fp64", R=4, bins=None, workspace=None, st
         for r in range(done[i]):
             rc = recs[i * R + r]
             rows.append(dict(
-                active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
+                recursion=rc.recursion, active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
                 fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
                 n_active=rc.n_active, total=rc.total,
                 list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],
                 popped=bool(rc.popped), tiles=rc.tiles, tiles_run=rc.tiles_run))
         out.append(rows)
+    if checkpoint:
+        return out, list(done), out_buf.raw
     return out, list(done)
 
 
 def _record_dict(rc, ns):
-    return dict(active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
+    return dict(recursion=rc.recursion, active=list(rc.active[:ns]), merged=list(rc.merged[:ns]),
                 fixed=list(rc.fixed[:ns]), fixed_vals=list(rc.fixed_vals[:ns]),
                 n_active=rc.n_active, total=rc.total,
                 list=[(rc.list_val[j], rc.list_rec[j], rc.list_bin[j]) for j in range(rc.n_list)],

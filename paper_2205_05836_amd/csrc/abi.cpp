@@ -656,13 +656,17 @@ struct DDBatch {
   int64_t slot = 0;   // lockstep: bytes per slot
   int64_t big = 0;    // otherwise: bytes of the shared region
   int64_t total = 0;  // workspace bytes
+  // set per call: states copied in from checkpoints before the first
+  // recursion, and copied out into the readback block after the last
+  bool resume = false, checkpoint = false;
 };
 
 // Beyond the slots (or the shared region and the control blocks): the
 // programs of all instances back to back in slot order (one upload per call;
 // a copy kernel at the head of the batch moves each into its control block)
-// and the readback block (records and recursion count of every slot back to
-// back, gathered by a copy kernel at the tail of the batch).
+// followed by the resumed states, and the readback block (records and
+// recursion count of every slot back to back, gathered by a copy kernel at
+// the tail of the batch) followed by the states to checkpoint.
 struct DDAreas {
   char* ctrl0;
   int64_t ctrl_stride;
@@ -670,7 +674,9 @@ struct DDAreas {
   int64_t region_stride;
   char* upload;
   char* gather;
-  int64_t prog_stride, rec_bytes, gather_stride, bytes;
+  char* states_in;   // resumed states, slot order
+  char* states_out;  // states after the call, slot order
+  int64_t prog_stride, rec_bytes, gather_stride, state_stride, bytes;
   char* ctrl(int k) const { return ctrl0 + (int64_t)k * ctrl_stride; }
   char* region(int k) const { return region0 + (int64_t)k * region_stride; }
 };
@@ -694,12 +700,17 @@ DDAreas dd_areas(char* ws, int n_inst, int R, const DDBatch& B) {
     A.region_stride = 0;
     up = ctrl + (int64_t)n_inst * L.bytes;
   }
-  const int64_t ga = up + align256((int64_t)n_inst * A.prog_stride);
-  A.bytes = ga + align256((int64_t)n_inst * A.gather_stride);
+  A.state_stride = ((int64_t)sizeof(DDState) + 15) / 16 * 16;
+  const int64_t sin = up + align256((int64_t)n_inst * A.prog_stride);
+  const int64_t ga = sin + align256((int64_t)n_inst * A.state_stride);
+  const int64_t sout = ga + align256((int64_t)n_inst * A.gather_stride);
+  A.bytes = sout + align256((int64_t)n_inst * A.state_stride);
   A.ctrl0 = ws ? ws + ctrl : nullptr;
   A.region0 = ws ? ws + region : nullptr;
   A.upload = ws ? ws + up : nullptr;
+  A.states_in = ws ? ws + sin : nullptr;
   A.gather = ws ? ws + ga : nullptr;
+  A.states_out = ws ? ws + sout : nullptr;
   return A;
 }
 
@@ -773,8 +784,11 @@ SymPow to_dev(const SymQ& q) {
 // Host image of an instance's device program; pointers refer to its region
 // `ws` and its control block `ctrl`.
 void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_params& p, char* ws,
-                char* ctrl, DDProgram& P) {
+                char* ctrl, int r0, int r_end, bool resume, DDProgram& P) {
   std::memset(&P, 0, sizeof(P));
+  P.resume = resume ? 1 : 0;
+  P.r0 = r0;
+  P.r_end = r_end;
   const CutMap& cm = D.cm;
   const Plan& plan = D.plan;
   const DType wt = work_dtype(p.prec);
@@ -1032,6 +1046,9 @@ cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
   const DDAreas A = dd_areas(ws, n_inst, p.R, B);
   hipError_t e = launch_dd_copy(A.upload, A.prog_stride, A.ctrl0 + L.prog, A.ctrl_stride,
                                 (int64_t)sizeof(DDProgram), n_inst, stream);
+  if (e == hipSuccess && B.resume)
+    e = launch_dd_copy(A.states_in, A.state_stride, A.ctrl0 + L.state, A.ctrl_stride, (int64_t)sizeof(DDState),
+                       n_inst, stream);
   if (e != hipSuccess) return hip_fail(e, "program scatter");
   if (!B.lockstep) {
     for (int i = 0; i < n_inst; ++i) {
@@ -1083,6 +1100,9 @@ cq_status dd_enqueue_all(int32_t n_inst, const cq_dd_params& p, int recursions,
   if (e == hipSuccess)
     e = launch_dd_copy(A.ctrl0 + L.state + offsetof(DDState, done), A.ctrl_stride, A.gather + A.rec_bytes,
                        A.gather_stride, 4, n_inst, stream);
+  if (e == hipSuccess && B.checkpoint)
+    e = launch_dd_copy(A.ctrl0 + L.state, A.ctrl_stride, A.states_out, A.state_stride, (int64_t)sizeof(DDState),
+                       n_inst, stream);
   if (e != hipSuccess) return hip_fail(e, "record gather");
   return CQ_OK;
 }
@@ -1142,7 +1162,7 @@ void dd_call_put(DDCall& x) {
 // The cache key, read straight from the arguments; empty (no caching) when
 // they are not well-formed enough to read -- the planner then reports why.
 std::string dd_call_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params& p, int recursions,
-                        void* const* bins, const void* ws) {
+                        void* const* bins, const void* ws, const std::vector<int>& r0) {
   std::string k;
   if (n_inst < 1 || !inst) return k;
   auto put = [&](const void* d, size_t n) { k.append(static_cast<const char*>(d), n); };
@@ -1157,6 +1177,9 @@ std::string dd_call_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_
   put(&recursions, sizeof recursions);
   put(&ws, sizeof ws);
   put(&lanes, sizeof lanes);
+  const int flags = (p.resume ? 1 : 0) | (p.checkpoint ? 2 : 0);
+  put(&flags, sizeof flags);
+  if (p.resume) put(r0.data(), sizeof(int) * r0.size());
   for (int i = 0; i < n_inst; ++i) {
     const cq_dd_instance& in = inst[i];
     if (in.n_sub < 1 || in.n_sub > CQ_MAX_SUBCIRCUITS || !in.subs || !in.entries || !in.active ||
@@ -1232,6 +1255,8 @@ cq_status dd_run_graph(int32_t n_inst, const cq_dd_params& p, int recursions, vo
 
 }  // namespace
 
+extern "C" size_t cq_dd_checkpoint_bytes(void) { return sizeof(DDState); }
+
 extern "C" cq_status cq_dd_workspace_size(int32_t n_inst, const cq_dd_instance* inst,
                                           const cq_dd_params* params, int32_t bins_stored,
                                           size_t* bytes) {
@@ -1249,46 +1274,117 @@ namespace {
 // Validates, plans and runs a batch: every instance for `recursions` (<= R)
 // recursions, R being the list capacity.  Records are instance-major, R per
 // instance.
+// A checkpoint fits an instance when its recursion index, list and masks
+// could have come from a run of that instance with capacity R: masks that
+// partition each subcircuit's outputs, no more active outputs than the plan
+// provides for, list entries of earlier recursions with bins in range.
+cq_status dd_check_state(const DDState& S, const DDInstancePlan& D, int R) {
+  auto bad = [](const std::string& why) { return fail(CQ_ERR_ARG, "resume checkpoint: " + why); };
+  if (S.done < 0 || S.done > R) return bad("recursion index out of range");
+  if (S.stop != 0 && S.stop != 1) return bad("corrupt stop flag");
+  if (S.n_list < 0 || S.n_list > R) return bad("list longer than R");
+  const int ns = D.cm.n_sub;
+  auto part = [&](int c, uint64_t act, uint64_t mer, uint64_t fix, uint64_t fv) {
+    const int n = D.cm.subs[c].n();
+    const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    return (act | mer | fix) == all && !(act & mer) && !(act & fix) && !(mer & fix) && !(fv & ~fix);
+  };
+  if (!S.stop)
+    for (int c = 0; c < ns; ++c) {
+      if (!part(c, S.active[c], S.merged[c], S.fixed[c], S.fixed_vals[c])) return bad("masks do not partition");
+      if (popc(S.active[c]) > D.amax[c]) return bad("more active outputs than the plan holds");
+    }
+  for (int q = 0; q < S.n_list; ++q) {
+    const DDEntry& e = S.list[q];
+    if (e.rec < 0 || e.rec >= S.done) return bad("list entry from a later recursion");
+    for (int c = 0; c < ns; ++c)
+      if (!part(c, 0, e.merged[c], e.fixed[c], e.fixed_vals[c])) return bad("list entry masks do not partition");
+  }
+  return CQ_OK;
+}
+
 cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_params* params,
-                       int recursions, cq_dd_record* records, void* const* bins,
-                       int32_t* recursions_done, void* workspace, size_t workspace_bytes,
-                       hipStream_t stream) {
+                       cq_dd_record* records, void* const* bins, int32_t* recursions_done, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
   if (n_inst < 1 || !inst || !params || !records || !recursions_done)
     return fail(CQ_ERR_ARG, "null or empty argument");
   if (!prec_supported(params->prec)) return fail(CQ_ERR_UNSUPPORTED, "precision not built");
   if (params->launch != CQ_DD_GRAPH && params->launch != CQ_DD_DIRECT)
     return fail(CQ_ERR_ARG, "unknown launch mode");
+  if (params->R < 1 || params->R > CQ_MAX_DD_R) return fail(CQ_ERR_ARG, "R out of range");
+  if (params->recursions < 0) return fail(CQ_ERR_ARG, "negative recursion count");
+  const int R = params->R;
+  // each instance's starting recursion (its checkpoint's, else 0) and the
+  // end of this call's range; the launches cover the longest range
+  std::vector<DDState> resumed;
+  std::vector<int> r0((size_t)n_inst, 0), r_end((size_t)n_inst, 0);
+  if (params->resume) {
+    resumed.resize((size_t)n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      std::memcpy(&resumed[i], static_cast<const char*>(params->resume) + (size_t)i * sizeof(DDState),
+                  sizeof(DDState));
+      r0[i] = resumed[i].done;
+      if (r0[i] < 0 || r0[i] > R) return fail(CQ_ERR_ARG, "resume checkpoint: recursion index out of range");
+    }
+  }
+  const int want = params->recursions > 0 ? params->recursions : R;
+  int recursions = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    r_end[i] = std::min(R, r0[i] + want);
+    recursions = std::max(recursions, r_end[i] - r0[i]);
+  }
   char* ws = static_cast<char*>(workspace);
   DDLaneSet lane_set;  // destroyed after the entry's graph (declared first)
   DDCallHold H;
-  const std::string key = dd_call_key(n_inst, inst, *params, recursions, bins, ws);
+  const std::string key = dd_call_key(n_inst, inst, *params, recursions, bins, ws, r0);
   if (key.empty() || !dd_call_take(key, H.x)) {
     // validate and plan everything before the first launch
     cq_status st = dd_plan_all(n_inst, inst, *params, bins != nullptr, H.x.plans, H.x.B);
     if (st != CQ_OK) return st;
-    if (recursions < 1 || recursions > params->R) return fail(CQ_ERR_ARG, "recursion count out of range");
     if (bins)
       for (int i = 0; i < n_inst; ++i)
-        for (int r = 0; r < params->R; ++r)
-          if (!bins[(size_t)i * params->R + r] && H.x.plans[i].bins_bytes == 0)
+        for (int r = 0; r < R; ++r)
+          if (!bins[(size_t)i * R + r] && H.x.plans[i].bins_bytes == 0)
             return fail(CQ_ERR_ARG, "null bin buffer");
+    H.x.B.resume = params->resume != nullptr;
+    H.x.B.checkpoint = params->checkpoint != nullptr;
     // every instance's device program (slot order), uploaded with one copy
-    const DDAreas A = dd_areas(ws, n_inst, params->R, H.x.B);
+    const DDAreas A = dd_areas(ws, n_inst, R, H.x.B);
     H.x.upload.assign((size_t)(n_inst * A.prog_stride), 0);
     for (int i = 0; i < n_inst; ++i) {
       const int k = H.x.B.slot_of[i];
       DDProgram prog;
-      dd_program(H.x.plans[i], inst[i], *params, A.region(k), A.ctrl(k), prog);
+      dd_program(H.x.plans[i], inst[i], *params, A.region(k), A.ctrl(k), r0[i], r_end[i], H.x.B.resume, prog);
       std::memcpy(H.x.upload.data() + (size_t)k * A.prog_stride, &prog, sizeof(DDProgram));
     }
     H.x.key = key;
   }
   const DDBatch& B = H.x.B;
+  for (int i = 0; i < (int)resumed.size(); ++i) {
+    cq_status st = dd_check_state(resumed[i], H.x.plans[i], R);
+    if (st != CQ_OK) return st;
+  }
   if (!workspace || (int64_t)workspace_bytes < B.total) return fail(CQ_ERR_WORKSPACE, "workspace too small");
   if (fault_injected("dd")) return fail(CQ_ERR_HIP, "injected fault before launch");
-  const DDAreas A = dd_areas(ws, n_inst, params->R, B);
+  std::memset(records, 0, sizeof(cq_dd_record) * (size_t)n_inst * (size_t)R);
+  if (recursions == 0) {  // every instance is at its end already
+    for (int i = 0; i < n_inst; ++i) recursions_done[i] = 0;
+    if (params->checkpoint && params->resume)
+      std::memcpy(params->checkpoint, params->resume, sizeof(DDState) * (size_t)n_inst);
+    H.keep = true;
+    return CQ_OK;
+  }
+  const DDAreas A = dd_areas(ws, n_inst, R, B);
   hipError_t e = hipMemcpyAsync(A.upload, H.x.upload.data(), H.x.upload.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "program upload");
+  std::vector<char> states;
+  if (B.resume) {
+    states.assign((size_t)(n_inst * A.state_stride), 0);
+    for (int i = 0; i < n_inst; ++i)
+      std::memcpy(states.data() + (size_t)B.slot_of[i] * A.state_stride, &resumed[i], sizeof(DDState));
+    e = hipMemcpyAsync(A.states_in, states.data(), states.size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint upload");
+  }
   cq_status st;
   if (params->launch == CQ_DD_GRAPH) {
     st = dd_run_graph(n_inst, *params, recursions, bins, ws, stream, H, lane_set);
@@ -1302,15 +1398,24 @@ cq_status dd_run_batch(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_p
   std::vector<char> back((size_t)(n_inst * A.gather_stride));
   e = hipMemcpyAsync(back.data(), A.gather, back.size(), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_fail(e, "record readback");
+  std::vector<char> out_states;
+  if (B.checkpoint) {
+    out_states.resize((size_t)(n_inst * A.state_stride));
+    e = hipMemcpyAsync(out_states.data(), A.states_out, out_states.size(), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint readback");
+  }
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "synchronise");
   H.keep = true;
   for (int i = 0; i < n_inst; ++i) {
     const char* b = back.data() + (size_t)B.slot_of[i] * A.gather_stride;
-    std::memcpy(records + (size_t)i * params->R, b, (size_t)A.rec_bytes);
+    std::memcpy(records + (size_t)i * R, b, (size_t)A.rec_bytes);
     int32_t done = 0;
     std::memcpy(&done, b + A.rec_bytes, sizeof done);
-    recursions_done[i] = done;
+    recursions_done[i] = done - r0[i];
+    if (B.checkpoint)
+      std::memcpy(static_cast<char*>(params->checkpoint) + (size_t)i * sizeof(DDState),
+                  out_states.data() + (size_t)B.slot_of[i] * A.state_stride, sizeof(DDState));
   }
   return CQ_OK;
 }
@@ -1353,6 +1458,9 @@ cq_dd_params bfs_batch_params(const cq_dd_bfs_params& p) {
   q.prec = p.prec;
   q.R = p.width;
   q.launch = p.launch;
+  q.recursions = 1;
+  q.resume = nullptr;
+  q.checkpoint = nullptr;
   return q;
 }
 
@@ -1363,8 +1471,7 @@ extern "C" cq_status cq_reconstruct_dd(int32_t n_inst, const cq_dd_instance* ins
                                        void* const* bins, int32_t* recursions_done, void* workspace,
                                        size_t workspace_bytes, hipStream_t stream) {
   if (!params) return fail(CQ_ERR_ARG, "null or empty argument");
-  return dd_run_batch(n_inst, inst, params, params->R, records, bins, recursions_done, workspace,
-                      workspace_bytes, stream);
+  return dd_run_batch(n_inst, inst, params, records, bins, recursions_done, workspace, workspace_bytes, stream);
 }
 
 extern "C" cq_status cq_dd_bfs_workspace_size(const cq_dd_instance* root, const cq_dd_bfs_params* params,
@@ -1417,7 +1524,7 @@ extern "C" cq_status cq_reconstruct_dd_bfs(const cq_dd_instance* root, const cq_
     }
     std::vector<cq_dd_record> recs((size_t)n * W);
     std::vector<int32_t> done((size_t)n, 0);
-    cq_status st = dd_run_batch(n, inst.data(), &q, 1, recs.data(), nullptr, done.data(), workspace,
+    cq_status st = dd_run_batch(n, inst.data(), &q, recs.data(), nullptr, done.data(), workspace,
                                 workspace_bytes, stream);
     if (st != CQ_OK) return st;
     // candidates of the level: (value, node, bin), best first

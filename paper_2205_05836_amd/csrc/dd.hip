@@ -662,7 +662,7 @@ __global__ void dd_init_kernel(const DDProgram* __restrict__ P, DDState* st, cq_
   uint64_t* w = reinterpret_cast<uint64_t*>(recs);
   const int64_t words = (int64_t)R * (int64_t)(sizeof(cq_dd_record) / 8);
   for (int64_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || P->resume) return;  // a resumed state was copied in before
   const DDInit& init = P->init;
   for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c) {
     st->active[c] = init.active[c];
@@ -700,7 +700,8 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
   const int tid = threadIdx.x;
   const int ns = P->n_sub, nsteps = P->n_steps;
   const int step = tid - 32;  // the step this thread describes, if in range
-  if (st->stop) {
+  // stopped, or past this instance's last recursion of the call: nothing runs
+  if (st->stop || P->r0 + r >= P->r_end) {
     if (tid < ns) {
       lv->merge[tid].outputs = 0;
       lv->rowsum[tid].outputs = 0;
@@ -833,6 +834,7 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
     }
   }
   if (tid == 0) {
+    rec.recursion = P->r0 + r;
     rec.n_active = sum;
     st->n_active = sum;
     st->count = count;
@@ -895,7 +897,8 @@ __global__ void __launch_bounds__(64) dd_update_kernel(const DDProgram* __restri
   st = inst_ptr(st, slot);
   recs = inst_ptr(recs, slot);
   const int tid = threadIdx.x;
-  if (st->stop) return;
+  if (st->stop || P->r0 + r >= P->r_end) return;
+  const int ra = P->r0 + r;  // the recursion's index (the list orders ties by it)
   const int ns = P->n_sub, R = P->R, C = st->C, nl = st->n_list;
   const int take = C < R ? C : R;
   cq_dd_record& rec = recs[r];
@@ -925,7 +928,7 @@ __global__ void __launch_bounds__(64) dd_update_kernel(const DDProgram* __restri
     const uint64_t o = list_ord(e.v);
     int pos = tid;
     for (int j = 0; j < C; ++j)
-      pos += (c_rank[j] < take && list_before(c_ord[j], r, c_bin[j], o, e.rec, e.bin)) ? 1 : 0;
+      pos += (c_rank[j] < take && list_before(c_ord[j], ra, c_bin[j], o, e.rec, e.bin)) ? 1 : 0;
     if (pos < R) {
       const uint64_t* src = reinterpret_cast<const uint64_t*>(&e);
       uint64_t* dst = reinterpret_cast<uint64_t*>(&new_l[pos]);
@@ -937,11 +940,11 @@ __global__ void __launch_bounds__(64) dd_update_kernel(const DDProgram* __restri
     const uint64_t o = c_ord[tid], bin = c_bin[tid];
     int pos = c_rank[tid];
     for (int q = 0; q < nl; ++q)
-      pos += list_before(list_ord(old_l[q].v), old_l[q].rec, old_l[q].bin, o, r, bin) ? 1 : 0;
+      pos += list_before(list_ord(old_l[q].v), old_l[q].rec, old_l[q].bin, o, ra, bin) ? 1 : 0;
     if (pos < R) {
       DDEntry& e = new_l[pos];
       e.v = c_val[tid];
-      e.rec = r;
+      e.rec = ra;
       e.pad = 0;
       e.bin = bin;
       // the bin's digits, subcircuit 0 most significant, fix the active
@@ -974,7 +977,7 @@ __global__ void __launch_bounds__(64) dd_update_kernel(const DDProgram* __restri
       rec.tiles = st->n_tiles;
       rec.tiles_run = st->warm_count + st->list_count;
     }
-    st->done = r + 1;
+    st->done = ra + 1;
   }
   if (tid < nl2) {
     rec.list_val[tid] = new_l[tid].v;

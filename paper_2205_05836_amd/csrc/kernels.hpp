@@ -346,7 +346,8 @@ struct DDInit {  // recursion-0 masks
 struct DDProgram {
   int32_t n_sub, K, R, n_steps;
   int32_t C_max;                             // min(4R, 64)
-  int32_t pad;
+  int32_t resume;                            // the state comes from a checkpoint, not `init`
+  int32_t r0, r_end;                         // recursions r0 .. r_end - 1 run; launch r is r0 + r
   int32_t n_out[CQ_MAX_SUBCIRCUITS];
   int32_t max_active[CQ_MAX_SUBCIRCUITS];
   int32_t kc[CQ_MAX_SUBCIRCUITS];

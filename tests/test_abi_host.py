@@ -161,6 +161,36 @@ def test_dd_mask_validation():
     assert e.value.status == -1
 
 
+def test_dd_resume_checkpoint_validated_before_launch():
+    """A checkpoint that no run of the instance could have written -- masks
+    that do not partition the outputs (all zero), or a recursion index out of
+    range (all ones) -- is rejected with CQ_ERR_ARG before any launch."""
+    import paper_2205_05836_amd as cq
+    from paper_2205_05836_amd import _lib
+    from paper_2205_05836_amd.api import _Instances
+    cm = syn.chain_cutmap([1], [3, 3])
+    fake = [_FakeTensor(0x1000), _FakeTensor(0x2000)]
+    base = dict(subs=cm, entries=fake, active=[0b011, 0b001], merged=[0b100, 0b110],
+                fixed=[0, 0], fixed_vals=[0, 0], max_active=[1, 1])
+    ck = cq.cq_dd_checkpoint_bytes()
+    assert ck > 0
+    ins = _Instances([base])
+    recs = (_lib.cq_dd_record * 2)()
+    done = (C.c_int32 * 1)()
+    ws = C.create_string_buffer(1 << 16)
+    for fill in (b"\x00", b"\xff"):
+        blob = C.create_string_buffer(fill * ck, ck)
+        par = _lib.cq_dd_params(_lib.PRECISION["fp64"], 2, 0, 0, C.cast(blob, C.c_void_p), None)
+        st = lib().cq_reconstruct_dd(1, ins.arr, C.byref(par), recs, None, done,
+                                     C.cast(ws, C.c_void_p), C.c_size_t(1 << 16), None)
+        assert st == -1, (fill, st)
+        assert "resume checkpoint" in lib().cq_last_error().decode()
+    par = _lib.cq_dd_params(_lib.PRECISION["fp64"], 2, 0, -1, None, None)
+    st = lib().cq_reconstruct_dd(1, ins.arr, C.byref(par), recs, None, done, C.cast(ws, C.c_void_p),
+                                 C.c_size_t(1 << 16), None)
+    assert st == -1
+
+
 class _FakeTensor:
     def __init__(self, p):
         self.p = p

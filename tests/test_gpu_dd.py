@@ -472,3 +472,46 @@ def test_graph_cache_reuse_and_eviction():
         m.cq_reconstruct_dd(other, "fp32", 3, workspace=w)
     torch.cuda.synchronize()
     assert m.cq_reconstruct_dd(first, "fp32", 4, workspace=ws) == ref
+
+
+# --- checkpoint and resume -----------------------------------------------------
+
+@pytest.mark.parametrize("launch", ["graph", "direct"])
+@pytest.mark.parametrize("split", [1, 3])
+def test_checkpoint_and_resume_continue_algorithm1(launch, split):
+    """Algorithm 1's state between recursions is the list L and the next
+    recursion index (with the masks it zooms into).  A run split over two
+    calls -- the first stopping after `split` recursions and saving that
+    state, the second resuming from it -- takes the very recursions one call
+    takes: the records agree field by field, recursion indices continue, and
+    a third call from the final state runs nothing.  Integer entries (exact,
+    with ties), a batch of two instances advancing in lockstep."""
+    m = cq()
+    rng = np.random.default_rng(71)
+    insts = []
+    for bonds, ns, M in (([1, 1], [4, 5, 4], [2, 1, 2]), ([2, 1], [4, 4, 5], [1, 2, 1])):
+        cm = syn.chain_cutmap(bonds, ns)
+        E = [syn.integer_entries(rng, k, n, lo=-3, hi=6) for k, n in zip(syn.chain_ks(bonds, 3), ns)]
+        insts.append(instance(cm, E, dd.initial_states(cm, M), M))
+    R = 5
+    print(f"resume {launch} split {split}", flush=True)
+    full, done_full = m.cq_reconstruct_dd(insts, "fp64", R, launch=launch)
+    a, done_a, ck = m.cq_reconstruct_dd(insts, "fp64", R, launch=launch, recursions=split, checkpoint=True)
+    assert len(ck) == 2 * m.cq_dd_checkpoint_bytes()
+    b, done_b, ck2 = m.cq_reconstruct_dd(insts, "fp64", R, launch=launch, resume=ck, checkpoint=True)
+    for i in range(2):
+        assert done_a[i] == min(split, done_full[i])
+        assert done_a[i] + done_b[i] == done_full[i]
+        assert a[i] + b[i] == full[i]
+        assert [r["recursion"] for r in a[i] + b[i]] == list(range(done_full[i]))
+    c, done_c = m.cq_reconstruct_dd(insts, "fp64", R, launch=launch, resume=ck2)
+    assert done_c == [0, 0] and c == [[], []]
+    # the stored-bin path resumes the same way
+    A = max(max_bins_log2(x["subs"], dd.initial_states(x["subs"], x["max_active"]), x["max_active"])
+            for x in insts)
+    bins = [torch.empty(2 ** A, dtype=torch.float64, device=DEV) for _ in range(2 * R)]
+    sa, sdone_a, sck = m.cq_reconstruct_dd(insts, "fp64", R, bins=bins, launch=launch, recursions=split,
+                                           checkpoint=True)
+    sb, sdone_b = m.cq_reconstruct_dd(insts, "fp64", R, bins=bins, launch=launch, resume=sck)
+    for i in range(2):
+        assert strip_tiles([sa[i] + sb[i]]) == strip_tiles([full[i]])
