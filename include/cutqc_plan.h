@@ -94,8 +94,27 @@ cq_status cq_label_balance_enable(int32_t mode);
  * Always CQ_OK. */
 cq_status cq_dd_lanes(int32_t lanes);
 
+/* Tuned choices kept across processes.  cq_autotune_save writes every cached
+ * choice to `path` (text, one shape per line, tagged with the kind of device
+ * -- architecture and compute-unit count -- it was timed on);
+ * cq_autotune_load adds the choices in `path` made on this kind of device to
+ * the cache (shapes cached already keep their choice; lines it does not
+ * recognise are skipped), so a caller that captures before its first eager
+ * call still launches tuned variants.  The environment variable
+ * CQ_TUNE_CACHE names a file that is loaded at the first tuned launch and
+ * extended with every shape tuned afterwards.  CQ_ERR_ARG when the file
+ * cannot be read or written. */
+cq_status cq_autotune_load(const char* path);
+cq_status cq_autotune_save(const char* path);
+
 /* The cached choices as JSON:
- *   [{"prec": ..., "M", "N", "K", "Z", "variant": v, "ms": [[v, ms], ...]}, ...]
+ *   [{"prec": ..., "M", "N", "K", "Z", "variant": v,
+ *     "schedule": {"kernel": "tiled" | "async" | "register" | "persistent" |
+ *                  "occupancy", "tile": [128, 128], "ring": operand stages in
+ *                  LDS (0: none), "workgroups_per_cu": resident workgroups the
+ *                  kernel is built for (0: as many as fit), "raster": "default"
+ *                  | "flipped"},
+ *     "ms": [[v, ms], ...]}, ...]
  * *needed receives the length including the terminating NUL; with buf null
  * or buf_bytes below it, nothing is written and CQ_ERR_ARG is returned. */
 cq_status cq_autotune_json(char* buf, size_t buf_bytes, size_t* needed);

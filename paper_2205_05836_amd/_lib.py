@@ -19,7 +19,7 @@ FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
             "cq_label_balance_enable", "cq_dd_lanes",
-            "cq_autotune_json",
+            "cq_autotune_json", "cq_autotune_load", "cq_autotune_save",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
             "cq_reconstruct_fd", "cq_reconstruct_fd_noalloc", "cq_dd_workspace_size", "cq_reconstruct_dd",
@@ -162,6 +162,10 @@ def lib():
     L.cq_label_balance_enable.argtypes = [C.c_int32]
     L.cq_dd_lanes.restype = st
     L.cq_dd_lanes.argtypes = [C.c_int32]
+    L.cq_autotune_load.restype = st
+    L.cq_autotune_load.argtypes = [C.c_char_p]
+    L.cq_autotune_save.restype = st
+    L.cq_autotune_save.argtypes = [C.c_char_p]
     L.cq_dd_checkpoint_bytes.restype = C.c_size_t
     L.cq_dd_checkpoint_bytes.argtypes = []
     L.cq_autotune_json.restype = st

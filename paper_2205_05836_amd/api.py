@@ -8,6 +8,7 @@ those attributes (see include/cutqc.h for the conventions).
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 from . import _lib
 from ._lib import check, lib
@@ -476,6 +477,16 @@ def cq_dd_lanes(lanes=0):
     """Parallel lanes of cq_reconstruct_dd (0: the default, 4; at most 8).
     Query the workspace size after changing it."""
     check(lib().cq_dd_lanes(int(lanes)))
+
+
+def cq_autotune_load(path):
+    """Add the tuned choices saved in `path` (this kind of device's) to the cache."""
+    check(lib().cq_autotune_load(os.fsencode(path)))
+
+
+def cq_autotune_save(path):
+    """Write the cached tuned choices to `path`."""
+    check(lib().cq_autotune_save(os.fsencode(path)))
 
 
 def cq_autotune_json():

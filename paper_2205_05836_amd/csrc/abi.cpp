@@ -1686,6 +1686,18 @@ extern "C" cq_status cq_autotune_enable(int32_t mode) {
   return CQ_OK;
 }
 
+extern "C" cq_status cq_autotune_load(const char* path) {
+  if (!path) return fail(CQ_ERR_ARG, "null path");
+  if (!autotune_load(path)) return fail(CQ_ERR_ARG, std::string("cannot read ") + path);
+  return CQ_OK;
+}
+
+extern "C" cq_status cq_autotune_save(const char* path) {
+  if (!path) return fail(CQ_ERR_ARG, "null path");
+  if (!autotune_save(path)) return fail(CQ_ERR_ARG, std::string("cannot write ") + path);
+  return CQ_OK;
+}
+
 extern "C" cq_status cq_autotune_json(char* buf, size_t buf_bytes, size_t* needed) {
   if (!needed) return fail(CQ_ERR_ARG, "null argument");
   const std::string js = autotune_json();

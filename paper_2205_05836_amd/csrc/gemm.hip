@@ -19,10 +19,13 @@
 
 #include <atomic>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "kernels.hpp"
 #include "select.hpp"
@@ -1782,6 +1785,86 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneEntry> g_tune;
 std::atomic<int> g_tune_on{-1};  // -1: not yet read from CQ_AUTOTUNE
 
+// Choices persist as text, one shape per line, tagged with the kind of device
+// they were timed on (architecture and compute-unit count):
+//   cq-tune-1 <device> prec tc nt za zb aligned M N K Z variant tried ms[0..11]
+// CQ_TUNE_CACHE names a file that is read at the first tuned launch and
+// extended by every shape tuned later (cq_autotune_load / _save do the same
+// on request).
+std::string tune_device() {
+  static std::mutex mu;
+  static std::string id[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  if (id[dev].empty()) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch = prop.gcnArchName;
+    for (char& c : arch)
+      if (c == ' ' || c == ':') c = '_';  // one token, no separators of the line format
+    id[dev] = arch + "-" + std::to_string(prop.multiProcessorCount) + "cu";
+  }
+  return id[dev];
+}
+
+std::string tune_line(const std::string& dev, const TuneKey& k, const TuneEntry& e) {
+  char buf[1024];
+  int n = std::snprintf(buf, sizeof(buf), "cq-tune-1 %s %d %d %d %d %d %d %lld %lld %lld %lld %d %d", dev.c_str(),
+                        k.prec, k.tc, k.nt, k.za, k.zb, k.aligned, (long long)k.M, (long long)k.N,
+                        (long long)k.K, (long long)k.Z, e.variant, e.tried);
+  std::string s(buf, (size_t)n);
+  for (int v = 0; v < kMaxVariants; ++v) {
+    n = std::snprintf(buf, sizeof(buf), " %.9g", (double)e.ms[v]);
+    s.append(buf, (size_t)n);
+  }
+  return s + "\n";
+}
+
+// Entries of `path` for this device; false when the file cannot be read.
+bool tune_read(const char* path, std::vector<std::pair<TuneKey, TuneEntry>>& out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string dev = tune_device();
+  char line[2048];
+  while (std::fgets(line, sizeof(line), f)) {
+    char tag[32], d[256];
+    TuneKey k;
+    TuneEntry e;
+    long long M, N, K, Z;
+    double ms[kMaxVariants];
+    const int got = std::sscanf(
+        line, "%31s %255s %d %d %d %d %d %d %lld %lld %lld %lld %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf",
+        tag, d, &k.prec, &k.tc, &k.nt, &k.za, &k.zb, &k.aligned, &M, &N, &K, &Z, &e.variant, &e.tried, &ms[0],
+        &ms[1], &ms[2], &ms[3], &ms[4], &ms[5], &ms[6], &ms[7], &ms[8], &ms[9], &ms[10], &ms[11]);
+    if (got != 14 + kMaxVariants || std::strcmp(tag, "cq-tune-1") != 0 || dev != d) continue;
+    if (k.prec < 0 || k.prec > 5 || e.variant < 0 || e.variant >= kMaxVariants || !((e.tried >> e.variant) & 1))
+      continue;
+    k.M = M;
+    k.N = N;
+    k.K = K;
+    k.Z = Z;
+    for (int v = 0; v < kMaxVariants; ++v) e.ms[v] = (float)ms[v];
+    out.emplace_back(k, e);
+  }
+  std::fclose(f);
+  return true;
+}
+
+// Adds entries not cached yet; returns whether the file could be read.
+bool tune_merge_file(const char* path) {
+  std::vector<std::pair<TuneKey, TuneEntry>> got;
+  if (!tune_read(path, got)) return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : got) g_tune.emplace(kv.first, kv.second);
+  return true;
+}
+
+const char* tune_cache_path() {
+  const char* p = std::getenv("CQ_TUNE_CACHE");
+  return (p && p[0]) ? p : nullptr;
+}
+
 // 0: variant 0 always, 1: tune, 2 + v: variant v always (where it applies)
 int tune_mode() {
   int on = g_tune_on.load();
@@ -1790,6 +1873,11 @@ int tune_mode() {
     on = (e && e[0] == '0') ? 0 : 1;
     g_tune_on.store(on);
   }
+  static std::once_flag loaded;
+  if (on == 1)
+    std::call_once(loaded, [] {
+      if (const char* p = tune_cache_path()) (void)tune_merge_file(p);
+    });
   return on;
 }
 
@@ -1919,11 +2007,67 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = te;
   }
+  if (const char* p = tune_cache_path()) {
+    const std::string line = tune_line(tune_device(), key, te);
+    if (FILE* f = std::fopen(p, "a")) {
+      std::fputs(line.c_str(), f);
+      std::fclose(f);
+    }
+  }
   // the output comes from the chosen variant, as on every later call
   return launch_variant(prec, a, g.tc, nt, te.variant, stream);
 }
 
 void autotune_set(int mode) { g_tune_on.store(mode < 0 ? 0 : mode); }
+
+bool autotune_load(const char* path) { return path && tune_merge_file(path); }
+
+bool autotune_save(const char* path) {
+  if (!path) return false;
+  const std::string dev = tune_device();
+  std::string text;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune) text += tune_line(dev, kv.first, kv.second);
+  }
+  FILE* f = std::fopen(path, "w");
+  if (!f) return false;
+  const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  return std::fclose(f) == 0 && ok;
+}
+
+namespace {
+
+// The schedule behind variant v: kernel, tile, ring depth (operand stages in
+// LDS), resident workgroups per compute unit and raster order.
+std::string variant_schedule(int prec, int v) {
+  const int impl = v >> 1;
+  const bool split = prec == CQ_BF16_SPLIT || prec == CQ_FP16_SPLIT;
+  const char* kernel = "tiled";
+  int ring = 0, wpc = 0;
+  if (prec == CQ_FP32 && impl == 3) {
+    kernel = "persistent";
+    ring = 4;
+    wpc = 2;
+  } else if (prec != CQ_FP64 && prec != CQ_FP32) {
+    switch (impl) {
+      case 0: kernel = "async"; ring = split ? 2 : 3; break;
+      case 1: kernel = "async"; ring = split ? 3 : 2; break;
+      case 2: kernel = "register"; break;
+      case 3: kernel = "persistent"; ring = split ? 2 : 4; wpc = 2; break;
+      case 4: kernel = "occupancy"; ring = 2; wpc = 4; break;
+      default: kernel = "occupancy"; ring = 3; wpc = 3; break;
+    }
+  }
+  char buf[256];
+  const int n = std::snprintf(buf, sizeof(buf),
+                              "{\"kernel\": \"%s\", \"tile\": [128, 128], \"ring\": %d, "
+                              "\"workgroups_per_cu\": %d, \"raster\": \"%s\"}",
+                              kernel, ring, wpc, (v & 1) ? "flipped" : "default");
+  return std::string(buf, (size_t)n);
+}
+
+}  // namespace
 
 std::string autotune_json() {
   static const char* pname[] = {"fp64", "fp32", "bf16", "bf16_split", "fp16", "fp16_split"};
@@ -1936,10 +2080,12 @@ std::string autotune_json() {
     char buf[512];
     int n = std::snprintf(buf, sizeof(buf),
                           "%s{\"prec\": \"%s\", \"M\": %lld, \"N\": %lld, \"K\": %lld, \"Z\": %lld, "
-                          "\"variant\": %d, \"ms\": [",
+                          "\"variant\": %d, \"schedule\": ",
                           first ? "" : ", ", pname[k.prec], (long long)k.M, (long long)k.N,
                           (long long)k.K, (long long)k.Z, e.variant);
     s.append(buf, n);
+    s += variant_schedule(k.prec, e.variant);
+    s += ", \"ms\": [";
     bool f2 = true;
     for (int v = 0; v < kMaxVariants; ++v)
       if ((e.tried >> v) & 1) {

@@ -67,6 +67,9 @@ struct GemmLaunch {
 hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t stream);
 void autotune_set(int mode);
 std::string autotune_json();
+// Tuned choices to and from a text file (this device's entries only).
+bool autotune_load(const char* path);
+bool autotune_save(const char* path);
 
 // Kernel-side GEMM description (also written by device code for shapes that
 // are only known on the device).  tiles = tilesM * tilesN * Z with 128 x 128

@@ -9,6 +9,8 @@ namespace cq {
 hipError_t launch_gemm(cq_precision, const GemmLaunch&, hipStream_t) { return hipErrorNoDevice; }
 void autotune_set(int) {}
 std::string autotune_json() { return "[]"; }
+bool autotune_load(const char*) { return false; }
+bool autotune_save(const char*) { return false; }
 hipError_t launch_prep(const double*, void*, int64_t, DType, bool, hipStream_t, const int32_t*, int) {
   return hipErrorNoDevice;
 }

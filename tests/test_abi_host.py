@@ -348,6 +348,36 @@ def test_autotune_json_and_modes_without_gpu():
     cq.cq_autotune_enable(True)
 
 
+def test_autotune_file_round_trip_without_gpu(tmp_path):
+    """Tuned choices saved as text come back through cq_autotune_load with
+    their schedule: lines of this kind of device are taken (without a GPU the
+    device reads as "unknown"), lines of another device, of an unknown
+    format or naming a variant that was not timed are skipped, and a file
+    that does not exist is an error."""
+    import paper_2205_05836_amd as cq
+    ms = " ".join(["0.5"] * 12)
+    good = f"cq-tune-1 unknown 3 1 0 1 0 1 1000003 1024 256 7 8 1023 {ms}\n"
+    lines = [good,
+             f"cq-tune-1 gfx942-304cu 3 1 0 1 0 1 1000005 1024 256 7 8 1023 {ms}\n",   # another device
+             "not a tuning line\n",
+             f"cq-tune-1 unknown 3 1 0 1 0 1 1000007 1024 256 7 9 255 {ms}\n"]         # 9 was not timed
+    src = tmp_path / "tune.txt"
+    src.write_text("".join(lines))
+    cq.cq_autotune_load(str(src))
+    got = [e for e in cq.cq_autotune_json() if e["M"] in (1000003, 1000005, 1000007)]
+    assert len(got) == 1
+    e = got[0]
+    assert (e["prec"], e["N"], e["K"], e["Z"], e["variant"]) == ("bf16_split", 1024, 256, 7, 8)
+    assert e["schedule"] == {"kernel": "occupancy", "tile": [128, 128], "ring": 2,
+                             "workgroups_per_cu": 4, "raster": "default"}
+    out = tmp_path / "saved.txt"
+    cq.cq_autotune_save(str(out))
+    assert good in out.read_text()
+    with pytest.raises(cq.CQError) as err:
+        cq.cq_autotune_load(str(tmp_path / "missing.txt"))
+    assert err.value.status == -1
+
+
 def test_plan_json_workspace_matches_fd_query():
     """The plan JSON reports the workspace cq_fd_workspace_size asks for, in
     every precision (the 16-bit forms include the per-label balance rows)."""
