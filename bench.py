@@ -19,6 +19,7 @@ and computes oracle values for sampled bins (the only use of the oracle here).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -68,6 +69,21 @@ def parse():
     return ap.parse_args()
 
 
+class no_gc:
+    """Collects garbage, then keeps the collector off for a timed region: a
+    full collection takes tens of milliseconds once torch is loaded, and one
+    falling between two launches of a timed loop leaves the GPU idle."""
+
+    def __enter__(self):
+        gc.collect()
+        self.was = gc.isenabled()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        if self.was:
+            gc.enable()
+
+
 def timed_steps(cq, torch, cm, ents, prec, out, steps, warmup):
     """Runs warmup + timed steps; returns (ms per step, per-launch records)."""
     ws = torch.empty(max(cq.cq_fd_workspace_size(cm, prec), 1), dtype=torch.uint8,
@@ -78,12 +94,13 @@ def timed_steps(cq, torch, cm, ents, prec, out, steps, warmup):
     cq.cq_profile_read()
     cq.cq_profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(steps):
-        cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out, workspace=ws)
-    stop.record()
-    torch.cuda.synchronize()
+    with no_gc():
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            cq.cq_reconstruct_fd(cm, ents, prec=prec, out=out, workspace=ws)
+        stop.record()
+        torch.cuda.synchronize()
     cq.cq_profile_enable(False)
     recs = cq.cq_profile_read()
     return start.elapsed_time(stop) / steps, recs
@@ -273,18 +290,26 @@ def _median(xs):
 def _time_calls(torch, fn, runs, warmup=1):
     """Median of `runs` timed calls (HIP events on the current stream) after
     `warmup` untimed ones."""
+    return _time_calls_last(torch, fn, runs, warmup)[0]
+
+
+def _time_calls_last(torch, fn, runs, warmup=1):
+    """(median ms of `runs` timed calls after `warmup` untimed ones, the last
+    call's result)."""
+    res = None
     for _ in range(warmup):
-        fn()
+        res = fn()
     torch.cuda.synchronize()
     ts = []
-    for _ in range(runs):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        fn()
-        b.record()
-        torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b))
-    return _median(ts)
+    with no_gc():
+        for _ in range(runs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            res = fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+    return _median(ts), res
 
 
 FD32_SEED, FD32_BONDS, FD32_NS = 3, [3, 2, 3], [8, 8, 8, 8]
@@ -392,18 +417,9 @@ def dd_leg(torch, cq, forms, runs):
     for f in forms:
         ws = torch.empty(cq.cq_dd_workspace_size(insts, f, DD_R), dtype=torch.uint8,
                          device="cuda:0")
-        recs, done = cq.cq_reconstruct_dd(insts, f, DD_R, workspace=ws)  # warm-up
-        times = []
-        for _ in range(runs):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            a.record()
-            recs, done = cq.cq_reconstruct_dd(insts, f, DD_R, workspace=ws)
-            b.record()
-            torch.cuda.synchronize()
-            times.append(a.elapsed_time(b))
+        ms, (recs, done) = _time_calls_last(
+            torch, lambda: cq.cq_reconstruct_dd(insts, f, DD_R, workspace=ws), runs)
         del ws
-        ms = sorted(times)[len(times) // 2]
         flops, bins, tiles, tiles_run = 0.0, 0, 0, 0
         plans = {}
         for inst, rr in zip(insts, recs):
@@ -436,10 +452,11 @@ def dd_leg(torch, cq, forms, runs):
                      dtype=torch.uint8, device="cuda:0")
     cq.cq_reconstruct_dd_bfs(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH, workspace=ws)  # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nodes = cq.cq_reconstruct_dd_bfs(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH, workspace=ws)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
+    with no_gc():
+        t0 = time.perf_counter()
+        nodes = cq.cq_reconstruct_dd_bfs(insts[0], f, DD_BFS_LEVELS, DD_BFS_WIDTH, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
     del ws
     bins = sum(2 ** nd["n_active"] for nd in nodes)
     out["bfs"] = {"precision": f, "levels": DD_BFS_LEVELS, "width": DD_BFS_WIDTH,
@@ -462,17 +479,7 @@ def attribution_leg(torch, cq, runs=3):
     V = torch.rand((16, 9, 2 ** 22), dtype=torch.float64, device="cuda:0", generator=gen)
     E = torch.empty((256, 2 ** 20), dtype=torch.float64, device="cuda:0")
     ws = torch.empty(cq.cq_attribute_workspace_size(sub), dtype=torch.uint8, device="cuda:0")
-    cq.cq_attribute(sub, V, E, workspace=ws)
-    times = []
-    for _ in range(runs):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        cq.cq_attribute(sub, V, E, workspace=ws)
-        b.record()
-        torch.cuda.synchronize()
-        times.append(a.elapsed_time(b))
-    ms = sorted(times)[len(times) // 2]
+    ms = _time_calls(torch, lambda: cq.cq_attribute(sub, V, E, workspace=ws), runs)
     alg = (V.numel() + E.numel()) * 8
     gbs = alg / (ms * 1e-3) / 1e9
     return {"workload": ATTR_WORKLOAD, "ms": round(ms, 3), "algorithmic_bytes": alg,
@@ -502,17 +509,7 @@ def shots_leg(torch, cq, runs=3):
     res = torch.empty(1, dtype=torch.float64, device="cuda:0")
 
     def timed(fn):
-        fn()
-        times = []
-        for _ in range(runs):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            times.append(a.elapsed_time(b))
-        return sorted(times)[len(times) // 2]
+        return _time_calls(torch, fn, runs)
 
     ms = timed(lambda: cq.cq_sample_shots(P, SHOTS_PER_VARIANT, 2022, out=F, workspace=ws))
     cms = timed(lambda: cq.cq_chi2(F.reshape(-1), P.reshape(-1), out=res, workspace=cws))
@@ -541,17 +538,7 @@ def statevector_leg(torch, cq, runs=3):
     from workloads import circuits as wc
 
     def timed(fn):
-        fn()
-        times = []
-        for _ in range(runs):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            times.append(a.elapsed_time(b))
-        return sorted(times)[len(times) // 2]
+        return _time_calls(torch, fn, runs)
 
     cc = wc.two_way_circuit_30q()
     out = torch.empty(2 ** 30, dtype=torch.float64, device="cuda:0")

@@ -30,12 +30,37 @@ cq_status hip_fail(hipError_t e, const char* what) {
 // ---- per-launch timing (cq_profile_enable / cq_profile_read) ----
 struct ProfRecord {
   std::string name;
-  hipEvent_t start, stop;
-  double flops;
+  hipEvent_t start = nullptr, stop = nullptr;
+  double flops = 0.0;
+  int dev = 0;
 };
 std::atomic<int> g_prof_on{0};
 std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof;
+// Idle timing events by device.  Creating and destroying two events per
+// launch stalled the issuing thread for milliseconds at times (long enough to
+// leave the GPU idle between launches), so events are reused.
+std::vector<std::pair<int, hipEvent_t>> g_prof_pool;
+
+hipEvent_t prof_event(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (size_t i = g_prof_pool.size(); i-- > 0;)
+      if (g_prof_pool[i].first == dev) {
+        const hipEvent_t e = g_prof_pool[i].second;
+        g_prof_pool.erase(g_prof_pool.begin() + (std::ptrdiff_t)i);
+        return e;
+      }
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void prof_release(int dev, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pool.emplace_back(dev, e);
+}
 
 // Brackets one launch with events when profiling is on.
 // Calls that may not create events (the no-allocation entry point) set
@@ -48,20 +73,25 @@ struct ProfScope {
   hipStream_t stream;
   ProfScope(const char* name, double flops, hipStream_t s) : stream(s) {
     if (t_quiet || !g_prof_on.load()) return;
+    if (hipGetDevice(&rec.dev) != hipSuccess) return;
     rec.name = name;
     rec.flops = flops;
-    if (hipEventCreate(&rec.start) != hipSuccess) return;
-    if (hipEventCreate(&rec.stop) != hipSuccess) {
-      (void)hipEventDestroy(rec.start);
-      return;
+    rec.start = prof_event(rec.dev);
+    rec.stop = prof_event(rec.dev);
+    on = rec.start && rec.stop && hipEventRecord(rec.start, stream) == hipSuccess;
+    if (!on) {
+      prof_release(rec.dev, rec.start);
+      prof_release(rec.dev, rec.stop);
     }
-    on = hipEventRecord(rec.start, stream) == hipSuccess;
   }
   ~ProfScope() {
     if (!on) return;
     if (hipEventRecord(rec.stop, stream) == hipSuccess) {
       std::lock_guard<std::mutex> lk(g_prof_mu);
       g_prof.push_back(rec);
+    } else {
+      prof_release(rec.dev, rec.start);
+      prof_release(rec.dev, rec.stop);
     }
   }
 };
@@ -1665,8 +1695,8 @@ extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int
       ms[i] = t;
       flops[i] = recs[i].flops;
     }
-    (void)hipEventDestroy(recs[i].start);
-    (void)hipEventDestroy(recs[i].stop);
+    prof_release(recs[i].dev, recs[i].start);
+    prof_release(recs[i].dev, recs[i].stop);
   }
   return st;
 }

@@ -158,6 +158,21 @@ __global__ void __launch_bounds__(256) rowmax_kernel(const double* __restrict__ 
 // Binary exponent of a positive finite x (x = f * 2^e, f in [1, 2)).
 __device__ inline int bexp(double x) { return ilogb(x); }
 
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ inline int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // One workgroup: per (subcircuit, digit position, digit) the largest row
 // maximum (LDS), then e_j(d) per cut and digit, then every row's exponent.
 // The largest row of a subcircuit sits at each digit's maximum over the other
@@ -165,45 +180,119 @@ __device__ inline int bexp(double x) { return ilogb(x); }
 // all its rows); a final constant per subcircuit, summing to zero over the
 // subcircuits (every term of Eq. 1 takes one row of each), brings every
 // subcircuit's largest scaled row to their common mean binary exponent.
+// Row maxima are FP64 bit patterns of values >= 0, so their unsigned order is
+// the value order.  Thread t reads rows l = 256 i + t: the digits held in the
+// low 8 bits of l (the last four positions) are fixed per thread, so one
+// running maximum serves them; the digits above come from i, the same for the
+// whole workgroup, and each thread keeps a maximum per (position, digit) for
+// those.  A handful of LDS atomics per thread remain (a contended atomic per
+// row and position took over a millisecond for 4^8 rows).
+constexpr int kBalanceRounds = 4;
+
 __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
+  constexpr int kHi = CQ_MAX_LOCAL_CUTS > 4 ? CQ_MAX_LOCAL_CUTS - 4 : 1;
   __shared__ unsigned long long pmax[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS][4];
   __shared__ int ej[CQ_MAX_CUTS][4];
+  __shared__ int stp[CQ_MAX_CUTS][4];
   __shared__ int smax[CQ_MAX_SUBCIRCUITS];
   __shared__ int goff[CQ_MAX_SUBCIRCUITS];
+  __shared__ int changed;
   const int tid = threadIdx.x;
-  for (int i = tid; i < CQ_MAX_SUBCIRCUITS * CQ_MAX_LOCAL_CUTS * 4; i += blockDim.x)
-    (&pmax[0][0][0])[i] = 0ull;
+  const int lane = tid & 63;
+  for (int i = tid; i < CQ_MAX_CUTS * 4; i += blockDim.x) (&ej[0][0])[i] = 0;
   if (tid < CQ_MAX_SUBCIRCUITS) smax[tid] = INT_MIN;
-  __syncthreads();
-  for (int c = 0; c < b.n_sub; ++c) {
-    const int k = b.k[c];
-    const int64_t rows = (int64_t)1 << (2 * k);
-    for (int64_t l = tid; l < rows; l += blockDim.x) {
-      const unsigned long long v = b.rowmax[c][l];
-      if (v == 0ull) continue;
-      for (int p = 0; p < k; ++p) {
-        const int d = (int)((l >> (2 * (k - 1 - p))) & 3);
-        atomicMax(&pmax[c][p][d], v);
+  // Each round measures the per-digit maxima of the rows as scaled by the
+  // current exponents and moves every cut's pair of exponents to meet them.
+  // In a subcircuit with many cuts the largest row with digit d at one
+  // position is decided by the other positions' extreme digits (one row out
+  // of 4^(k-1) when the labels are far apart), so a single round leaves much
+  // of the spread; a few rounds remove it.
+  for (int round = 0; round < kBalanceRounds; ++round) {
+    for (int i = tid; i < CQ_MAX_SUBCIRCUITS * CQ_MAX_LOCAL_CUTS * 4; i += blockDim.x)
+      (&pmax[0][0][0])[i] = 0ull;
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    for (int c = 0; c < b.n_sub; ++c) {
+      const int k = b.k[c];
+      const int64_t rows = (int64_t)1 << (2 * k);
+      const int nhi = k > 4 ? k - 4 : 0;  // positions 0..nhi-1 take their digit from i
+      auto sgn_e = [&](int p, int d) {
+        const int j = b.cut_of[c][p];
+        return b.up[j] == c ? ej[j][d] : -ej[j][d];
+      };
+      int elo = 0;  // exponent share of the positions fixed by tid
+      for (int p = nhi; p < k; ++p) elo += sgn_e(p, (tid >> (2 * (k - 1 - p))) & 3);
+      unsigned long long tm = 0ull;
+      unsigned long long hm[kHi][4];
+#pragma unroll
+      for (int q = 0; q < kHi; ++q)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) hm[q][d] = 0ull;
+      for (int64_t i = 0; (i << 8) < rows; ++i) {
+        const int64_t l = (i << 8) + tid;
+        int ehi = 0;
+        for (int q = 0; q < nhi; ++q) ehi += sgn_e(q, (int)((i >> (2 * (nhi - 1 - q))) & 3));
+        unsigned long long v = l < rows ? b.rowmax[c][l] : 0ull;
+        if (v) v = (unsigned long long)__double_as_longlong(ldexp(__longlong_as_double((long long)v), elo + ehi));
+        tm = v > tm ? v : tm;
+#pragma unroll
+        for (int q = 0; q < kHi; ++q) {
+          const int d = q < nhi ? (int)((i >> (2 * (nhi - 1 - q))) & 3) : -1;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) hm[q][e] = ((d == e) & (v > hm[q][e])) ? v : hm[q][e];
+        }
+      }
+      for (int p = nhi; p < k; ++p) {
+        const int d = (tid >> (2 * (k - 1 - p))) & 3;
+        if (tm) atomicMax(&pmax[c][p][d], tm);
+      }
+#pragma unroll
+      for (int q = 0; q < kHi; ++q) {
+        if (q >= nhi) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned long long w = wave_max_u64(hm[q][e]);
+          if (lane == 0 && w) atomicMax(&pmax[c][q][e], w);
+        }
       }
     }
-  }
-  __syncthreads();
-  for (int i = tid; i < b.K * 4; i += blockDim.x) {
-    const int j = i >> 2, d = i & 3;
-    const double mu = __longlong_as_double((long long)pmax[b.up[j]][b.pos_up[j]][d]);
-    const double md = __longlong_as_double((long long)pmax[b.down[j]][b.pos_down[j]][d]);
-    int e = 0;
-    if (mu > 0.0 && md > 0.0 && isfinite(mu) && isfinite(md)) {
-      const int diff = bexp(md) - bexp(mu);
-      e = diff >= 0 ? diff / 2 : -((-diff) / 2);  // round toward zero: exact halves
-      e = e > 200 ? 200 : (e < -200 ? -200 : e);
+    __syncthreads();
+    for (int i = tid; i < b.K * 4; i += blockDim.x) {
+      const int j = i >> 2, d = i & 3;
+      const double mu = __longlong_as_double((long long)pmax[b.up[j]][b.pos_up[j]][d]);
+      const double md = __longlong_as_double((long long)pmax[b.down[j]][b.pos_down[j]][d]);
+      int step = 0;
+      if (mu > 0.0 && md > 0.0 && isfinite(mu) && isfinite(md)) {
+        const int diff = bexp(md) - bexp(mu);
+        step = diff >= 0 ? diff / 2 : -((-diff) / 2);  // round toward zero: exact halves
+      }
+      stp[j][d] = step;
     }
-    ej[j][d] = e;
+    __syncthreads();
+    // A step common to a cut's four digits only moves scale between its two
+    // subcircuits (the final offsets undo that); applied round after round
+    // it overshoots in a subcircuit with many cuts, so only the part that
+    // differs between digits is applied.
+    for (int i = tid; i < b.K * 4; i += blockDim.x) {
+      const int j = i >> 2, d = i & 3;
+      const int sum = stp[j][0] + stp[j][1] + stp[j][2] + stp[j][3];
+      const int mean = sum >= 0 ? sum / 4 : -((-sum) / 4);
+      int e = ej[j][d] + stp[j][d] - mean;
+      e = e > 200 ? 200 : (e < -200 ? -200 : e);
+      if (e != ej[j][d]) {
+        ej[j][d] = e;
+        changed = 1;
+      }
+    }
+    __syncthreads();
+    const int more = changed;
+    __syncthreads();  // every thread has read the flag before the next round clears it
+    if (!more) break;
   }
-  __syncthreads();
   for (int c = 0; c < b.n_sub; ++c) {
     const int k = b.k[c];
     const int64_t rows = (int64_t)1 << (2 * k);
+    int sm = INT_MIN;
     for (int64_t l = tid; l < rows; l += blockDim.x) {
       int e = 0;
       for (int p = 0; p < k; ++p) {
@@ -213,8 +302,10 @@ __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
       }
       b.rexp[c][l] = e;
       const double v = __longlong_as_double((long long)b.rowmax[c][l]);
-      if (v > 0.0 && isfinite(v)) atomicMax(&smax[c], bexp(v) + e);
+      if (v > 0.0 && isfinite(v)) sm = max(sm, bexp(v) + e);
     }
+    sm = wave_max_i32(sm);
+    if (lane == 0 && sm != INT_MIN) atomicMax(&smax[c], sm);
   }
   __syncthreads();
   if (tid == 0) {

@@ -144,7 +144,9 @@ hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f1
 // first by 2^e and the second by 2^-e leaves every term unchanged.  e_j(d) is
 // half the difference of the binary exponents of the two sides' largest
 // |entry| among rows with digit d at j, so both sides end up within a factor
-// of two of each other.  rowmax: per subcircuit, max_b |E_c[l][b]| per row l.
+// of two of each other; the maxima are taken again on the scaled rows and
+// e_j(d) corrected, for up to four rounds (until nothing changes).  rowmax:
+// per subcircuit, max_b |E_c[l][b]| per row l.
 struct BalanceLaunch {
   int n_sub, K;
   const uint64_t* rowmax[CQ_MAX_SUBCIRCUITS];  // FP64 bit patterns, 4^k_c each

@@ -459,14 +459,17 @@ def test_label_balance_keeps_bf16_bits():
         m.cq_label_balance_enable(1)
 
 
+@pytest.mark.parametrize("bonds,ns", [([3, 2], [8, 6, 7]), ([4, 4], [6, 4, 6])])
 @pytest.mark.parametrize("prec", ["fp16", "fp16_split"])
-def test_label_balance_rescues_fp16_on_imbalanced_labels(prec):
+def test_label_balance_rescues_fp16_on_imbalanced_labels(prec, bonds, ns):
     """Label rows 2^+-20 apart within a subcircuit: without the balance the
     FP16 conversion loses the small rows (column scaling cannot help, the
     rows share columns); with it both sides of every cut meet in FP16's
-    range and the result matches the oracle as on balanced data."""
+    range and the result matches the oracle as on balanced data.  The second
+    shape has 4^8 label rows in the middle subcircuit, so four of its digit
+    positions lie above the balance kernel's 256-row stride."""
     m = cq()
-    cm, E = syn.chain_instance(12, [3, 2], [8, 6, 7])
+    cm, E = syn.chain_instance(12, bonds, ns)
     Ei = imbalance_labels(cm, E)
     ref = rc.fd_contract(cm, E)
     assert np.array_equal(rc.fd_contract(cm, Ei), ref)  # the input change is exact
