@@ -181,16 +181,22 @@ __device__ inline int wave_max_i32(int v) {
 // subcircuits (every term of Eq. 1 takes one row of each), brings every
 // subcircuit's largest scaled row to their common mean binary exponent.
 // Row maxima are FP64 bit patterns of values >= 0, so their unsigned order is
-// the value order.  Thread t reads rows l = 256 i + t: the digits held in the
-// low 8 bits of l (the last four positions) are fixed per thread, so one
-// running maximum serves them; the digits above come from i, the same for the
-// whole workgroup, and each thread keeps a maximum per (position, digit) for
-// those.  A handful of LDS atomics per thread remain (a contended atomic per
-// row and position took over a millisecond for 4^8 rows).
+// the value order.  Thread t reads rows l = 1024 i + t: the digits held in the
+// low 10 bits of l (the last five positions) are fixed per thread, so one
+// running maximum serves them, and their share of a row's exponent is one
+// number per thread; the digits above come from i, the same for the whole
+// workgroup, and each thread keeps a maximum per (position, digit) for those.
+// A handful of LDS atomics per thread remain (a contended atomic per row and
+// position took over a millisecond for 4^8 rows), and four rows are loaded
+// before any is used.
 constexpr int kBalanceRounds = 4;
+constexpr int kBalThreads = 1024;
+constexpr int kBalLog = 10;            // log2 kBalThreads
+constexpr int kBalFixed = kBalLog / 2;  // digit positions fixed per thread
+constexpr int kBalUnroll = 4;
 
-__global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
-  constexpr int kHi = CQ_MAX_LOCAL_CUTS > 4 ? CQ_MAX_LOCAL_CUTS - 4 : 1;
+__global__ void __launch_bounds__(kBalThreads) balance_kernel(BalanceLaunch b) {
+  constexpr int kHi = CQ_MAX_LOCAL_CUTS > kBalFixed ? CQ_MAX_LOCAL_CUTS - kBalFixed : 1;
   __shared__ unsigned long long pmax[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS][4];
   __shared__ int ej[CQ_MAX_CUTS][4];
   __shared__ int stp[CQ_MAX_CUTS][4];
@@ -201,12 +207,29 @@ __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
   const int lane = tid & 63;
   for (int i = tid; i < CQ_MAX_CUTS * 4; i += blockDim.x) (&ej[0][0])[i] = 0;
   if (tid < CQ_MAX_SUBCIRCUITS) smax[tid] = INT_MIN;
+  // exponent share of position p (digit d) in a row of subcircuit c
+  auto share = [&](int c, int p, int d) {
+    const int j = b.cut_of[c][p];
+    return b.up[j] == c ? ej[j][d] : -ej[j][d];
+  };
+  // the positions fixed by tid, and those taken from i
+  auto share_lo = [&](int c, int k, int nhi) {
+    int e = 0;
+    for (int p = nhi; p < k; ++p) e += share(c, p, (tid >> (2 * (k - 1 - p))) & 3);
+    return e;
+  };
+  auto share_hi = [&](int c, int nhi, int64_t i) {
+    int e = 0;
+    for (int q = 0; q < nhi; ++q) e += share(c, q, (int)((i >> (2 * (nhi - 1 - q))) & 3));
+    return e;
+  };
   // Each round measures the per-digit maxima of the rows as scaled by the
   // current exponents and moves every cut's pair of exponents to meet them.
   // In a subcircuit with many cuts the largest row with digit d at one
   // position is decided by the other positions' extreme digits (one row out
   // of 4^(k-1) when the labels are far apart), so a single round leaves much
   // of the spread; a few rounds remove it.
+  __syncthreads();
   for (int round = 0; round < kBalanceRounds; ++round) {
     for (int i = tid; i < CQ_MAX_SUBCIRCUITS * CQ_MAX_LOCAL_CUTS * 4; i += blockDim.x)
       (&pmax[0][0][0])[i] = 0ull;
@@ -215,31 +238,36 @@ __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
     for (int c = 0; c < b.n_sub; ++c) {
       const int k = b.k[c];
       const int64_t rows = (int64_t)1 << (2 * k);
-      const int nhi = k > 4 ? k - 4 : 0;  // positions 0..nhi-1 take their digit from i
-      auto sgn_e = [&](int p, int d) {
-        const int j = b.cut_of[c][p];
-        return b.up[j] == c ? ej[j][d] : -ej[j][d];
-      };
-      int elo = 0;  // exponent share of the positions fixed by tid
-      for (int p = nhi; p < k; ++p) elo += sgn_e(p, (tid >> (2 * (k - 1 - p))) & 3);
+      const int64_t iters = (rows + kBalThreads - 1) >> kBalLog;
+      const int nhi = k > kBalFixed ? k - kBalFixed : 0;  // positions 0..nhi-1 take their digit from i
+      const int elo = share_lo(c, k, nhi);
       unsigned long long tm = 0ull;
       unsigned long long hm[kHi][4];
 #pragma unroll
       for (int q = 0; q < kHi; ++q)
 #pragma unroll
         for (int d = 0; d < 4; ++d) hm[q][d] = 0ull;
-      for (int64_t i = 0; (i << 8) < rows; ++i) {
-        const int64_t l = (i << 8) + tid;
-        int ehi = 0;
-        for (int q = 0; q < nhi; ++q) ehi += sgn_e(q, (int)((i >> (2 * (nhi - 1 - q))) & 3));
-        unsigned long long v = l < rows ? b.rowmax[c][l] : 0ull;
-        if (v) v = (unsigned long long)__double_as_longlong(ldexp(__longlong_as_double((long long)v), elo + ehi));
-        tm = v > tm ? v : tm;
+      for (int64_t i0 = 0; i0 < iters; i0 += kBalUnroll) {
+        unsigned long long v[kBalUnroll];
 #pragma unroll
-        for (int q = 0; q < kHi; ++q) {
-          const int d = q < nhi ? (int)((i >> (2 * (nhi - 1 - q))) & 3) : -1;
+        for (int u = 0; u < kBalUnroll; ++u) {
+          const int64_t l = ((i0 + u) << kBalLog) + tid;
+          v[u] = ((i0 + u < iters) & (l < rows)) ? b.rowmax[c][l] : 0ull;
+        }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) hm[q][e] = ((d == e) & (v > hm[q][e])) ? v : hm[q][e];
+        for (int u = 0; u < kBalUnroll; ++u) {
+          const int64_t i = i0 + u;
+          unsigned long long x = v[u];
+          if (x)
+            x = (unsigned long long)__double_as_longlong(
+                ldexp(__longlong_as_double((long long)x), elo + share_hi(c, nhi, i)));
+          tm = x > tm ? x : tm;
+#pragma unroll
+          for (int q = 0; q < kHi; ++q) {
+            const int d = q < nhi ? (int)((i >> (2 * (nhi - 1 - q))) & 3) : -1;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) hm[q][e] = ((d == e) & (x > hm[q][e])) ? x : hm[q][e];
+          }
         }
       }
       for (int p = nhi; p < k; ++p) {
@@ -289,20 +317,26 @@ __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
     __syncthreads();  // every thread has read the flag before the next round clears it
     if (!more) break;
   }
+  // every subcircuit's largest scaled row (binary exponent)
   for (int c = 0; c < b.n_sub; ++c) {
     const int k = b.k[c];
     const int64_t rows = (int64_t)1 << (2 * k);
+    const int64_t iters = (rows + kBalThreads - 1) >> kBalLog;
+    const int nhi = k > kBalFixed ? k - kBalFixed : 0;
+    const int elo = share_lo(c, k, nhi);
     int sm = INT_MIN;
-    for (int64_t l = tid; l < rows; l += blockDim.x) {
-      int e = 0;
-      for (int p = 0; p < k; ++p) {
-        const int j = b.cut_of[c][p];
-        const int d = (int)((l >> (2 * (k - 1 - p))) & 3);
-        e += b.up[j] == c ? ej[j][d] : -ej[j][d];
+    for (int64_t i0 = 0; i0 < iters; i0 += kBalUnroll) {
+      unsigned long long v[kBalUnroll];
+#pragma unroll
+      for (int u = 0; u < kBalUnroll; ++u) {
+        const int64_t l = ((i0 + u) << kBalLog) + tid;
+        v[u] = ((i0 + u < iters) & (l < rows)) ? b.rowmax[c][l] : 0ull;
       }
-      b.rexp[c][l] = e;
-      const double v = __longlong_as_double((long long)b.rowmax[c][l]);
-      if (v > 0.0 && isfinite(v)) sm = max(sm, bexp(v) + e);
+#pragma unroll
+      for (int u = 0; u < kBalUnroll; ++u) {
+        const double x = __longlong_as_double((long long)v[u]);
+        if (x > 0.0 && isfinite(x)) sm = max(sm, bexp(x) + elo + share_hi(c, nhi, i0 + u));
+      }
     }
     sm = wave_max_i32(sm);
     if (lane == 0 && sm != INT_MIN) atomicMax(&smax[c], sm);
@@ -327,9 +361,16 @@ __global__ void __launch_bounds__(256) balance_kernel(BalanceLaunch b) {
     if (last >= 0) goff[last] -= (int)tot;  // the offsets sum to zero
   }
   __syncthreads();
+  // every row's exponent: its digits' shares plus its subcircuit's offset
   for (int c = 0; c < b.n_sub; ++c) {
-    const int64_t rows = (int64_t)1 << (2 * b.k[c]);
-    for (int64_t l = tid; l < rows; l += blockDim.x) b.rexp[c][l] += goff[c];
+    const int k = b.k[c];
+    const int64_t rows = (int64_t)1 << (2 * k);
+    const int nhi = k > kBalFixed ? k - kBalFixed : 0;
+    const int elo = share_lo(c, k, nhi) + goff[c];
+    for (int64_t i = 0; (i << kBalLog) < rows; ++i) {
+      const int64_t l = (i << kBalLog) + tid;
+      if (l < rows) b.rexp[c][l] = elo + share_hi(c, nhi, i);
+    }
   }
 }
 
@@ -773,7 +814,7 @@ hipError_t launch_rowmax(const double* E, int64_t rows, int cols_log2, uint64_t*
 }
 
 hipError_t launch_balance(const BalanceLaunch& b, hipStream_t stream) {
-  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(256), 0, stream, b);
+  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(kBalThreads), 0, stream, b);
   return hipGetLastError();
 }
 
