@@ -1279,6 +1279,147 @@ gemm_h16t_kernel(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 operands, occupancy form.  The persistent FP32 kernel keeps a finished
+// tile in registers while the next one runs (two waves per SIMD).  This form
+// takes one 128 x 128 tile per workgroup like gemm_h16t_kernel, with stages of
+// 8 labels (8 KB) in an NS-deep ring and the epilogue staged through the
+// ring, so that WPE workgroups share a CU and one's stage waits and stores
+// overlap the others' products.  Operand rows are 512 bytes (128 floats); a
+// DMA instruction fills two rows, odd rows with their 16-byte chunks swapped
+// by halves as in PersistF32.  Fragment reads, the product order (k ascending
+// in pairs, one 32x32x2 FP32 MFMA per pair and block) and the short-K
+// handling are those of the persistent FP32 kernel, so the sums are the same
+// bit for bit.
+// ---------------------------------------------------------------------------
+template <int OUT, int NS, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+gemm_f32t_kernel(GemmArgs g) {
+  constexpr int BM = 128, BN = 128, BK = 8;
+  constexpr int TILE = BK * 512;  // bytes of one operand stage
+  constexpr int STAGE = TILE * 2;  // A and B
+  constexpr int LPW = 2;           // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage; the
+  // build checks the assembly against this marker
+  asm volatile("; cq-vm-lpw %0" ::"n"(LPW));
+  constexpr int EROW = 288;  // bytes per staged output row (64 floats + pad)
+  constexpr int EPI = 4 * 8 * EROW;
+  constexpr int SMEM = NS * STAGE > EPI ? NS * STAGE : EPI;
+  static_assert(NS >= 2 && NS <= 4, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+  // wave w's instruction for an operand fills rows 2w (lanes 0-31) and
+  // 2w + 1 (lanes 32-63); lane slot q of row r holds the row's chunk q ^ 8r
+  const int r = lane >> 5, c = lane & 31;
+  const int lrow = 2 * wave + r;
+  const float* gbase[2];
+  int64_t lcol[2];
+  {
+    gbase[0] = static_cast<const float*>(g.A) + tc.z * g.sAz + m0;
+    gbase[1] = static_cast<const float*>(g.B) + tc.z * g.sBz + n0;
+    // last 16-byte chunk inside each operand (M, N are multiples of 4)
+    const int64_t capA = ((g.M - 4) & ~(int64_t)3) - m0, capB = ((g.N - 4) & ~(int64_t)3) - n0;
+    const int64_t col = (int64_t)(c ^ (8 * r)) * 4;
+    lcol[0] = col > capA ? capA : col;
+    lcol[1] = col > capB ? capB : col;
+  }
+  auto issue = [&](int s) {
+    int64_t k = (int64_t)s * BK + lrow;
+    if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const float* src = gbase[op] + k * (op ? g.sBk : g.sAk) + lcol[op];
+      const uint32_t dst = __builtin_amdgcn_readfirstlane(
+          (uint32_t)(uintptr_t)(lsm + (s % NS) * STAGE + op * TILE + wave * 1024));
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                   : "memory", "m0");
+    }
+  };
+  f16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  for (int s = 0; s < NS - 1 && s < nstages; ++s) issue(s);
+  for (int s = 0; s < nstages; ++s) {
+    // this wave's loads of stage s have landed once at most `ahead` later
+    // stages are outstanding; the barrier then covers every wave's loads
+    const int ahead = (nstages - 1 - s) < (NS - 2) ? (nstages - 1 - s) : (NS - 2);
+    if (ahead >= 2) wait_vm<2 * LPW>();
+    else if (ahead == 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (s + NS - 1 < nstages) issue(s + NS - 1);
+    const int sb = (s % NS) * STAGE;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      if (kk >= kvalid) break;  // short K (outer products): skip all-zero steps
+      const int row = kk + r;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int ca = wm + 32 * i + c, cb = wn + 32 * i + c;
+        a[i] = *(const CQ_LDS float*)(lsm + sb + row * 512 + (((ca >> 2) ^ (8 * r)) << 4) + (ca & 3) * 4);
+        b[i] = *(const CQ_LDS float*)(lsm + sb + TILE + row * 512 + (((cb >> 2) ^ (8 * r)) << 4) +
+                                      (cb & 3) * 4);
+        if (row >= kvalid) a[i] = 0.0f;  // rows past K hold a clamped copy of row K - 1
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: slab u of a wave holds rows 32*(u>>2) + 8*(u&3) .. +7 of its
+  // 64 x 64 block; it is staged in the ring so that every store instruction
+  // writes whole row segments
+  const float alpha = float(g.alpha);
+  __syncthreads();  // every wave is done with the ring
+  char* const wbuf = smem + wave * 8 * EROW;
+  const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u >> 2, vg = u & 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = 4 * (lane >> 5) + e;
+        const int cc = 32 * j + (lane & 31);
+        *reinterpret_cast<float*>(wbuf + rr * EROW + cc * 4) = alpha * acc[i][j][4 * vg + e];
+      }
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rl = 4 * h + (lane >> 4);
+      const int cc = 4 * (lane & 15);
+      const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + cc * 4);
+      const int64_t m = m0 + wm + 32 * i + 8 * vg + rl, n = n0 + wn + cc;
+      const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+      if (full || (m < g.M && n + 3 < g.N)) {
+        store_out<f4_t, OUT == 1>(reinterpret_cast<f4_t*>(static_cast<float*>(g.C) + idx), x);
+      } else if (m < g.M) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < g.N) store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx + e, x[e]);
+      }
+    }
+    // the slab's LDS reads are done before the next slab overwrites it
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent form (no output exponents), for 16-bit and FP32 operands, with
 // FP32 output or -- 16-bit operands -- 16-bit hi (and lo) output planes.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
 // workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
@@ -1680,6 +1821,14 @@ bool f32p_ok(const GemmArgs& a) {
          a.sCz % 4 == 0 && al(a.A) && al(a.B) && al(a.C);
 }
 
+template <int NS, int WPE>
+hipError_t launch_f32t(const GemmArgs& a, bool nt, hipStream_t s) {
+  const dim3 grid((unsigned)a.tiles), block(256);
+  if (nt) hipLaunchKernelGGL((gemm_f32t_kernel<1, NS, WPE>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_f32t_kernel<0, NS, WPE>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
 template <int SPLIT, bool F16, int NS, int WPE>
 hipError_t launch_h16t(const GemmArgs& a, DType tc, bool nt, hipStream_t s) {
   const dim3 grid((unsigned)a.tiles), block(256);
@@ -1740,6 +1889,11 @@ hipError_t launch_variant(cq_precision prec, GemmArgs a, DType tc, bool nt, int 
     case CQ_FP64:
       return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
     case CQ_FP32:
+      // 0 = tiled kernel (1 and 2 repeat it), 3 = persistent kernel, 4 and 5 =
+      // occupancy kernel (four workgroups per CU with a three-deep ring,
+      // three with a four-deep one)
+      if (impl == 4 && f32p_ok(a)) return launch_f32t<3, 4>(a, nt, stream);
+      if (impl == 5 && f32p_ok(a)) return launch_f32t<4, 3>(a, nt, stream);
       if (impl == 3 && f32p_ok(a)) {
         const int64_t grid = persistent_grid(a.tiles);
         if (nt) hipLaunchKernelGGL((gemm_persist_kernel<PersistF32, 1, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
@@ -1882,7 +2036,7 @@ int tune_mode() {
 }
 
 int variant_count(cq_precision prec) {
-  return prec == CQ_FP64 ? 2 : prec == CQ_FP32 ? 8 : kMaxVariants;
+  return prec == CQ_FP64 ? 2 : kMaxVariants;
 }
 
 // whether variant v has a kernel of its own for this launch (else it would
@@ -1891,7 +2045,7 @@ bool variant_applies(cq_precision prec, const GemmArgs& a, DType tc, int v) {
   const int impl = v >> 1;
   if (impl == 0) return true;
   if (v >= variant_count(prec)) return false;
-  if (prec == CQ_FP32) return impl == 3 && f32p_ok(a);
+  if (prec == CQ_FP32) return impl >= 3 && f32p_ok(a);
   return impl >= 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
 }
 
@@ -2045,10 +2199,10 @@ std::string variant_schedule(int prec, int v) {
   const bool split = prec == CQ_BF16_SPLIT || prec == CQ_FP16_SPLIT;
   const char* kernel = "tiled";
   int ring = 0, wpc = 0;
-  if (prec == CQ_FP32 && impl == 3) {
-    kernel = "persistent";
-    ring = 4;
-    wpc = 2;
+  if (prec == CQ_FP32 && impl >= 3) {
+    kernel = impl == 3 ? "persistent" : "occupancy";
+    ring = impl == 4 ? 3 : 4;
+    wpc = impl == 3 ? 2 : impl == 4 ? 4 : 3;
   } else if (prec != CQ_FP64 && prec != CQ_FP32) {
     switch (impl) {
       case 0: kernel = "async"; ring = split ? 2 : 3; break;
