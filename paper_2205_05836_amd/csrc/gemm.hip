@@ -1890,10 +1890,10 @@ hipError_t launch_variant(cq_precision prec, GemmArgs a, DType tc, bool nt, int 
       return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
     case CQ_FP32:
       // 0 = tiled kernel (1 and 2 repeat it), 3 = persistent kernel, 4 and 5 =
-      // occupancy kernel (four workgroups per CU with a three-deep ring,
-      // three with a four-deep one)
+      // occupancy kernel (four workgroups per CU with a three- or four-deep
+      // ring)
       if (impl == 4 && f32p_ok(a)) return launch_f32t<3, 4>(a, nt, stream);
-      if (impl == 5 && f32p_ok(a)) return launch_f32t<4, 3>(a, nt, stream);
+      if (impl == 5 && f32p_ok(a)) return launch_f32t<4, 4>(a, nt, stream);
       if (impl == 3 && f32p_ok(a)) {
         const int64_t grid = persistent_grid(a.tiles);
         if (nt) hipLaunchKernelGGL((gemm_persist_kernel<PersistF32, 1, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
@@ -2202,7 +2202,7 @@ std::string variant_schedule(int prec, int v) {
   if (prec == CQ_FP32 && impl >= 3) {
     kernel = impl == 3 ? "persistent" : "occupancy";
     ring = impl == 4 ? 3 : 4;
-    wpc = impl == 3 ? 2 : impl == 4 ? 4 : 3;
+    wpc = impl == 3 ? 2 : 4;
   } else if (prec != CQ_FP64 && prec != CQ_FP32) {
     switch (impl) {
       case 0: kernel = "async"; ring = split ? 2 : 3; break;

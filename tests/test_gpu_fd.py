@@ -212,7 +212,7 @@ RAGGED = [(22, [4, 4], [10, 4, 10]), (23, [3, 3], [10, 3, 10]), (24, [5, 2], [10
 def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
     """Variants 6 and 7 (persistent kernel, both rasters) and 8 and 10 (the
     occupancy kernels: for the 16-bit forms two- and three-deep rings, for
-    FP32 three- and four-deep) against variant 0 bit for bit -- same
+    FP32 three- and four-deep rings) against variant 0 bit for bit -- same
     products, same order -- and against the oracle."""
     m = cq()
     cm, E = syn.chain_instance(seed, bonds, ns)
