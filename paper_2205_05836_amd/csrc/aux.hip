@@ -100,11 +100,47 @@ __device__ inline void prep_body(const double* __restrict__ src, void* dst, void
   }
 }
 
+// Four elements a thread: two 16-byte loads, 8-byte (16-bit planes) or
+// 16-byte (FP32) stores; the per-element arithmetic is prep_body's.  Needs
+// n % 4 == 0, src 16-byte aligned, dst (and dst_lo) aligned to the stores,
+// and rows of at least 4 elements when rexp is given.
 template <int DK>
+__device__ inline void prep_body4(const double* __restrict__ src, void* dst, void* dst_lo, int64_t n,
+                                  const int32_t* __restrict__ rexp, int cols_log2) {
+  typedef double d2_t __attribute__((ext_vector_type(2)));
+  typedef float f4_t __attribute__((ext_vector_type(4)));
+  typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+  const int64_t n4 = n >> 2;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += step) {
+    const d2_t v0 = reinterpret_cast<const d2_t*>(src)[2 * i];
+    const d2_t v1 = reinterpret_cast<const d2_t*>(src)[2 * i + 1];
+    const double d[4] = {v0[0], v0[1], v1[0], v1[1]};
+    const int e = rexp ? rexp[(4 * i) >> cols_log2] : 0;
+    float x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = rexp ? float(ldexp(d[u], e)) : float(d[u]);
+    if constexpr (DK == kF32) {
+      reinterpret_cast<f4_t*>(dst)[i] = f4_t{x[0], x[1], x[2], x[3]};
+    } else {
+      u16x4 h, l;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        h[u] = f_to_h16(x[u], DK == kF16);
+        l[u] = f_to_h16(x[u] - h16_to_f(h[u], DK == kF16), DK == kF16);
+      }
+      reinterpret_cast<u16x4*>(dst)[i] = h;
+      if (dst_lo) reinterpret_cast<u16x4*>(dst_lo)[i] = l;
+    }
+  }
+}
+
+template <int DK, bool V4>
 __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ src, void* dst,
                                                    void* dst_lo, int64_t n,
                                                    const int32_t* __restrict__ rexp, int cols_log2) {
-  prep_body<DK>(src, dst, dst_lo, n, rexp, cols_log2);
+  if constexpr (V4) prep_body4<DK>(src, dst, dst_lo, n, rexp, cols_log2);
+  else prep_body<DK>(src, dst, dst_lo, n, rexp, cols_log2);
 }
 
 // blockIdx.y selects the argument block, blockIdx.z the instance
@@ -793,15 +829,21 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t stream) {
 hipError_t launch_prep(const double* src, void* dst, int64_t n, DType t, bool f16,
                        hipStream_t stream, const int32_t* rexp, int cols_log2) {
   if (n <= 0) return hipSuccess;
-  const dim3 grid(grid_for(n));
   void* lo = t == DType::H16X2 ? static_cast<char*>(dst) + n * 2 : nullptr;
-  if (t == DType::F32)
-    hipLaunchKernelGGL((prep_kernel<kF32>), grid, dim3(256), 0, stream, src, dst, nullptr, n, rexp,
-                       cols_log2);
-  else if (f16)
-    hipLaunchKernelGGL((prep_kernel<kF16>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
-  else
-    hipLaunchKernelGGL((prep_kernel<kBF16>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+  auto al = [](const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+  const bool v4 = n % 4 == 0 && (!rexp || cols_log2 >= 2) && al(src, 16) &&
+                  al(dst, t == DType::F32 ? 16 : 8) && (!lo || al(lo, 8));
+  const dim3 grid(grid_for(v4 ? n / 4 : n));
+  if (t == DType::F32) {
+    if (v4) hipLaunchKernelGGL((prep_kernel<kF32, true>), grid, dim3(256), 0, stream, src, dst, nullptr, n, rexp, cols_log2);
+    else hipLaunchKernelGGL((prep_kernel<kF32, false>), grid, dim3(256), 0, stream, src, dst, nullptr, n, rexp, cols_log2);
+  } else if (f16) {
+    if (v4) hipLaunchKernelGGL((prep_kernel<kF16, true>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+    else hipLaunchKernelGGL((prep_kernel<kF16, false>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+  } else {
+    if (v4) hipLaunchKernelGGL((prep_kernel<kBF16, true>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+    else hipLaunchKernelGGL((prep_kernel<kBF16, false>), grid, dim3(256), 0, stream, src, dst, lo, n, rexp, cols_log2);
+  }
   return hipGetLastError();
 }
 
