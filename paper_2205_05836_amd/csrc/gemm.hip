@@ -1420,6 +1420,100 @@ gemm_f32t_kernel(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 operands, 64 x 64 tiles: for GEMMs with few 128 x 128 tiles (a few
+// hundred outputs per side), four times as many workgroups reach the CUs.
+// Each wave owns one 32 x 32 block; stages hold 16 labels (4 KB per operand,
+// rows of 256 bytes) in an NS-deep ring, one DMA instruction per wave and
+// operand filling four rows, odd rows with their 16-byte chunks swapped by
+// halves so that the two rows an MFMA operand read touches fall into
+// different banks.  Products run in the persistent FP32 kernel's order (k
+// ascending in pairs, one 32x32x2 MFMA per pair), so the sums are the same
+// bit for bit; results are stored from registers.
+// ---------------------------------------------------------------------------
+template <int OUT, int NS>
+__global__ void __launch_bounds__(256) gemm_f32s_kernel(GemmArgs g) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  constexpr int TILE = BK * 256;  // bytes of one operand stage
+  constexpr int STAGE = TILE * 2;  // A and B
+  constexpr int LPW = 2;           // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage; the
+  // build checks the assembly against this marker
+  asm volatile("; cq-vm-lpw %0" ::"n"(LPW));
+  static_assert(NS >= 2 && NS <= 4, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[NS * STAGE];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+  // wave w's instruction for an operand fills rows 4w .. 4w + 3, sixteen
+  // lanes a row; slot q of row r holds the row's chunk q ^ 8(r & 1)
+  const int lrow = 4 * wave + (lane >> 4);
+  const int slot = lane & 15;
+  const float* gbase[2];
+  int64_t lcol[2];
+  {
+    gbase[0] = static_cast<const float*>(g.A) + tc.z * g.sAz + m0;
+    gbase[1] = static_cast<const float*>(g.B) + tc.z * g.sBz + n0;
+    // last 16-byte chunk inside each operand (M, N are multiples of 4)
+    const int64_t capA = ((g.M - 4) & ~(int64_t)3) - m0, capB = ((g.N - 4) & ~(int64_t)3) - n0;
+    const int64_t col = (int64_t)(slot ^ (8 * (lrow & 1))) * 4;
+    lcol[0] = col > capA ? capA : col;
+    lcol[1] = col > capB ? capB : col;
+  }
+  auto issue = [&](int s) {
+    int64_t k = (int64_t)s * BK + lrow;
+    if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const float* src = gbase[op] + k * (op ? g.sBk : g.sAk) + lcol[op];
+      const uint32_t dst = __builtin_amdgcn_readfirstlane(
+          (uint32_t)(uintptr_t)(lsm + (s % NS) * STAGE + op * TILE + wave * 1024));
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                   : "memory", "m0");
+    }
+  };
+  f16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  const int r = lane >> 5, c = lane & 31;
+
+  for (int s = 0; s < NS - 1 && s < nstages; ++s) issue(s);
+  for (int s = 0; s < nstages; ++s) {
+    // this wave's loads of stage s have landed once at most `ahead` later
+    // stages are outstanding; the barrier then covers every wave's loads
+    const int ahead = (nstages - 1 - s) < (NS - 2) ? (nstages - 1 - s) : (NS - 2);
+    if (ahead >= 2) wait_vm<2 * LPW>();
+    else if (ahead == 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (s + NS - 1 < nstages) issue(s + NS - 1);
+    const int sb = (s % NS) * STAGE;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      if (kk >= kvalid) break;  // short K (outer products): skip all-zero steps
+      const int row = kk + r;
+      const int ca = wm + c, cb = wn + c;
+      float a = *(const CQ_LDS float*)(lsm + sb + row * 256 + (((ca >> 2) ^ (8 * r)) << 4) + (ca & 3) * 4);
+      const float b =
+          *(const CQ_LDS float*)(lsm + sb + TILE + row * 256 + (((cb >> 2) ^ (8 * r)) << 4) + (cb & 3) * 4);
+      if (row >= kvalid) a = 0.0f;  // rows past K hold a clamped copy of row K - 1
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+  }
+
+  const float alpha = float(g.alpha);
+  float* const C = static_cast<float*>(g.C);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t m = m0 + wm + 8 * (v >> 2) + 4 * r + (v & 3), n = n0 + wn + c;
+    if (m < g.M && n < g.N) store_out<float, OUT == 1>(C + tc.z * g.sCz + m * g.ldc + n, alpha * acc[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent form (no output exponents), for 16-bit and FP32 operands, with
 // FP32 output or -- 16-bit operands -- 16-bit hi (and lo) output planes.  Same operand ring of LDS DMA stages as gemm_h16a_kernel, but each
 // workgroup walks tiles blockIdx.x, +gridDim.x, ... and the ring's stages run
@@ -1821,6 +1915,19 @@ bool f32p_ok(const GemmArgs& a) {
          a.sCz % 4 == 0 && al(a.A) && al(a.B) && al(a.C);
 }
 
+template <int NS>
+hipError_t launch_f32s(GemmArgs a, bool nt, hipStream_t s) {
+  const int64_t z = a.tiles / (a.tilesM * a.tilesN);  // batches (the tile counts are for 128 x 128)
+  a.tilesM = (a.M + 63) / 64;
+  a.tilesN = (a.N + 63) / 64;
+  a.tiles = a.tilesM * a.tilesN * z;
+  if (a.tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)a.tiles), block(256);
+  if (nt) hipLaunchKernelGGL((gemm_f32s_kernel<1, NS>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_f32s_kernel<0, NS>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
 template <int NS, int WPE>
 hipError_t launch_f32t(const GemmArgs& a, bool nt, hipStream_t s) {
   const dim3 grid((unsigned)a.tiles), block(256);
@@ -1889,9 +1996,10 @@ hipError_t launch_variant(cq_precision prec, GemmArgs a, DType tc, bool nt, int 
     case CQ_FP64:
       return nt ? launch(gemm_f64_kernel<true>, a, stream, 512) : launch(gemm_f64_kernel<false>, a, stream, 512);
     case CQ_FP32:
-      // 0 = tiled kernel (1 and 2 repeat it), 3 = persistent kernel, 4 and 5 =
-      // occupancy kernel (four workgroups per CU with a three- or four-deep
-      // ring)
+      // 0 = tiled kernel, 1 = 64 x 64 tiles (2 repeats 0), 3 = persistent
+      // kernel, 4 and 5 = occupancy kernel (four workgroups per CU with a
+      // three- or four-deep ring)
+      if (impl == 1 && f32p_ok(a)) return launch_f32s<3>(a, nt, stream);
       if (impl == 4 && f32p_ok(a)) return launch_f32t<3, 4>(a, nt, stream);
       if (impl == 5 && f32p_ok(a)) return launch_f32t<4, 4>(a, nt, stream);
       if (impl == 3 && f32p_ok(a)) {
@@ -2045,7 +2153,7 @@ bool variant_applies(cq_precision prec, const GemmArgs& a, DType tc, int v) {
   const int impl = v >> 1;
   if (impl == 0) return true;
   if (v >= variant_count(prec)) return false;
-  if (prec == CQ_FP32) return impl >= 3 && f32p_ok(a);
+  if (prec == CQ_FP32) return (impl == 1 || impl >= 3) && f32p_ok(a);
   return impl >= 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
 }
 
@@ -2198,8 +2306,12 @@ std::string variant_schedule(int prec, int v) {
   const int impl = v >> 1;
   const bool split = prec == CQ_BF16_SPLIT || prec == CQ_FP16_SPLIT;
   const char* kernel = "tiled";
-  int ring = 0, wpc = 0;
-  if (prec == CQ_FP32 && impl >= 3) {
+  int ring = 0, wpc = 0, tile = 128;
+  if (prec == CQ_FP32 && impl == 1) {
+    kernel = "small-tile";
+    ring = 3;
+    tile = 64;
+  } else if (prec == CQ_FP32 && impl >= 3) {
     kernel = impl == 3 ? "persistent" : "occupancy";
     ring = impl == 4 ? 3 : 4;
     wpc = impl == 3 ? 2 : 4;
@@ -2215,9 +2327,9 @@ std::string variant_schedule(int prec, int v) {
   }
   char buf[256];
   const int n = std::snprintf(buf, sizeof(buf),
-                              "{\"kernel\": \"%s\", \"tile\": [128, 128], \"ring\": %d, "
+                              "{\"kernel\": \"%s\", \"tile\": [%d, %d], \"ring\": %d, "
                               "\"workgroups_per_cu\": %d, \"raster\": \"%s\"}",
-                              kernel, ring, wpc, (v & 1) ? "flipped" : "default");
+                              kernel, tile, tile, ring, wpc, (v & 1) ? "flipped" : "default");
   return std::string(buf, (size_t)n);
 }
 
