@@ -1279,6 +1279,148 @@ gemm_h16t_kernel(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit operands, 64 x 64 tiles: for GEMMs with few 128 x 128 tiles.  Each
+// wave owns one 32 x 32 block; stages hold 32 labels in rows of 64 elements
+// (128 bytes) in an NS-deep ring, one DMA instruction per wave and plane
+// filling eight rows, 16-byte chunks of row r at slot chunk ^ (r & 7).  The
+// transposed fragment reads, the product order (per block and 16-label step:
+// hi*hi, then hi*lo, then lo*hi) and the masking of labels past K are those of
+// gemm_h16t_kernel, which runs no step that lies wholly past K, so the sums
+// are the same bit for bit; results are stored from registers.
+// ---------------------------------------------------------------------------
+__device__ inline int swz8(int row, int chunk) { return chunk ^ (row & 7); }
+
+template <int SPLIT, bool F16, int OUT, int NS>
+__global__ void __launch_bounds__(256) gemm_h16s_kernel(GemmArgs g) {
+  using H = Half<F16>;
+  using V8 = typename H::V8;
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int NP = SPLIT == 3 ? 2 : 1;
+  constexpr int TILE = BK * 128;        // bytes of one operand-plane stage
+  constexpr int STAGE = TILE * 2 * NP;  // A and B, all planes
+  constexpr int LPW = 2 * NP;           // DMA instructions per wave per stage
+  // the hand-counted vmcnt waits below assume LPW DMA loads per stage; the
+  // build checks the assembly against this marker
+  asm volatile("; cq-vm-lpw %0" ::"n"(LPW));
+  static_assert(NS >= 2 && NS <= 4, "stage count");
+  __shared__ __attribute__((aligned(16))) char smem[NS * STAGE];
+  CQ_LDS char* const lsm = (CQ_LDS char*)smem;
+  const TileCoord tc = tile_coord<BM, BN>(g);
+  const int64_t m0 = tc.m0, n0 = tc.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int nstages = (int)((g.K + BK - 1) / BK);
+  // wave w's instruction for (operand, plane) fills rows 8w .. 8w + 7
+  const uint16_t* gbase[2][NP];
+  int64_t ccap[2];
+  {
+    const int64_t za = tc.z * g.sAz, zb = tc.z * g.sBz;
+    gbase[0][0] = static_cast<const uint16_t*>(g.A) + za + m0;
+    gbase[1][0] = static_cast<const uint16_t*>(g.B) + zb + n0;
+    if constexpr (NP == 2) {
+      gbase[0][NP - 1] = static_cast<const uint16_t*>(g.A_lo) + za + m0;
+      gbase[1][NP - 1] = static_cast<const uint16_t*>(g.B_lo) + zb + n0;
+    }
+    ccap[0] = ((g.M - 8) & ~(int64_t)7) - m0;
+    ccap[1] = ((g.N - 8) & ~(int64_t)7) - n0;
+  }
+  const int lrow = 8 * wave + (lane >> 3);
+  int64_t lcol[2];
+#pragma unroll
+  for (int op = 0; op < 2; ++op) {
+    lcol[op] = (int64_t)swz8(lrow, lane & 7) * 8;
+    if (lcol[op] > ccap[op]) lcol[op] = ccap[op];
+  }
+  auto issue = [&](int s) {
+    int64_t k = (int64_t)s * BK + lrow;
+    if (k >= g.K) k = g.K - 1;  // rows past K are masked to zero when read
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const uint16_t* src = gbase[op][p] + k * (op ? g.sBk : g.sAk) + lcol[op];
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(lsm + (s % NS) * STAGE + (op * NP + p) * TILE + wave * 1024));
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(dst)
+                     : "memory", "m0");
+      }
+  };
+  f16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  const int grp = lane >> 4, r16 = lane & 15;
+  const int col_in_blk = 16 * (grp & 1) + 4 * (r16 & 3);
+  const int krow = 8 * (grp >> 1) + (r16 >> 2);
+  auto frag = [&](int tile, int kk, int c0, int64_t kvalid) -> V8 {
+    const int col = c0 + col_in_blk;
+    const int r0 = kk + krow, r1 = r0 + 4;
+    const int o0 = tile + r0 * 128 + (swz8(r0, col >> 3) << 4) + (col & 7) * 2;
+    const int o1 = tile + r1 * 128 + (swz8(r1, col >> 3) << 4) + (col & 7) * 2;
+    s4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o0));
+    s4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((CQ_LDS s4_t*)(lsm + o1));
+    if (kvalid < kk + 16) {
+      // slot e of the two reads holds label kk + 8*(grp>>1) + e (+4)
+      const int kb = kk + 8 * (grp >> 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kvalid) lo[e] = 0;
+        if (kb + 4 + e >= kvalid) hi[e] = 0;
+      }
+    }
+    typedef short s8_t __attribute__((ext_vector_type(8)));
+    const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(V8, v);
+  };
+
+  for (int s = 0; s < NS - 1 && s < nstages; ++s) issue(s);
+  for (int s = 0; s < nstages; ++s) {
+    // this wave's loads of stage s have landed once at most `ahead` later
+    // stages are outstanding; the barrier then covers every wave's loads
+    const int ahead = (nstages - 1 - s) < (NS - 2) ? (nstages - 1 - s) : (NS - 2);
+    if (ahead >= 2) wait_vm<2 * LPW>();
+    else if (ahead == 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (s + NS - 1 < nstages) issue(s + NS - 1);
+    const int sb = (s % NS) * STAGE;
+    const int64_t kvalid = g.K - (int64_t)s * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      if (kk >= kvalid) break;  // a 16-label step wholly past K
+      V8 a[NP], b[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        a[p] = frag(sb + (0 * NP + p) * TILE, kk, wm, kvalid);
+        b[p] = frag(sb + (1 * NP + p) * TILE, kk, wn, kvalid);
+      }
+      acc = H::mfma(a[0], b[0], acc);
+      if constexpr (SPLIT == 3) {
+        acc = H::mfma(a[0], b[NP - 1], acc);
+        acc = H::mfma(a[NP - 1], b[0], acc);
+      }
+    }
+  }
+
+  const float alpha = float(g.alpha);
+  const int r = lane >> 5, c = lane & 31;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t m = m0 + wm + 8 * (v >> 2) + 4 * r + (v & 3), n = n0 + wn + c;
+    if (m < g.M && n < g.N) {
+      const float x = alpha * acc[v];
+      const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+      if constexpr (OUT == 2) {
+        const uint16_t h = to_h16<F16>(x);
+        static_cast<uint16_t*>(g.C)[idx] = h;
+        if (g.C_lo) static_cast<uint16_t*>(g.C_lo)[idx] = to_h16<F16>(x - from_h16<F16>(h));
+      } else {
+        store_out<float, OUT == 1>(static_cast<float*>(g.C) + idx, x);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP32 operands, occupancy form.  The persistent FP32 kernel keeps a finished
 // tile in registers while the next one runs (two waves per SIMD).  This form
 // takes one 128 x 128 tile per workgroup like gemm_h16t_kernel, with stages of
@@ -1882,7 +2024,8 @@ bool h16_async_ok(const GemmArgs& a, DType tc) {
 }
 
 // Variant `impl` of the 16-bit launch: 0 = asynchronous kernel with its
-// default ring depth, 1 = the other depth, 2 = register-path kernel,
+// default ring depth, 1 = the other depth, 2 = 64 x 64 tiles (the
+// register-path kernel where those do not apply),
 // 3 = persistent kernel, 4 and 5 = occupancy kernel (four workgroups per CU
 // with a two-deep ring, three with a three-deep one).
 // Persistent grid: two workgroups per compute unit, a multiple of 8 so that
@@ -1913,6 +2056,20 @@ bool f32p_ok(const GemmArgs& a) {
   return a.rowexp == nullptr && a.K >= 1 && a.M >= 4 && a.N >= 4 && a.M % 4 == 0 && a.N % 4 == 0 &&
          a.sAk % 4 == 0 && a.sBk % 4 == 0 && a.sAz % 4 == 0 && a.sBz % 4 == 0 && a.ldc % 4 == 0 &&
          a.sCz % 4 == 0 && al(a.A) && al(a.B) && al(a.C);
+}
+
+template <int SPLIT, bool F16>
+hipError_t launch_h16s(GemmArgs a, DType tc, bool nt, hipStream_t s) {
+  const int64_t z = a.tiles / (a.tilesM * a.tilesN);  // batches (the tile counts are for 128 x 128)
+  a.tilesM = (a.M + 63) / 64;
+  a.tilesN = (a.N + 63) / 64;
+  a.tiles = a.tilesM * a.tilesN * z;
+  if (a.tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)a.tiles), block(256);
+  if (tc != DType::F32) hipLaunchKernelGGL((gemm_h16s_kernel<SPLIT, F16, 2, 2>), grid, block, 0, s, a);
+  else if (nt) hipLaunchKernelGGL((gemm_h16s_kernel<SPLIT, F16, 1, 2>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_h16s_kernel<SPLIT, F16, 0, 2>), grid, block, 0, s, a);
+  return hipGetLastError();
 }
 
 template <int NS>
@@ -1952,6 +2109,7 @@ hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int
   constexpr int NSP = SPLIT == 3 ? 2 : 4;
   // occupancy form: four workgroups per CU with a two-deep ring, or three
   // with a three-deep one
+  if (impl == 2 && h16p_ok(a, tc)) return launch_h16s<SPLIT, F16>(a, tc, nt, s);
   if (impl == 4 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 2, 4>(a, tc, nt, s);
   if (impl == 5 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 3, 3>(a, tc, nt, s);
   if (impl == 3 && h16p_ok(a, tc)) {
@@ -2319,7 +2477,7 @@ std::string variant_schedule(int prec, int v) {
     switch (impl) {
       case 0: kernel = "async"; ring = split ? 2 : 3; break;
       case 1: kernel = "async"; ring = split ? 3 : 2; break;
-      case 2: kernel = "register"; break;
+      case 2: kernel = "small-tile"; ring = 2; tile = 64; break;
       case 3: kernel = "persistent"; ring = split ? 2 : 4; wpc = 2; break;
       case 4: kernel = "occupancy"; ring = 2; wpc = 4; break;
       default: kernel = "occupancy"; ring = 3; wpc = 3; break;

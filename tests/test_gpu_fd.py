@@ -211,7 +211,8 @@ RAGGED = [(22, [4, 4], [10, 4, 10]), (23, [3, 3], [10, 3, 10]), (24, [5, 2], [10
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_split"])
 def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
     """Variant 2 (FP32: 64 x 64 tiles; 16-bit: the other ring depth),
-    variants 6 and 7 (persistent kernel, both rasters) and 8 and 10 (the
+    variant 4 (16-bit: 64 x 64 tiles), variants 6 and 7 (persistent kernel,
+    both rasters) and 8 and 10 (the
     occupancy kernels: for the 16-bit forms two- and three-deep rings, for
     FP32 three- and four-deep rings) against variant 0 bit for bit -- same
     products, same order -- and against the oracle."""
@@ -221,7 +222,7 @@ def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
     scale = rc.fd_contract(cm, [np.abs(e) for e in E])
     outs = {}
     try:
-        for v in (0, 2, 6, 7, 8, 10):
+        for v in (0, 2, 4, 6, 7, 8, 10):
             m.cq_autotune_enable(variant=v)
             print(f"{prec} {bonds} {ns} variant {v}", flush=True)
             outs[v] = gpu_fd(cm, E, prec)
@@ -229,7 +230,7 @@ def test_persistent_gemm_ragged_tiles(seed, bonds, ns, prec):
         m.cq_autotune_enable(True)
     err = np.abs(outs[0] - ref)
     assert np.all(err <= {"fp32": 1e-5, **H16_REL}[prec] * scale + fp32_floor(cm)), float(err.max())
-    for v in (2, 6, 7, 8, 10):
+    for v in (2, 4, 6, 7, 8, 10):
         assert np.array_equal(outs[v], outs[0]), v
 
 
