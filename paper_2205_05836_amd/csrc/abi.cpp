@@ -330,15 +330,14 @@ cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec
 }
 
 // The balance arguments of a plan on workspace ws.
-BalanceLaunch balance_args(const CutMap& cm, const Plan& plan, char* ws) {
+// The cut structure of a balance launch (pointers left null).
+BalanceLaunch balance_struct(const CutMap& cm) {
   BalanceLaunch b;
   std::memset(&b, 0, sizeof(b));
   b.n_sub = cm.n_sub;
   b.K = cm.K;
   for (int c = 0; c < cm.n_sub; ++c) {
     const SubInfo& si = cm.subs[c];
-    b.rowmax[c] = reinterpret_cast<const uint64_t*>(ws + plan.lbal_rowmax_offset[c]);
-    b.rexp[c] = reinterpret_cast<int32_t*>(ws + plan.lbal_rexp_offset[c]);
     b.k[c] = si.k();
     for (int p = 0; p < si.k(); ++p) b.cut_of[c][p] = si.cuts[p];
   }
@@ -347,6 +346,15 @@ BalanceLaunch balance_args(const CutMap& cm, const Plan& plan, char* ws) {
     b.down[j] = cm.down[j];
     b.pos_up[j] = cm.subs[cm.up[j]].digit_pos(j);
     b.pos_down[j] = cm.subs[cm.down[j]].digit_pos(j);
+  }
+  return b;
+}
+
+BalanceLaunch balance_args(const CutMap& cm, const Plan& plan, char* ws) {
+  BalanceLaunch b = balance_struct(cm);
+  for (int c = 0; c < cm.n_sub; ++c) {
+    b.rowmax[c] = reinterpret_cast<const uint64_t*>(ws + plan.lbal_rowmax_offset[c]);
+    b.rexp[c] = reinterpret_cast<int32_t*>(ws + plan.lbal_rexp_offset[c]);
   }
   return b;
 }
@@ -525,6 +533,8 @@ struct DDInstancePlan {
   int64_t seg_a = 0, seg_b = 0, bound_a_off = 0, bound_b_off = 0, bound_u_off = 0, list_off = 0;
   int64_t warm_out_off = 0;
   std::vector<int64_t> ep_off, rs_off;
+  bool lbal = false;                         // per-label balance of the 16-bit operands
+  std::vector<int64_t> rowmax_off, rexp_off;  // its row maxima and exponents (4^k_c each)
   int64_t plan_off = 0, bins_off = 0;
   int64_t big = 0;  // bytes of the region
 };
@@ -565,6 +575,16 @@ void dd_layout(DDInstancePlan& D, const DDSel& s) {
     D.rs_off.push_back(off);
     off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * 8);
   }
+  D.rowmax_off.clear();
+  D.rexp_off.clear();
+  if (D.lbal)
+    for (int c = 0; c < cm.n_sub; ++c) {
+      const int64_t rows = (int64_t)1 << (2 * cm.subs[c].k());
+      D.rowmax_off.push_back(off);
+      off = align256(off + rows * 8);
+      D.rexp_off.push_back(off);
+      off = align256(off + rows * 4);
+    }
   D.plan_off = off;
   off = align256(off + D.plan.workspace_bytes);
   D.bins_off = off;
@@ -600,6 +620,7 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   }
   st = make_sym_plan(cm, D.amax, work_elem_bytes(p.prec), D.plan, D.sp);
   if (st != CQ_OK) return st;
+  D.lbal = balance_applies(p.prec) && cm.K > 0;
   if ((int)D.plan.steps.size() > kDDMaxSteps || (int)D.plan.tensors.size() > kDDMaxTensors)
     return fail(CQ_ERR_UNSUPPORTED, "bin contraction plan too long for the device program");
   for (const Step& s : D.plan.steps)
@@ -859,6 +880,14 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
   T.nbins = 1;
   T.scale = std::ldexp(1.0, -cm.K);
   T.out = &st->total;
+  P.balance = D.lbal ? 1 : 0;
+  if (D.lbal) {
+    P.bal = balance_struct(cm);
+    for (int c = 0; c < cm.n_sub; ++c) {
+      P.bal.rowmax[c] = reinterpret_cast<const uint64_t*>(ws + D.rowmax_off[c]);
+      P.bal.rexp[c] = reinterpret_cast<int32_t*>(ws + D.rexp_off[c]);
+    }
+  }
   P.topc_step = D.topc_step;
   P.cand_v = reinterpret_cast<double*>(ws + D.cand_off);
   P.cand_i = reinterpret_cast<uint64_t*>(ws + D.cand_off + D.cand_cap * 8);
@@ -962,6 +991,13 @@ cq_status dd_enqueue_level(const std::vector<const DDInstancePlan*>& G, const cq
   if (e != hipSuccess) return hip_fail(e, "row-sum launch");
   e = launch_refine_indirect(&prog->total, 1, stream, span);
   if (e != hipSuccess) return hip_fail(e, "total launch");
+  if (D.lbal) {
+    int64_t max_rows = 0;
+    for (const DDInstancePlan* M : G)
+      for (int c = 0; c < ns; ++c) max_rows = std::max(max_rows, (int64_t)1 << (2 * M->cm.subs[c].k()));
+    e = launch_dd_balance(prog, lv, ns, max_rows, stream, span);
+    if (e != hipSuccess) return hip_fail(e, "label balance launch");
+  }
   if (work_dtype(prec) != DType::F64) {
     e = launch_prep_indirect(&lv->prep[0], ns, work_dtype(prec), is_f16(prec), prep_n, stream, span);
     if (e != hipSuccess) return hip_fail(e, "operand prep launch");
@@ -1199,7 +1235,9 @@ std::string dd_call_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_
   int dev = -1;
   (void)hipGetDevice(&dev);
   const int lanes = g_dd_lanes.load();
+  const int lbal = g_lbal_mode.load();
   put(&dev, sizeof dev);
+  put(&lbal, sizeof lbal);
   put(&n_inst, sizeof n_inst);
   put(&p.prec, sizeof p.prec);
   put(&p.R, sizeof p.R);

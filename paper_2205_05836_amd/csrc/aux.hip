@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ sr
 template <int DK>
 __global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a, int64_t slot) {
   const PrepArgs p = inst_ptr(a, slot)[blockIdx.y];
-  prep_body<DK>(p.src, p.dst, p.dst_lo, p.n);
+  prep_body<DK>(p.src, p.dst, p.dst_lo, p.n, p.rexp, p.cols_log2);
 }
 
 // Column maxima of |E| (rows x 2^cols_log2, FP64): each thread folds a run of
@@ -231,7 +231,7 @@ constexpr int kBalLog = 10;            // log2 kBalThreads
 constexpr int kBalFixed = kBalLog / 2;  // digit positions fixed per thread
 constexpr int kBalUnroll = 4;
 
-__global__ void __launch_bounds__(kBalThreads) balance_kernel(BalanceLaunch b) {
+__device__ __forceinline__ void balance_body(const BalanceLaunch& b) {
   constexpr int kHi = CQ_MAX_LOCAL_CUTS > kBalFixed ? CQ_MAX_LOCAL_CUTS - kBalFixed : 1;
   __shared__ unsigned long long pmax[CQ_MAX_SUBCIRCUITS][CQ_MAX_LOCAL_CUTS][4];
   __shared__ int ej[CQ_MAX_CUTS][4];
@@ -407,6 +407,49 @@ __global__ void __launch_bounds__(kBalThreads) balance_kernel(BalanceLaunch b) {
       const int64_t l = (i << kBalLog) + tid;
       if (l < rows) b.rexp[c][l] = elo + share_hi(c, nhi, i);
     }
+  }
+}
+
+__global__ void __launch_bounds__(kBalThreads) balance_kernel(BalanceLaunch b) { balance_body(b); }
+
+// The balance of one instance of a dynamic-definition batch (grid z), from
+// its program; nothing when the recursion converts nothing.
+__global__ void __launch_bounds__(kBalThreads) balance_ind_kernel(const DDProgram* P, const DDLevel* lv,
+                                                                  int64_t slot) {
+  P = inst_ptr(P, slot);
+  lv = inst_ptr(lv, slot);
+  if (!P->balance) return;
+  bool any = false;
+  for (int c = 0; c < P->n_sub; ++c) any = any | (lv->prep[c].n > 0);
+  if (!any) return;
+  balance_body(P->bal);
+}
+
+// Row maxima of the reduced entries for the balance: subcircuit blockIdx.y of
+// instance blockIdx.z, one wave per row of its current 2^cols_log2 columns
+// (zeros for a subcircuit the recursion does not convert).
+__global__ void __launch_bounds__(256) rowmax_ind_kernel(const DDProgram* P, const DDLevel* lv, int64_t slot) {
+  P = inst_ptr(P, slot);
+  lv = inst_ptr(lv, slot);
+  const int c = blockIdx.y;
+  if (!P->balance || c >= P->n_sub) return;
+  const PrepArgs& pa = lv->prep[c];
+  const bool live = pa.n > 0;
+  const int64_t rows = P->rows[c];
+  const int64_t cols = (int64_t)1 << pa.cols_log2;
+  uint64_t* const rm = const_cast<uint64_t*>(P->bal.rowmax[c]);
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wave; r < rows; r += waves) {
+    double m = 0.0;
+    if (live) {
+      const double* row = pa.src + (r << pa.cols_log2);
+      for (int64_t col = lane; col < cols; col += 64) m = fmax(m, fabs(row[col]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) rm[r] = (uint64_t)__double_as_longlong(m);
   }
 }
 
@@ -852,6 +895,18 @@ hipError_t launch_rowmax(const double* E, int64_t rows, int cols_log2, uint64_t*
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(rowmax_kernel, dim3(grid_for(rows * 64)), dim3(256), 0, stream, E, rows, cols_log2,
                      rowmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_balance(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_rows,
+                             hipStream_t stream, InstSpan span) {
+  if (n_sub <= 0 || max_rows <= 0 || span.n <= 0) return hipSuccess;
+  int64_t gx = (max_rows * 64 + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(rowmax_ind_kernel, dim3((unsigned)gx, (unsigned)n_sub, (unsigned)span.n), dim3(256), 0,
+                     stream, prog, lv, span.stride);
+  hipLaunchKernelGGL(balance_ind_kernel, dim3(1, 1, (unsigned)span.n), dim3(kBalThreads), 0, stream, prog, lv,
+                     span.stride);
   return hipGetLastError();
 }
 

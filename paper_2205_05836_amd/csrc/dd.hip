@@ -751,6 +751,9 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
     pa.dst = t >= 0 ? P->tensor[t].hi : nullptr;
     pa.dst_lo = t >= 0 ? P->tensor[t].lo : nullptr;
     pa.n = (t >= 0 && !skip) ? sym_pow(P->tensor_elems[t], na) : 0;
+    // per-label balance: the reduced entry's rows carry 2^na_c columns
+    pa.rexp = P->balance ? P->bal.rexp[c] : nullptr;
+    pa.cols_log2 = na[c];
   }
   if (step >= 0 && step < nsteps) {
     const int s = step;

@@ -244,6 +244,9 @@ struct PrepArgs {
   void* dst;
   void* dst_lo;
   int64_t n;
+  const int32_t* rexp;  // per-label balance: row exponents (rows of 2^cols_log2), or null
+  int32_t cols_log2;
+  int32_t pad;
 };
 
 struct MergeArgs {
@@ -375,6 +378,9 @@ struct DDProgram {
   uint64_t* warm_i;
   DDInit init;
   RefineArgs total;                          // the recursion total: the row sums' single bin
+  int32_t balance;                           // per-label balance of the 16-bit operands
+  int32_t pad3;
+  BalanceLaunch bal;                         // its row maxima and exponents (4^k_c each)
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -439,6 +445,12 @@ hipError_t launch_dd_init(const DDProgram* prog, DDState* st, cq_dd_record* recs
 // Descriptors of recursion r from the state; `bins` receives its bins.
 hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_dd_record* recs,
                            int r, void* bins, hipStream_t stream, InstSpan span = InstSpan());
+// Per-label balance of the recursion's reduced entries, for programs with
+// `balance` set: row maxima of every reduced entry (rows of its current
+// 2^na_c columns, from the level's preparation descriptors), then the
+// exponents; the preparation then applies them (PrepArgs::rexp).
+hipError_t launch_dd_balance(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_rows,
+                             hipStream_t stream, InstSpan span = InstSpan());
 // List update, record r and zoom into the popped bin.
 hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
                             hipStream_t stream, InstSpan span = InstSpan());

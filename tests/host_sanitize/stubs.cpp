@@ -36,6 +36,9 @@ hipError_t launch_dd_setup(const DDProgram*, DDState*, DDLevel*, cq_dd_record*, 
                            InstSpan) {
   return hipErrorNoDevice;
 }
+hipError_t launch_dd_balance(const DDProgram*, const DDLevel*, int, int64_t, hipStream_t, InstSpan) {
+  return hipErrorNoDevice;
+}
 hipError_t launch_dd_update(const DDProgram*, DDState*, cq_dd_record*, int, hipStream_t, InstSpan) {
   return hipErrorNoDevice;
 }

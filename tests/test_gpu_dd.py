@@ -169,6 +169,59 @@ def test_dirichlet_chain(prec, tol):
     compare(cm, E, dd.initial_states(cm, M), M, R=4, prec=prec, tol=tol)
 
 
+LABEL_SHIFT = {0: 0, 1: 20, 2: -20, 3: 10}   # digit I, X, Y, Z -> log2 factor
+
+
+def imbalance_labels(cm, E, shift=LABEL_SHIFT):
+    """Rows scaled per cut label: digit d at cut j gets 2^shift[d] on the
+    subcircuit measuring j and 2^-shift[d] on the one initialising it, so
+    every labelling term of Eq. 1 -- hence every bin -- keeps its value
+    exactly, while label rows within a subcircuit differ by up to 2^80."""
+    out = []
+    for sub, e in zip(cm, E):
+        _, init, meas = sub
+        cuts = cutmap.incident_cuts(sub)
+        k = len(cuts)
+        ex = np.zeros(4 ** k, dtype=np.int64)
+        for l in range(4 ** k):
+            for p, cut in enumerate(cuts):
+                d = (l >> (2 * (k - 1 - p))) & 3
+                ex[l] += shift[d] if cut in meas else -shift[d]
+        out.append(np.ldexp(e, ex[:, None]))
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp16_split", 1e-6), ("fp16", 1e-3)])
+def test_label_balance_on_imbalanced_labels(prec, tol):
+    """Dynamic definition in FP16 on label rows 2^+-20 apart per digit: with
+    the per-label balance of the reduced entries every recursion matches the
+    oracle as on balanced input; without it the FP16 operands overflow or
+    lose the small rows.  The fused top-C path (no bins stored) gives the
+    same records as the stored-bin path."""
+    m = cq()
+    cm, E = syn.chain_instance(61, [2, 2], [7, 6, 7])
+    Ei = imbalance_labels(cm, E)
+    M = [2, 2, 2]
+    st = dd.initial_states(cm, M)
+    try:
+        m.cq_label_balance_enable(1)
+        compare(cm, Ei, st, M, R=4, prec=prec, tol=tol)
+        stored, done_s, _ = run_gpu(cm, Ei, st, M, 4, prec)
+        fused, done_f = m.cq_reconstruct_dd([instance(cm, Ei, st, M)], prec, 4)
+        torch.cuda.synchronize()
+        m.cq_label_balance_enable(0)
+        _, _, bins_off = run_gpu(cm, Ei, st, M, 1, prec)
+    finally:
+        m.cq_label_balance_enable(1)
+    assert done_f[0] == done_s
+    assert strip_tiles(fused) == strip_tiles([stored])
+    ref = dd.run(cm, Ei, st, M, 1)
+    nb = ref[0]["bins"].size
+    err_off = np.max(np.abs(bins_off[0][:nb].cpu().numpy().astype(np.float64) - ref[0]["bins"]))
+    print(f"{prec}: recursion-0 bins without the balance, max abs err {err_off:.3e}", flush=True)
+    assert not err_off < tol  # overflowing operands give inf or nan, which also counts
+
+
 def test_initial_fixed_bits_and_single_recursion():
     cm, E = syn.chain_instance(62, [1, 2], [5, 5, 5])
     states = [dd.SubState([0], [2, 3, 4], {1: 1}), dd.SubState([], [0, 1, 2, 3, 4], {}),
