@@ -86,6 +86,21 @@ cq_status cq_autotune_enable(int32_t mode);
  * Always CQ_OK. */
 cq_status cq_label_balance_enable(int32_t mode);
 
+/* Column scaling of the FP16 and FP16-split operands of cq_reconstruct_fd
+ * and cq_reconstruct_dd (Eq. 1 is linear in each subcircuit's entry and an
+ * output bin takes one column of every entry, so a power of two per column,
+ * undone on the output, changes no term): every entry column is scaled by
+ * the power of two that brings its largest magnitude into [0.5, 1) before
+ * the conversion, and the contraction writing the output adds the exponents
+ * back (on the dynamic-definition path, before the top-C comparison and in
+ * its tile bounds).  It keeps bins that are tiny beside the largest ones
+ * accurate relative to their own size; a dynamic-definition plan whose last
+ * step is not a contraction writing the bins runs unscaled.  on: 1 (the
+ * default) or 0.  Process-wide; it changes what cq_fd_workspace_size and
+ * cq_dd_workspace_size report, so query the size after setting it.
+ * Always CQ_OK. */
+cq_status cq_column_scaling_enable(int32_t on);
+
 /* Parallel lanes of cq_reconstruct_dd (instances whose bins stay inside
  * the contraction run on up to this many streams forked from the caller's,
  * each with its own copy of the per-instance buffers).  lanes <= 0 restores

@@ -18,7 +18,7 @@ MAX_DD_R = 16
 FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["cq_profile_enable", "cq_profile_read", "cq_plan_json", "cq_autotune_enable",
-            "cq_label_balance_enable", "cq_dd_lanes",
+            "cq_label_balance_enable", "cq_column_scaling_enable", "cq_dd_lanes",
             "cq_autotune_json", "cq_autotune_load", "cq_autotune_save",
             "cq_status_string", "cq_last_error", "cq_validate_cutmap",
             "cq_attribute_workspace_size", "cq_attribute", "cq_fd_workspace_size",
@@ -160,6 +160,8 @@ def lib():
     L.cq_autotune_enable.argtypes = [C.c_int32]
     L.cq_label_balance_enable.restype = st
     L.cq_label_balance_enable.argtypes = [C.c_int32]
+    L.cq_column_scaling_enable.restype = st
+    L.cq_column_scaling_enable.argtypes = [C.c_int32]
     L.cq_dd_lanes.restype = st
     L.cq_dd_lanes.argtypes = [C.c_int32]
     L.cq_autotune_load.restype = st

@@ -473,6 +473,12 @@ def cq_label_balance_enable(mode=1):
     check(lib().cq_label_balance_enable(int(mode)))
 
 
+def cq_column_scaling_enable(on=True):
+    """Column scaling of the FP16 and FP16-split operands (FD and DD): on by
+    default.  Query workspace sizes after changing it."""
+    check(lib().cq_column_scaling_enable(1 if on else 0))
+
+
 def cq_dd_lanes(lanes=0):
     """Parallel lanes of cq_reconstruct_dd (0: the default, 4; at most 8).
     Query the workspace size after changing it."""

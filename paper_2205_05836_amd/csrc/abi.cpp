@@ -126,6 +126,11 @@ bool balance_applies(cq_precision p) {
   return is_h16(p) && (m == 2 || (m == 1 && is_f16(p)));
 }
 
+// Column scaling of the FP16 operands: 1 on (default), 0 off.
+std::atomic<int> g_cscale_mode{1};
+
+bool cscale_applies(cq_precision p) { return is_f16(p) && g_cscale_mode.load() != 0; }
+
 DType out_dtype(cq_precision p) { return p == CQ_FP64 ? DType::F64 : DType::F32; }
 
 cq_status check_perm(const int32_t* out_perm, int n, std::vector<int>& perm) {
@@ -324,7 +329,7 @@ cq_status fd_prepare(int32_t n_sub, const cq_subcircuit* subs, cq_precision prec
   if (st != CQ_OK) return st;
   std::vector<int> ol;
   for (auto& s : cm.subs) ol.push_back(s.n());
-  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
+  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, cscale_applies(prec));
   if (st == CQ_OK && is_h16(prec)) reserve_balance(cm, plan);
   return st;
 }
@@ -535,6 +540,14 @@ struct DDInstancePlan {
   std::vector<int64_t> ep_off, rs_off;
   bool lbal = false;                         // per-label balance of the 16-bit operands
   std::vector<int64_t> rowmax_off, rexp_off;  // its row maxima and exponents (4^k_c each)
+  // column scaling of the FP16 operands (the last step a GEMM writing the bins)
+  bool cscale = false;
+  std::vector<int64_t> colmax_off;
+  int64_t rowexp_off = 0, colexp_off = 0, rowtmax_off = 0, coltmax_off = 0;
+  int64_t rowexp_n = 0, colexp_n = 0, rowtmax_n = 0, coltmax_n = 0;  // at the largest counts
+  int fac_n[2] = {0, 0};
+  int fac_sub[2][CQ_MAX_SUBCIRCUITS] = {};
+  SymLog fac_shift[2][CQ_MAX_SUBCIRCUITS] = {};
   int64_t plan_off = 0, bins_off = 0;
   int64_t big = 0;  // bytes of the region
 };
@@ -575,6 +588,21 @@ void dd_layout(DDInstancePlan& D, const DDSel& s) {
     D.rs_off.push_back(off);
     off = align256(off + ((int64_t)1 << (2 * cm.subs[c].k())) * 8);
   }
+  D.colmax_off.clear();
+  if (D.cscale) {
+    for (int c = 0; c < cm.n_sub; ++c) {
+      D.colmax_off.push_back(off);
+      off = align256(off + ((int64_t)1 << D.amax[c]) * 8);
+    }
+    D.rowexp_off = off;
+    off = align256(off + D.rowexp_n * 4);
+    D.colexp_off = off;
+    off = align256(off + D.colexp_n * 4);
+    D.rowtmax_off = off;
+    off = align256(off + D.rowtmax_n * 4);
+    D.coltmax_off = off;
+    off = align256(off + D.coltmax_n * 4);
+  }
   D.rowmax_off.clear();
   D.rexp_off.clear();
   if (D.lbal)
@@ -604,6 +632,60 @@ DDCtrl dd_ctrl(int R) {
   c.recs = align256(c.level + (int64_t)sizeof(DDLevel));
   c.bytes = align256(c.recs + (int64_t)R * (int64_t)sizeof(cq_dd_record));
   return c;
+}
+
+// Exponent groups of the last GEMM's output for column scaling: its rows
+// (z * M + m) and columns (n) each concatenate output axes, one per
+// subcircuit, the last axis lowest; member c's bits start after the axes
+// below it, a shift of (labels' fixed bits) + sum of their subcircuits' na.
+// False (no scaling) unless every subcircuit has one output axis there and
+// the shifts reproduce the plan at the largest counts.
+bool dd_fac_groups(DDInstancePlan& D) {
+  const Plan& plan = D.plan;
+  const GemmStep& g = plan.steps.back().g;
+  const std::vector<Axis>& ax = plan.tensors[g.c].axes;
+  const int ns = D.cm.n_sub;
+  int row_bits = 0;
+  while (((int64_t)1 << row_bits) < g.Z * g.M) ++row_bits;
+  size_t split = 0;
+  for (int acc = 0; split < ax.size() && acc < row_bits; ++split) acc += ax[split].log2;
+  while (split < ax.size() && ax[split].log2 == 0) ++split;
+  int acc = 0;
+  for (size_t i = 0; i < split; ++i) acc += ax[i].log2;
+  if (acc != row_bits) return false;
+  std::vector<bool> seen(ns, false);
+  const size_t lo[2] = {0, split}, hi[2] = {split, ax.size()};
+  for (int q = 0; q < 2; ++q) {
+    D.fac_n[q] = 0;
+    int c0 = 0, shift = 0;
+    uint32_t mask = 0;
+    for (size_t i = hi[q]; i-- > lo[q];) {
+      const Axis& a = ax[i];
+      if (a.kind == 1) {
+        if (D.fac_n[q] >= CQ_MAX_SUBCIRCUITS || a.id < 0 || a.id >= ns || seen[a.id] || a.log2 != D.amax[a.id])
+          return false;
+        int at = c0;
+        for (int c = 0; c < ns; ++c)
+          if ((mask >> c) & 1u) at += D.amax[c];
+        if (at != shift) return false;
+        D.fac_sub[q][D.fac_n[q]] = a.id;
+        D.fac_shift[q][D.fac_n[q]] = SymLog{c0, mask};
+        ++D.fac_n[q];
+        seen[a.id] = true;
+        mask |= 1u << a.id;
+      } else {
+        c0 += a.log2;
+      }
+      shift += a.log2;
+    }
+  }
+  for (int c = 0; c < ns; ++c)
+    if (!seen[c]) return false;
+  D.rowexp_n = g.Z * g.M;
+  D.colexp_n = g.N;
+  D.rowtmax_n = g.Z * ((g.M + 127) / 128);
+  D.coltmax_n = (g.N + 127) / 128;
+  return true;
 }
 
 cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool bins_stored,
@@ -646,6 +728,7 @@ cq_status dd_plan_instance(const cq_dd_instance& in, const cq_dd_params& p, bool
   D.topc_step = -1;
   if (!bins_stored && last.is_gemm && D.plan.tensors[last.g.c].loc == Loc::Out)
     D.topc_step = (int)D.plan.steps.size() - 1;
+  D.cscale = cscale_applies(p.prec) && last.is_gemm && D.plan.tensors[last.g.c].loc == Loc::Out && dd_fac_groups(D);
   D.bins_bytes = (bins_stored || D.topc_step >= 0) ? 0 : align256(D.max_count * (p.prec == CQ_FP64 ? 8 : 4));
   D.sel = DDSel();
   if (D.topc_step >= 0) {
@@ -880,6 +963,21 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
   T.nbins = 1;
   T.scale = std::ldexp(1.0, -cm.K);
   T.out = &st->total;
+  P.cscale = D.cscale ? 1 : 0;
+  if (D.cscale) {
+    for (int q = 0; q < 2; ++q) {
+      P.fac_n[q] = D.fac_n[q];
+      for (int i = 0; i < D.fac_n[q]; ++i) {
+        P.fac_sub[q][i] = D.fac_sub[q][i];
+        P.fac_shift[q][i] = D.fac_shift[q][i];
+      }
+    }
+    for (int c = 0; c < cm.n_sub; ++c) P.colmax[c] = reinterpret_cast<uint64_t*>(ws + D.colmax_off[c]);
+    P.rowexp = reinterpret_cast<int32_t*>(ws + D.rowexp_off);
+    P.colexp = reinterpret_cast<int32_t*>(ws + D.colexp_off);
+    P.rowtmax = reinterpret_cast<int32_t*>(ws + D.rowtmax_off);
+    P.coltmax = reinterpret_cast<int32_t*>(ws + D.coltmax_off);
+  }
   P.balance = D.lbal ? 1 : 0;
   if (D.lbal) {
     P.bal = balance_struct(cm);
@@ -998,9 +1096,25 @@ cq_status dd_enqueue_level(const std::vector<const DDInstancePlan*>& G, const cq
     e = launch_dd_balance(prog, lv, ns, max_rows, stream, span);
     if (e != hipSuccess) return hip_fail(e, "label balance launch");
   }
+  if (D.cscale) {
+    int64_t max_cols = 0;
+    for (const DDInstancePlan* M : G)
+      for (int c = 0; c < ns; ++c) max_cols = std::max(max_cols, (int64_t)1 << M->amax[c]);
+    e = launch_dd_colmax(prog, lv, ns, max_cols, stream, span);
+    if (e != hipSuccess) return hip_fail(e, "column scaling launch");
+  }
   if (work_dtype(prec) != DType::F64) {
     e = launch_prep_indirect(&lv->prep[0], ns, work_dtype(prec), is_f16(prec), prep_n, stream, span);
     if (e != hipSuccess) return hip_fail(e, "operand prep launch");
+  }
+  if (D.cscale) {
+    int64_t max_rows = 0, max_cols = 0;
+    for (const DDInstancePlan* M : G) {
+      max_rows = std::max(max_rows, M->rowexp_n);
+      max_cols = std::max(max_cols, M->colexp_n);
+    }
+    e = launch_dd_expsum(prog, st, lv, (int)D.plan.steps.size() - 1, max_rows, max_cols, stream, span);
+    if (e != hipSuccess) return hip_fail(e, "scale exponent launch");
   }
   for (size_t si = 0; si < D.plan.steps.size(); ++si) {
     const Step& s = D.plan.steps[si];
@@ -1236,8 +1350,10 @@ std::string dd_call_key(int32_t n_inst, const cq_dd_instance* inst, const cq_dd_
   (void)hipGetDevice(&dev);
   const int lanes = g_dd_lanes.load();
   const int lbal = g_lbal_mode.load();
+  const int cscale = g_cscale_mode.load();
   put(&dev, sizeof dev);
   put(&lbal, sizeof lbal);
+  put(&cscale, sizeof cscale);
   put(&n_inst, sizeof n_inst);
   put(&p.prec, sizeof p.prec);
   put(&p.R, sizeof p.R);
@@ -1656,7 +1772,7 @@ extern "C" cq_status cq_plan_json(int32_t n_sub, const cq_subcircuit* subs, cq_p
   st = check_perm(out_perm, n_bits, perm);
   if (st != CQ_OK) return st;
   Plan plan;
-  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, is_f16(prec));
+  st = make_plan(cm, ol, work_elem_bytes(prec), perm, plan, false, cscale_applies(prec));
   if (st != CQ_OK) return st;
   // a full-definition plan reports the workspace cq_fd_workspace_size asks for
   if (!out_bits && is_h16(prec)) reserve_balance(cm, plan);
@@ -1737,6 +1853,11 @@ extern "C" cq_status cq_profile_read(char* names, double* ms, double* flops, int
     prof_release(recs[i].dev, recs[i].stop);
   }
   return st;
+}
+
+extern "C" cq_status cq_column_scaling_enable(int32_t on) {
+  g_cscale_mode.store(on != 0 ? 1 : 0);
+  return CQ_OK;
 }
 
 extern "C" cq_status cq_label_balance_enable(int32_t mode) {

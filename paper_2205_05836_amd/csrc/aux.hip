@@ -86,10 +86,15 @@ __global__ void __launch_bounds__(256) permute_ind_kernel(const PermArgs* __rest
 // rexp, row i >> cols_log2 is first scaled by its power of two.
 template <int DK>
 __device__ inline void prep_body(const double* __restrict__ src, void* dst, void* dst_lo, int64_t n,
-                                 const int32_t* __restrict__ rexp = nullptr, int cols_log2 = 0) {
+                                 const int32_t* __restrict__ rexp = nullptr, int cols_log2 = 0,
+                                 const uint64_t* __restrict__ colmax = nullptr) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cmask = ((int64_t)1 << cols_log2) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-    const float x = rexp ? float(ldexp(src[i], rexp[i >> cols_log2])) : float(src[i]);
+    // column scaling as prep_scaled_kernel: 2^-e of the column maximum, plus the row exponent
+    const float x = colmax ? float(ldexp(src[i], -colmax_exp(colmax[i & cmask]) +
+                                                     (rexp ? rexp[i >> cols_log2] : 0)))
+                           : rexp ? float(ldexp(src[i], rexp[i >> cols_log2])) : float(src[i]);
     if constexpr (DK == kF32) {
       static_cast<float*>(dst)[i] = x;
     } else {
@@ -147,7 +152,7 @@ __global__ void __launch_bounds__(256) prep_kernel(const double* __restrict__ sr
 template <int DK>
 __global__ void __launch_bounds__(256) prep_ind_kernel(const PrepArgs* __restrict__ a, int64_t slot) {
   const PrepArgs p = inst_ptr(a, slot)[blockIdx.y];
-  prep_body<DK>(p.src, p.dst, p.dst_lo, p.n, p.rexp, p.cols_log2);
+  prep_body<DK>(p.src, p.dst, p.dst_lo, p.n, p.rexp, p.cols_log2, p.colmax);
 }
 
 // Column maxima of |E| (rows x 2^cols_log2, FP64): each thread folds a run of
@@ -423,6 +428,95 @@ __global__ void __launch_bounds__(kBalThreads) balance_ind_kernel(const DDProgra
   for (int c = 0; c < P->n_sub; ++c) any = any | (lv->prep[c].n > 0);
   if (!any) return;
   balance_body(P->bal);
+}
+
+// Column maxima of the reduced entries for the column scaling: subcircuit
+// blockIdx.y of instance blockIdx.z, 64 columns a workgroup, its four waves
+// taking every fourth row; values carry the balance's row exponents, as the
+// conversion applies them.
+__global__ void __launch_bounds__(256) colmax_ind_kernel(const DDProgram* P, const DDLevel* lv, int64_t slot) {
+  __shared__ double part[4][64];
+  P = inst_ptr(P, slot);
+  lv = inst_ptr(lv, slot);
+  const int c = blockIdx.y;
+  if (!P->cscale || c >= P->n_sub) return;
+  const PrepArgs& pa = lv->prep[c];
+  const int64_t cols = (int64_t)1 << pa.cols_log2;
+  if (pa.n <= 0 || (int64_t)blockIdx.x * 64 >= cols) return;
+  const int64_t rows = P->rows[c];
+  const int32_t* rexp = P->balance ? P->bal.rexp[c] : nullptr;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+  double m = 0.0;
+  if (b < cols)
+    for (int64_t r = w; r < rows; r += 4) {
+      const double x = pa.src[(r << pa.cols_log2) + b];
+      m = fmax(m, fabs(rexp ? ldexp(x, rexp[r]) : x));
+    }
+  part[w][lane] = m;
+  __syncthreads();
+  if (w == 0 && b < cols)
+    P->colmax[c][b] = (uint64_t)__double_as_longlong(
+        fmax(fmax(part[0][lane], part[1][lane]), fmax(part[2][lane], part[3][lane])));
+}
+
+// Output exponents of the last GEMM (step `step`): blockIdx.y 0 its rows
+// (z * M + m), 1 its columns (n); each the sum over the group's subcircuits of
+// the exponent of the column that bits shift .. shift + na_c - 1 select.
+__global__ void __launch_bounds__(256) expsum_ind_kernel(const DDProgram* P, const DDState* st,
+                                                         const DDLevel* lv, int step, int64_t slot) {
+  P = inst_ptr(P, slot);
+  st = inst_ptr(st, slot);
+  lv = inst_ptr(lv, slot);
+  if (!P->cscale) return;
+  const GemmArgs& g = lv->gemm[step];
+  if (g.tiles <= 0) return;
+  const int q = blockIdx.y;
+  const int64_t count = q == 0 ? g.tiles / (g.tilesM * g.tilesN) * g.M : g.N;
+  int32_t* const out = q == 0 ? P->rowexp : P->colexp;
+  const int n = P->fac_n[q];
+  const int64_t stepg = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += stepg) {
+    int e = 0;
+    for (int i = 0; i < n; ++i) {
+      const int sub = P->fac_sub[q][i];
+      const SymLog& sl = P->fac_shift[q][i];
+      int sh = sl.c0;
+      for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c)
+        if ((sl.mask >> c) & 1u) sh += st->na[c];
+      const int64_t mk = ((int64_t)1 << st->na[sub]) - 1;
+      e += colmax_exp(P->colmax[sub][(r >> sh) & mk]);
+    }
+    out[r] = e;
+  }
+}
+
+// Tile maxima of those exponents: blockIdx.y 0 over the 128-row tiles of each
+// batch (z * tilesM + mt), 1 over the 128-column tiles.
+__global__ void __launch_bounds__(256) exptmax_ind_kernel(const DDProgram* P, const DDLevel* lv, int step,
+                                                          int64_t slot) {
+  P = inst_ptr(P, slot);
+  lv = inst_ptr(lv, slot);
+  if (!P->cscale) return;
+  const GemmArgs& g = lv->gemm[step];
+  if (g.tiles <= 0) return;
+  const int q = blockIdx.y;
+  const int64_t Z = g.tiles / (g.tilesM * g.tilesN);
+  const int64_t count = q == 0 ? Z * g.tilesM : g.tilesN;
+  const int64_t stepg = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stepg) {
+    int e = INT_MIN;
+    if (q == 0) {
+      const int64_t z = t / g.tilesM, m0 = (t - z * g.tilesM) * 128;
+      const int64_t m1 = m0 + 128 < g.M ? m0 + 128 : g.M;
+      for (int64_t m = m0; m < m1; ++m) e = max(e, P->rowexp[z * g.M + m]);
+      P->rowtmax[t] = e;
+    } else {
+      const int64_t n0 = t * 128, n1 = n0 + 128 < g.N ? n0 + 128 : g.N;
+      for (int64_t nn = n0; nn < n1; ++nn) e = max(e, P->colexp[nn]);
+      P->coltmax[t] = e;
+    }
+  }
 }
 
 // Row maxima of the reduced entries for the balance: subcircuit blockIdx.y of
@@ -907,6 +1001,25 @@ hipError_t launch_dd_balance(const DDProgram* prog, const DDLevel* lv, int n_sub
                      stream, prog, lv, span.stride);
   hipLaunchKernelGGL(balance_ind_kernel, dim3(1, 1, (unsigned)span.n), dim3(kBalThreads), 0, stream, prog, lv,
                      span.stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_colmax(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_cols,
+                            hipStream_t stream, InstSpan span) {
+  if (n_sub <= 0 || max_cols <= 0 || span.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(colmax_ind_kernel, dim3((unsigned)((max_cols + 63) / 64), (unsigned)n_sub, (unsigned)span.n),
+                     dim3(256), 0, stream, prog, lv, span.stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_expsum(const DDProgram* prog, const DDState* st, const DDLevel* lv, int step,
+                            int64_t max_rows, int64_t max_cols, hipStream_t stream, InstSpan span) {
+  if (span.n <= 0) return hipSuccess;
+  const int64_t most = max_rows > max_cols ? max_rows : max_cols;
+  hipLaunchKernelGGL(expsum_ind_kernel, dim3(grid_ind(most), 2, (unsigned)span.n), dim3(256), 0, stream, prog,
+                     st, lv, step, span.stride);
+  hipLaunchKernelGGL(exptmax_ind_kernel, dim3(grid_ind((most + 127) / 128 + 1), 2, (unsigned)span.n), dim3(256),
+                     0, stream, prog, lv, step, span.stride);
   return hipGetLastError();
 }
 

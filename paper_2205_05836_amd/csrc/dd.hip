@@ -754,6 +754,7 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
     // per-label balance: the reduced entry's rows carry 2^na_c columns
     pa.rexp = P->balance ? P->bal.rexp[c] : nullptr;
     pa.cols_log2 = na[c];
+    pa.colmax = P->cscale ? P->colmax[c] : nullptr;
   }
   if (step >= 0 && step < nsteps) {
     const int s = step;
@@ -781,8 +782,12 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.sCz = sym_pow(G.sCz, na);
       g.ldc = sym_pow(G.ldc, na);
       g.alpha = G.alpha;
-      g.rowexp = nullptr;
-      g.colexp = nullptr;
+      // column-scaled operands: the GEMM writing the bins adds the exponents back
+      const bool scaled = P->cscale && tc.is_out;
+      g.rowexp = scaled ? P->rowexp : nullptr;
+      g.colexp = scaled ? P->colexp : nullptr;
+      g.rowtmax = scaled ? P->rowtmax : nullptr;
+      g.coltmax = scaled ? P->coltmax : nullptr;
       const bool tc_here = s == P->topc_step;
       g.topc_publish_only = 0;
       g.tile_list = tc_here ? P->tile_list : nullptr;

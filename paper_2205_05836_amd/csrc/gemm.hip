@@ -787,6 +787,20 @@ __device__ __forceinline__ void gemm_h16_tile(const GemmArgs& g, int64_t vb) {
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[i][j][v] *= alpha;
+    if (g.rowexp) {
+      // column-scaled operands: the output exponents first, as the store applies them
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int rr = wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int cc = wn + j * 32 + (lane & 31);
+            if ((rr < rem_m) & (cc < rem_n))
+              acc[i][j][v] = __builtin_ldexpf(acc[i][j][v], g.rowexp[tc.z * g.M + m0 + rr] + g.colexp[n0 + cc]);
+          }
+    }
     // 32x32 accumulators: item v of lane l is row 8(v/4) + 4(l/32) + v%4, column l%32
     const int base = (wm + 4 * (lane >> 5)) * 128 + wn + (lane & 31);
     auto val = [&](int e) -> float { return acc[e >> 5][(e >> 4) & 1][e & 15]; };
@@ -2337,6 +2351,8 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.alpha = g.alpha;
   a.rowexp = g.rowexp;
   a.colexp = g.colexp;
+  a.rowtmax = nullptr;
+  a.coltmax = nullptr;
   a.topc_thr = nullptr;
   a.topc_count = nullptr;
   a.topc_C = nullptr;
@@ -2661,6 +2677,8 @@ __global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restr
     u += double(amax[(za * g.K + k) * g.tilesM + mt]) * double(bmax[(zb * g.K + k) * g.tilesN + nt]);
   // the kernels accumulate in FP32 (or FP64): allow K roundings of 2^-24
   u *= g.alpha * (1.0 + double(g.K + 4) * 0x1p-23);
+  // column-scaled operands: the tile's largest output exponent
+  if (g.rowtmax) u = ldexp(u, g.rowtmax[c.z * g.tilesM + mt] + g.coltmax[nt]);
   U[t] = __double2float_ru(u);
 }
 

@@ -88,6 +88,11 @@ struct GemmArgs {
   double alpha;
   const int32_t* rowexp;  // optional output exponents (see GemmLaunch)
   const int32_t* colexp;
+  // with rowexp: the largest rowexp over each 128-row tile of each batch
+  // (z * tilesM + mt) and the largest colexp over each 128-column tile, for
+  // the tile bounds of the fused top-C; null otherwise
+  const int32_t* rowtmax;
+  const int32_t* coltmax;
   // Top-C instead of the store (launch_gemm_indirect with topc): each tile
   // appends its C best (value, index) keys not below the running threshold
   // and raises the threshold to its C-th best value when it has C of them.
@@ -247,6 +252,7 @@ struct PrepArgs {
   const int32_t* rexp;  // per-label balance: row exponents (rows of 2^cols_log2), or null
   int32_t cols_log2;
   int32_t pad;
+  const uint64_t* colmax;  // column scaling: column maxima (FP64 bits, after rexp), or null
 };
 
 struct MergeArgs {
@@ -381,6 +387,21 @@ struct DDProgram {
   int32_t balance;                           // per-label balance of the 16-bit operands
   int32_t pad3;
   BalanceLaunch bal;                         // its row maxima and exponents (4^k_c each)
+  // Column scaling of the FP16 operands (the plan's last step a GEMM writing
+  // the bins): column maxima of every reduced entry, and the last GEMM's
+  // output exponents -- over its rows (z * M + m) and columns (n), each the
+  // sum over the subcircuits of a group of the exponent of the column that
+  // bits shift .. shift + na_c - 1 of the index select -- with their tile
+  // maxima.
+  int32_t cscale;
+  int32_t fac_n[2];
+  int32_t fac_sub[2][CQ_MAX_SUBCIRCUITS];
+  SymLog fac_shift[2][CQ_MAX_SUBCIRCUITS];
+  uint64_t* colmax[CQ_MAX_SUBCIRCUITS];     // 2^amax_c each
+  int32_t* rowexp;
+  int32_t* colexp;
+  int32_t* rowtmax;
+  int32_t* coltmax;
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -451,6 +472,16 @@ hipError_t launch_dd_setup(const DDProgram* prog, DDState* st, DDLevel* lv, cq_d
 // exponents; the preparation then applies them (PrepArgs::rexp).
 hipError_t launch_dd_balance(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_rows,
                              hipStream_t stream, InstSpan span = InstSpan());
+// Column scaling of the recursion's reduced entries (programs with `cscale`):
+// the column maxima of every reduced entry, after the balance's row
+// exponents; `max_cols` bounds 2^na_c over the group.
+hipError_t launch_dd_colmax(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_cols,
+                            hipStream_t stream, InstSpan span = InstSpan());
+// The last GEMM's output exponents and their tile maxima (GEMM step `step` of
+// the level); `max_rows` and `max_cols` bound its Z * M and N over the group.
+hipError_t launch_dd_expsum(const DDProgram* prog, const DDState* st, const DDLevel* lv, int step,
+                            int64_t max_rows, int64_t max_cols, hipStream_t stream,
+                            InstSpan span = InstSpan());
 // List update, record r and zoom into the popped bin.
 hipError_t launch_dd_update(const DDProgram* prog, DDState* st, cq_dd_record* recs, int r,
                             hipStream_t stream, InstSpan span = InstSpan());

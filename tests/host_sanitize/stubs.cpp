@@ -39,6 +39,13 @@ hipError_t launch_dd_setup(const DDProgram*, DDState*, DDLevel*, cq_dd_record*, 
 hipError_t launch_dd_balance(const DDProgram*, const DDLevel*, int, int64_t, hipStream_t, InstSpan) {
   return hipErrorNoDevice;
 }
+hipError_t launch_dd_colmax(const DDProgram*, const DDLevel*, int, int64_t, hipStream_t, InstSpan) {
+  return hipErrorNoDevice;
+}
+hipError_t launch_dd_expsum(const DDProgram*, const DDState*, const DDLevel*, int, int64_t, int64_t, hipStream_t,
+                            InstSpan) {
+  return hipErrorNoDevice;
+}
 hipError_t launch_dd_update(const DDProgram*, DDState*, cq_dd_record*, int, hipStream_t, InstSpan) {
   return hipErrorNoDevice;
 }

@@ -222,6 +222,59 @@ def test_label_balance_on_imbalanced_labels(prec, tol):
     assert not err_off < tol  # overflowing operands give inf or nan, which also counts
 
 
+COL_SHIFT = [0, 12, 10]   # per subcircuit: column b scaled by 2^(-shift * popcount(b))
+
+
+def imbalance_columns(E, shift=COL_SHIFT):
+    """Columns (output bit patterns) scaled down by 2^-shift per set bit:
+    recursion-0 bins then span about 2^-40 of each other, far below FP16's
+    range once converted without a per-column scale."""
+    out = []
+    for s, e in zip(shift, E):
+        pc = np.array([bin(b).count("1") for b in range(e.shape[1])], dtype=np.int64)
+        out.append(np.ldexp(e, -s * pc[None, :]))
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp16_split", 1e-5), ("fp16", 2e-3)])
+def test_column_scaling_on_imbalanced_columns(prec, tol):
+    """Dynamic definition in FP16 with output columns 2^-10 .. 2^-12 apart
+    per set bit (on top of imbalanced label rows): the column scaling of the
+    reduced entries keeps every recursion-0 bin accurate relative to its own
+    magnitude (the bins of |E|, which bound every term), tiny bins included;
+    the fused top-C path, whose tile bounds carry the exponents, gives the
+    same records as the stored-bin path."""
+    m = cq()
+    cm, E = syn.chain_instance(64, [2, 2], [7, 6, 7])
+    Ei = imbalance_columns(imbalance_labels(cm, E))
+    M = [2, 2, 2]
+    st = dd.initial_states(cm, M)
+    compare(cm, Ei, st, M, R=4, prec=prec, tol=tol)
+    stored, done_s, bins = run_gpu(cm, Ei, st, M, 4, prec)
+    fused, done_f = m.cq_reconstruct_dd([instance(cm, Ei, st, M)], prec, 4)
+    torch.cuda.synchronize()
+    try:
+        m.cq_column_scaling_enable(False)
+        _, _, bins_off = run_gpu(cm, Ei, st, M, 1, prec)
+    finally:
+        m.cq_column_scaling_enable(True)
+    assert done_f[0] == done_s
+    assert strip_tiles(fused) == strip_tiles([stored])
+    ref = dd.run(cm, Ei, st, M, 1)[0]["bins"]
+    scale = dd.run(cm, [np.abs(e) for e in Ei], st, M, 1)[0]["bins"]
+    assert scale.min() < 2.0 ** -30 * scale.max()   # the bins really span FP16's range
+
+    def rel_err(b):
+        got = b[0][:ref.size].cpu().numpy().astype(np.float64)
+        return np.max(np.abs(got - ref) / scale)
+
+    rel, rel_off = rel_err(bins), rel_err(bins_off)
+    print(f"{prec}: recursion-0 bins, max error relative to |E| bins {rel:.3e}, "
+          f"without column scaling {rel_off:.3e}", flush=True)
+    assert rel < tol
+    assert not rel_off < tol   # the small bins are lost (or nan) without it
+
+
 def test_initial_fixed_bits_and_single_recursion():
     cm, E = syn.chain_instance(62, [1, 2], [5, 5, 5])
     states = [dd.SubState([0], [2, 3, 4], {1: 1}), dd.SubState([], [0, 1, 2, 3, 4], {}),

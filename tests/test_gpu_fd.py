@@ -360,6 +360,32 @@ def test_h16_dirichlet_chain(prec):
     assert np.all(err <= H16_REL[prec] * scale + fp32_floor(cm))
 
 
+@pytest.mark.parametrize("prec", ["fp16", "fp16_split"])
+def test_fp16_column_scaling_on_imbalanced_columns(prec):
+    """Entry columns scaled down by 2^-6 (2^-5) per set output bit, so bins
+    span about 2^-70: with the column scaling every bin stays within the
+    FP16 rounding bound relative to its own magnitude (the bins of |E|);
+    without it the small columns underflow FP16 and that bound fails."""
+    m = cq()
+    cm, E = syn.chain_instance(13, [2, 2], [7, 6, 7])
+    E = [np.ldexp(e, -s * np.array([bin(b).count("1") for b in range(e.shape[1])])[None, :])
+         for s, e in zip([0, 6, 5], E)]
+    ref = rc.fd_contract(cm, E)
+    scale = rc.fd_contract(cm, [np.abs(e) for e in E])
+    bound = H16_REL[prec] * scale + fp32_floor(cm)
+    got = gpu_fd(cm, E, prec)
+    try:
+        m.cq_column_scaling_enable(False)
+        got_off = gpu_fd(cm, E, prec)
+    finally:
+        m.cq_column_scaling_enable(True)
+    r_on = np.max(np.abs(got - ref) / bound)
+    r_off = np.max(np.abs(got_off - ref) / bound)
+    print(f"{prec}: max err / bound {r_on:.3e}, without column scaling {r_off:.3e}", flush=True)
+    assert r_on <= 1.0
+    assert not r_off <= 1.0   # lost small bins (or nan) without it
+
+
 def test_h16_chain_of_four_split():
     cm, E = syn.chain_instance(15, [2, 1, 2], [5, 4, 5, 5])
     ref = rc.fd_contract(cm, E)
