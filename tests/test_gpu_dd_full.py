@@ -144,7 +144,7 @@ def full_batch():
     return insts, meta
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "fp16_split", "fp64"])
 def test_batch_full_size_lists_zoom_and_totals(prec, full_batch):
     m = cq()
     insts, meta = full_batch
@@ -245,8 +245,15 @@ def check_top_r_against_stored(b, rec, r, Rcap, states, bonds, ks, seed, rel, fl
     assert margin > 2 * bound.max()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16_split", "fp64"])
 def test_largest_instance_stored_bins_grid(prec):
+    """Stored bins of the batch's largest instance on a 16^4 grid of sampled
+    active values against the oracle.  FP16-split runs with the per-label
+    balance and the column scaling of the reduced entries; its bound relative
+    to each bin's |E| scale is the same 1e-5 as FP32's: hi + lo keeps 22 bits
+    of every scaled operand, and an operand flushed below FP16's range costs
+    at most 2^-25 of its column's largest value, whose term (the identity
+    row bounds every row of these entries) is part of the bin's scale."""
     m = cq()
     bonds_all = batch()
     i = int(np.argmax([sum(4 ** k for k in syn.chain_ks(b, 4)) for b in bonds_all]))
