@@ -31,6 +31,7 @@ constexpr int kScanThreads = 1024;      // row scans of block sums and counts
 constexpr int kShotsPerThread = 64;
 constexpr int kShotsPerGroup = kThreads * kShotsPerThread;
 constexpr int kLdsBins = 4096;          // rows with at most this many blocks search and count in LDS
+constexpr int kFewShots = 64;           // blocks with at most this many shots resolve in registers
 
 __device__ inline uint64_t quant52(double p) {
   const double c = p > 0.0 ? (p < 1.0 ? p : 1.0) : 0.0;
@@ -274,25 +275,123 @@ __global__ void __launch_bounds__(kThreads) shots_scatter_kernel(const uint64_t*
   }
 }
 
-// Pass 6: per block, the inclusive prefix of its quantised entries in LDS,
-// its bucket's shots resolved there (the first entry whose prefix exceeds
-// the shot's target), and count / shots written out.  A block without shots
-// writes zeros without reading its entries.  LDS layout: thread t's run of
-// kPer entries at [t kPad, t kPad + kPer).
-__global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* __restrict__ P, int64_t cols,
-                                                                 int64_t nblk, int64_t shots,
-                                                                 const uint32_t* __restrict__ bcnt,
-                                                                 const uint32_t* __restrict__ bptr,
-                                                                 const uint64_t* __restrict__ slots,
-                                                                 double* __restrict__ F) {
-  __shared__ unsigned long long C[kThreads * kPad];
-  __shared__ uint32_t cnt[kBlock];
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+// Pass 6, blocks with at most kFewShots shots (the usual case: a few shots
+// per block of 2048 outcomes): thread t holds entries t kPer .. t kPer +
+// kPer - 1 in registers, the block scan gives its run's offset, and every
+// thread tests the block's targets against its run (the first entry whose
+// inclusive prefix exceeds the target), counting in registers.  No LDS
+// staging of the entries, so many more blocks stay resident than in the LDS
+// form below; the counts, hence the frequencies, are the same.  A block
+// without shots writes zeros without reading its entries.
+__global__ void __launch_bounds__(kThreads) shots_resolve_few_kernel(const double* __restrict__ P, int64_t cols,
+                                                                     int64_t nblk, int64_t shots,
+                                                                     const uint32_t* __restrict__ bcnt,
+                                                                     const uint32_t* __restrict__ bptr,
+                                                                     const uint64_t* __restrict__ slots,
+                                                                     double* __restrict__ F) {
   __shared__ unsigned long long wtot[kThreads / 64];
+  __shared__ uint64_t tg[kFewShots];
   const int64_t row = blockIdx.y, blk = blockIdx.x;
   const int64_t c0 = blk * kBlock;
   const int n = (int)(cols - c0 < kBlock ? cols - c0 : kBlock);
   const int64_t k = row * nblk + blk;
   const uint32_t m = bcnt[k];
+  if (m > (uint32_t)kFewShots) return;
+  double* f = F + row * cols + c0;
+  const int e0 = threadIdx.x * kPer;
+  const bool vec = e0 + kPer <= n && ((reinterpret_cast<uintptr_t>(f) | reinterpret_cast<uintptr_t>(P + row * cols + c0)) & 15) == 0;
+  if (m == 0) {
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < kPer / 2; ++q) reinterpret_cast<d2_t*>(f + e0)[q] = d2_t{0.0, 0.0};
+    } else {
+      for (int e = e0; e < e0 + kPer && e < n; ++e) __builtin_nontemporal_store(0.0, f + e);
+    }
+    return;
+  }
+  const double* p = P + row * cols + c0 + e0;
+  unsigned long long v[kPer];
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < kPer / 2; ++q) {
+      const d2_t x = reinterpret_cast<const d2_t*>(p)[q];
+      v[2 * q] = quant52(x[0]);
+      v[2 * q + 1] = quant52(x[1]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) v[e] = e0 + e < n ? quant52(p[e]) : 0ull;
+  }
+  unsigned long long s = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    s += v[e];
+    v[e] = s;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned long long x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wtot[wid] = x;
+  if (threadIdx.x < m) tg[threadIdx.x] = slots[row * shots + bptr[k] + threadIdx.x];
+  __syncthreads();
+  unsigned long long before = x - s;
+  for (int w = 0; w < wid; ++w) before += wtot[w];
+  uint32_t c[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) c[e] = 0;
+  for (uint32_t j = 0; j < m; ++j) {
+    const uint64_t t = tg[j];
+    // this run holds the target when before <= t < before + s
+    if (t >= before && t - before < s) {
+      const uint64_t r = t - before;
+      bool found = false;
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const bool here = !found && v[e] > r;
+        c[e] += here ? 1u : 0u;
+        found = found || here;
+      }
+    }
+  }
+  const double ds = (double)shots;
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < kPer / 2; ++q) {
+      const d2_t y = {c[2 * q] ? (double)c[2 * q] / ds : 0.0, c[2 * q + 1] ? (double)c[2 * q + 1] / ds : 0.0};
+      reinterpret_cast<d2_t*>(f + e0)[q] = y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+      if (e0 + e < n) __builtin_nontemporal_store(c[e] ? (double)c[e] / ds : 0.0, f + e0 + e);
+  }
+}
+
+// Pass 6, blocks with many shots: the inclusive prefix of the block's
+// quantised entries in LDS, its bucket's shots resolved there by binary
+// search (the first entry whose prefix exceeds the shot's target), and
+// count / shots written out; a block without shots writes zeros without
+// reading its entries.  LDS layout: thread t's run of kPer entries at
+// [t kPad, t kPad + kPer).
+struct ResolveLds {
+  unsigned long long C[kThreads * kPad];
+  uint32_t cnt[kBlock];
+  unsigned long long wtot[kThreads / 64];
+};
+
+__device__ __forceinline__ void resolve_block_lds(ResolveLds& L, const double* __restrict__ P, int64_t cols,
+                                                  int64_t nblk, int64_t shots, int64_t k, uint32_t m,
+                                                  const uint32_t* __restrict__ bptr,
+                                                  const uint64_t* __restrict__ slots, double* __restrict__ F) {
+  const int64_t row = k / nblk, blk = k - row * nblk;
+  const int64_t c0 = blk * kBlock;
+  const int n = (int)(cols - c0 < kBlock ? cols - c0 : kBlock);
   double* f = F + row * cols + c0;
   if (m == 0) {
     for (int e = threadIdx.x; e < n; e += kThreads) __builtin_nontemporal_store(0.0, f + e);
@@ -301,11 +400,11 @@ __global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* _
   const double* p = P + row * cols + c0;
 #pragma unroll
   for (int e = threadIdx.x; e < kBlock; e += kThreads) {
-    C[(e / kPer) * kPad + e % kPer] = e < n ? quant52(__builtin_nontemporal_load(p + e)) : 0ull;
-    cnt[e] = 0;
+    L.C[(e / kPer) * kPad + e % kPer] = e < n ? quant52(__builtin_nontemporal_load(p + e)) : 0ull;
+    L.cnt[e] = 0;
   }
   __syncthreads();
-  unsigned long long* mine = C + threadIdx.x * kPad;
+  unsigned long long* mine = L.C + threadIdx.x * kPad;
   unsigned long long v[kPer];
   unsigned long long s = 0;
 #pragma unroll
@@ -320,10 +419,10 @@ __global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* _
     const unsigned long long y = __shfl_up(x, d);
     if (lane >= d) x += y;
   }
-  if (lane == 63) wtot[wid] = x;
+  if (lane == 63) L.wtot[wid] = x;
   __syncthreads();
   unsigned long long before = x - s;
-  for (int w = 0; w < wid; ++w) before += wtot[w];
+  for (int w = 0; w < wid; ++w) before += L.wtot[w];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) mine[e] = v[e] + before;
   __syncthreads();
@@ -333,16 +432,62 @@ __global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* _
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (C[(mid / kPer) * kPad + mid % kPer] > t) hi = mid;
+      if (L.C[(mid / kPer) * kPad + mid % kPer] > t) hi = mid;
       else lo = mid + 1;
     }
-    atomicAdd(&cnt[lo], 1u);
+    atomicAdd(&L.cnt[lo], 1u);
   }
   __syncthreads();
   const double ds = (double)shots;
   for (int e = threadIdx.x; e < n; e += kThreads) {
-    const uint32_t c = cnt[e];
+    const uint32_t c = L.cnt[e];
     __builtin_nontemporal_store(c ? (double)c / ds : 0.0, f + e);
+  }
+  __syncthreads();  // the workgroup's next block reuses the LDS
+}
+
+// Every block, one workgroup each (grid (nblk, rows)): for tables with many
+// shots per block on average.
+__global__ void __launch_bounds__(kThreads) shots_resolve_kernel(const double* __restrict__ P, int64_t cols,
+                                                                 int64_t nblk, int64_t shots,
+                                                                 const uint32_t* __restrict__ bcnt,
+                                                                 const uint32_t* __restrict__ bptr,
+                                                                 const uint64_t* __restrict__ slots,
+                                                                 double* __restrict__ F) {
+  __shared__ ResolveLds L;
+  const int64_t k = (int64_t)blockIdx.y * nblk + blockIdx.x;
+  resolve_block_lds(L, P, cols, nblk, shots, k, bcnt[k], bptr, slots, F);
+}
+
+// Only the blocks with more than kFewShots shots, after
+// shots_resolve_few_kernel: each workgroup reads the shot counts of
+// kManyChunk blocks (k = row * nblk + blk) at once, lists the heavy ones in
+// LDS and resolves them, so a table with few such blocks costs one pass
+// over the counts.
+constexpr int kManyChunk = 64;
+constexpr int64_t kManyGrid = 1 << 20;
+
+__global__ void __launch_bounds__(kThreads) shots_resolve_listed_kernel(const double* __restrict__ P, int64_t cols,
+                                                                        int64_t nblk, int64_t total, int64_t shots,
+                                                                        const uint32_t* __restrict__ bcnt,
+                                                                        const uint32_t* __restrict__ bptr,
+                                                                        const uint64_t* __restrict__ slots,
+                                                                        double* __restrict__ F) {
+  __shared__ ResolveLds L;
+  __shared__ uint32_t many[kManyChunk];
+  __shared__ uint32_t nmany;
+  for (int64_t base = (int64_t)blockIdx.x * kManyChunk; base < total; base += (int64_t)gridDim.x * kManyChunk) {
+    if (threadIdx.x == 0) nmany = 0;
+    __syncthreads();
+    if (threadIdx.x < kManyChunk && base + threadIdx.x < total && bcnt[base + threadIdx.x] > (uint32_t)kFewShots)
+      many[atomicAdd(&nmany, 1u)] = threadIdx.x;
+    __syncthreads();
+    const uint32_t listed = nmany;
+    for (uint32_t q = 0; q < listed; ++q) {
+      const int64_t k = base + many[q];
+      resolve_block_lds(L, P, cols, nblk, shots, k, bcnt[k], bptr, slots, F);
+    }
+    __syncthreads();  // every thread has read nmany and the list before they change
   }
 }
 
@@ -469,8 +614,20 @@ extern "C" cq_status cq_sample_shots(const double* probs, int64_t rows, int64_t 
   hipLaunchKernelGGL(shots_bptr_kernel, dim3((unsigned)rows), dim3(kScanThreads), 0, stream, bcnt, bptr, nblk);
   hipLaunchKernelGGL(shots_scatter_kernel, gs, dim3(kThreads), 0, stream, (const uint64_t*)bend, nblk, shots,
                      seed, (const uint32_t*)bptr, bfill, slots);
-  hipLaunchKernelGGL(shots_resolve_kernel, gt, dim3(kThreads), 0, stream, probs, cols, nblk, shots,
-                     (const uint32_t*)bcnt, (const uint32_t*)bptr, (const uint64_t*)slots, freqs);
+  if (shots >= (int64_t)kFewShots * nblk) {
+    // many shots per block on average: every block resolves in LDS
+    hipLaunchKernelGGL(shots_resolve_kernel, gt, dim3(kThreads), 0, stream, probs, cols, nblk, shots,
+                       (const uint32_t*)bcnt, (const uint32_t*)bptr, (const uint64_t*)slots, freqs);
+  } else {
+    hipLaunchKernelGGL(shots_resolve_few_kernel, gt, dim3(kThreads), 0, stream, probs, cols, nblk, shots,
+                       (const uint32_t*)bcnt, (const uint32_t*)bptr, (const uint64_t*)slots, freqs);
+    if (shots > kFewShots) {
+      const int64_t total = rows * nblk, chunks = (total + kManyChunk - 1) / kManyChunk;
+      const unsigned grid = (unsigned)(chunks < kManyGrid ? chunks : kManyGrid);
+      hipLaunchKernelGGL(shots_resolve_listed_kernel, dim3(grid), dim3(kThreads), 0, stream, probs, cols, nblk,
+                         total, shots, (const uint32_t*)bcnt, (const uint32_t*)bptr, (const uint64_t*)slots, freqs);
+    }
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "shot sampling launch");
   return CQ_OK;

@@ -7,7 +7,9 @@ frequencies must equal the oracle's bit for bit: on ragged widths that span
 several blocks of 2048 entries (rows of one block, rows counted in LDS, rows
 of more than 8192 blocks counted in global memory), on negative, zero,
 unnormalised and single-spike rows, on seeds above 2^32, and at the
-dynamic-definition subcircuit shape on sampled rows.
+dynamic-definition subcircuit shape on sampled rows.  Tables with fewer
+than 64 shots a block on average resolve light blocks in registers and list
+the heavy ones; others resolve every block in LDS: both mixes are covered.
 The loss is a floating-point sum in another order than the oracle's: it must
 agree within 1e-12 of the sum of the terms' magnitudes, and repeat bit for
 bit."""
@@ -76,6 +78,11 @@ def _table(rng, rows, cols, kind):
     (3, 10000, 100000, 6, "spike"),
     (4096, 16, 5000, 8, "dirichlet"),
     (1, (1 << 24) + 4099, 200000, 10, "dirichlet"),
+    # fewer than 64 shots a block on average: light blocks resolve in
+    # registers, heavy ones (the spike's block; Dirichlet blocks above 64)
+    # are listed and resolved in LDS
+    (2, 64 * 2048, 4000, 11, "spike"),
+    (3, 100 * 2048 + 77, 6000, 13, "dirichlet"),
 ])
 def test_frequencies_bit_exact(rows, cols, n, seed, kind):
     print(f"case rows={rows} cols={cols} shots={n} seed={seed} {kind}", flush=True)
