@@ -143,8 +143,21 @@ struct ExchangeCoef {
   double ar, ai, br, bi;  // coefficient of mine, of the partner
 };
 
+// A coefficient every lane reads alike, taken through the first lane so that
+// the per-lane choice below selects values, not addresses (a per-lane
+// address would turn each coefficient into a vector load that the gate
+// then waits for).
+__device__ inline double uniform_coef(const double* p) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, *p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
 __device__ inline ExchangeCoef exchange_coef(const double* u, int bit) {
-  return bit ? ExchangeCoef{u[6], u[7], u[4], u[5]} : ExchangeCoef{u[0], u[1], u[2], u[3]};
+  const ExchangeCoef c0{uniform_coef(u + 0), uniform_coef(u + 1), uniform_coef(u + 2), uniform_coef(u + 3)};
+  const ExchangeCoef c1{uniform_coef(u + 6), uniform_coef(u + 7), uniform_coef(u + 4), uniform_coef(u + 5)};
+  return bit ? c1 : c0;
 }
 
 __device__ inline double2 u_exchange(const ExchangeCoef& c, double2 mine, double2 y) {
@@ -169,16 +182,19 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
   const uint64_t w = blockIdx.x;
   for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
   const int tid = threadIdx.x, lane = tid & 63;
-  uint64_t addr[kPerThread];
+  // local index tid + 256 e: its bits 0-7 are tid's (one per-thread part of
+  // the address), bits 8-10 are e's (a part every thread shares), so no
+  // per-element address has to stay live from the load to the store
+  uint64_t tpart = base;
+  for (int i = 0; i < 8; ++i) tpart |= (uint64_t)((tid >> i) & 1) << G.bits[i];
+  auto addr_of = [&](int e) -> uint64_t {
+    uint64_t a = tpart;
+    for (int i = 8; i < kTileBits; ++i) a |= (uint64_t)((e >> (i - 8)) & 1) << G.bits[i];
+    return a;
+  };
   double2 v[kPerThread];
 #pragma unroll
-  for (int e = 0; e < kPerThread; ++e) {
-    const int t = tid + e * kSvThreads;
-    uint64_t a = base;
-    for (int i = 0; i < kTileBits; ++i) a |= (uint64_t)((t >> i) & 1) << G.bits[i];
-    addr[e] = a;
-    v[e] = in[a];
-  }
+  for (int e = 0; e < kPerThread; ++e) v[e] = in[addr_of(e)];
   for (int gi = 0; gi < G.ngates; ++gi) {
     const TileGate& g = G.g[gi];
     if (g.kind == CQ_GATE_CZ) {
@@ -212,8 +228,9 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
   }
 #pragma unroll
   for (int e = 0; e < kPerThread; ++e) {
-    if (G.mode == 0) out[addr[e]] = v[e];
-    else probs[addr[e]] = v[e].x * v[e].x + v[e].y * v[e].y;
+    const uint64_t a = addr_of(e);
+    if (G.mode == 0) out[a] = v[e];
+    else probs[a] = v[e].x * v[e].x + v[e].y * v[e].y;
   }
 }
 
