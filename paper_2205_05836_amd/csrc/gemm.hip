@@ -1048,6 +1048,18 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
       }
   __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
   const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+  // column-scaled operands: a lane's four columns are the same in every row
+  // it stores, so their exponents are read once
+  int32_t cexp[4] = {0, 0, 0, 0};
+  if constexpr (OUT != 2) {
+    if (g.rowexp) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t n = n0 + wn + 4 * (lane & 15) + e;
+        if (n < g.N) cexp[e] = g.colexp[n];
+      }
+    }
+  }
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     const int r = 4 * s + (lane >> 4);
@@ -1059,8 +1071,7 @@ __global__ void __launch_bounds__(256) gemm_h16a_kernel(GemmArgs gv, const GemmA
       if (g.rowexp && m < g.M) {
         const int32_t re = g.rowexp[tc.z * g.M + m];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (n + e < g.N) x[e] = __builtin_ldexpf(x[e], re + g.colexp[n + e]);
+        for (int e = 0; e < 4; ++e) x[e] = __builtin_ldexpf(x[e], re + cexp[e]);
       }
     }
     if (full || (m < g.M && n + 3 < g.N)) {
@@ -1239,6 +1250,18 @@ gemm_h16t_kernel(GemmArgs g) {
   __syncthreads();  // every wave is done with the ring
   char* const wbuf = smem + wave * 8 * EROW;
   const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+  // column-scaled operands: a lane's four columns are the same in every
+  // slab, so their exponents are read once
+  int32_t cexp[4] = {0, 0, 0, 0};
+  if constexpr (OUT != 2) {
+    if (g.rowexp) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t n = n0 + wn + 4 * (lane & 15) + e;
+        if (n < g.N) cexp[e] = g.colexp[n];
+      }
+    }
+  }
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int i = u >> 2, vg = u & 3;
@@ -1255,9 +1278,17 @@ gemm_h16t_kernel(GemmArgs g) {
     for (int h = 0; h < 2; ++h) {
       const int rl = 4 * h + (lane >> 4);
       const int c = 4 * (lane & 15);
-      const f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + c * 4);
+      f4_t x = *reinterpret_cast<const f4_t*>(wbuf + rl * EROW + c * 4);
       const int64_t m = m0 + wm + 32 * i + 8 * vg + rl, n = n0 + wn + c;
       const int64_t idx = tc.z * g.sCz + m * g.ldc + n;
+      if constexpr (OUT != 2) {
+        // column-scaled operands: the output exponents, after alpha as in the other forms
+        if (g.rowexp && m < g.M) {
+          const int32_t re = g.rowexp[tc.z * g.M + m];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[e] = __builtin_ldexpf(x[e], re + cexp[e]);
+        }
+      }
       if constexpr (OUT == 2) {
         typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
         u16x4 hh, ll;
@@ -2063,6 +2094,10 @@ bool h16p_ok(const GemmArgs& a, DType tc) {
   return a.rowexp == nullptr && a.K >= 1 && h16_async_ok(a, tc);
 }
 
+// the occupancy kernel applies: K >= 1, aligned rows (it applies output
+// exponents in its epilogue)
+bool h16t_ok(const GemmArgs& a, DType tc) { return a.K >= 1 && h16_async_ok(a, tc); }
+
 // FP32 operands for the persistent kernel: 16-byte aligned rows of at least
 // 4 columns, and an output whose rows take 16-byte stores
 bool f32p_ok(const GemmArgs& a) {
@@ -2124,8 +2159,8 @@ hipError_t dispatch_h16(const GemmArgs& a, DType tc, bool nt, hipStream_t s, int
   // occupancy form: four workgroups per CU with a two-deep ring, or three
   // with a three-deep one
   if (impl == 2 && h16p_ok(a, tc)) return launch_h16s<SPLIT, F16>(a, tc, nt, s);
-  if (impl == 4 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 2, 4>(a, tc, nt, s);
-  if (impl == 5 && h16p_ok(a, tc)) return launch_h16t<SPLIT, F16, 3, 3>(a, tc, nt, s);
+  if (impl == 4 && h16t_ok(a, tc)) return launch_h16t<SPLIT, F16, 2, 4>(a, tc, nt, s);
+  if (impl == 5 && h16t_ok(a, tc)) return launch_h16t<SPLIT, F16, 3, 3>(a, tc, nt, s);
   if (impl == 3 && h16p_ok(a, tc)) {
     const int64_t grid = persistent_grid(a.tiles);
     using P = PersistH16<SPLIT, F16>;
@@ -2326,7 +2361,8 @@ bool variant_applies(cq_precision prec, const GemmArgs& a, DType tc, int v) {
   if (impl == 0) return true;
   if (v >= variant_count(prec)) return false;
   if (prec == CQ_FP32) return (impl == 1 || impl >= 3) && f32p_ok(a);
-  return impl >= 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
+  if (impl == 4 || impl == 5) return h16t_ok(a, tc);
+  return impl == 3 ? h16p_ok(a, tc) : h16_async_ok(a, tc);
 }
 
 }  // namespace
