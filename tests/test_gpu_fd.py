@@ -426,8 +426,11 @@ def test_30_qubit_chain_variants_bit_equal(prec):
         m.cq_autotune_enable(True)
 
 
-@pytest.mark.parametrize("prec", ["bf16", "bf16_split"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16_split", "fp16", "fp16_split"])
 def test_30_qubit_chain_full_size_h16(prec):
+    """Sampled and heaviest bins of the 30-qubit chain against the oracle in
+    every 16-bit form; the FP16 forms run with the per-label balance and the
+    column scaling, their last GEMM applying the exponents in its epilogue."""
     m = cq()
     cm = syn.chain_cutmap(BONDS_30Q, NS_30Q)
     ents = _entries_30q()
