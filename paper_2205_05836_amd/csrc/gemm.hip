@@ -2634,6 +2634,13 @@ __device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i) 
 // wave takes a segment (four consecutive elements per lane), and a wave
 // loads four pairs of segments before reducing any, so sixteen loads per
 // lane are in flight; the waves of the grid take the segments in turn.
+// Column-scaled operands (rowtmax set): an element of output row z * M + m
+// of A counts as |a| 2^(rowexp - the tile's largest rowexp), one of column
+// n of B as |b| 2^(colexp - the tile's largest colexp), so the bound, which
+// adds both largest exponents back, is the sum over k of the largest
+// magnitudes the epilogue's exponents give (A's maxima are kept per batch
+// only when A varies with it; else A's rows count unweighted, a looser
+// bound that still holds).
 template <int KIND>
 __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __restrict__ gp, float* amax,
                                                           float* bmax, int64_t slot) {
@@ -2675,7 +2682,22 @@ __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __rest
         const void* hi = isA ? g.A : g.B;
         const void* lo = isA ? g.A_lo : g.B_lo;
         const int64_t c0 = t * 128 + sub * 4;
-        if (c0 + 4 <= lim) {
+        const int32_t* ex = nullptr;
+        int32_t top = 0;
+        if (g.rowtmax) {
+          if (isA && (g.sAz != 0 || Z == 1)) {
+            ex = g.rowexp + z * g.M;
+            top = g.rowtmax[z * g.tilesM + t];
+          } else if (!isA) {
+            ex = g.colexp;
+            top = g.coltmax[t];
+          }
+        }
+        if (ex) {
+          for (int q = 0; q < 4; ++q)
+            if (c0 + q < lim)
+              m[u] = fmax(m[u], ldexp(fabs(operand_at<KIND>(hi, lo, base + c0 + q)), ex[c0 + q] - top));
+        } else if (c0 + 4 <= lim) {
           m[u] = quad_absmax<KIND>(hi, lo, base + c0);
         } else {
           for (int q = 0; q < 4; ++q)
@@ -2713,7 +2735,8 @@ __global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restr
     u += double(amax[(za * g.K + k) * g.tilesM + mt]) * double(bmax[(zb * g.K + k) * g.tilesN + nt]);
   // the kernels accumulate in FP32 (or FP64): allow K roundings of 2^-24
   u *= g.alpha * (1.0 + double(g.K + 4) * 0x1p-23);
-  // column-scaled operands: the tile's largest output exponent
+  // column-scaled operands: the tile's largest exponents, which the maxima
+  // are relative to
   if (g.rowtmax) u = ldexp(u, g.rowtmax[c.z * g.tilesM + mt] + g.coltmax[nt]);
   U[t] = __double2float_ru(u);
 }
