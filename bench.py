@@ -53,7 +53,7 @@ def parse():
                     help="other precisions timed beside the headline and FP64")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--dd-forms", default="fp32,bf16_split,fp64",
+    ap.add_argument("--dd-forms", default="fp32,bf16_split,fp16_split,fp64",
                     help="precisions of the batched dynamic-definition leg ('' skips it)")
     ap.add_argument("--dd-runs", type=int, default=3)
     ap.add_argument("--skip-attribution", action="store_true",

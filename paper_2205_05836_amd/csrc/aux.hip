@@ -474,25 +474,38 @@ __global__ void __launch_bounds__(256) expsum_ind_kernel(const DDProgram* P, con
   const int q = blockIdx.y;
   const int64_t count = q == 0 ? g.tiles / (g.tilesM * g.tilesN) * g.M : g.N;
   int32_t* const out = q == 0 ? P->rowexp : P->colexp;
+  // each member's bit field, the same for every row: its shift and width
   const int n = P->fac_n[q];
+  int sh[CQ_MAX_SUBCIRCUITS], sub[CQ_MAX_SUBCIRCUITS];
+  int64_t mk[CQ_MAX_SUBCIRCUITS];
+#pragma unroll
+  for (int i = 0; i < CQ_MAX_SUBCIRCUITS; ++i) {
+    sh[i] = 0;
+    sub[i] = 0;
+    mk[i] = 0;
+    if (i < n) {
+      const SymLog& sl = P->fac_shift[q][i];
+      int s = sl.c0;
+      for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c)
+        if ((sl.mask >> c) & 1u) s += st->na[c];
+      sh[i] = s;
+      sub[i] = P->fac_sub[q][i];
+      mk[i] = ((int64_t)1 << st->na[sub[i]]) - 1;
+    }
+  }
   const int64_t stepg = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += stepg) {
     int e = 0;
-    for (int i = 0; i < n; ++i) {
-      const int sub = P->fac_sub[q][i];
-      const SymLog& sl = P->fac_shift[q][i];
-      int sh = sl.c0;
-      for (int c = 0; c < CQ_MAX_SUBCIRCUITS; ++c)
-        if ((sl.mask >> c) & 1u) sh += st->na[c];
-      const int64_t mk = ((int64_t)1 << st->na[sub]) - 1;
-      e += colmax_exp(P->colmax[sub][(r >> sh) & mk]);
-    }
+#pragma unroll
+    for (int i = 0; i < CQ_MAX_SUBCIRCUITS; ++i)
+      if (i < n) e += colmax_exp(P->colmax[sub[i]][(r >> sh[i]) & mk[i]]);
     out[r] = e;
   }
 }
 
 // Tile maxima of those exponents: blockIdx.y 0 over the 128-row tiles of each
-// batch (z * tilesM + mt), 1 over the 128-column tiles.
+// batch (z * tilesM + mt), 1 over the 128-column tiles; one wave a tile, its
+// lanes taking every 64th row (coalesced), then a wave maximum.
 __global__ void __launch_bounds__(256) exptmax_ind_kernel(const DDProgram* P, const DDLevel* lv, int step,
                                                           int64_t slot) {
   P = inst_ptr(P, slot);
@@ -503,19 +516,22 @@ __global__ void __launch_bounds__(256) exptmax_ind_kernel(const DDProgram* P, co
   const int q = blockIdx.y;
   const int64_t Z = g.tiles / (g.tilesM * g.tilesN);
   const int64_t count = q == 0 ? Z * g.tilesM : g.tilesN;
-  const int64_t stepg = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stepg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  // t is the same for every lane of a wave, so every lane reaches the shuffles
+  for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < count; t += waves) {
     int e = INT_MIN;
     if (q == 0) {
       const int64_t z = t / g.tilesM, m0 = (t - z * g.tilesM) * 128;
       const int64_t m1 = m0 + 128 < g.M ? m0 + 128 : g.M;
-      for (int64_t m = m0; m < m1; ++m) e = max(e, P->rowexp[z * g.M + m]);
-      P->rowtmax[t] = e;
+      for (int64_t m = m0 + lane; m < m1; m += 64) e = max(e, P->rowexp[z * g.M + m]);
     } else {
       const int64_t n0 = t * 128, n1 = n0 + 128 < g.N ? n0 + 128 : g.N;
-      for (int64_t nn = n0; nn < n1; ++nn) e = max(e, P->colexp[nn]);
-      P->coltmax[t] = e;
+      for (int64_t nn = n0 + lane; nn < n1; nn += 64) e = max(e, P->colexp[nn]);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) e = max(e, __shfl_xor(e, o));
+    if (lane == 0) (q == 0 ? P->rowtmax : P->coltmax)[t] = e;
   }
 }
 
@@ -1018,8 +1034,9 @@ hipError_t launch_dd_expsum(const DDProgram* prog, const DDState* st, const DDLe
   const int64_t most = max_rows > max_cols ? max_rows : max_cols;
   hipLaunchKernelGGL(expsum_ind_kernel, dim3(grid_ind(most), 2, (unsigned)span.n), dim3(256), 0, stream, prog,
                      st, lv, step, span.stride);
-  hipLaunchKernelGGL(exptmax_ind_kernel, dim3(grid_ind((most + 127) / 128 + 1), 2, (unsigned)span.n), dim3(256),
-                     0, stream, prog, lv, step, span.stride);
+  // one wave a tile: a few tiles a wave at most
+  hipLaunchKernelGGL(exptmax_ind_kernel, dim3(grid_ind(most / 2 + 1), 2, (unsigned)span.n), dim3(256), 0, stream,
+                     prog, lv, step, span.stride);
   return hipGetLastError();
 }
 
