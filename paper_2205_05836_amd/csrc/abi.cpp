@@ -543,8 +543,8 @@ struct DDInstancePlan {
   // column scaling of the FP16 operands (the last step a GEMM writing the bins)
   bool cscale = false;
   std::vector<int64_t> colmax_off;
-  int64_t rowexp_off = 0, colexp_off = 0, rowtmax_off = 0, coltmax_off = 0;
-  int64_t rowexp_n = 0, colexp_n = 0, rowtmax_n = 0, coltmax_n = 0;  // at the largest counts
+  int64_t rowexp_off = 0, colexp_off = 0, rowtmax_off = 0;
+  int64_t rowexp_n = 0, colexp_n = 0, rowtmax_n = 0;  // at the largest counts
   int fac_n[2] = {0, 0};
   int fac_sub[2][CQ_MAX_SUBCIRCUITS] = {};
   SymLog fac_shift[2][CQ_MAX_SUBCIRCUITS] = {};
@@ -600,8 +600,6 @@ void dd_layout(DDInstancePlan& D, const DDSel& s) {
     off = align256(off + D.colexp_n * 4);
     D.rowtmax_off = off;
     off = align256(off + D.rowtmax_n * 4);
-    D.coltmax_off = off;
-    off = align256(off + D.coltmax_n * 4);
   }
   D.rowmax_off.clear();
   D.rexp_off.clear();
@@ -684,7 +682,6 @@ bool dd_fac_groups(DDInstancePlan& D) {
   D.rowexp_n = g.Z * g.M;
   D.colexp_n = g.N;
   D.rowtmax_n = g.Z * ((g.M + 127) / 128);
-  D.coltmax_n = (g.N + 127) / 128;
   return true;
 }
 
@@ -976,7 +973,6 @@ void dd_program(const DDInstancePlan& D, const cq_dd_instance& in, const cq_dd_p
     P.rowexp = reinterpret_cast<int32_t*>(ws + D.rowexp_off);
     P.colexp = reinterpret_cast<int32_t*>(ws + D.colexp_off);
     P.rowtmax = reinterpret_cast<int32_t*>(ws + D.rowtmax_off);
-    P.coltmax = reinterpret_cast<int32_t*>(ws + D.coltmax_off);
   }
   P.balance = D.lbal ? 1 : 0;
   if (D.lbal) {

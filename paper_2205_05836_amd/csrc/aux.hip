@@ -503,9 +503,11 @@ __global__ void __launch_bounds__(256) expsum_ind_kernel(const DDProgram* P, con
   }
 }
 
-// Tile maxima of those exponents: blockIdx.y 0 over the 128-row tiles of each
-// batch (z * tilesM + mt), 1 over the 128-column tiles; one wave a tile, its
-// lanes taking every 64th row (coalesced), then a wave maximum.
+// Tile maxima of the row exponents over the 128-row tiles of each batch
+// (z * tilesM + mt), for the tile bounds when A is shared across batches
+// (else the bounds weight every element by its own exponents and this
+// exits); one wave a tile, its lanes taking every 64th row (coalesced), then
+// a wave maximum.
 __global__ void __launch_bounds__(256) exptmax_ind_kernel(const DDProgram* P, const DDLevel* lv, int step,
                                                           int64_t slot) {
   P = inst_ptr(P, slot);
@@ -513,25 +515,20 @@ __global__ void __launch_bounds__(256) exptmax_ind_kernel(const DDProgram* P, co
   if (!P->cscale) return;
   const GemmArgs& g = lv->gemm[step];
   if (g.tiles <= 0) return;
-  const int q = blockIdx.y;
   const int64_t Z = g.tiles / (g.tilesM * g.tilesN);
-  const int64_t count = q == 0 ? Z * g.tilesM : g.tilesN;
+  if (g.sAz != 0 || Z == 1) return;
+  const int64_t count = Z * g.tilesM;
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   // t is the same for every lane of a wave, so every lane reaches the shuffles
   for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < count; t += waves) {
     int e = INT_MIN;
-    if (q == 0) {
-      const int64_t z = t / g.tilesM, m0 = (t - z * g.tilesM) * 128;
-      const int64_t m1 = m0 + 128 < g.M ? m0 + 128 : g.M;
-      for (int64_t m = m0 + lane; m < m1; m += 64) e = max(e, P->rowexp[z * g.M + m]);
-    } else {
-      const int64_t n0 = t * 128, n1 = n0 + 128 < g.N ? n0 + 128 : g.N;
-      for (int64_t nn = n0 + lane; nn < n1; nn += 64) e = max(e, P->colexp[nn]);
-    }
+    const int64_t z = t / g.tilesM, m0 = (t - z * g.tilesM) * 128;
+    const int64_t m1 = m0 + 128 < g.M ? m0 + 128 : g.M;
+    for (int64_t m = m0 + lane; m < m1; m += 64) e = max(e, P->rowexp[z * g.M + m]);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) e = max(e, __shfl_xor(e, o));
-    if (lane == 0) (q == 0 ? P->rowtmax : P->coltmax)[t] = e;
+    if (lane == 0) P->rowtmax[t] = e;
   }
 }
 
@@ -1035,7 +1032,7 @@ hipError_t launch_dd_expsum(const DDProgram* prog, const DDState* st, const DDLe
   hipLaunchKernelGGL(expsum_ind_kernel, dim3(grid_ind(most), 2, (unsigned)span.n), dim3(256), 0, stream, prog,
                      st, lv, step, span.stride);
   // one wave a tile: a few tiles a wave at most
-  hipLaunchKernelGGL(exptmax_ind_kernel, dim3(grid_ind(most / 2 + 1), 2, (unsigned)span.n), dim3(256), 0, stream,
+  hipLaunchKernelGGL(exptmax_ind_kernel, dim3(grid_ind(most / 2 + 1), 1, (unsigned)span.n), dim3(256), 0, stream,
                      prog, lv, step, span.stride);
   return hipGetLastError();
 }

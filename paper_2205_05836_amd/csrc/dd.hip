@@ -787,7 +787,6 @@ __global__ void dd_setup_kernel(const DDProgram* __restrict__ P, DDState* st, DD
       g.rowexp = scaled ? P->rowexp : nullptr;
       g.colexp = scaled ? P->colexp : nullptr;
       g.rowtmax = scaled ? P->rowtmax : nullptr;
-      g.coltmax = scaled ? P->coltmax : nullptr;
       const bool tc_here = s == P->topc_step;
       g.topc_publish_only = 0;
       g.tile_list = tc_here ? P->tile_list : nullptr;

@@ -2388,7 +2388,6 @@ hipError_t launch_gemm(cq_precision prec, const GemmLaunch& g, hipStream_t strea
   a.rowexp = g.rowexp;
   a.colexp = g.colexp;
   a.rowtmax = nullptr;
-  a.coltmax = nullptr;
   a.topc_thr = nullptr;
   a.topc_count = nullptr;
   a.topc_C = nullptr;
@@ -2635,12 +2634,13 @@ __device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i) 
 // loads four pairs of segments before reducing any, so sixteen loads per
 // lane are in flight; the waves of the grid take the segments in turn.
 // Column-scaled operands (rowtmax set): an element of output row z * M + m
-// of A counts as |a| 2^(rowexp - the tile's largest rowexp), one of column
-// n of B as |b| 2^(colexp - the tile's largest colexp), so the bound, which
-// adds both largest exponents back, is the sum over k of the largest
-// magnitudes the epilogue's exponents give (A's maxima are kept per batch
-// only when A varies with it; else A's rows count unweighted, a looser
-// bound that still holds).
+// of A counts as |a| 2^rowexp, one of column n of B as |b| 2^colexp, so the
+// bound is the sum over k of the largest magnitudes the epilogue's
+// exponents give (these are the unscaled magnitudes, well inside FP32's
+// range; a maximum below it rounds up to the smallest subnormal, still an
+// upper bound).  A's maxima are kept per batch only when A varies with it;
+// else A's rows count unweighted and the bound adds the tile's largest row
+// exponent instead, looser but still a bound.
 template <int KIND>
 __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __restrict__ gp, float* amax,
                                                           float* bmax, int64_t slot) {
@@ -2683,20 +2683,14 @@ __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __rest
         const void* lo = isA ? g.A_lo : g.B_lo;
         const int64_t c0 = t * 128 + sub * 4;
         const int32_t* ex = nullptr;
-        int32_t top = 0;
         if (g.rowtmax) {
-          if (isA && (g.sAz != 0 || Z == 1)) {
-            ex = g.rowexp + z * g.M;
-            top = g.rowtmax[z * g.tilesM + t];
-          } else if (!isA) {
-            ex = g.colexp;
-            top = g.coltmax[t];
-          }
+          if (isA && (g.sAz != 0 || Z == 1)) ex = g.rowexp + z * g.M;
+          else if (!isA) ex = g.colexp;
         }
         if (ex) {
           for (int q = 0; q < 4; ++q)
             if (c0 + q < lim)
-              m[u] = fmax(m[u], ldexp(fabs(operand_at<KIND>(hi, lo, base + c0 + q)), ex[c0 + q] - top));
+              m[u] = fmax(m[u], ldexp(fabs(operand_at<KIND>(hi, lo, base + c0 + q)), ex[c0 + q]));
         } else if (c0 + 4 <= lim) {
           m[u] = quad_absmax<KIND>(hi, lo, base + c0);
         } else {
@@ -2735,9 +2729,9 @@ __global__ void __launch_bounds__(256) tile_bound_kernel(const GemmArgs* __restr
     u += double(amax[(za * g.K + k) * g.tilesM + mt]) * double(bmax[(zb * g.K + k) * g.tilesN + nt]);
   // the kernels accumulate in FP32 (or FP64): allow K roundings of 2^-24
   u *= g.alpha * (1.0 + double(g.K + 4) * 0x1p-23);
-  // column-scaled operands: the tile's largest exponents, which the maxima
-  // are relative to
-  if (g.rowtmax) u = ldexp(u, g.rowtmax[c.z * g.tilesM + mt] + g.coltmax[nt]);
+  // column-scaled operands with A shared across batches: A's rows counted
+  // unweighted, so the tile's largest row exponent is added here
+  if (g.rowtmax && g.sAz == 0 && g.tiles > g.tilesM * g.tilesN) u = ldexp(u, g.rowtmax[c.z * g.tilesM + mt]);
   U[t] = __double2float_ru(u);
 }
 

@@ -88,11 +88,10 @@ struct GemmArgs {
   double alpha;
   const int32_t* rowexp;  // optional output exponents (see GemmLaunch)
   const int32_t* colexp;
-  // with rowexp: the largest rowexp over each 128-row tile of each batch
-  // (z * tilesM + mt) and the largest colexp over each 128-column tile, for
-  // the tile bounds of the fused top-C; null otherwise
+  // with rowexp, for the tile bounds of the fused top-C (null otherwise):
+  // the largest rowexp over each 128-row tile of each batch (z * tilesM +
+  // mt), filled only when A is shared across batches
   const int32_t* rowtmax;
-  const int32_t* coltmax;
   // Top-C instead of the store (launch_gemm_indirect with topc): each tile
   // appends its C best (value, index) keys not below the running threshold
   // and raises the threshold to its C-th best value when it has C of them.
@@ -391,8 +390,8 @@ struct DDProgram {
   // the bins): column maxima of every reduced entry, and the last GEMM's
   // output exponents -- over its rows (z * M + m) and columns (n), each the
   // sum over the subcircuits of a group of the exponent of the column that
-  // bits shift .. shift + na_c - 1 of the index select -- with their tile
-  // maxima.
+  // bits shift .. shift + na_c - 1 of the index select -- and the rows'
+  // tile maxima (used when A is shared across batches).
   int32_t cscale;
   int32_t fac_n[2];
   int32_t fac_sub[2][CQ_MAX_SUBCIRCUITS];
@@ -401,7 +400,6 @@ struct DDProgram {
   int32_t* rowexp;
   int32_t* colexp;
   int32_t* rowtmax;
-  int32_t* coltmax;
   DDTensor tensor[kDDMaxTensors];
   SymPow tensor_elems[kDDMaxTensors];
   int32_t step_is_gemm[kDDMaxSteps];
@@ -477,8 +475,9 @@ hipError_t launch_dd_balance(const DDProgram* prog, const DDLevel* lv, int n_sub
 // exponents; `max_cols` bounds 2^na_c over the group.
 hipError_t launch_dd_colmax(const DDProgram* prog, const DDLevel* lv, int n_sub, int64_t max_cols,
                             hipStream_t stream, InstSpan span = InstSpan());
-// The last GEMM's output exponents and their tile maxima (GEMM step `step` of
-// the level); `max_rows` and `max_cols` bound its Z * M and N over the group.
+// The last GEMM's output exponents and, when its A is shared across batches,
+// the rows' tile maxima (GEMM step `step` of the level); `max_rows` and
+// `max_cols` bound its Z * M and N over the group.
 hipError_t launch_dd_expsum(const DDProgram* prog, const DDState* st, const DDLevel* lv, int step,
                             int64_t max_rows, int64_t max_cols, hipStream_t stream,
                             InstSpan span = InstSpan());
