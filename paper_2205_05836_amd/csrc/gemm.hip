@@ -2591,21 +2591,37 @@ __device__ inline double operand_at(const void* hi, const void* lo, int64_t i) {
 }
 
 // max |value| over elements i .. i+3, with one vector load per plane when
-// they are aligned for it
+// they are aligned for it; with `ex`, element i + q counts as
+// |value| 2^ex[q]
 template <int KIND>
-__device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i) {
+__device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i, const int32_t* ex = nullptr) {
+  int32_t e[4] = {0, 0, 0, 0};
+  if (ex) {
+    if ((reinterpret_cast<uintptr_t>(ex) & 15) == 0) {
+      const int4 v = *reinterpret_cast<const int4*>(ex);
+      e[0] = v.x;
+      e[1] = v.y;
+      e[2] = v.z;
+      e[3] = v.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) e[q] = ex[q];
+    }
+  }
+  auto w = [&](double v, int q) { return ex ? ldexp(fabs(v), e[q]) : fabs(v); };
   double m = 0.0;
   if constexpr (KIND == 1) {
     const float* p = static_cast<const float*>(hi) + i;
     if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
       const float4 v = *reinterpret_cast<const float4*>(p);
-      return double(fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      if (!ex) return double(fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      return fmax(fmax(w(v.x, 0), w(v.y, 1)), fmax(w(v.z, 2), w(v.w, 3)));
     }
   } else if constexpr (KIND == 0) {
     const double* p = static_cast<const double*>(hi) + i;
     if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
       const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
-      return fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(b.x), fabs(b.y)));
+      return fmax(fmax(w(a.x, 0), w(a.y, 1)), fmax(w(b.x, 2), w(b.y, 3)));
     }
   } else {
     const uint16_t* h = static_cast<const uint16_t*>(hi) + i;
@@ -2619,13 +2635,13 @@ __device__ inline double quad_absmax(const void* hi, const void* lo, int64_t i) 
       for (int q = 0; q < 4; ++q) {
         double v = double(from_h16<KIND == 3>(hs[q]));
         if (l) v += double(from_h16<KIND == 3>(ls[q]));
-        m = fmax(m, fabs(v));
+        m = fmax(m, w(v, q));
       }
       return m;
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) m = fmax(m, fabs(operand_at<KIND>(hi, lo, i + q)));
+  for (int q = 0; q < 4; ++q) m = fmax(m, w(operand_at<KIND>(hi, lo, i + q), q));
   return m;
 }
 
@@ -2687,7 +2703,9 @@ __global__ void __launch_bounds__(256) tile_rowmax_kernel(const GemmArgs* __rest
           if (isA && (g.sAz != 0 || Z == 1)) ex = g.rowexp + z * g.M;
           else if (!isA) ex = g.colexp;
         }
-        if (ex) {
+        if (ex && c0 + 4 <= lim) {
+          m[u] = quad_absmax<KIND>(hi, lo, base + c0, ex + c0);
+        } else if (ex) {
           for (int q = 0; q < 4; ++q)
             if (c0 + q < lim)
               m[u] = fmax(m[u], ldexp(fabs(operand_at<KIND>(hi, lo, base + c0 + q)), ex[c0 + q]));
