@@ -493,13 +493,30 @@ __global__ void __launch_bounds__(256) expsum_ind_kernel(const DDProgram* P, con
       mk[i] = ((int64_t)1 << st->na[sub[i]]) - 1;
     }
   }
-  const int64_t stepg = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += stepg) {
-    int e = 0;
+  // four consecutive rows a thread, one 16-byte store where the address
+  // allows it; a member whose field starts at bit 2 or above has the same
+  // column for all four
+  const int64_t stepg = (int64_t)gridDim.x * blockDim.x * 4;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; r < count; r += stepg) {
+    int e[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < CQ_MAX_SUBCIRCUITS; ++i)
-      if (i < n) e += colmax_exp(P->colmax[sub[i]][(r >> sh[i]) & mk[i]]);
-    out[r] = e;
+    for (int i = 0; i < CQ_MAX_SUBCIRCUITS; ++i) {
+      if (i >= n) continue;
+      const uint64_t* cm = P->colmax[sub[i]];
+      if (sh[i] >= 2) {
+        const int v = colmax_exp(cm[(r >> sh[i]) & mk[i]]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += v;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += colmax_exp(cm[((r + j) >> sh[i]) & mk[i]]);
+      }
+    }
+    if (r + 4 <= count && (reinterpret_cast<uintptr_t>(out + r) & 15) == 0) {
+      *reinterpret_cast<int4*>(out + r) = make_int4(e[0], e[1], e[2], e[3]);
+    } else {
+      for (int j = 0; j < 4 && r + j < count; ++j) out[r + j] = e[j];
+    }
   }
 }
 
