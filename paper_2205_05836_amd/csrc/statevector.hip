@@ -198,10 +198,32 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
   for (int gi = 0; gi < G.ngates; ++gi) {
     const TileGate& g = G.g[gi];
     if (g.kind == CQ_GATE_CZ) {
-      const int both = (1 << g.a) | (1 << g.b);
+      // A run of CZs is diagonal: element tid + 256 e changes sign by the
+      // parity, over the run's pairs, of the product of the pair's two bits.
+      // Bits 0-7 are tid's and bits 8-10 e's, so per thread: s, the parity of
+      // the pairs inside tid; p bit r, that of the tid bits paired with bit
+      // 8 + r; rr, which pairs of bits 8-10 occur (an odd number of times).
+      uint32_t sgn = 0, p = 0, rr = 0;
+      int j = gi;
+      for (; j < G.ngates && G.g[j].kind == CQ_GATE_CZ; ++j) {
+        const int a = G.g[j].a, b = G.g[j].b;
+        if (a < 8 && b < 8) sgn ^= ((uint32_t)tid >> a) & ((uint32_t)tid >> b) & 1u;
+        else if (a < 8) p ^= (((uint32_t)tid >> a) & 1u) << (b - 8);
+        else if (b < 8) p ^= (((uint32_t)tid >> b) & 1u) << (a - 8);
+        else rr ^= 1u << ((a - 8) + (b - 8) - 1);  // bits (8,9), (8,10), (9,10)
+      }
+      gi = j - 1;
 #pragma unroll
-      for (int e = 0; e < kPerThread; ++e)
-        if (((tid + e * kSvThreads) & both) == both) v[e] = make_double2(-v[e].x, -v[e].y);
+      for (int e = 0; e < kPerThread; ++e) {
+        uint32_t f = sgn;
+        if (e & 1) f ^= p & 1u;
+        if (e & 2) f ^= (p >> 1) & 1u;
+        if (e & 4) f ^= (p >> 2) & 1u;
+        if ((e & 3) == 3) f ^= rr & 1u;
+        if ((e & 5) == 5) f ^= (rr >> 1) & 1u;
+        if ((e & 6) == 6) f ^= (rr >> 2) & 1u;
+        if (f) v[e] = make_double2(-v[e].x, -v[e].y);
+      }
     } else if (g.a >= 8) {
       if (g.a == 8) u_reg<0>(v, g.u);
       else if (g.a == 9) u_reg<1>(v, g.u);

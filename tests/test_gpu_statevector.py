@@ -53,6 +53,27 @@ def test_random_circuits_match_oracle(n, count, seed):
     assert abs(got.sum() - 1.0) < 1e-12
 
 
+def test_cz_runs_on_every_pair():
+    """Runs of CZ gates on every pair of an 11-qubit register (one full
+    tile): qubits 2-4 carry the most one-qubit gates of the first group (40
+    gates), so the host puts them on the register bits (qubits 7-10, the
+    lowest index bits, always sit on lane bits), and that group's CZ run
+    opens with their three pairs; the runs hold pairs of two register bits,
+    of a register bit and a thread-index bit, and of two thread-index bits,
+    each folded into one sign per element."""
+    rng = np.random.default_rng(9)
+    n = 11
+    layer = lambda: [wc.Op("u", (q,), wc.haar_u2(rng)) for q in range(n)]
+    first = [(2, 3), (2, 4), (3, 4)]
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n) if (a, b) not in first]
+    ops = [wc.Op("u", (q,), wc.haar_u2(rng)) for q in (2, 3, 4) for _ in range(3)] + layer()
+    ops += [wc.Op("cz", pq) for pq in first] + [wc.Op("cz", pairs[i]) for i in rng.permutation(len(pairs))]
+    pairs += first
+    ops += layer() + [wc.Op("cz", pairs[i]) for i in rng.permutation(len(pairs))[:20]] + layer()
+    got = cq().cq_simulate_probabilities(n, ops).cpu().numpy()
+    assert np.max(np.abs(got - sv.probabilities(n, ops))) < 1e-12
+
+
 def test_many_gates_on_few_qubits():
     """60 gates on 3 qubits of a 12-qubit register: groups split on the gate
     count, not on the tile width."""
