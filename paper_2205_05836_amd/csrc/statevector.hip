@@ -63,7 +63,7 @@ __device__ inline Complex cmul(double ur, double ui, Complex x) {
 }
 
 // `in` and `out` may be the same array (each workgroup reads and writes only
-// its own tile).
+// its own tile); a null `in` stands for |0...0> (nothing is read).
 __global__ void __launch_bounds__(kSvThreads) sv_tile_kernel(const double2* in, double2* out, double* probs,
                                                              TileGroup G) {
   __shared__ double2 S[kTile];
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_tile_kernel(const double2* in, 
     uint64_t a = base;
     for (int i = 0; i < G.k; ++i) a |= (uint64_t)((t >> i) & 1) << G.bits[i];
     addr[e] = a;
-    if (t < n) S[t] = in[a];
+    if (t < n) S[t] = in ? in[a] : make_double2(a == 0 ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   for (int gi = 0; gi < G.ngates; ++gi) {
@@ -194,7 +194,10 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
   };
   double2 v[kPerThread];
 #pragma unroll
-  for (int e = 0; e < kPerThread; ++e) v[e] = in[addr_of(e)];
+  for (int e = 0; e < kPerThread; ++e) {
+    const uint64_t a = addr_of(e);
+    v[e] = in ? in[a] : make_double2(a == 0 ? 1.0 : 0.0, 0.0);  // null in: |0...0>
+  }
   for (int gi = 0; gi < G.ngates; ++gi) {
     const TileGate& g = G.g[gi];
     if (g.kind == CQ_GATE_CZ) {
@@ -275,12 +278,6 @@ __global__ void __launch_bounds__(kSvThreads) sv_product_kernel(double2* __restr
     }
     psi[x] = make_double2(re, im);
   }
-}
-
-__global__ void __launch_bounds__(kSvThreads) sv_zero_state_kernel(double2* __restrict__ psi, int64_t size) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < size; x += step)
-    psi[x] = make_double2(x == 0 ? 1.0 : 0.0, 0.0);
 }
 
 unsigned fill_grid(int64_t size) {
@@ -415,16 +412,17 @@ hipError_t launch_tiles(int n, const TileGroup& G, const double2* in, double2* o
 // Applies `gates` then `tail` to psi in place; the last group writes
 // |amplitude|^2 to probs instead when probs is set (psi then keeps the state
 // before that group), and a probability pass runs alone when there are no
-// gates at all.
+// gates at all.  With zero_start the state starts as |0...0>, which the
+// first pass generates instead of reading psi.
 hipError_t run_gates(int n, const cq_gate* gates, int n_gates, const std::vector<cq_gate>& tail, double2* psi,
-                     double* probs, hipStream_t stream) {
+                     double* probs, hipStream_t stream, bool zero_start = false) {
   std::vector<Group> groups = make_groups(n, gates, n_gates, tail);
-  if (groups.empty() && probs) groups.push_back(Group());
+  if (groups.empty() && (probs || zero_start)) groups.push_back(Group());
   for (size_t i = 0; i < groups.size(); ++i) {
     const bool last = i + 1 == groups.size();
     const int mode = last && probs ? 1 : 0;
     const TileGroup G = tile_group(n, groups[i], gates, n_gates, tail, mode);
-    const hipError_t e = launch_tiles(n, G, psi, psi, probs, stream);
+    const hipError_t e = launch_tiles(n, G, i == 0 && zero_start ? nullptr : psi, psi, probs, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -459,10 +457,8 @@ extern "C" cq_status cq_simulate_probabilities(int32_t n, const cq_gate* gates, 
   if (st != CQ_OK) return st;
   if (!workspace || workspace_bytes < ((size_t)16 << n)) return fail(CQ_ERR_WORKSPACE, "workspace too small");
   double2* psi = static_cast<double2*>(workspace);
-  const int64_t size = (int64_t)1 << n;
-  hipLaunchKernelGGL(sv_zero_state_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi, size);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = run_gates(n, gates, n_gates, {}, psi, probs, stream);
+  // the first pass generates |0...0> itself (no zero fill, no read of it)
+  const hipError_t e = run_gates(n, gates, n_gates, {}, psi, probs, stream, true);
   if (e != hipSuccess) return sv_hip_error(e, "state-vector launch");
   return CQ_OK;
 }

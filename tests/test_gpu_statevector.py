@@ -53,6 +53,16 @@ def test_random_circuits_match_oracle(n, count, seed):
     assert abs(got.sum() - 1.0) < 1e-12
 
 
+@pytest.mark.parametrize("n", [3, 11, 12])
+def test_no_gates_gives_the_zero_state(n):
+    """With no gates the probabilities are those of |0...0>: the first (here
+    the only) pass generates that state instead of reading it."""
+    got = cq().cq_simulate_probabilities(n, []).cpu().numpy()
+    want = np.zeros(2 ** n)
+    want[0] = 1.0
+    assert np.array_equal(got, want)
+
+
 def test_cz_runs_on_every_pair():
     """Runs of CZ gates on every pair of an 11-qubit register (one full
     tile): qubits 2-4 carry the most one-qubit gates of the first group (40
