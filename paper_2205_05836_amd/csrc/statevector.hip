@@ -31,6 +31,7 @@ constexpr int kTile = 1 << kTileBits;
 constexpr int kSvThreads = 256;
 constexpr int kPerThread = kTile / kSvThreads;
 constexpr int kMaxGroupGates = 40;
+constexpr int kMaxBases = 9;  // measurement bases one tile pass writes (two measured slots)
 
 struct TileGate {
   int32_t kind;  // CQ_GATE_U or CQ_GATE_CZ
@@ -50,6 +51,9 @@ struct TileGroup {
   uint8_t bits[kTileBits];
   uint8_t outer[CQ_MAX_SV_QUBITS];
   TileGate g[kMaxGroupGates];
+  int32_t nbasis;                // sv_reg_kernel<true>: bases and their gate ranges
+  int32_t boff[kMaxBases + 1];
+  int64_t pstride;               // elements between the bases' outputs
 };
 
 static_assert(sizeof(TileGroup) + 3 * sizeof(void*) <= 4096, "kernel arguments exceed 4 KiB");
@@ -174,31 +178,11 @@ __device__ inline void u_lane(double2 (&v)[kPerThread], const double* u, int lan
   }
 }
 
-__global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, double2* out, double* probs,
-                                                            TileGroup G) {
-  static_assert(kPerThread == 8 && kSvThreads == 256, "bit layout assumes 8 elements a thread, 256 threads");
-  __shared__ double2 S[kTile];
-  uint64_t base = 0;
-  const uint64_t w = blockIdx.x;
-  for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
-  const int tid = threadIdx.x, lane = tid & 63;
-  // local index tid + 256 e: its bits 0-7 are tid's (one per-thread part of
-  // the address), bits 8-10 are e's (a part every thread shares), so no
-  // per-element address has to stay live from the load to the store
-  uint64_t tpart = base;
-  for (int i = 0; i < 8; ++i) tpart |= (uint64_t)((tid >> i) & 1) << G.bits[i];
-  auto addr_of = [&](int e) -> uint64_t {
-    uint64_t a = tpart;
-    for (int i = 8; i < kTileBits; ++i) a |= (uint64_t)((e >> (i - 8)) & 1) << G.bits[i];
-    return a;
-  };
-  double2 v[kPerThread];
-#pragma unroll
-  for (int e = 0; e < kPerThread; ++e) {
-    const uint64_t a = addr_of(e);
-    v[e] = in ? in[a] : make_double2(a == 0 ? 1.0 : 0.0, 0.0);  // null in: |0...0>
-  }
-  for (int gi = 0; gi < G.ngates; ++gi) {
+// Gates g0 .. g1 - 1 of the group on a thread's elements (see sv_reg_kernel);
+// S is the workgroup's exchange buffer.
+__device__ __forceinline__ void reg_apply(double2 (&v)[kPerThread], const TileGroup& G, int g0, int g1, int tid,
+                                          int lane, double2* S) {
+  for (int gi = g0; gi < g1; ++gi) {
     const TileGate& g = G.g[gi];
     if (g.kind == CQ_GATE_CZ) {
       // A run of CZs is diagonal: element tid + 256 e changes sign by the
@@ -208,7 +192,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
       // 8 + r; rr, which pairs of bits 8-10 occur (an odd number of times).
       uint32_t sgn = 0, p = 0, rr = 0;
       int j = gi;
-      for (; j < G.ngates && G.g[j].kind == CQ_GATE_CZ; ++j) {
+      for (; j < g1 && G.g[j].kind == CQ_GATE_CZ; ++j) {
         const int a = G.g[j].a, b = G.g[j].b;
         if (a < 8 && b < 8) sgn ^= ((uint32_t)tid >> a) & ((uint32_t)tid >> b) & 1u;
         else if (a < 8) p ^= (((uint32_t)tid >> a) & 1u) << (b - 8);
@@ -251,11 +235,54 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
       for (int e = 0; e < kPerThread; ++e) v[e] = u_exchange(c, v[e], S[(tid + e * kSvThreads) ^ m]);
     }
   }
+}
+
+// MULTI: the group holds the rotations of nbasis measurement bases (gates
+// boff[b] .. boff[b+1] - 1 for basis b); the tile is read once and each
+// basis writes |amplitude|^2 of its rotated copy to probs + b * pstride.
+template <bool MULTI>
+__global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, double2* out, double* probs,
+                                                            TileGroup G) {
+  static_assert(kPerThread == 8 && kSvThreads == 256, "bit layout assumes 8 elements a thread, 256 threads");
+  __shared__ double2 S[kTile];
+  uint64_t base = 0;
+  const uint64_t w = blockIdx.x;
+  for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
+  const int tid = threadIdx.x, lane = tid & 63;
+  // local index tid + 256 e: its bits 0-7 are tid's (one per-thread part of
+  // the address), bits 8-10 are e's (a part every thread shares), so no
+  // per-element address has to stay live from the load to the store
+  uint64_t tpart = base;
+  for (int i = 0; i < 8; ++i) tpart |= (uint64_t)((tid >> i) & 1) << G.bits[i];
+  auto addr_of = [&](int e) -> uint64_t {
+    uint64_t a = tpart;
+    for (int i = 8; i < kTileBits; ++i) a |= (uint64_t)((e >> (i - 8)) & 1) << G.bits[i];
+    return a;
+  };
+  double2 v[kPerThread];
 #pragma unroll
   for (int e = 0; e < kPerThread; ++e) {
     const uint64_t a = addr_of(e);
-    if (G.mode == 0) out[a] = v[e];
-    else probs[a] = v[e].x * v[e].x + v[e].y * v[e].y;
+    v[e] = in ? in[a] : make_double2(a == 0 ? 1.0 : 0.0, 0.0);  // null in: |0...0>
+  }
+  if constexpr (MULTI) {
+    for (int b = 0; b < G.nbasis; ++b) {
+      double2 r[kPerThread];
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) r[e] = v[e];
+      reg_apply(r, G, G.boff[b], G.boff[b + 1], tid, lane, S);
+      double* const pb = probs + (int64_t)b * G.pstride;
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) pb[addr_of(e)] = r[e].x * r[e].x + r[e].y * r[e].y;
+    }
+  } else {
+    reg_apply(v, G, 0, G.ngates, tid, lane, S);
+#pragma unroll
+    for (int e = 0; e < kPerThread; ++e) {
+      const uint64_t a = addr_of(e);
+      if (G.mode == 0) out[a] = v[e];
+      else probs[a] = v[e].x * v[e].x + v[e].y * v[e].y;
+    }
   }
 }
 
@@ -403,7 +430,7 @@ hipError_t launch_tiles(int n, const TileGroup& G, const double2* in, double2* o
                         hipStream_t stream) {
   const unsigned tiles = (unsigned)(1ull << (n - G.k));
   if (G.k == kTileBits)
-    hipLaunchKernelGGL(sv_reg_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, in, out, probs, G);
+    hipLaunchKernelGGL(sv_reg_kernel<false>, dim3(tiles), dim3(kSvThreads), 0, stream, in, out, probs, G);
   else
     hipLaunchKernelGGL(sv_tile_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, in, out, probs, G);
   return hipGetLastError();
@@ -512,7 +539,8 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
     hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi, size, K);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = run_gates(w, gates, n_gates, {}, psi, nullptr, stream);
-    for (int64_t b = 0; b < n_basis && e == hipSuccess; ++b) {
+    // rotations of measurement basis b (digit 1: X, 2: Y per measured slot)
+    auto basis_rot = [&](int64_t b) {
       std::vector<cq_gate> rot;
       int64_t rest = b;
       std::vector<int> digits(o);
@@ -524,6 +552,32 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
         if (digits[u] == 1) rot.push_back(u_gate(si.meas_slots[u], rot_x));
         if (digits[u] == 2) rot.push_back(u_gate(si.meas_slots[u], rot_y));
       }
+      return rot;
+    };
+    if (e == hipSuccess && w >= kTileBits && n_basis <= kMaxBases) {
+      // one pass reads the post-circuit tile once and writes every basis
+      std::vector<cq_gate> all;
+      std::vector<int> off{0};
+      for (int64_t b = 0; b < n_basis; ++b) {
+        const std::vector<cq_gate> rot = basis_rot(b);
+        all.insert(all.end(), rot.begin(), rot.end());
+        off.push_back((int)all.size());
+      }
+      Group grp;
+      for (int i = 0; i < (int)all.size(); ++i) {
+        grp.gates.push_back(i);
+        grp.mask |= 1ull << (w - 1 - all[i].q0);
+      }
+      TileGroup G = tile_group(w, grp, nullptr, 0, all, 1);
+      G.nbasis = (int)n_basis;
+      for (int b = 0; b <= (int)n_basis; ++b) G.boff[b] = off[b];
+      G.pstride = size;
+      hipLaunchKernelGGL(sv_reg_kernel<true>, dim3((unsigned)(1ull << (w - kTileBits))), dim3(kSvThreads), 0,
+                         stream, (const double2*)psi, psi, variants + j * n_basis * size, G);
+      e = hipGetLastError();
+    }
+    for (int64_t b = 0; b < n_basis && e == hipSuccess && !(w >= kTileBits && n_basis <= kMaxBases); ++b) {
+      const std::vector<cq_gate> rot = basis_rot(b);
       // the rotations read psi and write probabilities only, so psi stays
       // the post-circuit state for the next basis; at most CQ_MAX_LOCAL_CUTS
       // measured slots, so they form one group

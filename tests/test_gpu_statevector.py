@@ -120,6 +120,27 @@ def test_variants_match_oracle(name, cc):
         assert np.allclose(got.sum(axis=-1), 1.0, atol=1e-12)
 
 
+@pytest.mark.parametrize("w,meas", [(13, (3, 9)), (11, (10,)), (12, ())])
+def test_variants_bases_in_one_pass(w, meas):
+    """A register of at least 11 slots with at most two measured cut ends:
+    one pass reads the post-circuit state once and writes every measurement
+    basis (up to nine); two initialised ends give 16 initial states."""
+    rng = np.random.default_rng(40 + w)
+    init = (0, 6)
+    ic = [-1] * w
+    mc = [-1] * w
+    for i, s_ in enumerate(init):
+        ic[s_] = i
+    for i, s_ in enumerate(meas):
+        mc[s_] = len(init) + i
+    ops = random_ops(rng, w, 6 * w)
+    spec = wc.SubcircuitSpec(w, ic, mc, [(q, 0) for q in range(w)], ops)
+    got = cq().cq_variant_probabilities(spec).cpu().numpy()
+    want = sv.variant_probabilities(spec)
+    assert got.shape == want.shape == (16, 3 ** len(meas), 2 ** w)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
 def test_slot_both_initialised_and_measured():
     """A wire cut twice leaves a middle segment that a cut initialises and
     another cut measures: init and basis digits both land on one slot."""
