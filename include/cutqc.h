@@ -419,7 +419,9 @@ cq_status cq_simulate_workspace_size(int32_t n, size_t* bytes);
 /* |psi|^2 of gates applied to |0...0>.  gates: host, read during the call.
  * probs: device, 2^n FP64, written.  workspace: device, at least
  * cq_simulate_workspace_size bytes; it holds the state before the last
- * group of gates on return.  Asynchronous on `stream`.  Errors (before any
+ * group of gates on return when there are two or more groups (the first
+ * group generates |0...0> itself, so a single group leaves it unwritten).
+ * Asynchronous on `stream`.  Errors (before any
  * launch): CQ_ERR_SHAPE for n out of range, CQ_ERR_ARG for a gate with an
  * unknown kind, a qubit out of range, equal CZ qubits or a non-finite
  * matrix entry, CQ_ERR_WORKSPACE. */
