@@ -428,7 +428,11 @@ cq_status cq_simulate_workspace_size(int32_t n, size_t* bytes);
 cq_status cq_simulate_probabilities(int32_t n, const cq_gate* gates, int32_t n_gates, double* probs,
                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* 16 * 2^width bytes (one state). */
+/* 16 * 2^width bytes per state.  Registers of at least 11 slots with at most
+ * two measured ends simulate several initial states at once: the size then
+ * covers up to 16 states (no more than the init strings, and within 4 GiB);
+ * cq_variant_probabilities takes as many as the workspace it is given
+ * holds, so one state's worth still works, more slowly. */
 cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t* bytes);
 
 /* Every variant of subcircuit `sub` running `gates` (qubits = its register
@@ -438,7 +442,8 @@ cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t* bytes);
  * 0..2, rotated by nothing, H, or H S^dagger before the computational-basis
  * measurement), the probabilities of the 2^width register outcomes.
  * variants: device, FP64, layout (4^r, 3^o, 2^width) as cq_attribute reads
- * it, written whole.  workspace: device, cq_variants_workspace_size bytes.
+ * it, written whole.  workspace: device, at least one state (16 * 2^width
+ * bytes); cq_variants_workspace_size bytes let it batch initial states.
  * Asynchronous on `stream`; errors as for cq_simulate_probabilities plus
  * the cut-map checks of the subcircuit. */
 cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq_gate* gates, int32_t n_gates,

@@ -54,6 +54,10 @@ struct TileGroup {
   int32_t nbasis;                // sv_reg_kernel<true>: bases and their gate ranges
   int32_t boff[kMaxBases + 1];
   int64_t pstride;               // elements between the bases' outputs
+  // sv_reg_kernel with blockIdx.y = state s of a batch: in and out start
+  // s * bstride elements on, probs s * pbstride on (both 0 without a batch)
+  int64_t bstride;
+  int64_t pbstride;
 };
 
 static_assert(sizeof(TileGroup) + 3 * sizeof(void*) <= 4096, "kernel arguments exceed 4 KiB");
@@ -245,6 +249,11 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
                                                             TileGroup G) {
   static_assert(kPerThread == 8 && kSvThreads == 256, "bit layout assumes 8 elements a thread, 256 threads");
   __shared__ double2 S[kTile];
+  if (blockIdx.y) {  // state blockIdx.y of a batch
+    if (in) in += blockIdx.y * G.bstride;
+    out += blockIdx.y * G.bstride;
+    if (probs) probs += blockIdx.y * G.pbstride;
+  }
   uint64_t base = 0;
   const uint64_t w = blockIdx.x;
   for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
@@ -455,6 +464,23 @@ hipError_t run_gates(int n, const cq_gate* gates, int n_gates, const std::vector
   return hipSuccess;
 }
 
+// Initial states simulated together by cq_variant_probabilities: all of
+// them, up to 16 and within 4 GiB of states, when the variants take the
+// one-pass-bases path (a full tile, at most kMaxBases bases), else one; and
+// no more than `ws` bytes hold.
+int64_t variant_batch(const SubInfo& si, size_t ws) {
+  const int w = si.width;
+  int64_t n_init = 1, n_basis = 1;
+  for (int i = 0; i < si.r(); ++i) n_init *= 4;
+  for (int i = 0; i < si.o(); ++i) n_basis *= 3;
+  if (w < kTileBits || n_basis > kMaxBases) return 1;
+  const size_t state = (size_t)16 << w;
+  int64_t b = std::min<int64_t>(n_init, 16);
+  b = std::min<int64_t>(b, (int64_t)(((size_t)4 << 30) / state));
+  b = std::min<int64_t>(b, (int64_t)(ws / state));
+  return b < 1 ? 1 : b;
+}
+
 cq_gate u_gate(int q, const double (&m)[8]) {
   cq_gate g{};
   g.kind = CQ_GATE_U;
@@ -496,7 +522,7 @@ extern "C" cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t
   cq_status st = build_subinfo(sub, si);
   if (st != CQ_OK) return st;
   if (si.width < 1) return fail(CQ_ERR_SHAPE, "subcircuit has no slots");
-  *bytes = (size_t)16 << si.width;
+  *bytes = ((size_t)16 << si.width) * (size_t)variant_batch(si, (size_t)-1);
   return CQ_OK;
 }
 
@@ -525,67 +551,95 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
   // Y (S^dagger then H, i.e. H S^dagger = [[1, -i], [1, i]] / sqrt 2)
   const double rot_x[8] = {h, 0, h, 0, h, 0, -h, 0};
   const double rot_y[8] = {h, 0, 0, -h, h, 0, 0, h};
-  for (int64_t j = 0; j < n_init; ++j) {
-    Kets K{};
-    K.n = w;
-    for (int q = 0; q < w; ++q) {
-      K.k[q][0] = 1.0;
-      K.k[q][1] = K.k[q][2] = K.k[q][3] = 0.0;
+  // rotations of measurement basis b (digit 1: X, 2: Y per measured slot)
+  auto basis_rot = [&](int64_t b) {
+    std::vector<cq_gate> rot;
+    int64_t rest = b;
+    std::vector<int> digits(o);
+    for (int u = o - 1; u >= 0; --u) {
+      digits[u] = (int)(rest % 3);
+      rest /= 3;
     }
-    for (int t = 0; t < r; ++t) {
-      const int digit = (int)((j >> (2 * (r - 1 - t))) & 3);
-      for (int c = 0; c < 4; ++c) K.k[si.init_slots[t]][c] = init_ket[digit][c];
+    for (int u = 0; u < o; ++u) {
+      if (digits[u] == 1) rot.push_back(u_gate(si.meas_slots[u], rot_x));
+      if (digits[u] == 2) rot.push_back(u_gate(si.meas_slots[u], rot_y));
     }
-    hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi, size, K);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = run_gates(w, gates, n_gates, {}, psi, nullptr, stream);
-    // rotations of measurement basis b (digit 1: X, 2: Y per measured slot)
-    auto basis_rot = [&](int64_t b) {
-      std::vector<cq_gate> rot;
-      int64_t rest = b;
-      std::vector<int> digits(o);
-      for (int u = o - 1; u >= 0; --u) {
-        digits[u] = (int)(rest % 3);
-        rest /= 3;
+    return rot;
+  };
+  // the one-pass-bases path (a full tile, at most kMaxBases bases) takes a
+  // batch of initial states at once, as many as the workspace holds
+  const bool one_pass = w >= kTileBits && n_basis <= kMaxBases;
+  const int64_t batch = variant_batch(si, workspace_bytes);
+  const unsigned tiles = one_pass ? (unsigned)(1ull << (w - kTileBits)) : 0u;
+  TileGroup GB{};
+  if (one_pass) {
+    std::vector<cq_gate> all;
+    std::vector<int> off{0};
+    for (int64_t b = 0; b < n_basis; ++b) {
+      const std::vector<cq_gate> rot = basis_rot(b);
+      all.insert(all.end(), rot.begin(), rot.end());
+      off.push_back((int)all.size());
+    }
+    Group grp;
+    for (int i = 0; i < (int)all.size(); ++i) {
+      grp.gates.push_back(i);
+      grp.mask |= 1ull << (w - 1 - all[i].q0);
+    }
+    GB = tile_group(w, grp, nullptr, 0, all, 1);
+    GB.nbasis = (int)n_basis;
+    for (int b = 0; b <= (int)n_basis; ++b) GB.boff[b] = off[b];
+    GB.pstride = size;
+    GB.bstride = size;
+    GB.pbstride = n_basis * size;
+  }
+  const std::vector<Group> circuit = one_pass ? make_groups(w, gates, n_gates, {}) : std::vector<Group>();
+  for (int64_t j0 = 0; j0 < n_init; j0 += batch) {
+    const int64_t nb = std::min<int64_t>(batch, n_init - j0);
+    hipError_t e = hipSuccess;
+    for (int64_t jj = 0; jj < nb && e == hipSuccess; ++jj) {
+      const int64_t j = j0 + jj;
+      Kets K{};
+      K.n = w;
+      for (int q = 0; q < w; ++q) {
+        K.k[q][0] = 1.0;
+        K.k[q][1] = K.k[q][2] = K.k[q][3] = 0.0;
       }
-      for (int u = 0; u < o; ++u) {
-        if (digits[u] == 1) rot.push_back(u_gate(si.meas_slots[u], rot_x));
-        if (digits[u] == 2) rot.push_back(u_gate(si.meas_slots[u], rot_y));
+      for (int t = 0; t < r; ++t) {
+        const int digit = (int)((j >> (2 * (r - 1 - t))) & 3);
+        for (int c = 0; c < 4; ++c) K.k[si.init_slots[t]][c] = init_ket[digit][c];
       }
-      return rot;
-    };
-    if (e == hipSuccess && w >= kTileBits && n_basis <= kMaxBases) {
-      // one pass reads the post-circuit tile once and writes every basis
-      std::vector<cq_gate> all;
-      std::vector<int> off{0};
-      for (int64_t b = 0; b < n_basis; ++b) {
-        const std::vector<cq_gate> rot = basis_rot(b);
-        all.insert(all.end(), rot.begin(), rot.end());
-        off.push_back((int)all.size());
-      }
-      Group grp;
-      for (int i = 0; i < (int)all.size(); ++i) {
-        grp.gates.push_back(i);
-        grp.mask |= 1ull << (w - 1 - all[i].q0);
-      }
-      TileGroup G = tile_group(w, grp, nullptr, 0, all, 1);
-      G.nbasis = (int)n_basis;
-      for (int b = 0; b <= (int)n_basis; ++b) G.boff[b] = off[b];
-      G.pstride = size;
-      hipLaunchKernelGGL(sv_reg_kernel<true>, dim3((unsigned)(1ull << (w - kTileBits))), dim3(kSvThreads), 0,
-                         stream, (const double2*)psi, psi, variants + j * n_basis * size, G);
+      hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi + jj * size, size,
+                         K);
       e = hipGetLastError();
     }
-    for (int64_t b = 0; b < n_basis && e == hipSuccess && !(w >= kTileBits && n_basis <= kMaxBases); ++b) {
-      const std::vector<cq_gate> rot = basis_rot(b);
-      // the rotations read psi and write probabilities only, so psi stays
-      // the post-circuit state for the next basis; at most CQ_MAX_LOCAL_CUTS
-      // measured slots, so they form one group
-      double* out = variants + (j * n_basis + b) * size;
-      std::vector<Group> groups = make_groups(w, nullptr, 0, rot);
-      if (groups.empty()) groups.push_back(Group());
-      const TileGroup G = tile_group(w, groups[0], nullptr, 0, rot, 1);
-      e = launch_tiles(w, G, psi, psi, out, stream);
+    if (one_pass) {
+      // the circuit on every state of the batch (grid y = state), then one
+      // pass that reads each post-circuit tile once and writes every basis
+      for (size_t g = 0; g < circuit.size() && e == hipSuccess; ++g) {
+        TileGroup G = tile_group(w, circuit[g], gates, n_gates, {}, 0);
+        G.bstride = size;
+        hipLaunchKernelGGL(sv_reg_kernel<false>, dim3(tiles, (unsigned)nb), dim3(kSvThreads), 0, stream,
+                           (const double2*)psi, psi, (double*)nullptr, G);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(sv_reg_kernel<true>, dim3(tiles, (unsigned)nb), dim3(kSvThreads), 0, stream,
+                           (const double2*)psi, psi, variants + j0 * n_basis * size, GB);
+        e = hipGetLastError();
+      }
+    } else {
+      if (e == hipSuccess) e = run_gates(w, gates, n_gates, {}, psi, nullptr, stream);
+      for (int64_t b = 0; b < n_basis && e == hipSuccess; ++b) {
+        const std::vector<cq_gate> rot = basis_rot(b);
+        // the rotations read psi and write probabilities only, so psi stays
+        // the post-circuit state for the next basis; at most
+        // CQ_MAX_LOCAL_CUTS measured slots, so they form one group
+        double* out = variants + (j0 * n_basis + b) * size;
+        std::vector<Group> groups = make_groups(w, nullptr, 0, rot);
+        if (groups.empty()) groups.push_back(Group());
+        const TileGroup G = tile_group(w, groups[0], nullptr, 0, rot, 1);
+        e = launch_tiles(w, G, psi, psi, out, stream);
+      }
     }
     if (e != hipSuccess) return sv_hip_error(e, "variant launch");
   }

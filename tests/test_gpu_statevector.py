@@ -141,6 +141,32 @@ def test_variants_bases_in_one_pass(w, meas):
     assert np.max(np.abs(got - want)) < 1e-12
 
 
+@pytest.mark.parametrize("states", [1, 3])
+def test_variants_with_a_smaller_workspace(states):
+    """A workspace of `states` states (fewer than the 16 the size query asks
+    for): the initial states run in batches of that many, the last one
+    partial, with the same results."""
+    from paper_2205_05836_amd import _lib
+    from paper_2205_05836_amd.api import _Subs, _dev_ptr, _gates, _stream
+    rng = np.random.default_rng(77)
+    w = 12
+    ic = [-1] * w
+    mc = [-1] * w
+    ic[1], ic[7], mc[4], mc[10] = 0, 1, 2, 3
+    ops = random_ops(rng, w, 5 * w)
+    spec = wc.SubcircuitSpec(w, ic, mc, [(q, 0) for q in range(w)], ops)
+    out = torch.full((16, 9, 2 ** w), -1.0, dtype=torch.float64, device=DEV)
+    nbytes = states * (16 << w)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    subs = _Subs([spec])
+    arr, cnt = _gates(ops)
+    assert _lib.lib().cq_variant_probabilities(subs.ptr(), arr, cnt, _dev_ptr(out), _dev_ptr(ws), nbytes,
+                                               _stream(None)) == 0
+    torch.cuda.synchronize()
+    want = sv.variant_probabilities(spec)
+    assert np.max(np.abs(out.cpu().numpy() - want)) < 1e-12
+
+
 def test_slot_both_initialised_and_measured():
     """A wire cut twice leaves a middle segment that a cut initialises and
     another cut measures: init and basis digits both land on one slot."""
