@@ -299,13 +299,21 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
 struct Kets {
   int32_t n;
   double k[CQ_MAX_WIDTH][4];  // (re, im) of <0|ket>, <1|ket> per qubit
+  uint64_t zero;              // index bits of the qubits whose ket is exactly |0>
 };
 
+// Qubits in |0> contribute a factor of exactly 1 where their bit is 0 and
+// make the amplitude 0 where it is 1, so only the others are multiplied.
 __global__ void __launch_bounds__(kSvThreads) sv_product_kernel(double2* __restrict__ psi, int64_t size, Kets K) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < size; x += step) {
+    if ((uint64_t)x & K.zero) {
+      psi[x] = make_double2(0.0, 0.0);
+      continue;
+    }
     double re = 1.0, im = 0.0;
     for (int q = 0; q < K.n; ++q) {
+      if ((K.zero >> (K.n - 1 - q)) & 1ull) continue;
       const int bit = (int)((x >> (K.n - 1 - q)) & 1);
       const double kr = K.k[q][2 * bit], ki = K.k[q][2 * bit + 1];
       const double nr = re * kr - im * ki;
@@ -608,6 +616,9 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
         const int digit = (int)((j >> (2 * (r - 1 - t))) & 3);
         for (int c = 0; c < 4; ++c) K.k[si.init_slots[t]][c] = init_ket[digit][c];
       }
+      K.zero = 0;
+      for (int q = 0; q < w; ++q)
+        if (K.k[q][0] == 1.0 && K.k[q][1] == 0.0 && K.k[q][2] == 0.0 && K.k[q][3] == 0.0) K.zero |= 1ull << (w - 1 - q);
       hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi + jj * size, size,
                          K);
       e = hipGetLastError();
