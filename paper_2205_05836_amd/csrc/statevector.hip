@@ -295,6 +295,77 @@ __global__ void __launch_bounds__(kSvThreads) sv_reg_kernel(const double2* in, d
   }
 }
 
+// Variants by linearity.  An init string prepares each init slot t in
+// ket(d_t) = c0(d_t)|0> + c1(d_t)|1> (|0>, |1>, |+>, |+i>), so its
+// post-circuit state is sum over c in {0,1}^r of w_j(c) S_c, with
+// w_j(c) = prod_t c_{c_t}(d_t) and S_c the post-circuit state of the
+// computational init string c (slot t in |c_t>, c_t bit r - 1 - t of c).  The
+// 2^r states S_c (r <= 2) sit `G.bstride` elements apart from `in`; for each
+// measurement basis b every S_c tile is read and rotated (gates
+// boff[b] .. boff[b+1] - 1), and each init string j (digit t of j base 4,
+// first slot most significant) writes |sum_c w_j(c) R_b S_c|^2 to
+// probs + (j * nbasis + b) * pstride.
+__device__ __constant__ double kInitKet[4][4] = {
+    {1.0, 0.0, 0.0, 0.0},
+    {0.0, 0.0, 1.0, 0.0},
+    {0.70710678118654752440, 0.0, 0.70710678118654752440, 0.0},
+    {0.70710678118654752440, 0.0, 0.0, 0.70710678118654752440}};
+
+__global__ void __launch_bounds__(kSvThreads) sv_combine_kernel(const double2* in, double* probs, TileGroup G,
+                                                                int r) {
+  __shared__ double2 S[kTile];
+  uint64_t base = 0;
+  const uint64_t w = blockIdx.x;
+  for (int i = 0; i < G.nouter; ++i) base |= ((w >> i) & 1ull) << G.outer[i];
+  const int tid = threadIdx.x, lane = tid & 63;
+  uint64_t tpart = base;
+  for (int i = 0; i < 8; ++i) tpart |= (uint64_t)((tid >> i) & 1) << G.bits[i];
+  auto addr_of = [&](int e) -> uint64_t {
+    uint64_t a = tpart;
+    for (int i = 8; i < kTileBits; ++i) a |= (uint64_t)((e >> (i - 8)) & 1) << G.bits[i];
+    return a;
+  };
+  const int nc = 1 << r, nj = 1 << (2 * r);
+  for (int b = 0; b < G.nbasis; ++b) {
+    double2 rs[4][kPerThread];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= nc) break;
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) rs[c][e] = in[c * G.bstride + addr_of(e)];
+      reg_apply(rs[c], G, G.boff[b], G.boff[b + 1], tid, lane, S);
+    }
+    for (int j = 0; j < nj; ++j) {
+      double wr[4], wi[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double ar = 1.0, ai = 0.0;
+        for (int t = 0; t < r; ++t) {
+          const int d = (j >> (2 * (r - 1 - t))) & 3, bit = (c >> (r - 1 - t)) & 1;
+          const double kr = kInitKet[d][2 * bit], ki = kInitKet[d][2 * bit + 1];
+          const double nr = ar * kr - ai * ki;
+          ai = ar * ki + ai * kr;
+          ar = nr;
+        }
+        wr[c] = ar;
+        wi[c] = ai;
+      }
+      double* const pj = probs + ((int64_t)j * G.nbasis + b) * G.pstride;
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) {
+        double xr = 0.0, xi = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (c >= nc) break;
+          xr += wr[c] * rs[c][e].x - wi[c] * rs[c][e].y;
+          xi += wr[c] * rs[c][e].y + wi[c] * rs[c][e].x;
+        }
+        pj[addr_of(e)] = xr * xr + xi * xi;
+      }
+    }
+  }
+}
+
 // Product state: amplitude(x) = prod over qubits q of ket_q[bit q of x].
 struct Kets {
   int32_t n;
@@ -601,6 +672,44 @@ extern "C" cq_status cq_variant_probabilities(const cq_subcircuit* sub, const cq
     GB.pbstride = n_basis * size;
   }
   const std::vector<Group> circuit = one_pass ? make_groups(w, gates, n_gates, {}) : std::vector<Group>();
+  // by linearity (one or two init slots): simulate the 2^r computational
+  // init strings only and combine them per init string in the bases pass
+  if (one_pass && r >= 1 && r <= 2 && workspace_bytes >= ((size_t)16 << w) * ((size_t)1 << r)) {
+    const int nc = 1 << r;
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < nc && e == hipSuccess; ++c) {
+      Kets K{};
+      K.n = w;
+      for (int q = 0; q < w; ++q) {
+        K.k[q][0] = 1.0;
+        K.k[q][1] = K.k[q][2] = K.k[q][3] = 0.0;
+      }
+      for (int t = 0; t < r; ++t) {
+        const int bit = (c >> (r - 1 - t)) & 1;
+        for (int q = 0; q < 4; ++q) K.k[si.init_slots[t]][q] = init_ket[bit][q];
+      }
+      K.zero = 0;
+      for (int q = 0; q < w; ++q)
+        if (K.k[q][0] == 1.0 && K.k[q][1] == 0.0 && K.k[q][2] == 0.0 && K.k[q][3] == 0.0) K.zero |= 1ull << (w - 1 - q);
+      hipLaunchKernelGGL(sv_product_kernel, dim3(fill_grid(size)), dim3(kSvThreads), 0, stream, psi + c * size, size,
+                         K);
+      e = hipGetLastError();
+    }
+    for (size_t g = 0; g < circuit.size() && e == hipSuccess; ++g) {
+      TileGroup G = tile_group(w, circuit[g], gates, n_gates, {}, 0);
+      G.bstride = size;
+      hipLaunchKernelGGL(sv_reg_kernel<false>, dim3(tiles, (unsigned)nc), dim3(kSvThreads), 0, stream,
+                         (const double2*)psi, psi, (double*)nullptr, G);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(sv_combine_kernel, dim3(tiles), dim3(kSvThreads), 0, stream, (const double2*)psi, variants, GB,
+                         r);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return sv_hip_error(e, "variant launch");
+    return CQ_OK;
+  }
   for (int64_t j0 = 0; j0 < n_init; j0 += batch) {
     const int64_t nb = std::min<int64_t>(batch, n_init - j0);
     hipError_t e = hipSuccess;

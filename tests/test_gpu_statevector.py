@@ -120,13 +120,14 @@ def test_variants_match_oracle(name, cc):
         assert np.allclose(got.sum(axis=-1), 1.0, atol=1e-12)
 
 
-@pytest.mark.parametrize("w,meas", [(13, (3, 9)), (11, (10,)), (12, ())])
-def test_variants_bases_in_one_pass(w, meas):
+@pytest.mark.parametrize("w,init,meas", [(13, (0, 6), (3, 9)), (11, (0, 6), (10,)), (12, (0, 6), ()),
+                                         (12, (5,), (2, 11))])
+def test_variants_bases_in_one_pass(w, init, meas):
     """A register of at least 11 slots with at most two measured cut ends:
-    one pass reads the post-circuit state once and writes every measurement
-    basis (up to nine); two initialised ends give 16 initial states."""
-    rng = np.random.default_rng(40 + w)
-    init = (0, 6)
+    one pass writes every measurement basis (up to nine).  With one or two
+    initialised ends only the 2^r computational init strings are simulated
+    and each of the 4^r init strings is combined from them in that pass."""
+    rng = np.random.default_rng(40 + w + len(init))
     ic = [-1] * w
     mc = [-1] * w
     for i, s_ in enumerate(init):
@@ -137,7 +138,7 @@ def test_variants_bases_in_one_pass(w, meas):
     spec = wc.SubcircuitSpec(w, ic, mc, [(q, 0) for q in range(w)], ops)
     got = cq().cq_variant_probabilities(spec).cpu().numpy()
     want = sv.variant_probabilities(spec)
-    assert got.shape == want.shape == (16, 3 ** len(meas), 2 ** w)
+    assert got.shape == want.shape == (4 ** len(init), 3 ** len(meas), 2 ** w)
     assert np.max(np.abs(got - want)) < 1e-12
 
 
