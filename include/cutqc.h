@@ -429,10 +429,11 @@ cq_status cq_simulate_probabilities(int32_t n, const cq_gate* gates, int32_t n_g
                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* 16 * 2^width bytes per state.  Registers of at least 11 slots with at most
- * two measured ends simulate several initial states at once: the size then
- * covers up to 16 states (no more than the init strings, and within 4 GiB);
- * cq_variant_probabilities takes as many as the workspace it is given
- * holds, so one state's worth still works, more slowly. */
+ * two measured ends hold several states at once: with one or two
+ * initialised ends the 2^r computational init strings (every variant is a
+ * combination of their results), else up to 16 init strings, within 4 GiB;
+ * the size covers that many.  cq_variant_probabilities works with any
+ * workspace of at least one state, more slowly below this size. */
 cq_status cq_variants_workspace_size(const cq_subcircuit* sub, size_t* bytes);
 
 /* Every variant of subcircuit `sub` running `gates` (qubits = its register

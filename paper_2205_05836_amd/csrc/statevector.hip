@@ -543,10 +543,10 @@ hipError_t run_gates(int n, const cq_gate* gates, int n_gates, const std::vector
   return hipSuccess;
 }
 
-// Initial states simulated together by cq_variant_probabilities: all of
-// them, up to 16 and within 4 GiB of states, when the variants take the
-// one-pass-bases path (a full tile, at most kMaxBases bases), else one; and
-// no more than `ws` bytes hold.
+// States cq_variant_probabilities holds at once on the one-pass-bases path
+// (a full tile, at most kMaxBases bases): the 2^r computational init strings
+// with one or two initialised ends (the linear path), else all init strings
+// up to 16; within 4 GiB and no more than `ws` bytes hold; one otherwise.
 int64_t variant_batch(const SubInfo& si, size_t ws) {
   const int w = si.width;
   int64_t n_init = 1, n_basis = 1;
@@ -554,7 +554,7 @@ int64_t variant_batch(const SubInfo& si, size_t ws) {
   for (int i = 0; i < si.o(); ++i) n_basis *= 3;
   if (w < kTileBits || n_basis > kMaxBases) return 1;
   const size_t state = (size_t)16 << w;
-  int64_t b = std::min<int64_t>(n_init, 16);
+  int64_t b = si.r() >= 1 && si.r() <= 2 ? ((int64_t)1 << si.r()) : std::min<int64_t>(n_init, 16);
   b = std::min<int64_t>(b, (int64_t)(((size_t)4 << 30) / state));
   b = std::min<int64_t>(b, (int64_t)(ws / state));
   return b < 1 ? 1 : b;
